@@ -1,0 +1,71 @@
+"""Pins of the refinement oracle and determinism of the input generator."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import refine
+from oracle import response as R
+
+
+def test_generator_is_deterministic():
+    a = synth.config1(0).spec
+    b = synth.config1(0).spec
+    c = synth.config1(1).spec
+    assert a.dtype == np.complex64 and a.size == 65536
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, c)
+    assert a[0] == 0
+    # median normalisation: noise powers ~ Exp(1)
+    p = np.abs(a.astype(np.complex128)) ** 2
+    assert abs(np.median(p[1:]) - math.log(2.0)) < 1e-4
+    assert abs(p.mean() - 1.0) < 0.03
+
+
+def test_refine_gradient_matches_finite_differences():
+    x = synth.random_spectrum(512, seed=11)
+    r = np.array([100.31, 200.77, 301.5, 50.2])
+    z = np.array([0.0, 3.3, -12.0, 40.0])
+    P, gr, gz = refine.power_grad(x, r, z)
+    h = 1e-3
+    fr = (refine.power(x, r + h, z)[0] - refine.power(x, r - h, z)[0]) / (2 * h)
+    fz = (refine.power(x, r, z + h)[0] - refine.power(x, r, z - h)[0]) / (2 * h)
+    scale = np.maximum(np.abs(P), 1.0)
+    assert np.max(np.abs(gr - fr) / scale) < 1e-5
+    assert np.max(np.abs(gz - fz) / scale) < 1e-5
+
+
+def test_refine_power_matches_template_correlation_at_integer_r():
+    # at integer r and the same z the 32-tap interpolated amplitude is the
+    # correlation with unnormalised taps over the bins k = r - 15 .. r + 16
+    x = synth.random_spectrum(256, seed=5).astype(np.complex128)
+    r, z = 120.0, 6.0
+    P, F = refine.power(x, [r], [z])
+    k = np.arange(int(r) - 15, int(r) + 17)
+    g = np.conj(R.response(r - z / 2 - k, z))
+    assert abs(F[0] - np.sum(x[k] * g)) < 1e-12
+
+
+def test_peak_curvature_and_ascent_converge_on_chirp():
+    # noise-free complex chirp at (r_bar, z0): the ascent from an offset start
+    # converges to the injected (r_bar, z0); curvatures -2 pi^2 P / 3 and
+    # -pi^2 P / 90 at the top
+    n_t, r_bar, z0 = 1 << 13, 1500.4, 8.6
+    x = synth.complex_chirp_spectrum(n_t, r_bar - z0 / 2, z0)
+    r, z, P, gr, gz = refine.ascend(x, [r_bar - 0.3], [z0 + 0.8], steps=20)
+    # converged: the gradient vanishes; the 32-bin window biases the maximum
+    # of the truncated power by a few thousandths of a bin (halving per
+    # doubling of the window)
+    assert abs(gr[0]) < 1e-6 * P[0] and abs(gz[0]) < 1e-6 * P[0]
+    assert abs(r[0] - r_bar) < 1e-2 and abs(z[0] - z0) < 2e-2
+    r2, z2, *_ = refine.ascend(x, [r_bar - 0.3], [z0 + 0.8], steps=30, taps=128)
+    assert abs(r2[0] - r_bar) < 0.5 * abs(r[0] - r_bar)
+    h = 0.05
+    pr = refine.power(x, [r[0] - h, r[0], r[0] + h], [z[0]] * 3)[0]
+    d2r = (pr[0] - 2 * pr[1] + pr[2]) / h ** 2
+    assert d2r / (-2 * math.pi ** 2 * pr[1] / 3) == pytest.approx(1.0, abs=0.05)
+    hz = 0.3
+    pz = refine.power(x, [r[0]] * 3, [z[0] - hz, z[0], z[0] + hz])[0]
+    d2z = (pz[0] - 2 * pz[1] + pz[2]) / hz ** 2
+    assert d2z / (-math.pi ** 2 * pz[1] / 90) == pytest.approx(1.0, abs=0.1)
