@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark of the FDAS hot path: f-fdot plane cells/s, BF16 vs FP32, on one GPU.
+
+Workload (single-DM): 2^23 samples at 64 us -> 4,194,304 complex bins,
+101 templates (z in [-100, 100] step 2), 256 taps, segment 8192, one injected
+8-harmonic binary pulsar (seeded, synthetic).  A step is one fdas_correlate of
+the whole plane (101 x 4,194,304 cells) with the spectrum already resident in
+device memory.  The headline value is the BF16 form (bfloat16 storage, FP32
+accumulation, raw bfloat16 plane); the FP32 form is timed beside it.
+
+Prints one JSON line.  --gpus N > 1 is refused: the path runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def time_correlate(pl, x, plane, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        pl.correlate(x, plane)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        pl.correlate(x, plane)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def cpu_baseline(spec, cfg, r_center, target_s=15.0):
+    """The FP64 oracle (direct correlation, OpenMP over r) on a window of
+    columns x all template rows, sized for ~target_s of CPU work."""
+    from oracle import plane as oplane
+    from oracle import response as oresp
+    zs = oresp.z_grid(cfg["z_min"], cfg["z_step"], cfg["n_z"])
+    taps = oresp.template_taps(zs, cfg["n_taps"])
+    w = 2048
+    a = max(r_center - w // 2, 0)
+    t = time.perf_counter()
+    oplane.plane(spec, taps, a, a + w)
+    dt = time.perf_counter() - t
+    w2 = int(min(max(w * target_s / max(dt, 1e-3), 2048), spec.size))
+    a = max(min(r_center - w2 // 2, spec.size - w2), 0)
+    t = time.perf_counter()
+    oplane.plane(spec, taps, a, a + w2)
+    dt = time.perf_counter() - t
+    cells = w2 * cfg["n_z"]
+    return {"value": cells / dt, "unit": "cells/s", "cores": oplane.threads(), "kind": "oracle",
+            "sample": f"FP64 direct correlation, columns [{a}, {a + w2}) x {cfg['n_z']} templates "
+                      f"({cells} cells, {dt:.1f} s), {cfg['n_taps']} taps"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this FDAS build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2206_12205_amd import metrics
+    from paper_2206_12205_amd.fdas import Plan
+
+    cfg = synth.CONFIGS[2]
+    dev = torch.device("cuda:0")
+    sp = synth.config2(0)
+    n = sp.spec.size
+    n_z = cfg["n_z"]
+    x = torch.from_numpy(sp.spec).to(dev)
+    cells = n_z * n
+
+    common = dict(max_bins=n, z_min=cfg["z_min"], z_step=cfg["z_step"], n_z=n_z,
+                  n_taps=cfg["n_taps"], seg_len=cfg["seg_len"], device=dev)
+    pl_b = Plan(compute="bf16", plane_dtype="bf16", **common)
+    pl_f = Plan(compute="fp32", plane_dtype="fp32", **common)
+    plane_b = pl_b.empty_plane(n)
+    plane_f = pl_f.empty_plane(n)
+    torch.cuda.synchronize()
+
+    ms_b, wall_b = time_correlate(pl_b, x, plane_b, args.steps, args.warmup)
+    ms_f, wall_f = time_correlate(pl_f, x, plane_f, args.steps, args.warmup)
+
+    # algorithmic HBM bytes per launch: the plane store plus one read of the
+    # complex64 spectrum (templates are served from cache)
+    bytes_b = cells * 2 + n * 8
+    bytes_f = cells * 4 + n * 8
+    ach_b = bytes_b / (ms_b * 1e-3) / 1e9
+
+    out = {
+        "metric": "f-fdot plane cells/s, BF16 vs FP32 on 1 MI355X, at peak-bin match vs FP64",
+        "value": cells / (ms_b * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_b,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "single-DM FDAS plane: 4,194,304 bins x 101 templates "
+                               "(z -100..100 step 2), 256 taps, segment 8192, BF16 storage / FP32 "
+                               "accumulation, raw BF16 plane",
+                   "n_bins": n, "n_z": n_z, "n_taps": cfg["n_taps"], "seg_len": cfg["seg_len"],
+                   "z_chunk": int(pl_b.layout.z_chunk)},
+        "roofline": {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach_b / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "correlate_valu<13, float, bf16c, bf16>",
+                     "bytes_per_launch": bytes_b},
+        "fp32": {"value": cells / (ms_f * 1e-3), "unit": "cells/s", "ms_per_step": ms_f,
+                 "hbm_frac": bytes_f / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "speedup_bf16_over_fp32": ms_f / ms_b,
+        "wall_s": {"bf16": wall_b, "fp32": wall_f},
+    }
+
+    if not args.no_accuracy:
+        # peak-bin match of BF16 against FP64 gold and FP32 on this trial's
+        # harmonic bands (Table 3), SNR differences by Eq. 2
+        pl_d = Plan(compute="fp64", plane_dtype="fp64", **common)
+        pd = pl_d.correlate(x)
+        pb = plane_b.to(torch.float32)
+        psr = sp.pulsars[0]
+        bands = metrics.harmonic_bands(psr.f, sp.T, n, 8)
+        md = metrics.band_maxima(pd, bands)
+        mb = metrics.band_maxima(pb, bands)
+        mf = metrics.band_maxima(plane_f, bands)
+        sd, sb, sf = float(pd.std()), float(pb.std()), float(plane_f.std())
+        bright = [i for i, m in enumerate(mf) if m[2] > cfg["threshold"]]
+        same_b = sum((mb[i][0], mb[i][1]) == (md[i][0], md[i][1]) for i in bright)
+        same_f = sum((mf[i][0], mf[i][1]) == (md[i][0], md[i][1]) for i in bright)
+        dsnr = [float(metrics.rel_diff_pct(mb[i][2] / sb, mf[i][2] / sf)) for i in bright]
+        # max relative power error of the BF16 plane vs FP64 (floor 1: noise mean)
+        err = ((pb.to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item()
+        err_f = ((plane_f.to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item()
+        out["accuracy"] = {"trial": 0, "bright_band_maxima": len(bright),
+                           "bf16_same_bin_vs_fp64": same_b, "fp32_same_bin_vs_fp64": same_f,
+                           "bf16_max_abs_dsnr_pct": max(map(abs, dsnr)) if dsnr else None,
+                           "bf16_max_rel_power_err": err, "fp32_max_rel_power_err": err_f}
+        del pd, pl_d
+
+    if not args.no_cpu_baseline:
+        r_c = int(round(sp.pulsars[0].r_bar(sp.T)))
+        out["cpu_baseline"] = cpu_baseline(sp.spec, cfg, r_c)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

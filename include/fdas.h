@@ -1,0 +1,186 @@
+/*
+ * fdas.h -- C ABI of libfdas, the Fourier Domain Acceleration Search (FDAS)
+ * hot path on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed.  A binary pulsar's pulse frequency drifts linearly over
+ * an observation of length T; its drift in Fourier bins is z = fdot T^2 and
+ * its acceleration a = z c / (f T^2) (Eq. 1).  FDAS correlates the normalised
+ * complex spectrum X[k], k in [0, N), with a bank of acceleration templates,
+ * one per z on a grid, and the |.|^2 of the result is the f-fdot plane, on
+ * which a pulsar shows as a peak with harmonics at integer multiples of f and
+ * fdot (Section "Detailed explanation").  The correlation uses the
+ * convolution theorem with overlap-save: the spectrum is cut into windows,
+ * each window is transformed, multiplied by each template's transform,
+ * inverse transformed, and the central part of each window is kept while the
+ * contaminated edges are discarded (Section "Detailed explanation" and the
+ * overlap-save flowchart figure there).
+ *
+ * Definitions used by every call (the paper prints no template formula; it
+ * cites Ransom et al. 2002 for the method, Section "Introduction"):
+ *   response   A(q, z) = int_0^1 exp(i pi (2 q u + z u^2)) du
+ *   z grid     z_j = z_min + j * z_step, j in [0, n_z)
+ *   taps       g_j[m] = conj(A(m - z_j/2, z_j)) / ||.||_2,  m in [-M/2, M/2)
+ *              (r is the mean Fourier frequency; unit l2 norm after truncation)
+ *   plane      P[j, r] = | sum_m X[r - m] g_j[m] |^2,  r in [0, N),
+ *              with X = 0 outside [0, N)
+ * Overlap-save with segment length L (power of two, L > M) keeps V = L - M
+ * outputs per segment; segment s reads X[s V - M/2 .. s V - M/2 + L).  The
+ * plane does not depend on L except through rounding.
+ *
+ * Precision forms (Section "Updating the pipeline to bfloat16"):
+ *   FDAS_FP32  single precision throughout.
+ *   FDAS_BF16  segment spectra, templates and transform stages stored in
+ *              bfloat16 (round to nearest even), arithmetic accumulated in
+ *              single precision.  The spectrum input stays single precision
+ *              (the paper keeps its real FFT in single precision).
+ *   FDAS_FP64  double precision throughout: the gold-standard plane.
+ * Plane dtypes: FDAS_FP32 (4 B/cell), FDAS_BF16 (2 B/cell raw bfloat16; a
+ * consumer widens it exactly to single precision by placing the two bytes in
+ * the high half of a zeroed 32-bit word, Section "Casting between
+ * single-precision and bfloat16"), FDAS_FP64 (8 B/cell, FP64 compute only).
+ *
+ * Conventions for every call:
+ *   Memory    the library owns only the opaque plan.  Every device buffer
+ *             (spectrum, plane, workspace, peak list) is allocated and owned
+ *             by the caller and must stay alive until the stream work that
+ *             uses it has finished.
+ *   Streams   calls that take a stream enqueue asynchronous work on it (NULL
+ *             = the null stream) and never synchronise the device; a plan is
+ *             used from one stream at a time.
+ *   Status    calls return FDAS_OK (0) or a negative fdas_status; nothing
+ *             throws across the ABI.  FDAS_E_HIP keeps the HIP error code,
+ *             readable through fdas_last_hip_error().
+ *   Alignment device pointers must be 16-byte aligned (FDAS_E_INVALID).
+ *   NaN/Inf   propagate; an Inf or NaN anywhere in a segment pollutes every
+ *             output of that segment after the inverse transform (Section
+ *             "IEEE-754 Half vs bfloat16 precision").  No checks on the hot
+ *             path.
+ */
+#ifndef FDAS_H
+#define FDAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdas_plan_s *fdas_plan_t;
+
+typedef enum {
+    FDAS_FP32 = 0,
+    FDAS_BF16 = 1,
+    FDAS_FP8E4M3 = 2,   /* reserved: rejected with FDAS_E_UNSUPPORTED */
+    FDAS_FP64 = 3
+} fdas_dtype;
+
+typedef enum {
+    FDAS_OK = 0,
+    FDAS_E_INVALID = -1,      /* bad argument or configuration */
+    FDAS_E_WORKSPACE = -2,    /* no workspace, or workspace too small */
+    FDAS_E_HIP = -3,          /* a HIP runtime call failed */
+    FDAS_E_CAPACITY = -4,     /* more peaks than the output can hold */
+    FDAS_E_UNSUPPORTED = -5,  /* valid request this build does not implement */
+    FDAS_E_STATE = -6         /* call out of order (e.g. correlate before templates) */
+} fdas_status;
+
+typedef struct {
+    int64_t max_bins;     /* N: largest spectrum length (complex bins) the plan serves */
+    double  z_min;        /* first template drift (bins) */
+    double  z_step;       /* template spacing (bins), > 0 unless n_z == 1 */
+    int32_t n_z;          /* number of templates, >= 1 */
+    int32_t n_taps;       /* M: even, >= 2; the overlap between segments */
+    int32_t seg_len;      /* L: power of two in [1024, 16384], L > M; 0 = choose */
+    int32_t compute;      /* FDAS_FP32 | FDAS_BF16 | FDAS_FP64 */
+    int32_t plane_dtype;  /* FDAS_FP32 | FDAS_BF16 (not with FP64 compute) | FDAS_FP64 (FP64 compute only) */
+    int32_t z_chunk;      /* templates per workgroup; 0 = choose */
+} fdas_config;
+
+/* One entry of a peak list (24 bytes).  r is the spectral bin, z_idx the
+ * template row, power the plane value widened to single precision. */
+typedef struct {
+    int64_t r;
+    int32_t z_idx;
+    int32_t job;
+    float   power;
+    float   reserved;
+} fdas_peak;
+
+/* Workspace layout of a plan, byte offsets from the workspace base. */
+typedef struct {
+    size_t total_bytes;
+    size_t bank_offset;      /* template bank: n_z x L complex, compute dtype, natural bin order */
+    size_t bank_bytes;
+    size_t twiddle_offset;   /* exp(-2 pi i e / L), e in [0, L), compute dtype (FP32 for BF16) */
+    size_t twiddle_bytes;
+    size_t scratch_offset;   /* peak-finder counters */
+    size_t scratch_bytes;
+    int32_t seg_len;         /* L actually used */
+    int32_t valid_per_seg;   /* V = L - M */
+    int32_t z_chunk;         /* templates per workgroup actually used */
+    int32_t bank_elem_bytes; /* bytes per complex template value */
+} fdas_layout;
+
+/* Create a plan (host only, no device work).  Validates the configuration:
+ * FDAS_E_INVALID for n_z < 1, odd or < 2 M, L not a power of two or not in
+ * [1024, 16384], M >= L, max_bins < 1, z_step <= 0 with n_z > 1, a plane
+ * dtype the compute dtype cannot produce; FDAS_E_UNSUPPORTED for FP8 and for
+ * FP64 compute with L > 8192.  On success *out owns a new plan and
+ * *workspace_bytes is the device workspace the caller must provide. */
+int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes);
+
+/* Free a plan (host only).  NULL is ignored. */
+void fdas_destroy(fdas_plan_t plan);
+
+/* Attach caller-owned device memory of at least the plan's workspace size
+ * (FDAS_E_WORKSPACE if smaller).  Replacing it invalidates the templates. */
+int fdas_set_workspace(fdas_plan_t plan, void *dev, size_t bytes);
+
+/* Byte layout of the workspace (host only). */
+int fdas_get_layout(fdas_plan_t plan, fdas_layout *out);
+
+/* Build the template bank (Section "Template conversion": templates are made
+ * in a higher precision and converted to the reduced one).  In double
+ * precision on the GPU: the response through Fresnel integrals, the M taps,
+ * their l2 normalisation, the length-L DFT of the circularly placed taps
+ * (h[m mod L] = g[m]) scaled by 1/L, then one round-to-nearest-even cast to
+ * the compute dtype.  Also writes the twiddle table.  Asynchronous on
+ * stream; FDAS_E_WORKSPACE without a workspace. */
+int fdas_make_templates(fdas_plan_t plan, void *stream);
+
+/* The f-fdot plane of one spectrum.
+ *   spectrum  device, n_bins complex64 values (interleaved re, im floats)
+ *   n_bins    N, 1 <= N <= max_bins
+ *   plane     device, n_z x N row-major cells of the plan's plane dtype
+ * Every cell of the plane is written.  FDAS_E_STATE before
+ * fdas_make_templates, FDAS_E_INVALID for bad pointers or sizes. */
+int fdas_correlate(fdas_plan_t plan, const void *spectrum, int64_t n_bins,
+                   void *plane, void *stream);
+
+/* Thresholded peaks of a plane written by fdas_correlate with the same plan
+ * (Sections "Detailed explanation" and "Peakfinding methodology").  A cell is
+ * a peak iff P > threshold, P > every existing 8-neighbour that precedes it
+ * in row-major (z_idx, r) order and P >= every existing 8-neighbour that
+ * follows it (edge cells compare only neighbours that exist; NaN is never a
+ * peak).  Peaks are written to out (device, capacity entries) in (z_idx, r)
+ * order with job = 0; the true count goes to *n_found (device int64).  When
+ * the count exceeds capacity the first capacity peaks are written and the
+ * caller sees it by comparing *n_found with capacity (the call itself cannot
+ * know without a device synchronisation and returns FDAS_OK). */
+int fdas_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, float threshold,
+               fdas_peak *out, int64_t capacity, int64_t *n_found, void *stream);
+
+/* Text for a status code (static storage). */
+const char *fdas_strerror(int status);
+
+/* The HIP error code behind the last FDAS_E_HIP on this thread. */
+int fdas_last_hip_error(void);
+
+/* Library version, e.g. "0.1.0". */
+const char *fdas_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDAS_H */

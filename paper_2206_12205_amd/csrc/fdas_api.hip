@@ -1,0 +1,181 @@
+// C ABI of libfdas: plan validation, workspace layout and dispatch.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return FDAS_OK;
+    g_last_hip = (int)e;
+    return FDAS_E_HIP;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int ilog2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+int elem_bytes(int dtype) {
+    switch (dtype) {
+        case FDAS_FP32: return 8;
+        case FDAS_BF16: return 4;
+        case FDAS_FP64: return 16;
+        default: return 0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fdas_version(void) { return "0.1.0"; }
+
+const char *fdas_strerror(int s) {
+    switch (s) {
+        case FDAS_OK: return "ok";
+        case FDAS_E_INVALID: return "invalid argument or configuration";
+        case FDAS_E_WORKSPACE: return "workspace missing or too small";
+        case FDAS_E_HIP: return "HIP runtime error";
+        case FDAS_E_CAPACITY: return "peak capacity exceeded";
+        case FDAS_E_UNSUPPORTED: return "unsupported configuration";
+        case FDAS_E_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+int fdas_last_hip_error(void) { return g_last_hip; }
+
+int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes) {
+    if (!cfg || !out || !workspace_bytes) return FDAS_E_INVALID;
+    *out = nullptr;
+    const fdas_config c = *cfg;
+    if (c.compute == FDAS_FP8E4M3) return FDAS_E_UNSUPPORTED;
+    if (c.compute != FDAS_FP32 && c.compute != FDAS_BF16 && c.compute != FDAS_FP64) return FDAS_E_INVALID;
+    if (c.n_z < 1 || c.max_bins < 1 || c.n_taps < 2 || (c.n_taps & 1) || c.n_taps > 4096) return FDAS_E_INVALID;
+    if (!std::isfinite(c.z_min) || !std::isfinite(c.z_step)) return FDAS_E_INVALID;
+    if (c.n_z > 1 && !(c.z_step > 0.0)) return FDAS_E_INVALID;
+    if (c.z_chunk < 0) return FDAS_E_INVALID;
+    // plane dtype: FP64 compute writes FP64 only; FP32/BF16 compute write FP32 or BF16
+    if (c.compute == FDAS_FP64) {
+        if (c.plane_dtype != FDAS_FP64) return FDAS_E_INVALID;
+    } else if (c.plane_dtype != FDAS_FP32 && c.plane_dtype != FDAS_BF16) {
+        return FDAS_E_INVALID;
+    }
+    int64_t L = c.seg_len;
+    if (L == 0) {
+        L = int64_t(1) << ilog2(32 * (int64_t)c.n_taps);
+        if (L < 1024) L = 1024;
+        const int64_t lmax = c.compute == FDAS_FP64 ? 8192 : 16384;
+        if (L > lmax) L = lmax;
+    }
+    if (L < 1024 || L > 16384 || (L & (L - 1))) return FDAS_E_INVALID;
+    if (c.n_taps >= L) return FDAS_E_INVALID;
+    if (c.compute == FDAS_FP64 && L > 8192) return FDAS_E_UNSUPPORTED;
+
+    fdas_plan_s *p = new (std::nothrow) fdas_plan_s();
+    if (!p) return FDAS_E_INVALID;
+    p->cfg = c;
+    p->L = (int32_t)L;
+    p->log2L = ilog2(L);
+    p->cfg.seg_len = p->L;
+    p->M = c.n_taps;
+    p->V = p->L - p->M;
+    int zc = c.z_chunk;
+    if (zc == 0) zc = (c.n_z + 7) / 8;       // eight chunks: one per XCD
+    if (zc > c.n_z) zc = c.n_z;
+    p->z_chunk = zc;
+    p->n_chunks = (c.n_z + zc - 1) / zc;
+    p->cfg.z_chunk = zc;
+    p->bank_elem = elem_bytes(c.compute);
+    p->tw_elem = c.compute == FDAS_FP64 ? 16 : 8;
+
+    size_t off = 0;
+    p->off_bank = off;
+    p->sz_bank = (size_t)c.n_z * (size_t)L * p->bank_elem;
+    off = align_up(off + p->sz_bank, 256);
+    p->off_tw = off;
+    p->sz_tw = (size_t)L * p->tw_elem;
+    off = align_up(off + p->sz_tw, 256);
+    p->off_taps = off;
+    p->sz_taps = (size_t)c.n_z * (size_t)c.n_taps * 16;
+    off = align_up(off + p->sz_taps, 256);
+    p->peak_tile_cap = (int64_t)c.n_z * ((c.max_bins + fdas::kPeakTileCols - 1) / fdas::kPeakTileCols);
+    p->off_scr = off;
+    p->sz_scr = fdas::peak_scratch_bytes(p->peak_tile_cap);
+    off = align_up(off + p->sz_scr, 256);
+    p->ws_bytes = off;
+
+    *workspace_bytes = p->ws_bytes;
+    *out = p;
+    return FDAS_OK;
+}
+
+void fdas_destroy(fdas_plan_t plan) { delete plan; }
+
+int fdas_set_workspace(fdas_plan_t p, void *dev, size_t bytes) {
+    if (!p) return FDAS_E_INVALID;
+    if (!dev) return FDAS_E_WORKSPACE;
+    if (!aligned16(dev)) return FDAS_E_INVALID;
+    if (bytes < p->ws_bytes) return FDAS_E_WORKSPACE;
+    p->ws = dev;
+    p->ws_size = bytes;
+    p->templates_ready = false;
+    return FDAS_OK;
+}
+
+int fdas_get_layout(fdas_plan_t p, fdas_layout *o) {
+    if (!p || !o) return FDAS_E_INVALID;
+    std::memset(o, 0, sizeof(*o));
+    o->total_bytes = p->ws_bytes;
+    o->bank_offset = p->off_bank;
+    o->bank_bytes = p->sz_bank;
+    o->twiddle_offset = p->off_tw;
+    o->twiddle_bytes = p->sz_tw;
+    o->scratch_offset = p->off_scr;
+    o->scratch_bytes = p->sz_scr;
+    o->seg_len = p->L;
+    o->valid_per_seg = p->V;
+    o->z_chunk = p->z_chunk;
+    o->bank_elem_bytes = p->bank_elem;
+    return FDAS_OK;
+}
+
+int fdas_make_templates(fdas_plan_t p, void *stream) {
+    if (!p) return FDAS_E_INVALID;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    const int s = hip_status(fdas::launch_make_templates(*p, static_cast<hipStream_t>(stream)));
+    if (s == FDAS_OK) p->templates_ready = true;
+    return s;
+}
+
+int fdas_correlate(fdas_plan_t p, const void *spectrum, int64_t n_bins, void *plane, void *stream) {
+    if (!p || !spectrum || !plane) return FDAS_E_INVALID;
+    if (!aligned16(spectrum) || !aligned16(plane)) return FDAS_E_INVALID;
+    if (n_bins < 1 || n_bins > p->cfg.max_bins) return FDAS_E_INVALID;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    if (!p->templates_ready) return FDAS_E_STATE;
+    return hip_status(fdas::launch_correlate(*p, spectrum, n_bins, plane, static_cast<hipStream_t>(stream)));
+}
+
+int fdas_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, float threshold, fdas_peak *out,
+               int64_t capacity, int64_t *n_found, void *stream) {
+    if (!p || !plane || !n_found || capacity < 0 || (capacity > 0 && !out)) return FDAS_E_INVALID;
+    if (!aligned16(plane) || (out && !aligned16(out)) || (reinterpret_cast<uintptr_t>(n_found) & 7u))
+        return FDAS_E_INVALID;
+    if (n_bins < 1 || n_bins > p->cfg.max_bins) return FDAS_E_INVALID;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    return hip_status(
+        fdas::launch_peaks(*p, plane, n_bins, threshold, out, capacity, n_found, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

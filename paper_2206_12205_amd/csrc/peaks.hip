@@ -1,0 +1,181 @@
+// Thresholded peak finding on the f-fdot plane.
+//
+// A pulsar appears as a peak on the plane (Section "Detailed explanation");
+// the paper's own analysis picks the highest point of each harmonic band
+// (Section "Peakfinding methodology") but does not describe a general peak
+// finder.  This one reports every cell that is above the threshold and is a
+// 3x3 local maximum: P > thr, P > each existing neighbour that precedes it in
+// row-major (z_idx, r) order and P >= each one that follows it.  Comparisons
+// are exact (values widened to double), NaN never qualifies.
+//
+// Deterministic three-kernel scheme with one tile = one plane row x
+// kPeakTileCols columns, tiles numbered in (z_idx, column block) order:
+//   count  every workgroup counts the peaks of its tile;
+//   scan   one workgroup turns the counts into exclusive offsets and the total;
+//   write  every workgroup recomputes its peaks and writes them at its offset
+//          in column order, dropping those at or beyond the capacity.
+// The list is therefore sorted by (z_idx, r) with no sort pass.
+#include "internal.hpp"
+
+namespace fdas {
+
+constexpr int kPeakThreads = 256;
+constexpr int kCellsPerThread = kPeakTileCols / kPeakThreads;   // 4
+
+size_t peak_scratch_bytes(int64_t n_tiles) {
+    return (size_t)n_tiles * (sizeof(int32_t) + sizeof(int64_t)) + 256;
+}
+
+template <class PT>
+__device__ __forceinline__ double plane_val(const PT *p, int64_t i);
+template <>
+__device__ __forceinline__ double plane_val<float>(const float *p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ double plane_val<double>(const double *p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ double plane_val<unsigned short>(const unsigned short *p, int64_t i) {
+    return __uint_as_float((uint32_t)p[i] << 16);   // exact widening of raw bfloat16
+}
+
+// Stage rows z-1..z+1, columns c0-1 .. c0+kPeakTileCols into LDS (-inf outside
+// the plane) and flag this thread's kCellsPerThread consecutive cells.
+template <class PT>
+__device__ __forceinline__ int tile_flags(const PT *plane, int64_t n, int n_z, int z, int64_t c0, double thr,
+                                          double (*buf)[kPeakTileCols + 2], bool *flag) {
+    for (int i = threadIdx.x; i < 3 * (kPeakTileCols + 2); i += kPeakThreads) {
+        const int row = i / (kPeakTileCols + 2);
+        const int col = i % (kPeakTileCols + 2);
+        const int zz = z + row - 1;
+        const int64_t cc = c0 + col - 1;
+        double v = -INFINITY;
+        if (zz >= 0 && zz < n_z && cc >= 0 && cc < n) v = plane_val<PT>(plane, (int64_t)zz * n + cc);
+        buf[row][col] = v;
+    }
+    __syncthreads();
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kCellsPerThread; ++q) {
+        const int col = threadIdx.x * kCellsPerThread + q + 1;
+        const int64_t cc = c0 + col - 1;
+        const double c = buf[1][col];
+        bool ok = cc < n && c > thr;
+        // preceding neighbours (strict), following neighbours (non-strict)
+        ok = ok && c > buf[0][col - 1] && c > buf[0][col] && c > buf[0][col + 1] && c > buf[1][col - 1];
+        ok = ok && c >= buf[1][col + 1] && c >= buf[2][col - 1] && c >= buf[2][col] && c >= buf[2][col + 1];
+        flag[q] = ok;
+        cnt += ok ? 1 : 0;
+    }
+    return cnt;
+}
+
+template <class PT>
+__global__ void __launch_bounds__(kPeakThreads)
+k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, double thr, int32_t *counts) {
+    __shared__ double buf[3][kPeakTileCols + 2];
+    const int64_t tile = blockIdx.x;
+    const int z = (int)(tile / n_cb);
+    const int64_t c0 = (tile % n_cb) * kPeakTileCols;
+    __shared__ int sum;
+    if (threadIdx.x == 0) sum = 0;   // visible after the barrier inside tile_flags
+    bool flag[kCellsPerThread];
+    const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
+    if (cnt) atomicAdd(&sum, cnt);
+    __syncthreads();
+    if (threadIdx.x == 0) counts[tile] = sum;
+}
+
+// Single workgroup: exclusive scan of counts -> offsets, total -> *n_found.
+__global__ void __launch_bounds__(1024) k_peak_scan(const int32_t *counts, int64_t *offsets, int64_t n_tiles,
+                                                    int64_t *n_found) {
+    __shared__ int64_t part[1024];
+    const int64_t per = (n_tiles + 1023) / 1024;
+    const int64_t b = threadIdx.x * per;
+    const int64_t e = min(b + per, n_tiles);
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += counts[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    // inclusive Hillis-Steele scan over the 1024 partial sums
+    for (int w = 1; w < 1024; w <<= 1) {
+        const int64_t v = threadIdx.x >= (unsigned)w ? part[threadIdx.x - w] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int64_t i = b; i < e; ++i) {
+        offsets[i] = run;
+        run += counts[i];
+    }
+    if (threadIdx.x == 1023) *n_found = part[1023];
+}
+
+template <class PT>
+__global__ void __launch_bounds__(kPeakThreads)
+k_peak_write(const PT *plane, int64_t n, int n_z, int64_t n_cb, double thr, const int64_t *offsets,
+             fdas_peak *out, int64_t capacity) {
+    __shared__ double buf[3][kPeakTileCols + 2];
+    __shared__ int pre[kPeakThreads];
+    const int64_t tile = blockIdx.x;
+    const int z = (int)(tile / n_cb);
+    const int64_t c0 = (tile % n_cb) * kPeakTileCols;
+    bool flag[kCellsPerThread];
+    const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
+    pre[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = 1; w < kPeakThreads; w <<= 1) {
+        const int v = threadIdx.x >= (unsigned)w ? pre[threadIdx.x - w] : 0;
+        __syncthreads();
+        pre[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t pos = offsets[tile] + pre[threadIdx.x] - cnt;
+#pragma unroll
+    for (int q = 0; q < kCellsPerThread; ++q) {
+        if (!flag[q]) continue;
+        if (pos < capacity) {
+            const int col = threadIdx.x * kCellsPerThread + q + 1;
+            fdas_peak pk;
+            pk.r = c0 + col - 1;
+            pk.z_idx = z;
+            pk.job = 0;
+            pk.power = (float)buf[1][col];
+            pk.reserved = 0.0f;
+            out[pos] = pk;
+        }
+        ++pos;
+    }
+}
+
+namespace {
+template <class PT>
+hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, fdas_peak *out, int64_t cap,
+               int64_t *n_found, hipStream_t st) {
+    const int64_t n_cb = (n + kPeakTileCols - 1) / kPeakTileCols;
+    const int64_t n_tiles = n_cb * p.cfg.n_z;
+    if (n_tiles > p.peak_tile_cap || n_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    unsigned char *scr = static_cast<unsigned char *>(p.ws) + p.off_scr;
+    int64_t *offsets = reinterpret_cast<int64_t *>(scr);
+    int32_t *counts = reinterpret_cast<int32_t *>(scr + (size_t)n_tiles * sizeof(int64_t));
+    hipLaunchKernelGGL(k_peak_count<PT>, dim3((unsigned)n_tiles), dim3(kPeakThreads), 0, st, plane, n,
+                       p.cfg.n_z, n_cb, (double)thr, counts);
+    hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, st, counts, offsets, n_tiles, n_found);
+    hipLaunchKernelGGL(k_peak_write<PT>, dim3((unsigned)n_tiles), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z,
+                       n_cb, (double)thr, offsets, out, cap);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_peaks(const fdas_plan_s &p, const void *plane, int64_t n, float thr, fdas_peak *out,
+                        int64_t capacity, int64_t *n_found, hipStream_t st) {
+    switch (p.cfg.plane_dtype) {
+        case FDAS_FP32: return run<float>(p, static_cast<const float *>(plane), n, thr, out, capacity, n_found, st);
+        case FDAS_BF16:
+            return run<unsigned short>(p, static_cast<const unsigned short *>(plane), n, thr, out, capacity,
+                                       n_found, st);
+        case FDAS_FP64: return run<double>(p, static_cast<const double *>(plane), n, thr, out, capacity, n_found, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fdas

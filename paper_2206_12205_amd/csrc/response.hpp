@@ -1,0 +1,166 @@
+// Double-precision acceleration response on the device.
+//
+// A(q, z) = int_0^1 exp(i pi (2 q u + z u^2)) du is the normalised Fourier
+// response of a linearly drifting sinusoid (the method of Ransom et al. 2002,
+// cited in Section "Introduction"; the paper gives no formula).  Completing
+// the square expresses it through the Fresnel integral E(x) = C(x) + i S(x) =
+// int_0^x exp(i pi t^2 / 2) dt:
+//
+//   z > 0:  A = exp(-i pi q^2 / z) / sqrt(2 z) * (E(Y2) - E(Y1)),
+//           Y1 = q sqrt(2/z),  Y2 = (q + z) sqrt(2/z).
+//
+// With G(x) = (1 + i)/2 * erfcx(sqrt(pi)/2 (1 - i) x) for x >= 0 one has
+// E(x) = (1 + i)/2 - G(x) exp(i pi x^2 / 2), which lets the large phases
+// cancel analytically when Y1, Y2 share a sign:
+//
+//   Y1 >= 0:  A = (G(Y1) - G(Y2) exp(i pi (2q + z))) / sqrt(2 z)
+//   Y2 <= 0:  A = (G(-Y2) exp(i pi (2q + z)) - G(-Y1)) / sqrt(2 z)
+//
+// z < 0 uses A(q, z) = conj(A(-q, -z)); z = 0 is Fourier interpolation
+// exp(i pi q) sin(pi q) / (pi q); 0 < |z| < 1e-6 adds the first-order term
+// z * dA/dz(q, 0) = z * i pi int_0^1 u^2 exp(2 pi i q u) du.
+//
+// Numerical methods (written for this library):
+//   E(x), |x| < 2   Maclaurin series  sum_n (i pi/2)^n x^(2n+1) / (n! (2n+1))
+//   erfcx(w)        Laplace continued fraction (Abramowitz & Stegun 7.1.14)
+//                   evaluated bottom-up with 64 levels, used for |x| >= 2
+//                   (relative error ~1e-15 there).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fdas {
+
+struct cd {
+    double re, im;
+};
+__device__ __forceinline__ cd mk(double r, double i) { return cd{r, i}; }
+__device__ __forceinline__ cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd operator-(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd operator*(cd a, cd b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cd operator*(double s, cd a) { return {s * a.re, s * a.im}; }
+__device__ __forceinline__ cd conj(cd a) { return {a.re, -a.im}; }
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+    // Smith's algorithm
+    if (fabs(b.re) >= fabs(b.im)) {
+        double r = b.im / b.re, d = b.re + r * b.im;
+        return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+    }
+    double r = b.re / b.im, d = b.im + r * b.re;
+    return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+// exp(i pi t) with t reduced mod 2 first
+__device__ __forceinline__ cd expipi(double t) {
+    double tr = fmod(t, 2.0);
+    double s, c;
+    sincospi(tr, &s, &c);
+    return {c, s};
+}
+
+constexpr double kSqrtPi = 1.7724538509055160273;
+
+// Fresnel integral E(x) = C(x) + i S(x) for |x| < 2 by its Maclaurin series.
+__device__ inline cd fresnel_series(double x) {
+    const double a = 0.5 * M_PI * x * x;      // term ratio (i a) / (n + 1)
+    cd term = {x, 0.0};                        // (i a)^n x / n!
+    cd sum = {0.0, 0.0};
+    for (int n = 0; n < 48; ++n) {
+        const double inv = 1.0 / (2 * n + 1);
+        sum = sum + inv * term;
+        // term *= i a / (n + 1)
+        const double f = a / (n + 1);
+        term = {-term.im * f, term.re * f};
+    }
+    return sum;
+}
+
+// erfcx(w) = exp(w^2) erfc(w), Re w > 0, by the Laplace continued fraction.
+__device__ inline cd erfcx_cf(cd w) {
+    cd f = w;
+    for (int k = 64; k >= 1; --k) f = w + cdiv(mk(0.5 * k, 0.0), f);
+    return cdiv(mk(1.0 / kSqrtPi, 0.0), f);
+}
+
+// G(x) = (1 + i)/2 erfcx(sqrt(pi)/2 (1 - i) x), x >= 0 (so that
+// E(x) = (1 + i)/2 - G(x) exp(i pi x^2 / 2)).
+__device__ inline cd aux_g(double x) {
+    if (x >= 2.0) {
+        const double s = 0.5 * kSqrtPi * x;
+        return mk(0.5, 0.5) * erfcx_cf(mk(s, -s));
+    }
+    // small x: from the series, no cancellation at this size
+    cd e = fresnel_series(x);
+    cd d = mk(0.5, 0.5) - e;
+    return d * conj(expipi(0.5 * x * x));
+}
+
+// E(x) for any real x (odd function).
+__device__ inline cd fresnel_e(double x) {
+    const double ax = fabs(x);
+    cd e;
+    if (ax < 2.0) {
+        e = fresnel_series(ax);
+    } else {
+        e = mk(0.5, 0.5) - aux_g(ax) * expipi(0.5 * ax * ax);
+    }
+    return x < 0.0 ? mk(-e.re, -e.im) : e;
+}
+
+// Response for z > 0.
+__device__ inline cd response_pos(double q, double z) {
+    const double s = sqrt(2.0 / z);
+    const double y1 = q * s, y2 = (q + z) * s;
+    const double rt = sqrt(2.0 * z);
+    if (y1 >= 0.0) {
+        cd v = aux_g(y1) - aux_g(y2) * expipi(2.0 * q + z);
+        return (1.0 / rt) * v;
+    }
+    if (y2 <= 0.0) {
+        cd v = aux_g(-y2) * expipi(2.0 * q + z) - aux_g(-y1);
+        return (1.0 / rt) * v;
+    }
+    cd d = fresnel_e(y2) - fresnel_e(y1);
+    return (1.0 / rt) * (conj(expipi(q * q / z)) * d);
+}
+
+// int_0^1 u^2 exp(a u) du for a = 2 pi i q.
+__device__ inline cd moment2(double q) {
+    const double w = 2.0 * M_PI * q;     // a = i w
+    if (fabs(w) < 0.5) {
+        // sum_n a^n / (n! (n + 3))
+        cd term = {1.0, 0.0}, sum = {0.0, 0.0};
+        for (int n = 0; n < 24; ++n) {
+            sum = sum + (1.0 / (n + 3)) * term;
+            term = mk(-term.im * w / (n + 1), term.re * w / (n + 1));
+        }
+        return sum;
+    }
+    // e^a (1/a - 2/a^2 + 2/a^3) - 2/a^3 with a = i w
+    const cd a = {0.0, w};
+    const cd ia = cdiv(mk(1.0, 0.0), a);
+    const cd ia2 = ia * ia, ia3 = ia2 * ia;
+    const cd ea = expipi(2.0 * q);
+    return ea * (ia - 2.0 * ia2 + 2.0 * ia3) - 2.0 * ia3;
+}
+
+// A(q, z) for any real q, z.
+__device__ inline cd response(double q, double z) {
+    if (fabs(z) < 1e-6) {
+        cd a0;
+        if (q == 0.0) {
+            a0 = {1.0, 0.0};
+        } else {
+            const double sn = sinpi(q) / (M_PI * q);
+            a0 = sn * expipi(q);
+        }
+        if (z == 0.0) return a0;
+        cd d = moment2(q);                       // dA/dz = i pi * moment2
+        return a0 + z * (mk(0.0, M_PI) * d);
+    }
+    if (z > 0.0) return response_pos(q, z);
+    return conj(response_pos(-q, -z));
+}
+
+}  // namespace fdas

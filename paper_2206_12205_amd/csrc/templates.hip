@@ -1,0 +1,136 @@
+// Template bank and twiddle table, built on the GPU in double precision.
+//
+// The paper generates its templates in a higher precision and converts them
+// to the reduced one with a GPU kernel (Section "Template conversion"; the
+// bfloat16 conversion statistics are Table 1).  Here:
+//   taps      g_j[m] = conj(A(m - z_j/2, z_j)),  m in [-M/2, M/2)   (FP64)
+//   norm      g_j /= ||g_j||_2                                       (FP64)
+//   spectrum  H_j[k] = (1/L) sum_m g_j[m] exp(-2 pi i k m / L),  k in [0, L)
+//             i.e. the length-L DFT of the circularly placed taps h[m mod L],
+//             summed directly over the M nonzero taps in FP64, with the 1/L
+//             of the inverse transform folded in
+//   cast      FP32: one round-to-nearest-even cast of the FP64 value;
+//             BF16: the FP32 value rounded again to bfloat16 (the paper
+//             converts single-precision templates to bfloat16);
+//             FP64: stored as is.
+//   twiddles  tw[e] = exp(-2 pi i e / L), e in [0, L), FP64 -> compute type.
+#include "fft_valu.hpp"
+#include "internal.hpp"
+#include "response.hpp"
+
+namespace fdas {
+
+__global__ void k_taps(cd *taps, int32_t n_z, int32_t M, double z_min, double z_step) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_z * M) return;
+    const int j = (int)(i / M);
+    const int m = (int)(i % M) - M / 2;
+    const double z = z_min + z_step * j;
+    taps[i] = conj(response((double)m - 0.5 * z, z));
+}
+
+// One workgroup per template: l2 norm by a fixed-order tree reduction.
+__global__ void __launch_bounds__(256) k_normalise(cd *taps, int32_t M) {
+    __shared__ double red[256];
+    cd *g = taps + (int64_t)blockIdx.x * M;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < M; i += 256) s += g[i].re * g[i].re + g[i].im * g[i].im;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double inv = 1.0 / sqrt(red[0]);
+    for (int i = threadIdx.x; i < M; i += 256) g[i] = inv * g[i];
+}
+
+template <class B>
+__device__ __forceinline__ B bank_cast(cd v);
+template <>
+__device__ __forceinline__ cpx<float> bank_cast<cpx<float>>(cd v) { return {(float)v.re, (float)v.im}; }
+template <>
+__device__ __forceinline__ cpx<double> bank_cast<cpx<double>>(cd v) { return {v.re, v.im}; }
+template <>
+__device__ __forceinline__ bf16c bank_cast<bf16c>(cd v) { return {bf16_pack((float)v.re, (float)v.im)}; }
+
+// Grid: (L / 256, n_z); taps of template j staged in LDS.
+template <class B>
+__global__ void __launch_bounds__(256) k_spectrum(const cd *taps, B *bank, int32_t M, int32_t L) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cd *g = reinterpret_cast<cd *>(smem_raw);
+    const int j = blockIdx.y;
+    for (int i = threadIdx.x; i < M; i += 256) g[i] = taps[(int64_t)j * M + i];
+    __syncthreads();
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= L) return;
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < M; ++i) {
+        const int64_t m = i - M / 2;
+        int64_t e = (m * (int64_t)k) % L;       // exp(-2 pi i e / L), exact integer reduction
+        if (e < 0) e += L;
+        double sn, cs;
+        sincospi(-2.0 * (double)e / (double)L, &sn, &cs);
+        re += g[i].re * cs - g[i].im * sn;
+        im += g[i].re * sn + g[i].im * cs;
+    }
+    const double invL = 1.0 / (double)L;
+    bank[(int64_t)j * L + k] = bank_cast<B>(cd{re * invL, im * invL});
+}
+
+template <class R>
+__global__ void k_twiddles(cpx<R> *tw, int32_t L) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= L) return;
+    double sn, cs;
+    sincospi(-2.0 * (double)e / (double)L, &sn, &cs);
+    tw[e] = {(R)cs, (R)sn};
+}
+
+hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st) {
+    unsigned char *ws = static_cast<unsigned char *>(p.ws);
+    cd *taps = reinterpret_cast<cd *>(ws + p.off_taps);
+    const int64_t nt = (int64_t)p.cfg.n_z * p.M;
+    hipLaunchKernelGGL(k_taps, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, taps, p.cfg.n_z, p.M,
+                       p.cfg.z_min, p.cfg.z_step);
+    hipLaunchKernelGGL(k_normalise, dim3(p.cfg.n_z), dim3(256), 0, st, taps, p.M);
+    const dim3 grid((unsigned)((p.L + 255) / 256), (unsigned)p.cfg.n_z);
+    const size_t lds = (size_t)p.M * sizeof(cd);
+    void *bank = ws + p.off_bank;
+    hipError_t e = hipSuccess;
+    switch (p.cfg.compute) {
+        case FDAS_FP32: e = hipFuncSetAttribute((const void *)k_spectrum<cpx<float>>,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
+        case FDAS_BF16: e = hipFuncSetAttribute((const void *)k_spectrum<bf16c>,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
+        case FDAS_FP64: e = hipFuncSetAttribute((const void *)k_spectrum<cpx<double>>,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    switch (p.cfg.compute) {
+        case FDAS_FP32:
+            hipLaunchKernelGGL(k_spectrum<cpx<float>>, grid, dim3(256), lds, st, taps,
+                               static_cast<cpx<float> *>(bank), p.M, p.L);
+            hipLaunchKernelGGL(k_twiddles<float>, dim3((p.L + 255) / 256), dim3(256), 0, st,
+                               reinterpret_cast<cpx<float> *>(ws + p.off_tw), p.L);
+            break;
+        case FDAS_BF16:
+            hipLaunchKernelGGL(k_spectrum<bf16c>, grid, dim3(256), lds, st, taps, static_cast<bf16c *>(bank), p.M,
+                               p.L);
+            hipLaunchKernelGGL(k_twiddles<float>, dim3((p.L + 255) / 256), dim3(256), 0, st,
+                               reinterpret_cast<cpx<float> *>(ws + p.off_tw), p.L);
+            break;
+        case FDAS_FP64:
+            hipLaunchKernelGGL(k_spectrum<cpx<double>>, grid, dim3(256), lds, st, taps,
+                               static_cast<cpx<double> *>(bank), p.M, p.L);
+            hipLaunchKernelGGL(k_twiddles<double>, dim3((p.L + 255) / 256), dim3(256), 0, st,
+                               reinterpret_cast<cpx<double> *>(ws + p.off_tw), p.L);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fdas

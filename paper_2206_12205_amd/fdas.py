@@ -1,0 +1,207 @@
+"""Python binding of libfdas (ctypes).  Argument marshalling only: every step
+of the hot path runs in the library's HIP kernels; PyTorch provides device
+memory and streams.  The names follow the C ABI in include/fdas.h.
+
+Loading fails loudly when the HIP library has not been built (there is no
+fallback of any kind).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdas.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "fdas.h")
+
+FP32, BF16, FP8E4M3, FP64 = 0, 1, 2, 3
+DTYPES = {"fp32": FP32, "bf16": BF16, "fp8": FP8E4M3, "fp64": FP64}
+
+OK, E_INVALID, E_WORKSPACE, E_HIP, E_CAPACITY, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+
+
+class FdasConfig(ctypes.Structure):
+    _fields_ = [("max_bins", ctypes.c_int64), ("z_min", ctypes.c_double),
+                ("z_step", ctypes.c_double), ("n_z", ctypes.c_int32),
+                ("n_taps", ctypes.c_int32), ("seg_len", ctypes.c_int32),
+                ("compute", ctypes.c_int32), ("plane_dtype", ctypes.c_int32),
+                ("z_chunk", ctypes.c_int32)]
+
+
+class FdasPeak(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int64), ("z_idx", ctypes.c_int32), ("job", ctypes.c_int32),
+                ("power", ctypes.c_float), ("reserved", ctypes.c_float)]
+
+
+class FdasLayout(ctypes.Structure):
+    _fields_ = [("total_bytes", ctypes.c_size_t), ("bank_offset", ctypes.c_size_t),
+                ("bank_bytes", ctypes.c_size_t), ("twiddle_offset", ctypes.c_size_t),
+                ("twiddle_bytes", ctypes.c_size_t), ("scratch_offset", ctypes.c_size_t),
+                ("scratch_bytes", ctypes.c_size_t), ("seg_len", ctypes.c_int32),
+                ("valid_per_seg", ctypes.c_int32), ("z_chunk", ctypes.c_int32),
+                ("bank_elem_bytes", ctypes.c_int32)]
+
+
+class FdasError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = lib().fdas_strerror(status).decode()
+        if status == E_HIP:
+            msg += f" (hip error {lib().fdas_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{status}]")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libfdas.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2206_12205_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.fdas_plan.argtypes = [ctypes.POINTER(FdasConfig), ctypes.POINTER(P),
+                                ctypes.POINTER(ctypes.c_size_t)]
+        L.fdas_plan.restype = ctypes.c_int
+        L.fdas_destroy.argtypes = [P]
+        L.fdas_destroy.restype = None
+        L.fdas_set_workspace.argtypes = [P, P, ctypes.c_size_t]
+        L.fdas_get_layout.argtypes = [P, ctypes.POINTER(FdasLayout)]
+        L.fdas_make_templates.argtypes = [P, P]
+        L.fdas_correlate.argtypes = [P, P, I64, P, P]
+        L.fdas_peaks.argtypes = [P, P, I64, ctypes.c_float, P, I64, P, P]
+        L.fdas_strerror.argtypes = [ctypes.c_int]
+        L.fdas_strerror.restype = ctypes.c_char_p
+        L.fdas_last_hip_error.restype = ctypes.c_int
+        L.fdas_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list:
+    """Names of the functions include/fdas.h declares."""
+    with open(HEADER) as f:
+        txt = f.read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdas_[a-z_]+)\s*\(", txt)))
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise FdasError(status, what)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_config(max_bins, z_min, z_step, n_z, n_taps, seg_len=0, compute="fp32",
+                plane_dtype=None, z_chunk=0) -> FdasConfig:
+    c = DTYPES[compute] if isinstance(compute, str) else int(compute)
+    if plane_dtype is None:
+        plane_dtype = {FP32: FP32, BF16: BF16, FP64: FP64}.get(c, FP32)
+    pd = DTYPES[plane_dtype] if isinstance(plane_dtype, str) else int(plane_dtype)
+    return FdasConfig(int(max_bins), float(z_min), float(z_step), int(n_z), int(n_taps),
+                      int(seg_len), c, pd, int(z_chunk))
+
+
+class Plan:
+    """An FDAS plan with its device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, max_bins, z_min, z_step, n_z, n_taps, seg_len=0,
+                 compute="fp32", plane_dtype=None, z_chunk=0, device="cuda:0",
+                 make_templates=True):
+        import torch
+        self.cfg = make_config(max_bins, z_min, z_step, n_z, n_taps, seg_len, compute,
+                               plane_dtype, z_chunk)
+        h = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t()
+        _check(lib().fdas_plan(ctypes.byref(self.cfg), ctypes.byref(h), ctypes.byref(nbytes)),
+               "fdas_plan")
+        self._h = h
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        _check(lib().fdas_set_workspace(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                        self.workspace.numel()), "fdas_set_workspace")
+        self.layout = FdasLayout()
+        _check(lib().fdas_get_layout(self._h, ctypes.byref(self.layout)), "fdas_get_layout")
+        self.n_z = int(n_z)
+        self.plane_dtype = self.cfg.plane_dtype
+        if make_templates:
+            self.make_templates()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.fdas_destroy(h)
+            self._h = None
+
+    @property
+    def seg_len(self) -> int:
+        return int(self.layout.seg_len)
+
+    def make_templates(self, stream=None):
+        _check(lib().fdas_make_templates(self._h, _stream_ptr(stream)), "fdas_make_templates")
+
+    def torch_plane_dtype(self):
+        import torch
+        return {FP32: torch.float32, BF16: torch.bfloat16, FP64: torch.float64}[self.plane_dtype]
+
+    def empty_plane(self, n_bins):
+        import torch
+        return torch.empty((self.n_z, int(n_bins)), dtype=self.torch_plane_dtype(),
+                           device=self.device)
+
+    def correlate(self, spectrum, plane=None, stream=None):
+        """f-fdot plane of a complex64 device spectrum -> (n_z, N) tensor."""
+        import torch
+        if spectrum.dtype != torch.complex64 or not spectrum.is_contiguous():
+            raise ValueError("spectrum must be a contiguous complex64 tensor")
+        n = spectrum.numel()
+        if plane is None:
+            plane = self.empty_plane(n)
+        if plane.dtype != self.torch_plane_dtype() or tuple(plane.shape) != (self.n_z, n) \
+                or not plane.is_contiguous():
+            raise ValueError("plane has the wrong dtype, shape or layout")
+        _check(lib().fdas_correlate(self._h, ctypes.c_void_p(spectrum.data_ptr()), n,
+                                    ctypes.c_void_p(plane.data_ptr()), _stream_ptr(stream)),
+               "fdas_correlate")
+        return plane
+
+    def peaks(self, plane, threshold, capacity=1 << 16, stream=None):
+        """Peaks of a plane -> dict of numpy arrays z_idx, r, power and n_found."""
+        import numpy as np
+        import torch
+        n = plane.shape[1]
+        out = torch.empty((max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
+        nf = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().fdas_peaks(self._h, ctypes.c_void_p(plane.data_ptr()), n,
+                                float(threshold), ctypes.c_void_p(out.data_ptr()),
+                                int(capacity), ctypes.c_void_p(nf.data_ptr()),
+                                _stream_ptr(stream)), "fdas_peaks")
+        found = int(nf.item())
+        k = min(found, int(capacity))
+        raw = out[:k].cpu().numpy()
+        rec = raw.view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
+                                 ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
+        return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(),
+                "power": rec["power"].copy(), "n_found": found}
+
+    def bank(self):
+        """Template bank as a complex tensor view (FP32/FP64) or raw uint16
+        pairs (BF16), shape (n_z, L[, 2])."""
+        import torch
+        L = self.seg_len
+        b = self.workspace[self.layout.bank_offset:self.layout.bank_offset + self.layout.bank_bytes]
+        if self.cfg.compute == FP32:
+            return b.view(torch.float32).view(self.n_z, L, 2)
+        if self.cfg.compute == FP64:
+            return b.view(torch.float64).view(self.n_z, L, 2)
+        return b.view(torch.int16).view(self.n_z, L, 2)

@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+the header declares, and rejects bad arguments without touching a device."""
+import ctypes
+
+import pytest
+
+from paper_2206_12205_amd import fdas as F
+
+
+def make(**kw):
+    base = dict(max_bins=65536, z_min=-16.0, z_step=2.0, n_z=17, n_taps=64, seg_len=1024,
+                compute="fp32", plane_dtype=None, z_chunk=0)
+    base.update(kw)
+    return F.make_config(**base)
+
+
+def plan_status(cfg):
+    h = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    s = F.lib().fdas_plan(ctypes.byref(cfg), ctypes.byref(h), ctypes.byref(n))
+    if s == F.OK:
+        F.lib().fdas_destroy(h)
+    return s, n.value
+
+
+def test_library_exports_every_header_function():
+    names = F.header_functions()
+    assert "fdas_correlate" in names and "fdas_plan" in names and len(names) >= 10
+    L = F.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert F.lib().fdas_version().decode().count(".") == 2
+
+
+def test_struct_sizes():
+    assert ctypes.sizeof(F.FdasPeak) == 24
+    assert ctypes.sizeof(F.FdasConfig) == 48
+
+
+@pytest.mark.parametrize("kw,want", [
+    (dict(), F.OK),
+    (dict(n_taps=63), F.E_INVALID),          # odd M
+    (dict(n_taps=0), F.E_INVALID),
+    (dict(n_taps=1024), F.E_INVALID),        # M >= L
+    (dict(seg_len=3000), F.E_INVALID),       # not a power of two
+    (dict(seg_len=512), F.E_INVALID),        # below the supported range
+    (dict(seg_len=32768), F.E_INVALID),
+    (dict(n_z=0), F.E_INVALID),
+    (dict(max_bins=0), F.E_INVALID),
+    (dict(z_step=0.0), F.E_INVALID),
+    (dict(n_z=1, z_step=0.0), F.OK),         # a single template needs no step
+    (dict(compute="fp8"), F.E_UNSUPPORTED),
+    (dict(compute="fp64", plane_dtype="fp32"), F.E_INVALID),
+    (dict(compute="fp32", plane_dtype="fp64"), F.E_INVALID),
+    (dict(compute="fp64", seg_len=16384, n_taps=512), F.E_UNSUPPORTED),
+    (dict(compute="bf16", plane_dtype="fp32"), F.OK),
+    (dict(z_chunk=-1), F.E_INVALID),
+    (dict(seg_len=0, n_taps=256), F.OK),     # automatic L
+])
+def test_plan_validation(kw, want):
+    assert plan_status(make(**kw))[0] == want
+
+
+def test_layout_and_workspace_checks_on_host():
+    L = F.lib()
+    cfg = make(max_bins=4096, seg_len=0, n_taps=256, n_z=5, z_min=-4.0, compute="bf16")
+    h = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    assert L.fdas_plan(ctypes.byref(cfg), ctypes.byref(h), ctypes.byref(n)) == F.OK
+    try:
+        lay = F.FdasLayout()
+        assert L.fdas_get_layout(h, ctypes.byref(lay)) == F.OK
+        assert lay.seg_len == 8192 and lay.valid_per_seg == 8192 - 256
+        assert lay.bank_bytes == 5 * 8192 * 4 and lay.total_bytes == n.value
+        assert lay.bank_offset % 256 == 0 and lay.twiddle_offset % 256 == 0
+        fake = ctypes.c_void_p(0x10000)           # never dereferenced on these paths
+        assert L.fdas_correlate(h, fake, 100, fake, None) == F.E_WORKSPACE
+        assert L.fdas_set_workspace(h, fake, n.value - 1) == F.E_WORKSPACE
+        assert L.fdas_set_workspace(h, ctypes.c_void_p(0x10008), n.value) == F.E_INVALID
+        assert L.fdas_set_workspace(h, None, n.value) == F.E_WORKSPACE
+        assert L.fdas_set_workspace(h, fake, n.value) == F.OK
+        assert L.fdas_correlate(h, fake, 100, fake, None) == F.E_STATE      # no templates yet
+        assert L.fdas_correlate(h, fake, 0, fake, None) == F.E_INVALID
+        assert L.fdas_correlate(h, fake, 4097, fake, None) == F.E_INVALID
+        assert L.fdas_correlate(h, ctypes.c_void_p(0x10004), 100, fake, None) == F.E_INVALID
+        assert L.fdas_correlate(h, None, 100, fake, None) == F.E_INVALID
+        nf = ctypes.c_void_p(0x20000)
+        assert L.fdas_peaks(h, fake, 100, 1.0, None, 5, nf, None) == F.E_INVALID   # capacity>0, no out
+        assert L.fdas_peaks(h, fake, 100, 1.0, fake, -1, nf, None) == F.E_INVALID
+        assert L.fdas_peaks(h, fake, 100, 1.0, fake, 5, ctypes.c_void_p(0x20004), None) == F.E_INVALID
+    finally:
+        L.fdas_destroy(h)
+    L.fdas_destroy(None)
+    assert L.fdas_strerror(F.E_CAPACITY).decode() == "peak capacity exceeded"
+
+
+def test_null_arguments():
+    L = F.lib()
+    assert L.fdas_plan(None, None, None) == F.E_INVALID
+    assert L.fdas_make_templates(None, None) == F.E_INVALID
+    assert L.fdas_get_layout(None, None) == F.E_INVALID
