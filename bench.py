@@ -96,14 +96,17 @@ def main():
 
     common = dict(max_bins=n, z_min=cfg["z_min"], z_step=cfg["z_step"], n_z=n_z,
                   n_taps=cfg["n_taps"], seg_len=cfg["seg_len"], device=dev)
-    pl_b = Plan(compute="bf16", plane_dtype="bf16", **common)
+    pl_b = Plan(compute="bf16", plane_dtype="bf16", **common)            # matrix-core kernel
+    pl_v = Plan(compute="bf16", plane_dtype="bf16", algo="valu", **common)
     pl_f = Plan(compute="fp32", plane_dtype="fp32", **common)
     plane_b = pl_b.empty_plane(n)
     plane_f = pl_f.empty_plane(n)
     torch.cuda.synchronize()
 
     ms_b, wall_b = time_correlate(pl_b, x, plane_b, args.steps, args.warmup)
+    ms_v, _ = time_correlate(pl_v, x, pl_v.empty_plane(n), args.steps, args.warmup)
     ms_f, wall_f = time_correlate(pl_f, x, plane_f, args.steps, args.warmup)
+    del pl_v
 
     # algorithmic HBM bytes per launch: the plane store plus one read of the
     # complex64 spectrum (templates are served from cache)
@@ -131,10 +134,11 @@ def main():
                    "z_chunk": int(pl_b.layout.z_chunk)},
         "roofline": {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach_b / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "correlate_valu<13, float, bf16c, bf16>",
+                     "kernel": f"correlate_{pl_b.algo}8192 (BF16 form, raw BF16 plane)",
                      "bytes_per_launch": bytes_b},
         "fp32": {"value": cells / (ms_f * 1e-3), "unit": "cells/s", "ms_per_step": ms_f,
                  "hbm_frac": bytes_f / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "bf16_valu": {"value": cells / (ms_v * 1e-3), "unit": "cells/s", "ms_per_step": ms_v},
         "speedup_bf16_over_fp32": ms_f / ms_b,
         "wall_s": {"bf16": wall_b, "fp32": wall_f},
     }

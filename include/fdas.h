@@ -95,7 +95,15 @@ typedef struct {
     int32_t compute;      /* FDAS_FP32 | FDAS_BF16 | FDAS_FP64 */
     int32_t plane_dtype;  /* FDAS_FP32 | FDAS_BF16 (not with FP64 compute) | FDAS_FP64 (FP64 compute only) */
     int32_t z_chunk;      /* templates per workgroup; 0 = choose */
+    int32_t algo;         /* FDAS_ALGO_AUTO | FDAS_ALGO_VALU | FDAS_ALGO_MFMA */
 } fdas_config;
+
+/* Kernel family of the correlation.  AUTO picks the matrix-core kernel where
+ * one exists (BF16 compute with L = 8192) and the vector-ALU kernel
+ * otherwise; MFMA on a configuration without a matrix-core kernel is
+ * FDAS_E_UNSUPPORTED.  Both compute the same plane (the MFMA kernel rounds
+ * its DFT operators to bfloat16 as well). */
+typedef enum { FDAS_ALGO_AUTO = 0, FDAS_ALGO_VALU = 1, FDAS_ALGO_MFMA = 2 } fdas_algo;
 
 /* One entry of a peak list (24 bytes).  r is the spectral bin, z_idx the
  * template row, power the plane value widened to single precision. */
@@ -110,7 +118,8 @@ typedef struct {
 /* Workspace layout of a plan, byte offsets from the workspace base. */
 typedef struct {
     size_t total_bytes;
-    size_t bank_offset;      /* template bank: n_z x L complex, compute dtype, natural bin order */
+    size_t bank_offset;      /* template bank: n_z x L complex, compute dtype; natural bin order for
+                                the vector-ALU kernel, matrix-core lane order for the MFMA kernel */
     size_t bank_bytes;
     size_t twiddle_offset;   /* exp(-2 pi i e / L), e in [0, L), compute dtype (FP32 for BF16) */
     size_t twiddle_bytes;
@@ -120,6 +129,9 @@ typedef struct {
     int32_t valid_per_seg;   /* V = L - M */
     int32_t z_chunk;         /* templates per workgroup actually used */
     int32_t bank_elem_bytes; /* bytes per complex template value */
+    int32_t algo;            /* kernel family actually used (FDAS_ALGO_VALU or FDAS_ALGO_MFMA) */
+    size_t tables_offset;    /* matrix-core operator and twiddle tables (MFMA only) */
+    size_t tables_bytes;
 } fdas_layout;
 
 /* Create a plan (host only, no device work).  Validates the configuration:

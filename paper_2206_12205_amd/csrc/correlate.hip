@@ -18,26 +18,9 @@
 // L2 serves a fixed subset of the bank.
 #include "fft_valu.hpp"
 #include "internal.hpp"
+#include "plane_io.hpp"
 
 namespace fdas {
-
-template <class P>
-struct plane_store;
-template <>
-struct plane_store<float> {
-    static __device__ __forceinline__ void put(float *p, float v) { __builtin_nontemporal_store(v, p); }
-};
-template <>
-struct plane_store<double> {
-    static __device__ __forceinline__ void put(double *p, double v) { __builtin_nontemporal_store(v, p); }
-};
-template <>
-struct plane_store<__bf16> {
-    static __device__ __forceinline__ void put(__bf16 *p, float v) {
-        const __bf16 b = (__bf16)v;   // round to nearest even
-        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, b), (unsigned short *)p);
-    }
-};
 
 // Bank element -> compute complex.
 template <class T, class B>

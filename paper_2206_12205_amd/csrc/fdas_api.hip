@@ -4,6 +4,7 @@
 #include <new>
 
 #include "internal.hpp"
+#include "mfma8192.hpp"
 
 namespace {
 
@@ -65,6 +66,7 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     if (!std::isfinite(c.z_min) || !std::isfinite(c.z_step)) return FDAS_E_INVALID;
     if (c.n_z > 1 && !(c.z_step > 0.0)) return FDAS_E_INVALID;
     if (c.z_chunk < 0) return FDAS_E_INVALID;
+    if (c.algo < FDAS_ALGO_AUTO || c.algo > FDAS_ALGO_MFMA) return FDAS_E_INVALID;
     // plane dtype: FP64 compute writes FP64 only; FP32/BF16 compute write FP32 or BF16
     if (c.compute == FDAS_FP64) {
         if (c.plane_dtype != FDAS_FP64) return FDAS_E_INVALID;
@@ -90,8 +92,18 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     p->cfg.seg_len = p->L;
     p->M = c.n_taps;
     p->V = p->L - p->M;
+    const bool mfma_ok = c.compute == FDAS_BF16 && L == fdas::m8k::kL;
+    if (c.algo == FDAS_ALGO_MFMA && !mfma_ok) {
+        delete p;
+        return FDAS_E_UNSUPPORTED;
+    }
+    p->mfma = mfma_ok && c.algo != FDAS_ALGO_VALU;
     int zc = c.z_chunk;
-    if (zc == 0) zc = (c.n_z + 7) / 8;       // eight chunks: one per XCD
+    if (zc == 0) {
+        // vector-ALU kernel: eight chunks, one per XCD; matrix-core kernel:
+        // four chunks (its per-segment forward transform costs about one template)
+        zc = p->mfma ? (c.n_z + 3) / 4 : (c.n_z + 7) / 8;
+    }
     if (zc > c.n_z) zc = c.n_z;
     p->z_chunk = zc;
     p->n_chunks = (c.n_z + zc - 1) / zc;
@@ -113,7 +125,11 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     p->off_scr = off;
     p->sz_scr = fdas::peak_scratch_bytes(p->peak_tile_cap);
     off = align_up(off + p->sz_scr, 256);
+    p->off_tab = off;
+    p->sz_tab = p->mfma ? fdas::m8k::kTableBytes : 0;
+    off = align_up(off + p->sz_tab, 256);
     p->ws_bytes = off;
+    p->cfg.algo = p->mfma ? FDAS_ALGO_MFMA : FDAS_ALGO_VALU;
 
     *workspace_bytes = p->ws_bytes;
     *out = p;
@@ -147,6 +163,9 @@ int fdas_get_layout(fdas_plan_t p, fdas_layout *o) {
     o->valid_per_seg = p->V;
     o->z_chunk = p->z_chunk;
     o->bank_elem_bytes = p->bank_elem;
+    o->algo = p->cfg.algo;
+    o->tables_offset = p->off_tab;
+    o->tables_bytes = p->sz_tab;
     return FDAS_OK;
 }
 
@@ -164,7 +183,9 @@ int fdas_correlate(fdas_plan_t p, const void *spectrum, int64_t n_bins, void *pl
     if (n_bins < 1 || n_bins > p->cfg.max_bins) return FDAS_E_INVALID;
     if (!p->ws) return FDAS_E_WORKSPACE;
     if (!p->templates_ready) return FDAS_E_STATE;
-    return hip_status(fdas::launch_correlate(*p, spectrum, n_bins, plane, static_cast<hipStream_t>(stream)));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->mfma) return hip_status(fdas::launch_correlate_mfma(*p, spectrum, n_bins, plane, st));
+    return hip_status(fdas::launch_correlate(*p, spectrum, n_bins, plane, st));
 }
 
 int fdas_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, float threshold, fdas_peak *out,

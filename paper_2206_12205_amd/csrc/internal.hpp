@@ -27,6 +27,8 @@ struct fdas_plan_s {
     size_t off_tw = 0, sz_tw = 0;
     size_t off_taps = 0, sz_taps = 0;      // FP64 taps, n_z x M complex (template build)
     size_t off_scr = 0, sz_scr = 0;        // peak counters
+    size_t off_tab = 0, sz_tab = 0;        // matrix-core operator/twiddle tables
+    bool mfma = false;                     // matrix-core correlation kernel
     int64_t peak_tile_cap = 0;             // number of peak tiles the scratch holds
     void *ws = nullptr;
     size_t ws_size = 0;
@@ -37,6 +39,10 @@ namespace fdas {
 
 // Template bank + twiddle table (templates.hip).
 hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t s);
+
+// Matrix-core correlation, L = 8192, BF16 form (correlate_mfma.hip).
+hipError_t launch_correlate_mfma(const fdas_plan_s &p, const void *spec, int64_t n,
+                                 void *plane, hipStream_t s);
 
 // Correlation (correlate.hip).
 hipError_t launch_correlate(const fdas_plan_s &p, const void *spec, int64_t n,

@@ -16,6 +16,7 @@
 //   twiddles  tw[e] = exp(-2 pi i e / L), e in [0, L), FP64 -> compute type.
 #include "fft_valu.hpp"
 #include "internal.hpp"
+#include "mfma8192.hpp"
 #include "response.hpp"
 
 namespace fdas {
@@ -55,8 +56,17 @@ template <>
 __device__ __forceinline__ bf16c bank_cast<bf16c>(cd v) { return {bf16_pack((float)v.re, (float)v.im)}; }
 
 // Grid: (L / 256, n_z); taps of template j staged in LDS.
+// Position of frequency bin k of template j in the bank: natural order, or
+// the lane order of the length-8192 matrix-core kernel (m8k).
+__device__ __forceinline__ int64_t bank_pos(int j, int k, int L, bool m8k_order) {
+    if (!m8k_order) return (int64_t)j * L + k;
+    const int k1 = k & 31, k2 = (k >> 5) & 15, k3 = k >> 9;
+    const int wave = k1 >> 2, q = k1 & 3, lane = k2 + 16 * (k3 >> 2), p = k3 & 3;
+    return (int64_t)j * L + (((wave * 4 + q) * 64 + lane) * 4 + p);
+}
+
 template <class B>
-__global__ void __launch_bounds__(256) k_spectrum(const cd *taps, B *bank, int32_t M, int32_t L) {
+__global__ void __launch_bounds__(256) k_spectrum(const cd *taps, B *bank, int32_t M, int32_t L, int m8k_order) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cd *g = reinterpret_cast<cd *>(smem_raw);
     const int j = blockIdx.y;
@@ -75,7 +85,89 @@ __global__ void __launch_bounds__(256) k_spectrum(const cd *taps, B *bank, int32
         im += g[i].re * sn + g[i].im * cs;
     }
     const double invL = 1.0 / (double)L;
-    bank[(int64_t)j * L + k] = bank_cast<B>(cd{re * invL, im * invL});
+    bank[bank_pos(j, k, L, m8k_order != 0)] = bank_cast<B>(cd{re * invL, im * invL});
+}
+
+// exp(s 2 pi i m / N) for integer m, FP64.
+__device__ __forceinline__ cd unit_root(int64_t m, int64_t N, int s) {
+    int64_t r = m % N;
+    if (r < 0) r += N;
+    double sn, cs;
+    sincospi(2.0 * (double)r / (double)N, &sn, &cs);
+    return {cs, s > 0 ? sn : -sn};
+}
+
+// Operators and per-lane twiddles of the length-8192 matrix-core kernel.
+// One thread per (op, lane) or per twiddle slot; see mfma8192.hpp.
+__global__ void k_m8k_tables(uint32_t *tab) {
+    using namespace m8k;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n_op_threads = kNumOps * 64;
+    if (t < n_op_threads) {
+        const int op = t / 64, lane = t % 64, c = lane & 15, g = lane >> 4;
+        uint32_t w[4];
+        for (int e = 0; e < 8; e += 2) {
+            float v[2];
+            for (int h = 0; h < 2; ++h) {
+                const int el = e + h;
+                const int part_in = el & 1;
+                cd a;
+                int part_out;
+                if (op >= OP_A32P && op < OP_AF2M) {          // DFT32 (inverse or forward)
+                    const int rel = (op - (op < OP_A32M ? OP_A32P : OP_A32M));
+                    const int mb = rel >> 1, kb = rel & 1;
+                    const int n1 = 8 * mb + (c >> 1);
+                    part_out = c & 1;
+                    const int k1 = 16 * kb + 4 * g + (el >> 1);
+                    a = unit_root((int64_t)n1 * k1, 32, op < OP_A32M ? +1 : -1);
+                } else {                                       // DFT16 variants
+                    const int row = c, pin = 4 * g + (el >> 1);
+                    int imrows;
+                    if (op < OP_A2P) {                         // inverse DFT16
+                        imrows = op - OP_A16P;
+                        a = unit_root((int64_t)row * pin, 16, +1);
+                    } else if (op < OP_A32P) {                 // inverse DFT16 with T1(k2 = pin; n3)
+                        const int n3 = (op - OP_A2P) >> 1;
+                        imrows = (op - OP_A2P) & 1;
+                        a = unit_root((int64_t)16 * row * pin + (int64_t)n3 * pin, 256, +1);
+                    } else if (op < OP_A16M) {                 // forward DFT16 with conj T1(k2 = row; n3)
+                        const int n3 = (op - OP_AF2M) >> 1;
+                        imrows = (op - OP_AF2M) & 1;
+                        a = unit_root((int64_t)16 * row * pin + (int64_t)n3 * row, 256, -1);
+                    } else {                                   // forward DFT16
+                        imrows = op - OP_A16M;
+                        a = unit_root((int64_t)row * pin, 16, -1);
+                    }
+                    part_out = imrows;
+                }
+                double val;
+                if (part_out == 0) val = part_in ? -a.im : a.re;
+                else val = part_in ? a.re : a.im;
+                v[h] = (float)val;
+            }
+            w[e >> 1] = bf16_pack(v[0], v[1]);
+        }
+        for (int i = 0; i < 4; ++i) tab[op * kOpWords + lane * 4 + i] = w[i];
+        return;
+    }
+    const int u = t - n_op_threads;
+    float2 *tw = reinterpret_cast<float2 *>(tab + kNumOps * kOpWords);
+    if (u < kT2Count) {                                        // inverse T2: [wave][lane][q][e]
+        const int e = u & 3, q = (u >> 2) & 3, lane = (u >> 4) & 63, wave = u >> 10;
+        const int c = lane & 15, g = lane >> 4;
+        const int k1 = 16 * (wave >> 2) + c, n2 = 4 * g + e, n3 = 4 * (wave & 3) + q;
+        const cd r = unit_root((int64_t)(16 * n2 + n3) * k1, kL, +1);
+        tw[u] = make_float2((float)r.re, (float)r.im);
+        return;
+    }
+    const int v = u - kT2Count;
+    if (v < kT2FCount) {                                       // forward conj T2: [wave][lane][q][mb][e2]
+        const int e2 = v & 1, mb = (v >> 1) & 3, q = (v >> 3) & 1, lane = (v >> 4) & 63, wave = v >> 10;
+        const int c = lane & 15, g = lane >> 4;
+        const int n2 = 2 * wave + q, n3 = c, k1 = 8 * mb + 2 * g + e2;
+        const cd r = unit_root((int64_t)(16 * n2 + n3) * k1, kL, -1);
+        tw[kT2Count + v] = make_float2((float)r.re, (float)r.im);
+    }
 }
 
 template <class R>
@@ -111,19 +203,24 @@ hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st) {
     switch (p.cfg.compute) {
         case FDAS_FP32:
             hipLaunchKernelGGL(k_spectrum<cpx<float>>, grid, dim3(256), lds, st, taps,
-                               static_cast<cpx<float> *>(bank), p.M, p.L);
+                               static_cast<cpx<float> *>(bank), p.M, p.L, 0);
             hipLaunchKernelGGL(k_twiddles<float>, dim3((p.L + 255) / 256), dim3(256), 0, st,
                                reinterpret_cast<cpx<float> *>(ws + p.off_tw), p.L);
             break;
         case FDAS_BF16:
             hipLaunchKernelGGL(k_spectrum<bf16c>, grid, dim3(256), lds, st, taps, static_cast<bf16c *>(bank), p.M,
-                               p.L);
+                               p.L, p.mfma ? 1 : 0);
+            if (p.mfma) {
+                const int nthreads = m8k::kNumOps * 64 + m8k::kT2Count + m8k::kT2FCount;
+                hipLaunchKernelGGL(k_m8k_tables, dim3((nthreads + 255) / 256), dim3(256), 0, st,
+                                   reinterpret_cast<uint32_t *>(ws + p.off_tab));
+            }
             hipLaunchKernelGGL(k_twiddles<float>, dim3((p.L + 255) / 256), dim3(256), 0, st,
                                reinterpret_cast<cpx<float> *>(ws + p.off_tw), p.L);
             break;
         case FDAS_FP64:
             hipLaunchKernelGGL(k_spectrum<cpx<double>>, grid, dim3(256), lds, st, taps,
-                               static_cast<cpx<double> *>(bank), p.M, p.L);
+                               static_cast<cpx<double> *>(bank), p.M, p.L, 0);
             hipLaunchKernelGGL(k_twiddles<double>, dim3((p.L + 255) / 256), dim3(256), 0, st,
                                reinterpret_cast<cpx<double> *>(ws + p.off_tw), p.L);
             break;

@@ -17,6 +17,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "fdas.h")
 
 FP32, BF16, FP8E4M3, FP64 = 0, 1, 2, 3
 DTYPES = {"fp32": FP32, "bf16": BF16, "fp8": FP8E4M3, "fp64": FP64}
+ALGO_AUTO, ALGO_VALU, ALGO_MFMA = 0, 1, 2
+ALGOS = {"auto": ALGO_AUTO, "valu": ALGO_VALU, "mfma": ALGO_MFMA}
 
 OK, E_INVALID, E_WORKSPACE, E_HIP, E_CAPACITY, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 
@@ -26,7 +28,7 @@ class FdasConfig(ctypes.Structure):
                 ("z_step", ctypes.c_double), ("n_z", ctypes.c_int32),
                 ("n_taps", ctypes.c_int32), ("seg_len", ctypes.c_int32),
                 ("compute", ctypes.c_int32), ("plane_dtype", ctypes.c_int32),
-                ("z_chunk", ctypes.c_int32)]
+                ("z_chunk", ctypes.c_int32), ("algo", ctypes.c_int32)]
 
 
 class FdasPeak(ctypes.Structure):
@@ -40,7 +42,8 @@ class FdasLayout(ctypes.Structure):
                 ("twiddle_bytes", ctypes.c_size_t), ("scratch_offset", ctypes.c_size_t),
                 ("scratch_bytes", ctypes.c_size_t), ("seg_len", ctypes.c_int32),
                 ("valid_per_seg", ctypes.c_int32), ("z_chunk", ctypes.c_int32),
-                ("bank_elem_bytes", ctypes.c_int32)]
+                ("bank_elem_bytes", ctypes.c_int32), ("algo", ctypes.c_int32),
+                ("tables_offset", ctypes.c_size_t), ("tables_bytes", ctypes.c_size_t)]
 
 
 class FdasError(RuntimeError):
@@ -103,13 +106,14 @@ def _stream_ptr(stream):
 
 
 def make_config(max_bins, z_min, z_step, n_z, n_taps, seg_len=0, compute="fp32",
-                plane_dtype=None, z_chunk=0) -> FdasConfig:
+                plane_dtype=None, z_chunk=0, algo="auto") -> FdasConfig:
     c = DTYPES[compute] if isinstance(compute, str) else int(compute)
     if plane_dtype is None:
         plane_dtype = {FP32: FP32, BF16: BF16, FP64: FP64}.get(c, FP32)
     pd = DTYPES[plane_dtype] if isinstance(plane_dtype, str) else int(plane_dtype)
+    a = ALGOS[algo] if isinstance(algo, str) else int(algo)
     return FdasConfig(int(max_bins), float(z_min), float(z_step), int(n_z), int(n_taps),
-                      int(seg_len), c, pd, int(z_chunk))
+                      int(seg_len), c, pd, int(z_chunk), a)
 
 
 class Plan:
@@ -117,10 +121,10 @@ class Plan:
 
     def __init__(self, max_bins, z_min, z_step, n_z, n_taps, seg_len=0,
                  compute="fp32", plane_dtype=None, z_chunk=0, device="cuda:0",
-                 make_templates=True):
+                 make_templates=True, algo="auto"):
         import torch
         self.cfg = make_config(max_bins, z_min, z_step, n_z, n_taps, seg_len, compute,
-                               plane_dtype, z_chunk)
+                               plane_dtype, z_chunk, algo)
         h = ctypes.c_void_p()
         nbytes = ctypes.c_size_t()
         _check(lib().fdas_plan(ctypes.byref(self.cfg), ctypes.byref(h), ctypes.byref(nbytes)),
@@ -146,6 +150,10 @@ class Plan:
     @property
     def seg_len(self) -> int:
         return int(self.layout.seg_len)
+
+    @property
+    def algo(self) -> str:
+        return {ALGO_VALU: "valu", ALGO_MFMA: "mfma"}[int(self.layout.algo)]
 
     def make_templates(self, stream=None):
         _check(lib().fdas_make_templates(self._h, _stream_ptr(stream)), "fdas_make_templates")

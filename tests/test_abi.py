@@ -34,7 +34,8 @@ def test_library_exports_every_header_function():
 
 def test_struct_sizes():
     assert ctypes.sizeof(F.FdasPeak) == 24
-    assert ctypes.sizeof(F.FdasConfig) == 48
+    assert ctypes.sizeof(F.FdasConfig) == 56
+    assert ctypes.sizeof(F.FdasLayout) == 7 * 8 + 5 * 4 + 4 + 2 * 8
 
 
 @pytest.mark.parametrize("kw,want", [
@@ -56,6 +57,10 @@ def test_struct_sizes():
     (dict(compute="bf16", plane_dtype="fp32"), F.OK),
     (dict(z_chunk=-1), F.E_INVALID),
     (dict(seg_len=0, n_taps=256), F.OK),     # automatic L
+    (dict(compute="bf16", seg_len=8192, n_taps=256, algo="mfma"), F.OK),
+    (dict(compute="fp32", seg_len=8192, n_taps=256, algo="mfma"), F.E_UNSUPPORTED),
+    (dict(compute="bf16", seg_len=4096, n_taps=256, algo="mfma"), F.E_UNSUPPORTED),
+    (dict(algo=3), F.E_INVALID),
 ])
 def test_plan_validation(kw, want):
     assert plan_status(make(**kw))[0] == want
@@ -72,6 +77,8 @@ def test_layout_and_workspace_checks_on_host():
         assert L.fdas_get_layout(h, ctypes.byref(lay)) == F.OK
         assert lay.seg_len == 8192 and lay.valid_per_seg == 8192 - 256
         assert lay.bank_bytes == 5 * 8192 * 4 and lay.total_bytes == n.value
+        assert lay.algo == F.ALGO_MFMA and lay.tables_bytes > 0
+        assert lay.tables_offset + lay.tables_bytes <= lay.total_bytes
         assert lay.bank_offset % 256 == 0 and lay.twiddle_offset % 256 == 0
         fake = ctypes.c_void_p(0x10000)           # never dereferenced on these paths
         assert L.fdas_correlate(h, fake, 100, fake, None) == F.E_WORKSPACE

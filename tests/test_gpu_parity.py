@@ -273,3 +273,124 @@ def test_config2_bf16_peaks_same_bins(dev, cfg2):
         assert (ma[i][0], ma[i][1]) == (mb[i][0], mb[i][1]), (i, ma[i], mb[i])
         d = float(metrics.rel_diff_pct(mb[i][2] / sb, ma[i][2] / sa))
         assert abs(d) <= 3.0, (i, d)
+
+
+# ---------------------------------------------------------------------------
+# Matrix-core (MFMA) BF16 kernel, L = 8192.
+#
+# Bar (derived from the arithmetic): every bf16 rounding has relative error
+# <= u = 2^-9; a value passes about six of them (input, template, product,
+# two stage outputs, operator entries) and the power doubles relative errors,
+# so bright cells (P64 > 20, where the signal dominates) must be within 3 %
+# (the paper's own bound on bf16 SNR differences), and every cell within
+# 0.15 * max(P64, 1) with a mean below 0.02 * max(P64, 1).
+# ---------------------------------------------------------------------------
+
+def assert_bf16_close(p, ref, what):
+    err = np.abs(p - ref) / np.maximum(ref, 1.0)
+    bright = ref > 20.0
+    i = np.unravel_index(np.argmax(err), err.shape)
+    assert err.max() <= 0.15, f"{what}: max err {err.max():.3e} at {i} gpu={p[i]} ref={ref[i]}"
+    assert err.mean() <= 0.02, f"{what}: mean err {err.mean():.3e}"
+    if bright.any():
+        rb = np.abs(p[bright] - ref[bright]) / ref[bright]
+        assert rb.max() <= 0.03, f"{what}: bright-cell err {rb.max():.3e}"
+    return err
+
+
+def m8k_bank_natural(raw, n_z):
+    """Undo the matrix-core bank order: entry [j][wave][q][lane][p] holds bin
+    k = (4 wave + q) + 32 (lane % 16) + 512 (4 (lane // 16) + p)."""
+    w, q, lane, p = np.meshgrid(np.arange(8), np.arange(4), np.arange(64), np.arange(4), indexing="ij")
+    k = (4 * w + q) + 32 * (lane % 16) + 512 * (4 * (lane // 16) + p)
+    out = np.empty_like(raw)
+    out[:, k.ravel()] = raw
+    return out
+
+
+def test_mfma_template_bank_order(dev):
+    say("[mfma] bank")
+    pl = plan(dev, max_bins=20000, z_min=-12.0, z_step=4.0, n_z=7, n_taps=256, seg_len=8192,
+              compute="bf16", algo="mfma")
+    assert pl.algo == "mfma"
+    import torch
+    torch.cuda.synchronize()
+    raw = pl.bank().cpu().numpy().astype(np.int32) & 0xFFFF        # (7, 8192, 2)
+    H = R.template_spectra(R.z_grid(-12.0, 4.0, 7), 256, 8192)
+    for k, ref in ((0, H.real), (1, H.imag)):
+        got = m8k_bank_natural(raw[..., k], 7)
+        want = casts.bf16_bits(ref.astype(np.float32)).astype(np.int32)
+        big = np.abs(ref) > 1e-6 * np.max(np.abs(H))
+        d = np.abs(got - want)[big]
+        assert d.max() <= 1 and np.mean(d != 0) < 1e-4
+
+
+MFMA_CASES = [
+    # n, M, n_z, z_min, z_step, z_chunk, plane dtype
+    (30000, 256, 9, -16.0, 4.0, 0, "bf16"),
+    (30000, 256, 9, -16.0, 4.0, 2, "fp32"),
+    (1, 256, 3, -2.0, 2.0, 0, "fp32"),
+    (100, 64, 2, 0.0, 3.0, 0, "fp32"),
+    (7936, 256, 5, -8.0, 4.0, 1, "fp32"),
+    (7937, 256, 5, -8.0, 4.0, 0, "fp32"),
+    (15873, 1000, 4, -50.0, 25.0, 0, "fp32"),
+    (20000, 2, 3, -1.0, 1.0, 0, "fp32"),
+]
+
+
+@pytest.mark.parametrize("n,M,nz,zmin,zstep,zc,pd", MFMA_CASES)
+def test_mfma_plane_vs_oracle(dev, n, M, nz, zmin, zstep, zc, pd):
+    say(f"[mfma] n={n} M={M} nz={nz} zc={zc} {pd}")
+    x = synth.random_spectrum(n, seed=7 * n + M)
+    taps = R.template_taps(R.z_grid(zmin, zstep, nz), M)
+    ref = OP.plane(x, taps)
+    pl = plan(dev, max_bins=n, z_min=zmin, z_step=zstep, n_z=nz, n_taps=M, seg_len=8192,
+              compute="bf16", plane_dtype=pd, z_chunk=zc, algo="mfma")
+    p = widen(pl.correlate(to_dev(x, dev)))
+    err = assert_bf16_close(p, ref, f"mfma n={n} M={M}")
+    say(f"  max {err.max():.3e} mean {err.mean():.3e}")
+
+
+def test_mfma_chirp_peak(dev):
+    say("[mfma] chirp")
+    n_t, r_bar, z = 1 << 16, 12345, 20.0
+    x = synth.complex_chirp_spectrum(n_t, r_bar - z / 2, z, amp=0.05)
+    zs = R.z_grid(-40.0, 4.0, 21)
+    taps = R.template_taps(zs, 256)
+    ref = OP.plane(x, taps, r_bar - 64, r_bar + 64)
+    pl = plan(dev, max_bins=x.size, z_min=-40.0, z_step=4.0, n_z=21, n_taps=256, seg_len=8192,
+              compute="bf16", plane_dtype="fp32", algo="mfma")
+    p = widen(pl.correlate(to_dev(x, dev)))[:, r_bar - 64:r_bar + 64]
+    jr, rr = np.unravel_index(np.argmax(ref), ref.shape)
+    jg, rg = np.unravel_index(np.argmax(p), p.shape)
+    assert (jg, rg) == (jr, rr) == (15, 64)
+    assert abs(p[jg, rg] / ref[jr, rr] - 1.0) < 0.02
+
+
+def test_mfma_matches_valu_bf16(dev, cfg2):
+    """Both BF16 kernels on the single-DM spectrum: same precision form, so the
+    planes agree to the bf16 bar and the injected pulsar's band maxima sit in
+    the same cells."""
+    import torch
+    from paper_2206_12205_amd import metrics
+    c = synth.CONFIGS[2]
+    sp = cfg2
+    n = sp.spec.size
+    say("[mfma] vs valu bf16 on cfg2")
+    common = dict(max_bins=n, z_min=c["z_min"], z_step=c["z_step"], n_z=c["n_z"], n_taps=c["n_taps"],
+                  seg_len=c["seg_len"], compute="bf16", plane_dtype="fp32")
+    x = to_dev(sp.spec, dev)
+    pm = plan(dev, algo="mfma", **common).correlate(x)
+    pv = plan(dev, algo="valu", **common).correlate(x)
+    p32 = plan(dev, max_bins=n, z_min=c["z_min"], z_step=c["z_step"], n_z=c["n_z"], n_taps=c["n_taps"],
+               seg_len=c["seg_len"], compute="fp32").correlate(x)
+    for what, p in (("mfma", pm), ("valu", pv)):
+        err = ((p.double() - p32.double()).abs() / p32.double().clamp(min=1.0))
+        say(f"  {what} vs fp32: max {err.max().item():.3e} mean {err.mean().item():.3e}")
+        assert err.max().item() <= 0.15 and err.mean().item() <= 0.02
+    bands = metrics.harmonic_bands(sp.pulsars[0].f, sp.T, n, 8)
+    mm = metrics.band_maxima(pm, bands)
+    m32 = metrics.band_maxima(p32, bands)
+    for a, b in zip(mm, m32):
+        if b[2] > c["threshold"]:
+            assert (a[0], a[1]) == (b[0], b[1])
