@@ -74,10 +74,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--seg-len", type=int, default=None,
+                    help="segment length of the BF16 matrix-core plan (default: the workload's 8192)")
+    ap.add_argument("--only", choices=["bf16", "bf16_valu", "fp32", "copy"], default=None,
+                    help="time one kernel only (for profiler runs); 'copy' is a plain 256 MiB "
+                         "device copy used to calibrate the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this FDAS build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.only == "copy":
+        import torch
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(args.warmup + args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4}))
+        return
 
     import numpy as np
     import torch
@@ -96,6 +110,17 @@ def main():
 
     common = dict(max_bins=n, z_min=cfg["z_min"], z_step=cfg["z_step"], n_z=n_z,
                   n_taps=cfg["n_taps"], seg_len=cfg["seg_len"], device=dev)
+    if args.only:
+        kw = {"bf16": dict(compute="bf16", plane_dtype="bf16", seg_len=args.seg_len or cfg["seg_len"]),
+              "bf16_valu": dict(compute="bf16", plane_dtype="bf16", algo="valu"),
+              "fp32": dict(compute="fp32", plane_dtype="fp32")}[args.only]
+        cm = dict(common)
+        cm.update(kw)
+        pl = Plan(**cm)
+        ms, wall = time_correlate(pl, x, pl.empty_plane(n), args.steps, args.warmup)
+        print(json.dumps({"only": args.only, "algo": pl.algo, "ms_per_step": ms,
+                          "cells_per_s": cells / (ms * 1e-3), "steps": args.steps}), flush=True)
+        return
     pl_b = Plan(compute="bf16", plane_dtype="bf16", **common)            # matrix-core kernel
     pl_v = Plan(compute="bf16", plane_dtype="bf16", algo="valu", **common)
     pl_f = Plan(compute="fp32", plane_dtype="fp32", **common)

@@ -99,7 +99,7 @@ typedef struct {
 } fdas_config;
 
 /* Kernel family of the correlation.  AUTO picks the matrix-core kernel where
- * one exists (BF16 compute with L = 8192) and the vector-ALU kernel
+ * one exists (BF16 compute with L = 4096 or 8192) and the vector-ALU kernel
  * otherwise; MFMA on a configuration without a matrix-core kernel is
  * FDAS_E_UNSUPPORTED.  Both compute the same plane (the MFMA kernel rounds
  * its DFT operators to bfloat16 as well). */

@@ -1,0 +1,283 @@
+// Overlap-save correlation on the matrix cores: BF16 form, segment L = 4096.
+//
+// Same plane as the other kernels (Section "Detailed explanation": windows,
+// transform, multiply by each template's transform, inverse transform, keep
+// the central V = L - M outputs).  Every stage of every transform is a
+// 16-point DFT on the matrix cores (16x16x32 bf16 MFMA, FP32 accumulation);
+// factorisation, work split and LDS layouts are in mfma4096.hpp.  One
+// workgroup of 8 waves owns a segment and a chunk of templates:
+//
+//   forward  F1 (input rounded to bf16) -> conj(T2) -> LDS B -> F2 (conj(T1)
+//            folded) -> LDS A -> F3: the segment spectrum X[k1, k2, k3] ends in
+//            registers in the first inverse stage's B-operand layout, kept as
+//            (Re, -Im) and (Im, Re) bf16 pairs for v_dot2_f32_bf16 products.
+//   template j: the bank entry of j + 1 is prefetched; Y = X * H_j -> I1 ->
+//            LDS A -> barrier -> (coalesced flush of template j - 1's powers)
+//            -> I2 (T1 folded) -> T2 -> LDS B -> barrier -> I3 -> |y|^2 -> LDS
+//            staging, written to the plane with 16-byte stores one barrier
+//            later.
+// Register use stays under 128 VGPRs so two workgroups share a CU.
+#include "fft_valu.hpp"
+#include "internal.hpp"
+#include "mfma4096.hpp"
+#include "plane_io.hpp"
+
+namespace fdas {
+namespace m4k {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+struct alignas(16) Op {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ f32x4_t mma(const Op &a, const Op &b) {
+    const f32x4_t z = {0.f, 0.f, 0.f, 0.f};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), z,
+                                                   0, 0, 0);
+}
+
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), 0.0f,
+                                           false);
+}
+
+__device__ __forceinline__ Op load_op(const uint32_t *tab, int op, int lane) {
+    const uint4 v = reinterpret_cast<const uint4 *>(tab + op * kOpWords)[lane];
+    return Op{{v.x, v.y, v.z, v.w}};
+}
+
+// staging index of time sample t (one pad word set per 1024 keeps the I3
+// writes of the two lane-group halves in different banks)
+__device__ __forceinline__ int stage_idx(int t) { return t + 16 * (t >> 10); }
+constexpr int kStageWords = kL + 16 * 4;
+
+template <class PT>
+struct flush_chunk;
+template <>
+struct flush_chunk<__bf16> {
+    static constexpr int kAlign = 8;   // elements per 16-byte store
+    static __device__ __forceinline__ void vec(__bf16 *dst, const float *v) {
+        u32x4_t u;
+        u.x = bf16_pack(v[0], v[1]);
+        u.y = bf16_pack(v[2], v[3]);
+        u.z = bf16_pack(v[4], v[5]);
+        u.w = bf16_pack(v[6], v[7]);
+        __builtin_nontemporal_store(u, reinterpret_cast<u32x4_t *>(dst));
+    }
+};
+template <>
+struct flush_chunk<float> {
+    static constexpr int kAlign = 4;
+    static __device__ __forceinline__ void vec(float *dst, const float *v) {
+        const f32x4_t lo = {v[0], v[1], v[2], v[3]}, hi = {v[4], v[5], v[6], v[7]};
+        __builtin_nontemporal_store(lo, reinterpret_cast<f32x4_t *>(dst));
+        __builtin_nontemporal_store(hi, reinterpret_cast<f32x4_t *>(dst + 4));
+    }
+};
+
+// Write the staged powers of one template: thread tid owns t in [8 tid, 8 tid + 8).
+template <class PT>
+__device__ __forceinline__ void flush(const float *stage, PT *row, int64_t seg0, int64_t n, int half, bool full,
+                                      int tid) {
+    const int t0 = 8 * tid;
+    const float4 a = *reinterpret_cast<const float4 *>(stage + stage_idx(t0));
+    const float4 b = *reinterpret_cast<const float4 *>(stage + stage_idx(t0) + 4);
+    const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    const int64_t col = seg0 + t0;
+    const bool inside = t0 >= half && t0 + 8 <= kL - half && (full || col + 8 <= n);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(row + col)) & 15u) == 0;
+    if (inside && aligned) {
+        flush_chunk<PT>::vec(row + col, v);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int t = t0 + i;
+            if (t >= half && t < kL - half && col + i < n) plane_store<PT>::put(row + col + i, v[i]);
+        }
+    }
+}
+
+template <class PT>
+__global__ void __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(4)))
+correlate_mfma4096(const float2 *__restrict__ spec, int64_t n, const uint32_t *__restrict__ bank,
+                   const uint32_t *__restrict__ tab, PT *__restrict__ plane, int32_t M, int32_t V, int32_t n_z,
+                   int32_t z_chunk, int32_t n_chunks) {
+    __shared__ __align__(16) uint32_t bufA[kBufWords];
+    __shared__ __align__(16) uint32_t bufB[kBufWords];
+    __shared__ __align__(16) float stage[kStageWords];
+
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63, c = lane & 15, g = lane >> 4;
+    const int chunk = blockIdx.x % n_chunks;
+    const int64_t s = blockIdx.x / n_chunks;
+    const int j0 = chunk * z_chunk;
+    const int j1 = min(j0 + z_chunk, n_z);
+    if (j0 >= j1) return;
+    const int half = M / 2;
+    const int64_t seg0 = s * (int64_t)V - half;   // plane column of time index t is seg0 + t
+    const bool full = seg0 + (kL - half) <= n;
+    const float2 *t2inv = reinterpret_cast<const float2 *>(tab + kNumOps * kOpWords);
+    const float2 *t2fwd = t2inv + kT2Count;
+
+    // ---------------- forward transform ----------------
+    {
+        const Op are = load_op(tab, OP_A16M, lane), aim = load_op(tab, OP_A16M + 1, lane);
+        // F1: n2 = Q, column n3 = c, K: n1 = 4 g + p  ->  rows k1 = 4 g + e  -> buffer B
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int Q = 2 * w + q;
+            Op b;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int64_t idx = seg0 + 256 * (4 * g + p) + 16 * Q + c;
+                float2 v = make_float2(0.f, 0.f);
+                if (idx >= 0 && idx < n) v = spec[idx];
+                b.w[p] = bf16_pack(v.x, v.y);
+            }
+            const f32x4_t dre = mma(are, b), dim = mma(aim, b);
+            uint4 o;
+            uint32_t *ow = reinterpret_cast<uint32_t *>(&o);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float2 t = t2fwd[((w * 64 + lane) * 2 + q) * 4 + e];
+                ow[e] = bf16_pack(dre[e] * t.x - dim[e] * t.y, dre[e] * t.y + dim[e] * t.x);
+            }
+            *reinterpret_cast<uint4 *>(&bufB[addrB(4 * g, Q, c)]) = o;   // 4 consecutive k1
+        }
+        __syncthreads();
+        // F2: n3 = Q, column k1 = c, K: n2 = 4 g + p  ->  rows k2 = 4 g + e  -> buffer A
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int Q = 2 * w + q;
+            Op b;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) b.w[p] = bufB[addrB(c, 4 * g + p, Q)];
+            const f32x4_t dre = mma(load_op(tab, OP_AF2M + 2 * Q, lane), b);
+            const f32x4_t dim = mma(load_op(tab, OP_AF2M + 2 * Q + 1, lane), b);
+            uint4 o;
+            o.x = bf16_pack(dre[0], dim[0]);
+            o.y = bf16_pack(dre[1], dim[1]);
+            o.z = bf16_pack(dre[2], dim[2]);
+            o.w = bf16_pack(dre[3], dim[3]);
+            *reinterpret_cast<uint4 *>(&bufA[addrA(c, 4 * g, Q)]) = o;   // 4 consecutive k2
+        }
+        __syncthreads();
+    }
+    // F3: k1 = Q, column k2 = c, K: n3 = 4 g + p -> X[Q, c, 4 g + e] in registers.
+    // Each wave reads exactly the buffer-A words its own I1 writes later, so
+    // no barrier is needed before the template loop.
+    uint32_t sA[2][4], sB[2][4];
+    {
+        const Op are = load_op(tab, OP_A16M, lane), aim = load_op(tab, OP_A16M + 1, lane);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int Q = 2 * w + q;
+            Op b;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) b.w[p] = bufA[addrA(Q, c, 4 * g + p)];
+            const f32x4_t dre = mma(are, b), dim = mma(aim, b);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                sA[q][p] = bf16_pack(dre[p], -dim[p]);
+                sB[q][p] = bf16_pack(dim[p], dre[p]);
+            }
+        }
+    }
+
+    // ---------------- persistent inverse operators ----------------
+    const Op a16re = load_op(tab, OP_A16P, lane), a16im = load_op(tab, OP_A16P + 1, lane);
+    Op a2re[2], a2im[2];
+    float2 t2[2][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int Q = 2 * w + q;
+        a2re[q] = load_op(tab, OP_A2P + 2 * Q, lane);
+        a2im[q] = load_op(tab, OP_A2P + 2 * Q + 1, lane);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t2[q][e] = t2inv[((w * 64 + lane) * 2 + q) * 4 + e];
+    }
+
+    const uint4 *bank4 = reinterpret_cast<const uint4 *>(bank);
+    uint4 h[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) h[q] = bank4[(size_t)j0 * (kL / 4) + (2 * w + q) * 64 + lane];
+
+    for (int j = j0; j < j1; ++j) {
+        uint4 hc[2] = {h[0], h[1]};
+        if (j + 1 < j1) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) h[q] = bank4[(size_t)(j + 1) * (kL / 4) + (2 * w + q) * 64 + lane];
+        }
+        // I1: Y = X * H_j, DFT16 over k3; rows n3 = 4 g + e -> buffer A (4 x b32)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int Q = 2 * w + q;
+            const uint32_t hw[4] = {hc[q].x, hc[q].y, hc[q].z, hc[q].w};
+            Op b;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) b.w[p] = bf16_pack(dot2(sA[q][p], hw[p]), dot2(sB[q][p], hw[p]));
+            const f32x4_t dre = mma(a16re, b), dim = mma(a16im, b);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bufA[addrA(Q, c, 4 * g + e)] = bf16_pack(dre[e], dim[e]);
+        }
+        __syncthreads();
+        if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n, seg0, n, half, full, tid);
+        // I2: DFT16 over k2 with T1 folded, then T2; rows n2 = 4 g + e -> buffer B (4 x b32)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int Q = 2 * w + q;
+            const uint4 v = *reinterpret_cast<const uint4 *>(&bufA[addrA(c, 4 * g, Q)]);   // 4 consecutive k2
+            const Op b = {{v.x, v.y, v.z, v.w}};
+            const f32x4_t dre = mma(a2re[q], b), dim = mma(a2im[q], b);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float2 t = t2[q][e];
+                bufB[addrB(c, 4 * g + e, Q)] = bf16_pack(dre[e] * t.x - dim[e] * t.y, dre[e] * t.y + dim[e] * t.x);
+            }
+        }
+        __syncthreads();
+        // I3: DFT16 over k1; rows n1 = 4 g + e; |y|^2 -> staging
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int Q = 2 * w + q;
+            const uint4 v = *reinterpret_cast<const uint4 *>(&bufB[addrB(4 * g, Q, c)]);   // 4 consecutive k1
+            const Op b = {{v.x, v.y, v.z, v.w}};
+            const f32x4_t dre = mma(a16re, b), dim = mma(a16im, b);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                stage[stage_idx(256 * (4 * g + e) + 16 * Q + c)] = dre[e] * dre[e] + dim[e] * dim[e];
+        }
+    }
+    __syncthreads();
+    flush<PT>(stage, plane + (int64_t)(j1 - 1) * n, seg0, n, half, full, tid);
+}
+
+namespace {
+template <class PT>
+hipError_t launch(const fdas_plan_s &p, const void *spec, int64_t n, void *plane, hipStream_t st) {
+    const int64_t n_seg = (n + p.V - 1) / p.V;
+    const int64_t blocks = n_seg * p.n_chunks;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const auto *ws = static_cast<const unsigned char *>(p.ws);
+    hipLaunchKernelGGL(correlate_mfma4096<PT>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+                       static_cast<const float2 *>(spec), n, reinterpret_cast<const uint32_t *>(ws + p.off_bank),
+                       reinterpret_cast<const uint32_t *>(ws + p.off_tab), static_cast<PT *>(plane), p.M, p.V,
+                       p.cfg.n_z, p.z_chunk, p.n_chunks);
+    return hipGetLastError();
+}
+}  // namespace
+
+}  // namespace m4k
+
+hipError_t launch_correlate_m4k(const fdas_plan_s &p, const void *spec, int64_t n, void *plane, hipStream_t st) {
+    if (p.L != m4k::kL || p.cfg.compute != FDAS_BF16) return hipErrorInvalidValue;
+    if (p.cfg.plane_dtype == FDAS_BF16) return m4k::launch<__bf16>(p, spec, n, plane, st);
+    if (p.cfg.plane_dtype == FDAS_FP32) return m4k::launch<float>(p, spec, n, plane, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fdas

@@ -4,6 +4,7 @@
 #include <new>
 
 #include "internal.hpp"
+#include "mfma4096.hpp"
 #include "mfma8192.hpp"
 
 namespace {
@@ -92,7 +93,7 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     p->cfg.seg_len = p->L;
     p->M = c.n_taps;
     p->V = p->L - p->M;
-    const bool mfma_ok = c.compute == FDAS_BF16 && L == fdas::m8k::kL;
+    const bool mfma_ok = c.compute == FDAS_BF16 && (L == fdas::m8k::kL || L == fdas::m4k::kL);
     if (c.algo == FDAS_ALGO_MFMA && !mfma_ok) {
         delete p;
         return FDAS_E_UNSUPPORTED;
@@ -126,7 +127,7 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     p->sz_scr = fdas::peak_scratch_bytes(p->peak_tile_cap);
     off = align_up(off + p->sz_scr, 256);
     p->off_tab = off;
-    p->sz_tab = p->mfma ? fdas::m8k::kTableBytes : 0;
+    p->sz_tab = !p->mfma ? 0 : (L == fdas::m8k::kL ? fdas::m8k::kTableBytes : fdas::m4k::kTableBytes);
     off = align_up(off + p->sz_tab, 256);
     p->ws_bytes = off;
     p->cfg.algo = p->mfma ? FDAS_ALGO_MFMA : FDAS_ALGO_VALU;
@@ -184,6 +185,7 @@ int fdas_correlate(fdas_plan_t p, const void *spectrum, int64_t n_bins, void *pl
     if (!p->ws) return FDAS_E_WORKSPACE;
     if (!p->templates_ready) return FDAS_E_STATE;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->mfma && p->L == fdas::m4k::kL) return hip_status(fdas::launch_correlate_m4k(*p, spectrum, n_bins, plane, st));
     if (p->mfma) return hip_status(fdas::launch_correlate_mfma(*p, spectrum, n_bins, plane, st));
     return hip_status(fdas::launch_correlate(*p, spectrum, n_bins, plane, st));
 }

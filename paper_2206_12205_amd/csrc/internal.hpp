@@ -28,7 +28,7 @@ struct fdas_plan_s {
     size_t off_taps = 0, sz_taps = 0;      // FP64 taps, n_z x M complex (template build)
     size_t off_scr = 0, sz_scr = 0;        // peak counters
     size_t off_tab = 0, sz_tab = 0;        // matrix-core operator/twiddle tables
-    bool mfma = false;                     // matrix-core correlation kernel
+    bool mfma = false;                     // matrix-core correlation kernel (L = 4096 or 8192)
     int64_t peak_tile_cap = 0;             // number of peak tiles the scratch holds
     void *ws = nullptr;
     size_t ws_size = 0;
@@ -43,6 +43,10 @@ hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t s);
 // Matrix-core correlation, L = 8192, BF16 form (correlate_mfma.hip).
 hipError_t launch_correlate_mfma(const fdas_plan_s &p, const void *spec, int64_t n,
                                  void *plane, hipStream_t s);
+
+// Matrix-core correlation, L = 4096, BF16 form (correlate_m4k.hip).
+hipError_t launch_correlate_m4k(const fdas_plan_s &p, const void *spec, int64_t n,
+                                void *plane, hipStream_t s);
 
 // Correlation (correlate.hip).
 hipError_t launch_correlate(const fdas_plan_s &p, const void *spec, int64_t n,

@@ -16,6 +16,7 @@
 //   twiddles  tw[e] = exp(-2 pi i e / L), e in [0, L), FP64 -> compute type.
 #include "fft_valu.hpp"
 #include "internal.hpp"
+#include "mfma4096.hpp"
 #include "mfma8192.hpp"
 #include "response.hpp"
 
@@ -56,17 +57,18 @@ template <>
 __device__ __forceinline__ bf16c bank_cast<bf16c>(cd v) { return {bf16_pack((float)v.re, (float)v.im)}; }
 
 // Grid: (L / 256, n_z); taps of template j staged in LDS.
-// Position of frequency bin k of template j in the bank: natural order, or
-// the lane order of the length-8192 matrix-core kernel (m8k).
-__device__ __forceinline__ int64_t bank_pos(int j, int k, int L, bool m8k_order) {
-    if (!m8k_order) return (int64_t)j * L + k;
+// Position of frequency bin k of template j in the bank: natural order (0),
+// or the lane order of the matrix-core kernels for L = 8192 (1) / 4096 (2).
+__device__ __forceinline__ int64_t bank_pos(int j, int k, int L, int order) {
+    if (order == 0) return (int64_t)j * L + k;
+    if (order == 2) return (int64_t)j * L + m4k::bank_pos_of(k);
     const int k1 = k & 31, k2 = (k >> 5) & 15, k3 = k >> 9;
     const int wave = k1 >> 2, q = k1 & 3, lane = k2 + 16 * (k3 >> 2), p = k3 & 3;
     return (int64_t)j * L + (((wave * 4 + q) * 64 + lane) * 4 + p);
 }
 
 template <class B>
-__global__ void __launch_bounds__(256) k_spectrum(const cd *taps, B *bank, int32_t M, int32_t L, int m8k_order) {
+__global__ void __launch_bounds__(256) k_spectrum(const cd *taps, B *bank, int32_t M, int32_t L, int order) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cd *g = reinterpret_cast<cd *>(smem_raw);
     const int j = blockIdx.y;
@@ -85,7 +87,7 @@ __global__ void __launch_bounds__(256) k_spectrum(const cd *taps, B *bank, int32
         im += g[i].re * sn + g[i].im * cs;
     }
     const double invL = 1.0 / (double)L;
-    bank[bank_pos(j, k, L, m8k_order != 0)] = bank_cast<B>(cd{re * invL, im * invL});
+    bank[bank_pos(j, k, L, order)] = bank_cast<B>(cd{re * invL, im * invL});
 }
 
 // exp(s 2 pi i m / N) for integer m, FP64.
@@ -170,6 +172,60 @@ __global__ void k_m8k_tables(uint32_t *tab) {
     }
 }
 
+// Operators and per-lane twiddles of the length-4096 matrix-core kernel
+// (mfma4096.hpp).  One thread per (op, lane) or twiddle slot.
+__global__ void k_m4k_tables(uint32_t *tab) {
+    using namespace m4k;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kNumOps * 64) {
+        const int op = t / 64, lane = t % 64, c = lane & 15, g = lane >> 4;
+        uint32_t w[4];
+        for (int e = 0; e < 8; e += 2) {
+            float v[2];
+            for (int h = 0; h < 2; ++h) {
+                const int el = e + h, part_in = el & 1;
+                const int row = c, pin = 4 * g + (el >> 1);
+                int part_out;
+                cd a;
+                if (op < OP_A2P) {                        // inverse DFT16
+                    part_out = op - OP_A16P;
+                    a = unit_root((int64_t)row * pin, 16, +1);
+                } else if (op < OP_A16M) {                // inverse DFT16, T1(k2 = pin; n3)
+                    const int n3 = (op - OP_A2P) >> 1;
+                    part_out = (op - OP_A2P) & 1;
+                    a = unit_root((int64_t)16 * row * pin + (int64_t)n3 * pin, 256, +1);
+                } else if (op < OP_AF2M) {                // forward DFT16
+                    part_out = op - OP_A16M;
+                    a = unit_root((int64_t)row * pin, 16, -1);
+                } else {                                  // forward DFT16, conj T1(k2 = row; n3)
+                    const int n3 = (op - OP_AF2M) >> 1;
+                    part_out = (op - OP_AF2M) & 1;
+                    a = unit_root((int64_t)16 * row * pin + (int64_t)n3 * row, 256, -1);
+                }
+                const double val = part_out == 0 ? (part_in ? -a.im : a.re) : (part_in ? a.re : a.im);
+                v[h] = (float)val;
+            }
+            w[e >> 1] = bf16_pack(v[0], v[1]);
+        }
+        for (int i = 0; i < 4; ++i) tab[op * kOpWords + lane * 4 + i] = w[i];
+        return;
+    }
+    const int u = t - kNumOps * 64;
+    float2 *tw = reinterpret_cast<float2 *>(tab + kNumOps * kOpWords);
+    if (u < 2 * kT2Count) {
+        const int v = u % kT2Count;
+        const int e = v & 3, q = (v >> 2) & 1, lane = (v >> 3) & 63, wave = v >> 9;
+        const int c = lane & 15, g = lane >> 4, Q = 2 * wave + q;
+        cd r;
+        if (u < kT2Count) {   // inverse T2: k1 = c, n2 = 4 g + e, n3 = Q
+            r = unit_root((int64_t)(16 * (4 * g + e) + Q) * c, kL, +1);
+        } else {              // forward conj T2: n2 = Q, n3 = c, k1 = 4 g + e
+            r = unit_root((int64_t)(16 * Q + c) * (4 * g + e), kL, -1);
+        }
+        tw[u] = make_float2((float)r.re, (float)r.im);
+    }
+}
+
 template <class R>
 __global__ void k_twiddles(cpx<R> *tw, int32_t L) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,10 +265,14 @@ hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st) {
             break;
         case FDAS_BF16:
             hipLaunchKernelGGL(k_spectrum<bf16c>, grid, dim3(256), lds, st, taps, static_cast<bf16c *>(bank), p.M,
-                               p.L, p.mfma ? 1 : 0);
-            if (p.mfma) {
+                               p.L, !p.mfma ? 0 : (p.L == m8k::kL ? 1 : 2));
+            if (p.mfma && p.L == m8k::kL) {
                 const int nthreads = m8k::kNumOps * 64 + m8k::kT2Count + m8k::kT2FCount;
                 hipLaunchKernelGGL(k_m8k_tables, dim3((nthreads + 255) / 256), dim3(256), 0, st,
+                                   reinterpret_cast<uint32_t *>(ws + p.off_tab));
+            } else if (p.mfma) {
+                const int nthreads = m4k::kNumOps * 64 + 2 * m4k::kT2Count;
+                hipLaunchKernelGGL(k_m4k_tables, dim3((nthreads + 255) / 256), dim3(256), 0, st,
                                    reinterpret_cast<uint32_t *>(ws + p.off_tab));
             }
             hipLaunchKernelGGL(k_twiddles<float>, dim3((p.L + 255) / 256), dim3(256), 0, st,

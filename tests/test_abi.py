@@ -59,7 +59,8 @@ def test_struct_sizes():
     (dict(seg_len=0, n_taps=256), F.OK),     # automatic L
     (dict(compute="bf16", seg_len=8192, n_taps=256, algo="mfma"), F.OK),
     (dict(compute="fp32", seg_len=8192, n_taps=256, algo="mfma"), F.E_UNSUPPORTED),
-    (dict(compute="bf16", seg_len=4096, n_taps=256, algo="mfma"), F.E_UNSUPPORTED),
+    (dict(compute="bf16", seg_len=4096, n_taps=256, algo="mfma"), F.OK),
+    (dict(compute="bf16", seg_len=2048, n_taps=256, algo="mfma"), F.E_UNSUPPORTED),
     (dict(algo=3), F.E_INVALID),
 ])
 def test_plan_validation(kw, want):

@@ -298,27 +298,33 @@ def assert_bf16_close(p, ref, what):
     return err
 
 
-def m8k_bank_natural(raw, n_z):
-    """Undo the matrix-core bank order: entry [j][wave][q][lane][p] holds bin
-    k = (4 wave + q) + 32 (lane % 16) + 512 (4 (lane // 16) + p)."""
-    w, q, lane, p = np.meshgrid(np.arange(8), np.arange(4), np.arange(64), np.arange(4), indexing="ij")
-    k = (4 * w + q) + 32 * (lane % 16) + 512 * (4 * (lane // 16) + p)
+def mfma_bank_natural(raw, L):
+    """Undo the matrix-core bank order.
+    L = 8192: entry [wave][q][lane][p] holds bin k = (4 wave + q) + 32 (lane % 16) + 512 (4 (lane // 16) + p);
+    L = 4096: entry [Q][lane][p] holds bin k = Q + 16 (lane % 16) + 256 (4 (lane // 16) + p)."""
+    if L == 8192:
+        w, q, lane, p = np.meshgrid(np.arange(8), np.arange(4), np.arange(64), np.arange(4), indexing="ij")
+        k = (4 * w + q) + 32 * (lane % 16) + 512 * (4 * (lane // 16) + p)
+    else:
+        Q, lane, p = np.meshgrid(np.arange(16), np.arange(64), np.arange(4), indexing="ij")
+        k = Q + 16 * (lane % 16) + 256 * (4 * (lane // 16) + p)
     out = np.empty_like(raw)
     out[:, k.ravel()] = raw
     return out
 
 
-def test_mfma_template_bank_order(dev):
-    say("[mfma] bank")
-    pl = plan(dev, max_bins=20000, z_min=-12.0, z_step=4.0, n_z=7, n_taps=256, seg_len=8192,
+@pytest.mark.parametrize("L", [4096, 8192])
+def test_mfma_template_bank_order(dev, L):
+    say(f"[mfma] bank L={L}")
+    pl = plan(dev, max_bins=20000, z_min=-12.0, z_step=4.0, n_z=7, n_taps=256, seg_len=L,
               compute="bf16", algo="mfma")
     assert pl.algo == "mfma"
     import torch
     torch.cuda.synchronize()
-    raw = pl.bank().cpu().numpy().astype(np.int32) & 0xFFFF        # (7, 8192, 2)
-    H = R.template_spectra(R.z_grid(-12.0, 4.0, 7), 256, 8192)
+    raw = pl.bank().cpu().numpy().astype(np.int32) & 0xFFFF        # (7, L, 2)
+    H = R.template_spectra(R.z_grid(-12.0, 4.0, 7), 256, L)
     for k, ref in ((0, H.real), (1, H.imag)):
-        got = m8k_bank_natural(raw[..., k], 7)
+        got = mfma_bank_natural(raw[..., k], L)
         want = casts.bf16_bits(ref.astype(np.float32)).astype(np.int32)
         big = np.abs(ref) > 1e-6 * np.max(np.abs(H))
         d = np.abs(got - want)[big]
@@ -333,32 +339,39 @@ MFMA_CASES = [
     (100, 64, 2, 0.0, 3.0, 0, "fp32"),
     (7936, 256, 5, -8.0, 4.0, 1, "fp32"),
     (7937, 256, 5, -8.0, 4.0, 0, "fp32"),
+    (3840, 256, 4, -8.0, 4.0, 0, "bf16"),
+    (3841, 256, 4, -8.0, 4.0, 3, "bf16"),
+    (12001, 130, 6, -10.0, 4.0, 0, "bf16"),
     (15873, 1000, 4, -50.0, 25.0, 0, "fp32"),
     (20000, 2, 3, -1.0, 1.0, 0, "fp32"),
 ]
 
 
+@pytest.mark.parametrize("L", [4096, 8192])
 @pytest.mark.parametrize("n,M,nz,zmin,zstep,zc,pd", MFMA_CASES)
-def test_mfma_plane_vs_oracle(dev, n, M, nz, zmin, zstep, zc, pd):
-    say(f"[mfma] n={n} M={M} nz={nz} zc={zc} {pd}")
+def test_mfma_plane_vs_oracle(dev, n, M, nz, zmin, zstep, zc, pd, L):
+    if M >= L:
+        pytest.skip("taps must be fewer than the segment length")
+    say(f"[mfma] L={L} n={n} M={M} nz={nz} zc={zc} {pd}")
     x = synth.random_spectrum(n, seed=7 * n + M)
     taps = R.template_taps(R.z_grid(zmin, zstep, nz), M)
     ref = OP.plane(x, taps)
-    pl = plan(dev, max_bins=n, z_min=zmin, z_step=zstep, n_z=nz, n_taps=M, seg_len=8192,
+    pl = plan(dev, max_bins=n, z_min=zmin, z_step=zstep, n_z=nz, n_taps=M, seg_len=L,
               compute="bf16", plane_dtype=pd, z_chunk=zc, algo="mfma")
     p = widen(pl.correlate(to_dev(x, dev)))
     err = assert_bf16_close(p, ref, f"mfma n={n} M={M}")
     say(f"  max {err.max():.3e} mean {err.mean():.3e}")
 
 
-def test_mfma_chirp_peak(dev):
-    say("[mfma] chirp")
+@pytest.mark.parametrize("L", [4096, 8192])
+def test_mfma_chirp_peak(dev, L):
+    say(f"[mfma] chirp L={L}")
     n_t, r_bar, z = 1 << 16, 12345, 20.0
     x = synth.complex_chirp_spectrum(n_t, r_bar - z / 2, z, amp=0.05)
     zs = R.z_grid(-40.0, 4.0, 21)
     taps = R.template_taps(zs, 256)
     ref = OP.plane(x, taps, r_bar - 64, r_bar + 64)
-    pl = plan(dev, max_bins=x.size, z_min=-40.0, z_step=4.0, n_z=21, n_taps=256, seg_len=8192,
+    pl = plan(dev, max_bins=x.size, z_min=-40.0, z_step=4.0, n_z=21, n_taps=256, seg_len=L,
               compute="bf16", plane_dtype="fp32", algo="mfma")
     p = widen(pl.correlate(to_dev(x, dev)))[:, r_bar - 64:r_bar + 64]
     jr, rr = np.unravel_index(np.argmax(ref), ref.shape)
@@ -367,7 +380,8 @@ def test_mfma_chirp_peak(dev):
     assert abs(p[jg, rg] / ref[jr, rr] - 1.0) < 0.02
 
 
-def test_mfma_matches_valu_bf16(dev, cfg2):
+@pytest.mark.parametrize("L", [4096, 8192])
+def test_mfma_matches_valu_bf16(dev, cfg2, L):
     """Both BF16 kernels on the single-DM spectrum: same precision form, so the
     planes agree to the bf16 bar and the injected pulsar's band maxima sit in
     the same cells."""
@@ -376,12 +390,12 @@ def test_mfma_matches_valu_bf16(dev, cfg2):
     c = synth.CONFIGS[2]
     sp = cfg2
     n = sp.spec.size
-    say("[mfma] vs valu bf16 on cfg2")
+    say(f"[mfma] L={L} vs valu bf16 on cfg2")
     common = dict(max_bins=n, z_min=c["z_min"], z_step=c["z_step"], n_z=c["n_z"], n_taps=c["n_taps"],
-                  seg_len=c["seg_len"], compute="bf16", plane_dtype="fp32")
+                  compute="bf16", plane_dtype="fp32")
     x = to_dev(sp.spec, dev)
-    pm = plan(dev, algo="mfma", **common).correlate(x)
-    pv = plan(dev, algo="valu", **common).correlate(x)
+    pm = plan(dev, algo="mfma", seg_len=L, **common).correlate(x)
+    pv = plan(dev, algo="valu", seg_len=c["seg_len"], **common).correlate(x)
     p32 = plan(dev, max_bins=n, z_min=c["z_min"], z_step=c["z_step"], n_z=c["n_z"], n_taps=c["n_taps"],
                seg_len=c["seg_len"], compute="fp32").correlate(x)
     for what, p in (("mfma", pm), ("valu", pv)):
