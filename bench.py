@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--seg-len", type=int, default=None,
                     help="segment length of the BF16 matrix-core plan (default: the workload's 8192)")
+    ap.add_argument("--z-chunk", type=int, default=0,
+                    help="templates per workgroup of the BF16 plan (0: the library's choice)")
     ap.add_argument("--only", choices=["bf16", "bf16_valu", "fp32", "copy"], default=None,
                     help="time one kernel only (for profiler runs); 'copy' is a plain 256 MiB "
                          "device copy used to calibrate the HBM byte counters")
@@ -111,14 +113,16 @@ def main():
     common = dict(max_bins=n, z_min=cfg["z_min"], z_step=cfg["z_step"], n_z=n_z,
                   n_taps=cfg["n_taps"], seg_len=cfg["seg_len"], device=dev)
     if args.only:
-        kw = {"bf16": dict(compute="bf16", plane_dtype="bf16", seg_len=args.seg_len or cfg["seg_len"]),
+        kw = {"bf16": dict(compute="bf16", plane_dtype="bf16", seg_len=args.seg_len or cfg["seg_len"],
+                           z_chunk=args.z_chunk),
               "bf16_valu": dict(compute="bf16", plane_dtype="bf16", algo="valu"),
               "fp32": dict(compute="fp32", plane_dtype="fp32")}[args.only]
         cm = dict(common)
         cm.update(kw)
         pl = Plan(**cm)
         ms, wall = time_correlate(pl, x, pl.empty_plane(n), args.steps, args.warmup)
-        print(json.dumps({"only": args.only, "algo": pl.algo, "ms_per_step": ms,
+        print(json.dumps({"only": args.only, "algo": pl.algo, "seg_len": pl.seg_len,
+                          "z_chunk": int(pl.layout.z_chunk), "ms_per_step": ms,
                           "cells_per_s": cells / (ms * 1e-3), "steps": args.steps}), flush=True)
         return
     pl_b = Plan(compute="bf16", plane_dtype="bf16", **common)            # matrix-core kernel

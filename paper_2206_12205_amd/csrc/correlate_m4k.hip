@@ -7,15 +7,17 @@
 // factorisation, work split and LDS layouts are in mfma4096.hpp.  One
 // workgroup of 8 waves owns a segment and a chunk of templates:
 //
-//   forward  F1 (input rounded to bf16) -> conj(T2) -> LDS B -> F2 (conj(T1)
-//            folded) -> LDS A -> F3: the segment spectrum X[k1, k2, k3] ends in
-//            registers in the first inverse stage's B-operand layout, kept as
-//            (Re, -Im) and (Im, Re) bf16 pairs for v_dot2_f32_bf16 products.
+//   forward  F1 (input rounded to bf16) -> LDS B -> F2 -> LDS A -> F3: the
+//            segment spectrum X[k1, k2, k3] ends in registers in the first
+//            inverse stage's B-operand layout, kept as (Re, -Im) and (Im, Re)
+//            bf16 pairs so each product with a template value is two
+//            v_dot2_f32_bf16.
 //   template j: the bank entry of j + 1 is prefetched; Y = X * H_j -> I1 ->
 //            LDS A -> barrier -> (coalesced flush of template j - 1's powers)
-//            -> I2 (T1 folded) -> T2 -> LDS B -> barrier -> I3 -> |y|^2 -> LDS
-//            staging, written to the plane with 16-byte stores one barrier
-//            later.
+//            -> I2 -> LDS B -> barrier -> I3 -> |y|^2 -> LDS staging, written
+//            to the plane with 16-byte stores one barrier later.
+// All twiddles live in the per-group stage operators, so the vector ALU only
+// forms the template product, packs stage outputs to bf16 and squares.
 // Register use stays under 128 VGPRs so two workgroups share a CU.
 #include "fft_valu.hpp"
 #include "internal.hpp"
@@ -40,6 +42,7 @@ __device__ __forceinline__ f32x4_t mma(const Op &a, const Op &b) {
                                                    0, 0, 0);
 }
 
+// a.lo * b.lo + a.hi * b.hi of two bf16 pairs, accumulated in FP32
 __device__ __forceinline__ float dot2(uint32_t a, uint32_t b) {
     return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), 0.0f,
                                            false);
@@ -120,85 +123,74 @@ correlate_mfma4096(const float2 *__restrict__ spec, int64_t n, const uint32_t *_
     const int half = M / 2;
     const int64_t seg0 = s * (int64_t)V - half;   // plane column of time index t is seg0 + t
     const bool full = seg0 + (kL - half) <= n;
-    const float2 *t2inv = reinterpret_cast<const float2 *>(tab + kNumOps * kOpWords);
-    const float2 *t2fwd = t2inv + kT2Count;
-
     // ---------------- forward transform ----------------
-    {
-        const Op are = load_op(tab, OP_A16M, lane), aim = load_op(tab, OP_A16M + 1, lane);
-        // F1: n2 = Q, column n3 = c, K: n1 = 4 g + p  ->  rows k1 = 4 g + e  -> buffer B
+    // F1: n2 = Q, column n3 = c, K: n1 = 4 g + p  ->  rows k1 = 4 g + e  -> buffer B
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int Q = 2 * w + q;
-            Op b;
+    for (int q = 0; q < 2; ++q) {
+        const int Q = 2 * w + q;
+        Op b;
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int64_t idx = seg0 + 256 * (4 * g + p) + 16 * Q + c;
-                float2 v = make_float2(0.f, 0.f);
-                if (idx >= 0 && idx < n) v = spec[idx];
-                b.w[p] = bf16_pack(v.x, v.y);
-            }
-            const f32x4_t dre = mma(are, b), dim = mma(aim, b);
-            uint4 o;
-            uint32_t *ow = reinterpret_cast<uint32_t *>(&o);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float2 t = t2fwd[((w * 64 + lane) * 2 + q) * 4 + e];
-                ow[e] = bf16_pack(dre[e] * t.x - dim[e] * t.y, dre[e] * t.y + dim[e] * t.x);
-            }
-            *reinterpret_cast<uint4 *>(&bufB[addrB(4 * g, Q, c)]) = o;   // 4 consecutive k1
+        for (int p = 0; p < 4; ++p) {
+            const int64_t idx = seg0 + 256 * (4 * g + p) + 16 * Q + c;
+            float2 v = make_float2(0.f, 0.f);
+            if (idx >= 0 && idx < n) v = spec[idx];
+            b.w[p] = bf16_pack(v.x, v.y);
         }
-        __syncthreads();
-        // F2: n3 = Q, column k1 = c, K: n2 = 4 g + p  ->  rows k2 = 4 g + e  -> buffer A
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int Q = 2 * w + q;
-            Op b;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) b.w[p] = bufB[addrB(c, 4 * g + p, Q)];
-            const f32x4_t dre = mma(load_op(tab, OP_AF2M + 2 * Q, lane), b);
-            const f32x4_t dim = mma(load_op(tab, OP_AF2M + 2 * Q + 1, lane), b);
-            uint4 o;
-            o.x = bf16_pack(dre[0], dim[0]);
-            o.y = bf16_pack(dre[1], dim[1]);
-            o.z = bf16_pack(dre[2], dim[2]);
-            o.w = bf16_pack(dre[3], dim[3]);
-            *reinterpret_cast<uint4 *>(&bufA[addrA(c, 4 * g, Q)]) = o;   // 4 consecutive k2
-        }
-        __syncthreads();
+        const f32x4_t dre = mma(load_op(tab, OP_F12 + 2 * Q, lane), b);
+        const f32x4_t dim = mma(load_op(tab, OP_F12 + 2 * Q + 1, lane), b);
+        uint4 o;
+        o.x = bf16_pack(dre[0], dim[0]);
+        o.y = bf16_pack(dre[1], dim[1]);
+        o.z = bf16_pack(dre[2], dim[2]);
+        o.w = bf16_pack(dre[3], dim[3]);
+        *reinterpret_cast<uint4 *>(&bufB[addrB(4 * g, Q, c)]) = o;   // 4 consecutive k1
     }
+    __syncthreads();
+    // F2: n3 = Q, column k1 = c, K: n2 = 4 g + p  ->  rows k2 = 4 g + e  -> buffer A
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int Q = 2 * w + q;
+        Op b;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) b.w[p] = bufB[addrB(c, 4 * g + p, Q)];
+        const f32x4_t dre = mma(load_op(tab, OP_F12 + 2 * Q, lane), b);
+        const f32x4_t dim = mma(load_op(tab, OP_F12 + 2 * Q + 1, lane), b);
+        uint4 o;
+        o.x = bf16_pack(dre[0], dim[0]);
+        o.y = bf16_pack(dre[1], dim[1]);
+        o.z = bf16_pack(dre[2], dim[2]);
+        o.w = bf16_pack(dre[3], dim[3]);
+        *reinterpret_cast<uint4 *>(&bufA[addrA(c, 4 * g, Q)]) = o;   // 4 consecutive k2
+    }
+    __syncthreads();
     // F3: k1 = Q, column k2 = c, K: n3 = 4 g + p -> X[Q, c, 4 g + e] in registers.
     // Each wave reads exactly the buffer-A words its own I1 writes later, so
     // no barrier is needed before the template loop.
     uint32_t sA[2][4], sB[2][4];
-    {
-        const Op are = load_op(tab, OP_A16M, lane), aim = load_op(tab, OP_A16M + 1, lane);
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int Q = 2 * w + q;
-            Op b;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) b.w[p] = bufA[addrA(Q, c, 4 * g + p)];
-            const f32x4_t dre = mma(are, b), dim = mma(aim, b);
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                sA[q][p] = bf16_pack(dre[p], -dim[p]);
-                sB[q][p] = bf16_pack(dim[p], dre[p]);
-            }
-        }
-    }
-
-    // ---------------- persistent inverse operators ----------------
-    const Op a16re = load_op(tab, OP_A16P, lane), a16im = load_op(tab, OP_A16P + 1, lane);
-    Op a2re[2], a2im[2];
-    float2 t2[2][4];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int Q = 2 * w + q;
-        a2re[q] = load_op(tab, OP_A2P + 2 * Q, lane);
-        a2im[q] = load_op(tab, OP_A2P + 2 * Q + 1, lane);
+        Op b;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) t2[q][e] = t2inv[((w * 64 + lane) * 2 + q) * 4 + e];
+        for (int p = 0; p < 4; ++p) b.w[p] = bufA[addrA(Q, c, 4 * g + p)];
+        const f32x4_t dre = mma(load_op(tab, OP_F3 + 2 * Q, lane), b);
+        const f32x4_t dim = mma(load_op(tab, OP_F3 + 2 * Q + 1, lane), b);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            sA[q][p] = bf16_pack(dre[p], -dim[p]);
+            sB[q][p] = bf16_pack(dim[p], dre[p]);
+        }
+    }
+
+    // ---------------- per-group inverse operators ----------------
+    Op a1re[2], a1im[2], a23re[2], a23im[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int Q = 2 * w + q;
+        a1re[q] = load_op(tab, OP_I1 + 2 * Q, lane);
+        a1im[q] = load_op(tab, OP_I1 + 2 * Q + 1, lane);
+        a23re[q] = load_op(tab, OP_I23 + 2 * Q, lane);
+        a23im[q] = load_op(tab, OP_I23 + 2 * Q + 1, lane);
     }
 
     const uint4 *bank4 = reinterpret_cast<const uint4 *>(bank);
@@ -212,7 +204,7 @@ correlate_mfma4096(const float2 *__restrict__ spec, int64_t n, const uint32_t *_
 #pragma unroll
             for (int q = 0; q < 2; ++q) h[q] = bank4[(size_t)(j + 1) * (kL / 4) + (2 * w + q) * 64 + lane];
         }
-        // I1: Y = X * H_j, DFT16 over k3; rows n3 = 4 g + e -> buffer A (4 x b32)
+        // I1 (group k1 = Q): Y = X * H_j, DFT16 over k3 with e(n3 k1); rows n3 = 4 g + e -> buffer A
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int Q = 2 * w + q;
@@ -220,33 +212,30 @@ correlate_mfma4096(const float2 *__restrict__ spec, int64_t n, const uint32_t *_
             Op b;
 #pragma unroll
             for (int p = 0; p < 4; ++p) b.w[p] = bf16_pack(dot2(sA[q][p], hw[p]), dot2(sB[q][p], hw[p]));
-            const f32x4_t dre = mma(a16re, b), dim = mma(a16im, b);
+            const f32x4_t dre = mma(a1re[q], b), dim = mma(a1im[q], b);
 #pragma unroll
             for (int e = 0; e < 4; ++e) bufA[addrA(Q, c, 4 * g + e)] = bf16_pack(dre[e], dim[e]);
         }
         __syncthreads();
         if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n, seg0, n, half, full, tid);
-        // I2: DFT16 over k2 with T1 folded, then T2; rows n2 = 4 g + e -> buffer B (4 x b32)
+        // I2 (group n3 = Q): DFT16 over k2 with e(16 n3 k2); rows n2 = 4 g + e -> buffer B
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int Q = 2 * w + q;
             const uint4 v = *reinterpret_cast<const uint4 *>(&bufA[addrA(c, 4 * g, Q)]);   // 4 consecutive k2
             const Op b = {{v.x, v.y, v.z, v.w}};
-            const f32x4_t dre = mma(a2re[q], b), dim = mma(a2im[q], b);
+            const f32x4_t dre = mma(a23re[q], b), dim = mma(a23im[q], b);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float2 t = t2[q][e];
-                bufB[addrB(c, 4 * g + e, Q)] = bf16_pack(dre[e] * t.x - dim[e] * t.y, dre[e] * t.y + dim[e] * t.x);
-            }
+            for (int e = 0; e < 4; ++e) bufB[addrB(c, 4 * g + e, Q)] = bf16_pack(dre[e], dim[e]);
         }
         __syncthreads();
-        // I3: DFT16 over k1; rows n1 = 4 g + e; |y|^2 -> staging
+        // I3 (group n2 = Q): DFT16 over k1 with e(16 n2 k1); rows n1 = 4 g + e; |y|^2 -> staging
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int Q = 2 * w + q;
             const uint4 v = *reinterpret_cast<const uint4 *>(&bufB[addrB(4 * g, Q, c)]);   // 4 consecutive k1
             const Op b = {{v.x, v.y, v.z, v.w}};
-            const f32x4_t dre = mma(a16re, b), dim = mma(a16im, b);
+            const f32x4_t dre = mma(a23re[q], b), dim = mma(a23im[q], b);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 stage[stage_idx(256 * (4 * g + e) + 16 * Q + c)] = dre[e] * dre[e] + dim[e] * dim[e];

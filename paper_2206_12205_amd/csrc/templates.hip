@@ -172,58 +172,26 @@ __global__ void k_m8k_tables(uint32_t *tab) {
     }
 }
 
-// Operators and per-lane twiddles of the length-4096 matrix-core kernel
-// (mfma4096.hpp).  One thread per (op, lane) or twiddle slot.
+// Stage operators of the length-4096 matrix-core kernel (mfma4096.hpp), one
+// thread per (op, lane).
 __global__ void k_m4k_tables(uint32_t *tab) {
     using namespace m4k;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < kNumOps * 64) {
-        const int op = t / 64, lane = t % 64, c = lane & 15, g = lane >> 4;
-        uint32_t w[4];
-        for (int e = 0; e < 8; e += 2) {
-            float v[2];
-            for (int h = 0; h < 2; ++h) {
-                const int el = e + h, part_in = el & 1;
-                const int row = c, pin = 4 * g + (el >> 1);
-                int part_out;
-                cd a;
-                if (op < OP_A2P) {                        // inverse DFT16
-                    part_out = op - OP_A16P;
-                    a = unit_root((int64_t)row * pin, 16, +1);
-                } else if (op < OP_A16M) {                // inverse DFT16, T1(k2 = pin; n3)
-                    const int n3 = (op - OP_A2P) >> 1;
-                    part_out = (op - OP_A2P) & 1;
-                    a = unit_root((int64_t)16 * row * pin + (int64_t)n3 * pin, 256, +1);
-                } else if (op < OP_AF2M) {                // forward DFT16
-                    part_out = op - OP_A16M;
-                    a = unit_root((int64_t)row * pin, 16, -1);
-                } else {                                  // forward DFT16, conj T1(k2 = row; n3)
-                    const int n3 = (op - OP_AF2M) >> 1;
-                    part_out = (op - OP_AF2M) & 1;
-                    a = unit_root((int64_t)16 * row * pin + (int64_t)n3 * row, 256, -1);
-                }
-                const double val = part_out == 0 ? (part_in ? -a.im : a.re) : (part_in ? a.re : a.im);
-                v[h] = (float)val;
-            }
-            w[e >> 1] = bf16_pack(v[0], v[1]);
+    if (t >= kNumOps * 64) return;
+    const int op = t / 64, lane = t % 64, c = lane & 15, g = lane >> 4;
+    const int op0 = op & ~31, G = (op & 31) >> 1, part_out = op & 1;
+    uint32_t w[4];
+    for (int e = 0; e < 8; e += 2) {
+        float v[2];
+        for (int h = 0; h < 2; ++h) {
+            const int el = e + h, part_in = el & 1;
+            const cd a = unit_root(op_exponent(op0, G, c, 4 * g + (el >> 1)), kL, +1);
+            const double val = part_out == 0 ? (part_in ? -a.im : a.re) : (part_in ? a.re : a.im);
+            v[h] = (float)val;
         }
-        for (int i = 0; i < 4; ++i) tab[op * kOpWords + lane * 4 + i] = w[i];
-        return;
+        w[e >> 1] = bf16_pack(v[0], v[1]);
     }
-    const int u = t - kNumOps * 64;
-    float2 *tw = reinterpret_cast<float2 *>(tab + kNumOps * kOpWords);
-    if (u < 2 * kT2Count) {
-        const int v = u % kT2Count;
-        const int e = v & 3, q = (v >> 2) & 1, lane = (v >> 3) & 63, wave = v >> 9;
-        const int c = lane & 15, g = lane >> 4, Q = 2 * wave + q;
-        cd r;
-        if (u < kT2Count) {   // inverse T2: k1 = c, n2 = 4 g + e, n3 = Q
-            r = unit_root((int64_t)(16 * (4 * g + e) + Q) * c, kL, +1);
-        } else {              // forward conj T2: n2 = Q, n3 = c, k1 = 4 g + e
-            r = unit_root((int64_t)(16 * Q + c) * (4 * g + e), kL, -1);
-        }
-        tw[u] = make_float2((float)r.re, (float)r.im);
-    }
+    for (int i = 0; i < 4; ++i) tab[op * kOpWords + lane * 4 + i] = w[i];
 }
 
 template <class R>
@@ -271,7 +239,7 @@ hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st) {
                 hipLaunchKernelGGL(k_m8k_tables, dim3((nthreads + 255) / 256), dim3(256), 0, st,
                                    reinterpret_cast<uint32_t *>(ws + p.off_tab));
             } else if (p.mfma) {
-                const int nthreads = m4k::kNumOps * 64 + 2 * m4k::kT2Count;
+                const int nthreads = m4k::kNumOps * 64;
                 hipLaunchKernelGGL(k_m4k_tables, dim3((nthreads + 255) / 256), dim3(256), 0, st,
                                    reinterpret_cast<uint32_t *>(ws + p.off_tab));
             }
