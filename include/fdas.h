@@ -91,11 +91,13 @@ typedef struct {
     double  z_step;       /* template spacing (bins), > 0 unless n_z == 1 */
     int32_t n_z;          /* number of templates, >= 1 */
     int32_t n_taps;       /* M: even, >= 2; the overlap between segments */
-    int32_t seg_len;      /* L: power of two in [1024, 16384], L > M; 0 = choose */
+    int32_t seg_len;      /* L: power of two in [1024, 16384], L > M; 0 = choose (BF16: 4096 for
+                             M <= 512, 8192 for M <= 2048; otherwise the power of two >= 32 M) */
     int32_t compute;      /* FDAS_FP32 | FDAS_BF16 | FDAS_FP64 */
     int32_t plane_dtype;  /* FDAS_FP32 | FDAS_BF16 (not with FP64 compute) | FDAS_FP64 (FP64 compute only) */
     int32_t z_chunk;      /* templates per workgroup; 0 = choose */
     int32_t algo;         /* FDAS_ALGO_AUTO | FDAS_ALGO_VALU | FDAS_ALGO_MFMA */
+    int32_t max_jobs;     /* largest batch fdas_set_batch accepts (0: batches unused) */
 } fdas_config;
 
 /* Kernel family of the correlation.  AUTO picks the matrix-core kernel where
@@ -104,6 +106,15 @@ typedef struct {
  * FDAS_E_UNSUPPORTED.  Both compute the same plane (the MFMA kernel rounds
  * its DFT operators to bfloat16 as well). */
 typedef enum { FDAS_ALGO_AUTO = 0, FDAS_ALGO_VALU = 1, FDAS_ALGO_MFMA = 2 } fdas_algo;
+
+/* One spectrum of a batch (offsets in elements): its n_bins complex64 bins
+ * start at spectra[spec_off], its n_z x n_bins plane (row stride n_bins) at
+ * planes[plane_off]. */
+typedef struct {
+    int64_t spec_off;
+    int64_t n_bins;
+    int64_t plane_off;
+} fdas_job;
 
 /* One entry of a peak list (24 bytes).  r is the spectral bin, z_idx the
  * template row, power the plane value widened to single precision. */
@@ -170,6 +181,27 @@ int fdas_make_templates(fdas_plan_t plan, void *stream);
 int fdas_correlate(fdas_plan_t plan, const void *spectrum, int64_t n_bins,
                    void *plane, void *stream);
 
+/* Many spectra of uneven length, e.g. dedispersion trials, correlated with
+ * the same template bank in one launch.
+ *
+ * fdas_set_batch (host, synchronous on stream; call it outside any graph
+ * capture) validates the jobs against the caller's buffer sizes (n_bins in
+ * [1, max_bins], spec_off + n_bins <= spectra_bins, plane_off + n_z * n_bins
+ * <= plane_cells, no negative offsets, n_jobs in [1, max_jobs]) and stores the
+ * job table in the workspace.  FDAS_E_INVALID names a bad job; the previous
+ * batch is then cleared.
+ *
+ * fdas_correlate_batch enqueues the batch on stream: a counter reset kernel
+ * and one persistent launch whose workgroups pull (job, segment, template
+ * chunk) tiles until none is left (BF16 matrix-core plans), or one
+ * correlation launch per job (other plans).  It records only kernels, so it
+ * can be captured in a HIP graph and replayed; each job's plane is exactly
+ * what fdas_correlate writes for that spectrum.  FDAS_E_STATE without
+ * templates or a batch. */
+int fdas_set_batch(fdas_plan_t plan, const fdas_job *jobs, int32_t n_jobs, int64_t spectra_bins,
+                   int64_t plane_cells, void *stream);
+int fdas_correlate_batch(fdas_plan_t plan, const void *spectra, void *planes, void *stream);
+
 /* Thresholded peaks of a plane written by fdas_correlate with the same plan
  * (Sections "Detailed explanation" and "Peakfinding methodology").  A cell is
  * a peak iff P > threshold, P > every existing 8-neighbour that precedes it
@@ -182,6 +214,37 @@ int fdas_correlate(fdas_plan_t plan, const void *spectrum, int64_t n_bins,
  * know without a device synchronisation and returns FDAS_OK). */
 int fdas_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, float threshold,
                fdas_peak *out, int64_t capacity, int64_t *n_found, void *stream);
+
+/* Candidate refinement: matched-filter power at continuous (r, z) and its
+ * gradient (no plan needed).  The plane samples the power on integer r and a
+ * z grid, and quantisation in both axes moves peaks into adjacent bins
+ * (Section "Peakfinding methodology"); this evaluates the same matched filter
+ * off the grid from the taps spectral bins around r:
+ *   F(r, z) = sum_{k = floor(r) - taps/2 + 1}^{floor(r) + taps/2} X[k] conj(A(r - z/2 - k, z)),
+ *   P = |F|^2,  dP/dr, dP/dz analytic (X = 0 outside [0, N)).
+ *   spectrum   device, n_bins complex64
+ *   r, z       device, n_cand doubles each: start points in, final points out
+ *   power, dp_dr, dp_dz   device, n_cand doubles each (may be NULL): values at
+ *              the final points
+ *   taps       even, 2..64 (32 is the usual choice)
+ *   n_steps    0: evaluate only; > 0: that many ascent steps
+ *              r += eta_r_scale * 3 / (2 pi^2 P) dP/dr,
+ *              z += eta_z_scale * 90 / (pi^2 P) dP/dz  (a Newton step on the
+ *              curvature of an isolated peak), then evaluate.
+ * Positions and arithmetic are FP64 (an FP32 bin index near 4e6 has a
+ * spacing of half a bin).  FDAS_E_INVALID for bad sizes or pointers
+ * (device pointers 8-byte aligned, the spectrum 8-byte aligned). */
+int fdas_refine(const void *spectrum, int64_t n_bins, int32_t n_cand, double *r, double *z,
+                double *power, double *dp_dr, double *dp_dz, int32_t taps, int32_t n_steps,
+                double eta_r_scale, double eta_z_scale, void *stream);
+
+/* Backward pass of P(r, z) for automatic differentiation: with grad_power
+ * the upstream gradient dL/dP, writes grad_r = grad_power * dP/dr and
+ * grad_z = grad_power * dP/dz at the given points (all device, n_cand
+ * doubles). */
+int fdas_refine_backward(const void *spectrum, int64_t n_bins, int32_t n_cand, const double *r,
+                         const double *z, const double *grad_power, double *grad_r, double *grad_z,
+                         int32_t taps, void *stream);
 
 /* Text for a status code (static storage). */
 const char *fdas_strerror(int status);

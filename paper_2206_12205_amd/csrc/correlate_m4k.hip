@@ -24,6 +24,8 @@
 #include "mfma4096.hpp"
 #include "plane_io.hpp"
 
+#include <algorithm>
+
 namespace fdas {
 namespace m4k {
 
@@ -62,64 +64,80 @@ template <class PT>
 struct flush_chunk;
 template <>
 struct flush_chunk<__bf16> {
-    static constexpr int kAlign = 8;   // elements per 16-byte store
-    static __device__ __forceinline__ void vec(__bf16 *dst, const float *v) {
-        u32x4_t u;
-        u.x = bf16_pack(v[0], v[1]);
-        u.y = bf16_pack(v[2], v[3]);
-        u.z = bf16_pack(v[4], v[5]);
-        u.w = bf16_pack(v[6], v[7]);
-        __builtin_nontemporal_store(u, reinterpret_cast<u32x4_t *>(dst));
+    static __device__ __forceinline__ void vec(__bf16 *dst, float4 v) {
+        typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+        u32x2_t u;
+        u.x = bf16_pack(v.x, v.y);
+        u.y = bf16_pack(v.z, v.w);
+        __builtin_nontemporal_store(u, reinterpret_cast<u32x2_t *>(dst));
     }
 };
 template <>
 struct flush_chunk<float> {
-    static constexpr int kAlign = 4;
-    static __device__ __forceinline__ void vec(float *dst, const float *v) {
-        const f32x4_t lo = {v[0], v[1], v[2], v[3]}, hi = {v[4], v[5], v[6], v[7]};
-        __builtin_nontemporal_store(lo, reinterpret_cast<f32x4_t *>(dst));
-        __builtin_nontemporal_store(hi, reinterpret_cast<f32x4_t *>(dst + 4));
+    static __device__ __forceinline__ void vec(float *dst, float4 v) {
+        const f32x4_t u = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(u, reinterpret_cast<f32x4_t *>(dst));
     }
 };
 
-// Write the staged powers of one template: thread tid owns t in [8 tid, 8 tid + 8).
+// Per-thread flush plan: thread tid owns time samples [4 tid, 4 tid + 4) and
+// [2048 + 4 tid, 2048 + 4 tid + 4) (consecutive lanes read consecutive
+// 16-byte LDS chunks).  vec[h] says chunk h is entirely kept, inside the
+// plane and aligned for a vector store in every template row.
+struct FlushPlan {
+    int t0[2];
+    bool vec[2];
+};
+
 template <class PT>
-__device__ __forceinline__ void flush(const float *stage, PT *row, int64_t seg0, int64_t n, int half, bool full,
-                                      int tid) {
-    const int t0 = 8 * tid;
-    const float4 a = *reinterpret_cast<const float4 *>(stage + stage_idx(t0));
-    const float4 b = *reinterpret_cast<const float4 *>(stage + stage_idx(t0) + 4);
-    const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-    const int64_t col = seg0 + t0;
-    const bool inside = t0 >= half && t0 + 8 <= kL - half && (full || col + 8 <= n);
-    const bool aligned = ((reinterpret_cast<uintptr_t>(row + col)) & 15u) == 0;
-    if (inside && aligned) {
-        flush_chunk<PT>::vec(row + col, v);
-    } else {
+__device__ __forceinline__ FlushPlan flush_plan(const PT *plane, int64_t seg0, int64_t n, int half, bool full,
+                                                int tid) {
+    FlushPlan f;
+    constexpr uintptr_t kChunkBytes = 4 * sizeof(PT);   // 4 elements: 8 B (bf16) or 16 B (fp32)
+    const bool rows_aligned = (n % 4) == 0;             // every row start keeps the chunk alignment
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int t = t0 + i;
-            if (t >= half && t < kL - half && col + i < n) plane_store<PT>::put(row + col + i, v[i]);
+    for (int h = 0; h < 2; ++h) {
+        const int t0 = 2048 * h + 4 * tid;
+        const int64_t col = seg0 + t0;
+        f.t0[h] = t0;
+        f.vec[h] = rows_aligned && (reinterpret_cast<uintptr_t>(plane + col) % kChunkBytes) == 0 && t0 >= half &&
+                   t0 + 4 <= kL - half && (full || col + 4 <= n);
+    }
+    return f;
+}
+
+// Write the staged powers of one template row.
+template <class PT>
+__device__ __forceinline__ void flush(const float *stage, PT *row, int64_t seg0, int64_t n, int half,
+                                      const FlushPlan &f) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int t0 = f.t0[h];
+        const float4 v = *reinterpret_cast<const float4 *>(stage + stage_idx(t0));
+        const int64_t col = seg0 + t0;
+        if (f.vec[h]) {
+            flush_chunk<PT>::vec(row + col, v);
+        } else {
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int t = t0 + i;
+                if (t >= half && t < kL - half && col + i < n) plane_store<PT>::put(row + col + i, vv[i]);
+            }
         }
     }
 }
 
+// One tile: segment s of the spectrum (n bins) against templates [j0, j1),
+// writing plane rows j0 .. j1 - 1 (row stride n).  Called by the whole
+// workgroup; contains barriers.
 template <class PT>
-__global__ void __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(4)))
-correlate_mfma4096(const float2 *__restrict__ spec, int64_t n, const uint32_t *__restrict__ bank,
-                   const uint32_t *__restrict__ tab, PT *__restrict__ plane, int32_t M, int32_t V, int32_t n_z,
-                   int32_t z_chunk, int32_t n_chunks) {
-    __shared__ __align__(16) uint32_t bufA[kBufWords];
-    __shared__ __align__(16) uint32_t bufB[kBufWords];
-    __shared__ __align__(16) float stage[kStageWords];
-
+__device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_t n, const uint32_t *__restrict__ bank,
+                                         const uint32_t *__restrict__ tab, PT *__restrict__ plane, int32_t M,
+                                         int32_t V, int64_t s, int j0, int j1, uint32_t *bufA, uint32_t *bufB,
+                                         float *stage) {
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, c = lane & 15, g = lane >> 4;
-    const int chunk = blockIdx.x % n_chunks;
-    const int64_t s = blockIdx.x / n_chunks;
-    const int j0 = chunk * z_chunk;
-    const int j1 = min(j0 + z_chunk, n_z);
-    if (j0 >= j1) return;
     const int half = M / 2;
     const int64_t seg0 = s * (int64_t)V - half;   // plane column of time index t is seg0 + t
     const bool full = seg0 + (kL - half) <= n;
@@ -193,18 +211,12 @@ correlate_mfma4096(const float2 *__restrict__ spec, int64_t n, const uint32_t *_
         a23im[q] = load_op(tab, OP_I23 + 2 * Q + 1, lane);
     }
 
-    const uint4 *bank4 = reinterpret_cast<const uint4 *>(bank);
-    uint4 h[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) h[q] = bank4[(size_t)j0 * (kL / 4) + (2 * w + q) * 64 + lane];
+    const FlushPlan fp = flush_plan<PT>(plane, seg0, n, half, full, tid);
+    const uint4 *bank4 = reinterpret_cast<const uint4 *>(bank) + (2 * w) * 64 + lane;
 
-    for (int j = j0; j < j1; ++j) {
-        uint4 hc[2] = {h[0], h[1]};
-        if (j + 1 < j1) {
-#pragma unroll
-            for (int q = 0; q < 2; ++q) h[q] = bank4[(size_t)(j + 1) * (kL / 4) + (2 * w + q) * 64 + lane];
-        }
-        // I1 (group k1 = Q): Y = X * H_j, DFT16 over k3 with e(n3 k1); rows n3 = 4 g + e -> buffer A
+    // One template: I1 (group k1 = Q) on X * H_j, I2 (group n3), I3 (group n2).
+    auto one_template = [&](int j, const uint4 (&hc)[2]) {
+        // I1: DFT16 over k3 with e(n3 k1); rows n3 = 4 g + e -> buffer A
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int Q = 2 * w + q;
@@ -217,8 +229,8 @@ correlate_mfma4096(const float2 *__restrict__ spec, int64_t n, const uint32_t *_
             for (int e = 0; e < 4; ++e) bufA[addrA(Q, c, 4 * g + e)] = bf16_pack(dre[e], dim[e]);
         }
         __syncthreads();
-        if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n, seg0, n, half, full, tid);
-        // I2 (group n3 = Q): DFT16 over k2 with e(16 n3 k2); rows n2 = 4 g + e -> buffer B
+        if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n, seg0, n, half, fp);
+        // I2: DFT16 over k2 with e(16 n3 k2); rows n2 = 4 g + e -> buffer B
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int Q = 2 * w + q;
@@ -229,7 +241,7 @@ correlate_mfma4096(const float2 *__restrict__ spec, int64_t n, const uint32_t *_
             for (int e = 0; e < 4; ++e) bufB[addrB(c, 4 * g + e, Q)] = bf16_pack(dre[e], dim[e]);
         }
         __syncthreads();
-        // I3 (group n2 = Q): DFT16 over k1 with e(16 n2 k1); rows n1 = 4 g + e; |y|^2 -> staging
+        // I3: DFT16 over k1 with e(16 n2 k1); rows n1 = 4 g + e; |y|^2 -> staging
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int Q = 2 * w + q;
@@ -240,9 +252,103 @@ correlate_mfma4096(const float2 *__restrict__ spec, int64_t n, const uint32_t *_
             for (int e = 0; e < 4; ++e)
                 stage[stage_idx(256 * (4 * g + e) + 16 * Q + c)] = dre[e] * dre[e] + dim[e] * dim[e];
         }
+    };
+
+    // templates in pairs with two statically assigned bank registers: the
+    // next template's bank entry is in flight while the current one runs
+    uint4 hA[2], hB[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) hA[q] = bank4[(size_t)j0 * (kL / 4) + q * 64];
+    for (int j = j0; j < j1; j += 2) {
+        if (j + 1 < j1) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) hB[q] = bank4[(size_t)(j + 1) * (kL / 4) + q * 64];
+        }
+        one_template(j, hA);
+        if (j + 1 >= j1) break;
+        if (j + 2 < j1) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) hA[q] = bank4[(size_t)(j + 2) * (kL / 4) + q * 64];
+        }
+        one_template(j + 1, hB);
     }
     __syncthreads();
-    flush<PT>(stage, plane + (int64_t)(j1 - 1) * n, seg0, n, half, full, tid);
+    flush<PT>(stage, plane + (int64_t)(j1 - 1) * n, seg0, n, half, fp);
+}
+
+// Out-of-line copy for the persistent kernel: inlined into its tile loop the
+// body spills; called, it keeps every value in registers (the call saves a few
+// registers once per tile).
+template <class PT>
+__device__ __noinline__ void m4k_tile_call(const float2 *__restrict__ spec, int64_t n,
+                                           const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
+                                           PT *__restrict__ plane, int32_t M, int32_t V, int64_t s, int j0, int j1,
+                                           uint32_t *bufA, uint32_t *bufB, float *stage) {
+    m4k_tile<PT>(spec, n, bank, tab, plane, M, V, s, j0, j1, bufA, bufB, stage);
+}
+
+#define M4K_ATTR __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(4)))
+
+// One spectrum: workgroup b takes template chunk b mod n_chunks of segment b / n_chunks.
+template <class PT>
+__global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int64_t n,
+                                            const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
+                                            PT *__restrict__ plane, int32_t M, int32_t V, int32_t n_z,
+                                            int32_t z_chunk, int32_t n_chunks) {
+    __shared__ __align__(16) uint32_t bufA[kBufWords];
+    __shared__ __align__(16) uint32_t bufB[kBufWords];
+    __shared__ __align__(16) float stage[kStageWords];
+    const int chunk = blockIdx.x % n_chunks;
+    const int64_t s = blockIdx.x / n_chunks;
+    const int j0 = chunk * z_chunk;
+    const int j1 = min(j0 + z_chunk, n_z);
+    if (j0 >= j1) return;
+    m4k_tile<PT>(spec, n, bank, tab, plane, M, V, s, j0, j1, bufA, bufB, stage);
+}
+
+// Many spectra in one persistent launch: every workgroup pulls tiles
+// (job, segment, template chunk) from a device counter until none is left,
+// so ragged lengths balance across the CUs.  Tile t belongs to the last job
+// whose tile_base is <= t.
+template <class PT>
+__global__ void M4K_ATTR correlate_mfma4096_batch(const float2 *__restrict__ spectra,
+                                                  const fdas_batch_job *__restrict__ jobs, int32_t n_jobs,
+                                                  int64_t n_tiles, int32_t *__restrict__ counter,
+                                                  const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
+                                                  PT *__restrict__ planes, int32_t M, int32_t V, int32_t n_z,
+                                                  int32_t z_chunk, int32_t n_chunks) {
+    __shared__ __align__(16) uint32_t bufA[kBufWords];
+    __shared__ __align__(16) uint32_t bufB[kBufWords];
+    __shared__ __align__(16) float stage[kStageWords];
+    __shared__ int s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+        __syncthreads();
+        // the tile and everything derived from it are the same on every lane:
+        // keep them in scalar registers
+        const int t = __builtin_amdgcn_readfirstlane((int)s_tile);
+        if (t >= n_tiles) return;                 // uniform: every wave leaves together
+        int lo = 0, hi = n_jobs - 1;              // last job with tile_base <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_base <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const int64_t spec_off = jobs[lo].spec_off, nb = jobs[lo].n_bins;
+        const int64_t plane_off = jobs[lo].plane_off;
+        const int local = t - (int)jobs[lo].tile_base;
+        const int chunk = local % n_chunks;
+        const int s = local / n_chunks;
+        const int j0 = chunk * z_chunk;
+        const int j1 = min(j0 + z_chunk, n_z);
+        // an opaque zero keeps the per-tile operator loads inside the loop, so
+        // they are not hoisted out and held in registers across tiles
+        int opaque = 0;
+        asm volatile("" : "+s"(opaque));
+        m4k_tile_call<PT>(spectra + spec_off + opaque, nb, bank + opaque, tab + opaque, planes + plane_off + opaque, M,
+                          V + opaque, s, j0, j1, bufA, bufB, stage);
+    }
 }
 
 namespace {
@@ -258,9 +364,36 @@ hipError_t launch(const fdas_plan_s &p, const void *spec, int64_t n, void *plane
                        p.cfg.n_z, p.z_chunk, p.n_chunks);
     return hipGetLastError();
 }
+template <class PT>
+hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes, hipStream_t st) {
+    auto *ws = static_cast<unsigned char *>(p.ws);
+    int32_t *counter = reinterpret_cast<int32_t *>(ws + p.off_batch);
+    const auto *jobs = reinterpret_cast<const fdas_batch_job *>(ws + p.off_batch + 256);
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
+    int dev = 0, cus = 256;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t grid = std::min<int64_t>((int64_t)cus * 2, std::max<int64_t>(p.batch_tiles, 1));
+    hipLaunchKernelGGL(correlate_mfma4096_batch<PT>, dim3((unsigned)grid), dim3(kThreads), 0, st,
+                       static_cast<const float2 *>(spectra), jobs, p.batch_jobs, p.batch_tiles, counter,
+                       reinterpret_cast<const uint32_t *>(ws + p.off_bank),
+                       reinterpret_cast<const uint32_t *>(ws + p.off_tab), static_cast<PT *>(planes), p.M, p.V,
+                       p.cfg.n_z, p.z_chunk, p.n_chunks);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 }  // namespace m4k
+
+hipError_t launch_correlate_m4k_batch(const fdas_plan_s &p, const void *spectra, void *planes, hipStream_t st) {
+    if (p.L != m4k::kL || p.cfg.compute != FDAS_BF16) return hipErrorInvalidValue;
+    if (p.cfg.plane_dtype == FDAS_BF16) return m4k::launch_batch<__bf16>(p, spectra, planes, st);
+    if (p.cfg.plane_dtype == FDAS_FP32) return m4k::launch_batch<float>(p, spectra, planes, st);
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_correlate_m4k(const fdas_plan_s &p, const void *spec, int64_t n, void *plane, hipStream_t st) {
     if (p.L != m4k::kL || p.cfg.compute != FDAS_BF16) return hipErrorInvalidValue;

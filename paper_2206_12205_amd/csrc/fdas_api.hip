@@ -68,6 +68,7 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     if (c.n_z > 1 && !(c.z_step > 0.0)) return FDAS_E_INVALID;
     if (c.z_chunk < 0) return FDAS_E_INVALID;
     if (c.algo < FDAS_ALGO_AUTO || c.algo > FDAS_ALGO_MFMA) return FDAS_E_INVALID;
+    if (c.max_jobs < 0 || c.max_jobs > (1 << 24)) return FDAS_E_INVALID;
     // plane dtype: FP64 compute writes FP64 only; FP32/BF16 compute write FP32 or BF16
     if (c.compute == FDAS_FP64) {
         if (c.plane_dtype != FDAS_FP64) return FDAS_E_INVALID;
@@ -76,10 +77,16 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     }
     int64_t L = c.seg_len;
     if (L == 0) {
-        L = int64_t(1) << ilog2(32 * (int64_t)c.n_taps);
-        if (L < 1024) L = 1024;
-        const int64_t lmax = c.compute == FDAS_FP64 ? 8192 : 16384;
-        if (L > lmax) L = lmax;
+        if (c.compute == FDAS_BF16 && c.algo != FDAS_ALGO_VALU && c.n_taps <= 512) {
+            L = 4096;   // the 16x16x16 matrix-core kernel; overlap waste M / L <= 12.5 %
+        } else if (c.compute == FDAS_BF16 && c.algo != FDAS_ALGO_VALU && c.n_taps <= 2048) {
+            L = 8192;
+        } else {
+            L = int64_t(1) << ilog2(32 * (int64_t)c.n_taps);
+            if (L < 1024) L = 1024;
+            const int64_t lmax = c.compute == FDAS_FP64 ? 8192 : 16384;
+            if (L > lmax) L = lmax;
+        }
     }
     if (L < 1024 || L > 16384 || (L & (L - 1))) return FDAS_E_INVALID;
     if (c.n_taps >= L) return FDAS_E_INVALID;
@@ -129,6 +136,9 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     p->off_tab = off;
     p->sz_tab = !p->mfma ? 0 : (L == fdas::m8k::kL ? fdas::m8k::kTableBytes : fdas::m4k::kTableBytes);
     off = align_up(off + p->sz_tab, 256);
+    p->off_batch = off;
+    p->sz_batch = c.max_jobs > 0 ? 256 + (size_t)c.max_jobs * sizeof(fdas_batch_job) : 0;
+    off = align_up(off + p->sz_batch, 256);
     p->ws_bytes = off;
     p->cfg.algo = p->mfma ? FDAS_ALGO_MFMA : FDAS_ALGO_VALU;
 
@@ -147,6 +157,7 @@ int fdas_set_workspace(fdas_plan_t p, void *dev, size_t bytes) {
     p->ws = dev;
     p->ws_size = bytes;
     p->templates_ready = false;
+    p->batch_jobs = 0;
     return FDAS_OK;
 }
 
@@ -199,6 +210,82 @@ int fdas_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, float threshold
     if (!p->ws) return FDAS_E_WORKSPACE;
     return hip_status(
         fdas::launch_peaks(*p, plane, n_bins, threshold, out, capacity, n_found, static_cast<hipStream_t>(stream)));
+}
+
+int fdas_set_batch(fdas_plan_t p, const fdas_job *jobs, int32_t n_jobs, int64_t spectra_bins, int64_t plane_cells,
+                   void *stream) {
+    if (!p || !jobs || n_jobs < 1) return FDAS_E_INVALID;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    p->batch_jobs = 0;
+    if (n_jobs > p->cfg.max_jobs) return FDAS_E_INVALID;
+    std::vector<fdas_batch_job> tab((size_t)n_jobs);
+    int64_t tiles = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const fdas_job &j = jobs[i];
+        if (j.n_bins < 1 || j.n_bins > p->cfg.max_bins || j.spec_off < 0 || j.plane_off < 0) return FDAS_E_INVALID;
+        if (j.spec_off > spectra_bins - j.n_bins) return FDAS_E_INVALID;
+        if (j.n_bins > (plane_cells - j.plane_off) / p->cfg.n_z || j.plane_off > plane_cells) return FDAS_E_INVALID;
+        tab[i] = {j.spec_off, j.n_bins, j.plane_off, tiles};
+        tiles += (j.n_bins + p->V - 1) / p->V * p->n_chunks;
+        // tile indices are 32-bit on the device, and the counter runs one past
+        // the last tile per workgroup
+        if (tiles > 0x7fffffffLL - (1 << 20)) return FDAS_E_INVALID;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(static_cast<unsigned char *>(p->ws) + p->off_batch + 256, tab.data(),
+                                  tab.size() * sizeof(fdas_batch_job), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e);
+    p->batch_host = std::move(tab);
+    p->batch_jobs = n_jobs;
+    p->batch_tiles = tiles;
+    return FDAS_OK;
+}
+
+int fdas_correlate_batch(fdas_plan_t p, const void *spectra, void *planes, void *stream) {
+    if (!p || !spectra || !planes) return FDAS_E_INVALID;
+    if (!aligned16(spectra) || !aligned16(planes)) return FDAS_E_INVALID;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    if (!p->templates_ready || p->batch_jobs < 1) return FDAS_E_STATE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->mfma && p->L == fdas::m4k::kL) return hip_status(fdas::launch_correlate_m4k_batch(*p, spectra, planes, st));
+    const size_t pe = p->cfg.plane_dtype == FDAS_FP64 ? 8 : p->cfg.plane_dtype == FDAS_FP32 ? 4 : 2;
+    for (const fdas_batch_job &j : p->batch_host) {
+        const void *sp = static_cast<const unsigned char *>(spectra) + (size_t)j.spec_off * 8;
+        void *pl = static_cast<unsigned char *>(planes) + (size_t)j.plane_off * pe;
+        const hipError_t e = p->mfma ? fdas::launch_correlate_mfma(*p, sp, j.n_bins, pl, st)
+                                     : fdas::launch_correlate(*p, sp, j.n_bins, pl, st);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    return FDAS_OK;
+}
+
+static bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+int fdas_refine(const void *spectrum, int64_t n_bins, int32_t n_cand, double *r, double *z, double *power,
+                double *dp_dr, double *dp_dz, int32_t taps, int32_t n_steps, double eta_r_scale, double eta_z_scale,
+                void *stream) {
+    if (!spectrum || n_bins < 1 || n_cand < 0 || n_steps < 0) return FDAS_E_INVALID;
+    if (taps < 2 || taps > 64 || (taps & 1)) return FDAS_E_INVALID;
+    if (n_cand > 0 && (!r || !z)) return FDAS_E_INVALID;
+    if (!aligned8(spectrum) || !aligned8(r) || !aligned8(z) || !aligned8(power) || !aligned8(dp_dr) ||
+        !aligned8(dp_dz))
+        return FDAS_E_INVALID;
+    if (!std::isfinite(eta_r_scale) || !std::isfinite(eta_z_scale)) return FDAS_E_INVALID;
+    return hip_status(fdas::launch_refine(spectrum, n_bins, n_cand, r, z, power, dp_dr, dp_dz, taps, n_steps,
+                                          eta_r_scale, eta_z_scale, static_cast<hipStream_t>(stream)));
+}
+
+int fdas_refine_backward(const void *spectrum, int64_t n_bins, int32_t n_cand, const double *r, const double *z,
+                         const double *grad_power, double *grad_r, double *grad_z, int32_t taps, void *stream) {
+    if (!spectrum || n_bins < 1 || n_cand < 0) return FDAS_E_INVALID;
+    if (taps < 2 || taps > 64 || (taps & 1)) return FDAS_E_INVALID;
+    if (n_cand > 0 && (!r || !z || !grad_power || !grad_r || !grad_z)) return FDAS_E_INVALID;
+    if (!aligned8(spectrum) || !aligned8(r) || !aligned8(z) || !aligned8(grad_power) || !aligned8(grad_r) ||
+        !aligned8(grad_z))
+        return FDAS_E_INVALID;
+    return hip_status(fdas::launch_refine_backward(spectrum, n_bins, n_cand, r, z, grad_power, grad_r, grad_z, taps,
+                                                   static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/fdas.h"
 
@@ -15,6 +16,14 @@ constexpr int kMinLog2L = 10;
 constexpr int kMaxLog2L = 14;
 
 }  // namespace fdas
+
+// One job of a batched launch as the device sees it (offsets in elements).
+struct fdas_batch_job {
+    int64_t spec_off;     // first bin of the job's spectrum in the spectra buffer
+    int64_t n_bins;       // its length N
+    int64_t plane_off;    // first cell of its n_z x N plane in the planes buffer
+    int64_t tile_base;    // index of its first (segment, template chunk) tile
+};
 
 struct fdas_plan_s {
     fdas_config cfg;
@@ -29,6 +38,10 @@ struct fdas_plan_s {
     size_t off_scr = 0, sz_scr = 0;        // peak counters
     size_t off_tab = 0, sz_tab = 0;        // matrix-core operator/twiddle tables
     bool mfma = false;                     // matrix-core correlation kernel (L = 4096 or 8192)
+    size_t off_batch = 0, sz_batch = 0;    // batch counter (256 B) + job table
+    int32_t batch_jobs = 0;                // jobs set by fdas_set_batch (0: none)
+    int64_t batch_tiles = 0;
+    std::vector<fdas_batch_job> batch_host;   // host copy of the job table
     int64_t peak_tile_cap = 0;             // number of peak tiles the scratch holds
     void *ws = nullptr;
     size_t ws_size = 0;
@@ -48,9 +61,21 @@ hipError_t launch_correlate_mfma(const fdas_plan_s &p, const void *spec, int64_t
 hipError_t launch_correlate_m4k(const fdas_plan_s &p, const void *spec, int64_t n,
                                 void *plane, hipStream_t s);
 
+hipError_t launch_correlate_m4k_batch(const fdas_plan_s &p, const void *spectra, void *planes, hipStream_t s);
+
+// Resets the batch tile counter (batch.hip); a kernel, so graph capture records no memset.
+__global__ void k_batch_reset(int32_t *counter);
+
 // Correlation (correlate.hip).
 hipError_t launch_correlate(const fdas_plan_s &p, const void *spec, int64_t n,
                             void *plane, hipStream_t s);
+
+// Refinement (refine.hip).
+hipError_t launch_refine(const void *spec, int64_t n, int32_t n_cand, double *r, double *z, double *power,
+                         double *dp_dr, double *dp_dz, int32_t taps, int32_t n_steps, double s_r, double s_z,
+                         hipStream_t st);
+hipError_t launch_refine_backward(const void *spec, int64_t n, int32_t n_cand, const double *r, const double *z,
+                                  const double *grad_p, double *grad_r, double *grad_z, int32_t taps, hipStream_t st);
 
 // Peaks (peaks.hip).
 constexpr int kPeakTileCols = 1024;   // columns per peak tile (one row per tile)

@@ -28,7 +28,13 @@ class FdasConfig(ctypes.Structure):
                 ("z_step", ctypes.c_double), ("n_z", ctypes.c_int32),
                 ("n_taps", ctypes.c_int32), ("seg_len", ctypes.c_int32),
                 ("compute", ctypes.c_int32), ("plane_dtype", ctypes.c_int32),
-                ("z_chunk", ctypes.c_int32), ("algo", ctypes.c_int32)]
+                ("z_chunk", ctypes.c_int32), ("algo", ctypes.c_int32),
+                ("max_jobs", ctypes.c_int32)]
+
+
+class FdasJob(ctypes.Structure):
+    _fields_ = [("spec_off", ctypes.c_int64), ("n_bins", ctypes.c_int64),
+                ("plane_off", ctypes.c_int64)]
 
 
 class FdasPeak(ctypes.Structure):
@@ -76,7 +82,12 @@ def lib() -> ctypes.CDLL:
         L.fdas_get_layout.argtypes = [P, ctypes.POINTER(FdasLayout)]
         L.fdas_make_templates.argtypes = [P, P]
         L.fdas_correlate.argtypes = [P, P, I64, P, P]
+        L.fdas_set_batch.argtypes = [P, ctypes.POINTER(FdasJob), I32, I64, I64, P]
+        L.fdas_correlate_batch.argtypes = [P, P, P, P]
         L.fdas_peaks.argtypes = [P, P, I64, ctypes.c_float, P, I64, P, P]
+        D = ctypes.c_double
+        L.fdas_refine.argtypes = [P, I64, I32, P, P, P, P, P, I32, I32, D, D, P]
+        L.fdas_refine_backward.argtypes = [P, I64, I32, P, P, P, P, P, I32, P]
         L.fdas_strerror.argtypes = [ctypes.c_int]
         L.fdas_strerror.restype = ctypes.c_char_p
         L.fdas_last_hip_error.restype = ctypes.c_int
@@ -106,14 +117,14 @@ def _stream_ptr(stream):
 
 
 def make_config(max_bins, z_min, z_step, n_z, n_taps, seg_len=0, compute="fp32",
-                plane_dtype=None, z_chunk=0, algo="auto") -> FdasConfig:
+                plane_dtype=None, z_chunk=0, algo="auto", max_jobs=0) -> FdasConfig:
     c = DTYPES[compute] if isinstance(compute, str) else int(compute)
     if plane_dtype is None:
         plane_dtype = {FP32: FP32, BF16: BF16, FP64: FP64}.get(c, FP32)
     pd = DTYPES[plane_dtype] if isinstance(plane_dtype, str) else int(plane_dtype)
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
     return FdasConfig(int(max_bins), float(z_min), float(z_step), int(n_z), int(n_taps),
-                      int(seg_len), c, pd, int(z_chunk), a)
+                      int(seg_len), c, pd, int(z_chunk), a, int(max_jobs))
 
 
 class Plan:
@@ -121,10 +132,10 @@ class Plan:
 
     def __init__(self, max_bins, z_min, z_step, n_z, n_taps, seg_len=0,
                  compute="fp32", plane_dtype=None, z_chunk=0, device="cuda:0",
-                 make_templates=True, algo="auto"):
+                 make_templates=True, algo="auto", max_jobs=0):
         import torch
         self.cfg = make_config(max_bins, z_min, z_step, n_z, n_taps, seg_len, compute,
-                               plane_dtype, z_chunk, algo)
+                               plane_dtype, z_chunk, algo, max_jobs)
         h = ctypes.c_void_p()
         nbytes = ctypes.c_size_t()
         _check(lib().fdas_plan(ctypes.byref(self.cfg), ctypes.byref(h), ctypes.byref(nbytes)),
@@ -183,6 +194,49 @@ class Plan:
                "fdas_correlate")
         return plane
 
+    def set_batch(self, lengths, spectra_bins=None, plane_cells=None, stream=None):
+        """Store a batch of spectra packed back to back (job i: lengths[i] bins
+        at the running offset, its plane at n_z times that offset).  Returns
+        the (spec_off, plane_off) lists."""
+        lengths = [int(v) for v in lengths]
+        jobs = (FdasJob * max(len(lengths), 1))()
+        so, po, offs = 0, 0, []
+        for i, nb in enumerate(lengths):
+            jobs[i] = FdasJob(so, nb, po)
+            offs.append((so, po))
+            so += nb
+            po += self.n_z * nb
+        self.batch_lengths = lengths
+        self.batch_offsets = offs
+        self.batch_bins = so if spectra_bins is None else int(spectra_bins)
+        self.batch_cells = po if plane_cells is None else int(plane_cells)
+        _check(lib().fdas_set_batch(self._h, jobs, len(lengths), self.batch_bins, self.batch_cells,
+                                    _stream_ptr(stream)), "fdas_set_batch")
+        return offs
+
+    def correlate_batch(self, spectra, planes=None, stream=None):
+        """Planes of the stored batch: spectra is the packed complex64 device
+        tensor, planes a flat tensor of the plane dtype (allocated if None)."""
+        import torch
+        if spectra.dtype != torch.complex64 or not spectra.is_contiguous() \
+                or spectra.numel() < self.batch_bins:
+            raise ValueError("spectra must be a contiguous complex64 tensor of the batch's size")
+        if planes is None:
+            planes = torch.empty(self.batch_cells, dtype=self.torch_plane_dtype(), device=self.device)
+        if planes.dtype != self.torch_plane_dtype() or not planes.is_contiguous() \
+                or planes.numel() < self.batch_cells:
+            raise ValueError("planes has the wrong dtype, size or layout")
+        _check(lib().fdas_correlate_batch(self._h, ctypes.c_void_p(spectra.data_ptr()),
+                                          ctypes.c_void_p(planes.data_ptr()), _stream_ptr(stream)),
+               "fdas_correlate_batch")
+        return planes
+
+    def batch_plane(self, planes, i):
+        """(n_z, n_i) view of job i's plane inside the flat batch planes."""
+        nb = self.batch_lengths[i]
+        po = self.batch_offsets[i][1]
+        return planes[po:po + self.n_z * nb].view(self.n_z, nb)
+
     def peaks(self, plane, threshold, capacity=1 << 16, stream=None):
         """Peaks of a plane -> dict of numpy arrays z_idx, r, power and n_found."""
         import numpy as np
@@ -213,3 +267,70 @@ class Plan:
         if self.cfg.compute == FP64:
             return b.view(torch.float64).view(self.n_z, L, 2)
         return b.view(torch.int16).view(self.n_z, L, 2)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def refine(spectrum, r, z, taps=32, n_steps=0, eta_r_scale=1.0, eta_z_scale=1.0, stream=None):
+    """fdas_refine on device tensors.  r, z: float64 start points (copied);
+    returns (r, z, power, dP/dr, dP/dz) float64 tensors at the final points."""
+    import torch
+    if spectrum.dtype != torch.complex64 or not spectrum.is_contiguous():
+        raise ValueError("spectrum must be a contiguous complex64 tensor")
+    r = r.to(device=spectrum.device, dtype=torch.float64).contiguous().clone()
+    z = z.to(device=spectrum.device, dtype=torch.float64).contiguous().clone()
+    if r.shape != z.shape or r.dim() != 1:
+        raise ValueError("r and z must be 1-D tensors of equal length")
+    n = r.numel()
+    P = torch.empty_like(r)
+    gr = torch.empty_like(r)
+    gz = torch.empty_like(r)
+    _check(lib().fdas_refine(ctypes.c_void_p(spectrum.data_ptr()), spectrum.numel(), n, _ptr(r),
+                             _ptr(z), _ptr(P), _ptr(gr), _ptr(gz), int(taps), int(n_steps),
+                             float(eta_r_scale), float(eta_z_scale), _stream_ptr(stream)),
+           "fdas_refine")
+    return r, z, P, gr, gz
+
+
+def _make_power_fn():
+    import torch
+
+    class InterpolatedPower(torch.autograd.Function):
+        """P(r, z) of the taps-bin interpolated matched filter; the backward
+        pass is the library's fdas_refine_backward kernel."""
+
+        @staticmethod
+        def forward(ctx, r, z, spectrum, taps):
+            _, _, P, _, _ = refine(spectrum, r.detach(), z.detach(), taps=taps, n_steps=0)
+            ctx.save_for_backward(r.detach().to(torch.float64).contiguous(),
+                                  z.detach().to(torch.float64).contiguous())
+            ctx.spectrum = spectrum
+            ctx.taps = taps
+            return P.to(r.dtype)
+
+        @staticmethod
+        def backward(ctx, grad_p):
+            r, z = ctx.saved_tensors
+            g = grad_p.to(torch.float64).contiguous()
+            gr = torch.empty_like(r)
+            gz = torch.empty_like(r)
+            _check(lib().fdas_refine_backward(
+                ctypes.c_void_p(ctx.spectrum.data_ptr()), ctx.spectrum.numel(), r.numel(), _ptr(r),
+                _ptr(z), _ptr(g), _ptr(gr), _ptr(gz), int(ctx.taps), _stream_ptr(None)),
+                "fdas_refine_backward")
+            return gr.to(grad_p.dtype), gz.to(grad_p.dtype), None, None
+
+    return InterpolatedPower
+
+
+_power_fn = None
+
+
+def interpolated_power(r, z, spectrum, taps=32):
+    """Differentiable P(r, z) (torch.autograd) on device tensors r, z."""
+    global _power_fn
+    if _power_fn is None:
+        _power_fn = _make_power_fn()
+    return _power_fn.apply(r, z, spectrum, taps)

@@ -76,8 +76,8 @@ def test_layout_and_workspace_checks_on_host():
     try:
         lay = F.FdasLayout()
         assert L.fdas_get_layout(h, ctypes.byref(lay)) == F.OK
-        assert lay.seg_len == 8192 and lay.valid_per_seg == 8192 - 256
-        assert lay.bank_bytes == 5 * 8192 * 4 and lay.total_bytes == n.value
+        assert lay.seg_len == 4096 and lay.valid_per_seg == 4096 - 256
+        assert lay.bank_bytes == 5 * 4096 * 4 and lay.total_bytes == n.value
         assert lay.algo == F.ALGO_MFMA and lay.tables_bytes > 0
         assert lay.tables_offset + lay.tables_bytes <= lay.total_bytes
         assert lay.bank_offset % 256 == 0 and lay.twiddle_offset % 256 == 0
@@ -107,3 +107,65 @@ def test_null_arguments():
     assert L.fdas_plan(None, None, None) == F.E_INVALID
     assert L.fdas_make_templates(None, None) == F.E_INVALID
     assert L.fdas_get_layout(None, None) == F.E_INVALID
+
+
+def test_refine_argument_checks_on_host():
+    L = F.lib()
+    fake = ctypes.c_void_p(0x10000)
+    D = ctypes.c_double
+    args = lambda **kw: [kw.get("spec", fake), kw.get("n", 100), kw.get("nc", 4), fake, fake, fake, fake, fake,
+                         kw.get("taps", 32), kw.get("steps", 0), D(1.0), D(kw.get("eta", 1.0)), None]
+    assert L.fdas_refine(*args(taps=31)) == F.E_INVALID
+    assert L.fdas_refine(*args(taps=66)) == F.E_INVALID
+    assert L.fdas_refine(*args(taps=0)) == F.E_INVALID
+    assert L.fdas_refine(*args(nc=-1)) == F.E_INVALID
+    assert L.fdas_refine(*args(steps=-1)) == F.E_INVALID
+    assert L.fdas_refine(*args(n=0)) == F.E_INVALID
+    assert L.fdas_refine(*args(spec=ctypes.c_void_p(0x10004))) == F.E_INVALID
+    assert L.fdas_refine(*args(spec=None)) == F.E_INVALID
+    assert L.fdas_refine(*args(eta=float("nan"))) == F.E_INVALID
+    assert L.fdas_refine_backward(fake, 100, 4, fake, fake, fake, fake, fake, 33, None) == F.E_INVALID
+    assert L.fdas_refine_backward(fake, 100, 4, fake, None, fake, fake, fake, 32, None) == F.E_INVALID
+
+
+def test_batch_argument_checks_on_host():
+    L = F.lib()
+    cfg = make(max_bins=4096, seg_len=0, n_taps=256, n_z=5, z_min=-4.0, compute="bf16", max_jobs=3)
+    assert plan_status(make(max_jobs=-1))[0] == F.E_INVALID
+    assert ctypes.sizeof(F.FdasJob) == 24
+    h = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    assert L.fdas_plan(ctypes.byref(cfg), ctypes.byref(h), ctypes.byref(n)) == F.OK
+    try:
+        fake = ctypes.c_void_p(0x10000)           # never dereferenced on these paths
+        jobs = (F.FdasJob * 4)(F.FdasJob(0, 100, 0), F.FdasJob(100, 50, 500), F.FdasJob(150, 4096, 750),
+                               F.FdasJob(0, 1, 0))
+        assert L.fdas_set_batch(h, jobs, 2, 1000, 10 ** 6, None) == F.E_WORKSPACE
+        assert L.fdas_set_workspace(h, fake, n.value) == F.OK
+        big = 10 ** 6
+        assert L.fdas_set_batch(h, jobs, 0, big, big, None) == F.E_INVALID
+        assert L.fdas_set_batch(h, None, 1, big, big, None) == F.E_INVALID
+        assert L.fdas_set_batch(h, jobs, 4, big, big * 10, None) == F.E_INVALID     # above max_jobs
+        assert L.fdas_set_batch(h, jobs, 3, 4245, big, None) == F.E_INVALID        # spectra too short
+        assert L.fdas_set_batch(h, jobs, 3, 4246, 750 + 5 * 4096 - 1, None) == F.E_INVALID  # planes too short
+        bad = (F.FdasJob * 1)(F.FdasJob(0, 4097, 0))                                # above max_bins
+        assert L.fdas_set_batch(h, bad, 1, big, big * 10, None) == F.E_INVALID
+        bad = (F.FdasJob * 1)(F.FdasJob(0, 0, 0))                                   # empty spectrum
+        assert L.fdas_set_batch(h, bad, 1, big, big, None) == F.E_INVALID
+        bad = (F.FdasJob * 1)(F.FdasJob(-1, 10, 0))
+        assert L.fdas_set_batch(h, bad, 1, big, big, None) == F.E_INVALID
+        bad = (F.FdasJob * 1)(F.FdasJob(0, 10, -5))
+        assert L.fdas_set_batch(h, bad, 1, big, big, None) == F.E_INVALID
+        assert L.fdas_correlate_batch(h, fake, fake, None) == F.E_STATE            # no templates, no batch
+        assert L.fdas_correlate_batch(h, ctypes.c_void_p(0x10008), fake, None) == F.E_INVALID
+        assert L.fdas_correlate_batch(h, None, fake, None) == F.E_INVALID
+    finally:
+        L.fdas_destroy(h)
+    cfg0 = make(max_bins=4096, n_z=5, z_min=-4.0)     # max_jobs = 0: no batches
+    assert L.fdas_plan(ctypes.byref(cfg0), ctypes.byref(h), ctypes.byref(n)) == F.OK
+    try:
+        assert L.fdas_set_workspace(h, ctypes.c_void_p(0x10000), n.value) == F.OK
+        jobs = (F.FdasJob * 1)(F.FdasJob(0, 100, 0))
+        assert L.fdas_set_batch(h, jobs, 1, 100, 500, None) == F.E_INVALID
+    finally:
+        L.fdas_destroy(h)
