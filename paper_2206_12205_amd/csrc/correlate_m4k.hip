@@ -4,8 +4,9 @@
 // transform, multiply by each template's transform, inverse transform, keep
 // the central V = L - M outputs).  Every stage of every transform is a
 // 16-point DFT on the matrix cores (16x16x32 bf16 MFMA, FP32 accumulation);
-// factorisation, work split and LDS layouts are in mfma4096.hpp.  One
-// workgroup of 8 waves owns a segment and a chunk of templates:
+// factorisation and LDS layouts are in mfma4096.hpp.  One workgroup of 16
+// waves owns a segment and a chunk of templates; wave w owns MFMA group
+// Q = w of every stage:
 //
 //   forward  F1 (input rounded to bf16) -> LDS B -> F2 -> LDS A -> F3: the
 //            segment spectrum X[k1, k2, k3] ends in registers in the first
@@ -13,12 +14,15 @@
 //            bf16 pairs so each product with a template value is two
 //            v_dot2_f32_bf16.
 //   template j: the bank entry of j + 1 is prefetched; Y = X * H_j -> I1 ->
-//            LDS A -> barrier -> (coalesced flush of template j - 1's powers)
-//            -> I2 -> LDS B -> barrier -> I3 -> |y|^2 -> LDS staging, written
-//            to the plane with 16-byte stores one barrier later.
+//            LDS A -> barrier -> (flush of template j - 1's row) -> I2 ->
+//            LDS B -> barrier -> I3, computed with the operands swapped so
+//            each lane holds four consecutive time samples -> |y|^2 staged in
+//            LDS in the plane's type (one 8- or 16-byte write), written to the
+//            plane one barrier later with coalesced vector stores.
 // All twiddles live in the per-group stage operators, so the vector ALU only
 // forms the template product, packs stage outputs to bf16 and squares.
-// Register use stays under 128 VGPRs so two workgroups share a CU.
+// Register use stays at 64 VGPRs or fewer, so two workgroups (eight waves per
+// SIMD) share a CU.
 #include "fft_valu.hpp"
 #include "internal.hpp"
 #include "mfma4096.hpp"
@@ -28,6 +32,11 @@
 
 namespace fdas {
 namespace m4k {
+
+constexpr int kWv = 16;           // waves per workgroup
+constexpr int kThr = 64 * kWv;
+constexpr int kGpw = 16 / kWv;    // MFMA groups (of 16 columns) per wave and stage
+constexpr int kWavesPerEU = 8;    // two workgroups per CU
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -55,76 +64,92 @@ __device__ __forceinline__ Op load_op(const uint32_t *tab, int op, int lane) {
     return Op{{v.x, v.y, v.z, v.w}};
 }
 
-// staging index of time sample t (one pad word set per 1024 keeps the I3
-// writes of the two lane-group halves in different banks)
-__device__ __forceinline__ int stage_idx(int t) { return t + 16 * (t >> 10); }
-constexpr int kStageWords = kL + 16 * 4;
-
+// Staging of one template row's powers between I3 and the plane store.
+// FP32 plane: one float per sample at t + 4 (t >> 8); BF16 plane: the bf16
+// value, two samples per word, at word t / 2 + 2 (t >> 8).  The pads keep the
+// I3 writes (lanes 256 samples apart) and the flush reads conflict-free.
 template <class PT>
-struct flush_chunk;
+struct Stage;
 template <>
-struct flush_chunk<__bf16> {
-    static __device__ __forceinline__ void vec(__bf16 *dst, float4 v) {
-        typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
-        u32x2_t u;
-        u.x = bf16_pack(v.x, v.y);
-        u.y = bf16_pack(v.z, v.w);
-        __builtin_nontemporal_store(u, reinterpret_cast<u32x2_t *>(dst));
+struct Stage<float> {
+    static constexpr int kWords = kL + 4 * 16;
+    static __device__ __forceinline__ void put4(uint32_t *st, int t0, float a, float b, float c, float d) {
+        *reinterpret_cast<float4 *>(&st[t0 + 4 * (t0 >> 8)]) = make_float4(a, b, c, d);
+    }
+    // samples t0 .. t0 + 3 -> plane, vector or element-wise
+    static __device__ __forceinline__ void flush4(const uint32_t *st, int t0, float *row, bool vec, int lo, int hi) {
+        const float4 v = *reinterpret_cast<const float4 *>(&st[t0 + 4 * (t0 >> 8)]);
+        if (vec) {
+            const f32x4_t u = {v.x, v.y, v.z, v.w};
+            __builtin_nontemporal_store(u, reinterpret_cast<f32x4_t *>(row + t0));
+        } else {
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (t0 + i >= lo && t0 + i < hi) row[t0 + i] = vv[i];
+        }
     }
 };
 template <>
-struct flush_chunk<float> {
-    static __device__ __forceinline__ void vec(float *dst, float4 v) {
-        const f32x4_t u = {v.x, v.y, v.z, v.w};
-        __builtin_nontemporal_store(u, reinterpret_cast<f32x4_t *>(dst));
+struct Stage<__bf16> {
+    static constexpr int kWords = kL / 2 + 2 * 16;
+    static __device__ __forceinline__ void put4(uint32_t *st, int t0, float a, float b, float c, float d) {
+        uint2 u;
+        u.x = bf16_pack(a, b);
+        u.y = bf16_pack(c, d);
+        *reinterpret_cast<uint2 *>(&st[t0 / 2 + 2 * (t0 >> 8)]) = u;
+    }
+    static __device__ __forceinline__ void flush4(const uint32_t *st, int t0, __bf16 *row, bool vec, int lo, int hi) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(&st[t0 / 2 + 2 * (t0 >> 8)]);
+        if (vec) {
+            typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+            u32x2_t w;
+            w.x = u.x;
+            w.y = u.y;
+            __builtin_nontemporal_store(w, reinterpret_cast<u32x2_t *>(row + t0));
+        } else {
+            const uint32_t ww[2] = {u.x, u.y};
+            uint16_t *r16 = reinterpret_cast<uint16_t *>(row);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (t0 + i >= lo && t0 + i < hi) r16[t0 + i] = (uint16_t)(ww[i >> 1] >> (16 * (i & 1)));
+        }
     }
 };
 
-// Per-thread flush plan: thread tid owns time samples [4 tid, 4 tid + 4) and
-// [2048 + 4 tid, 2048 + 4 tid + 4) (consecutive lanes read consecutive
-// 16-byte LDS chunks).  vec[h] says chunk h is entirely kept, inside the
-// plane and aligned for a vector store in every template row.
+// Per-thread flush plan: thread tid owns time samples [t0, t0 + 4) with
+// t0 = 4 (tid + h kThr), h < kFlushChunks (consecutive lanes take
+// consecutive chunks).  vec[h]: the chunk is entirely kept, inside the plane
+// and aligned for one vector store in every template row.  Samples
+// [lo, hi) of a row are kept.
+constexpr int kFlushChunks = kL / (4 * kThr);
 struct FlushPlan {
-    int t0[2];
-    bool vec[2];
+    bool vec[kFlushChunks];
+    int lo, hi;
 };
 
 template <class PT>
-__device__ __forceinline__ FlushPlan flush_plan(const PT *plane, int64_t seg0, int64_t n, int half, bool full,
-                                                int tid) {
+__device__ __forceinline__ FlushPlan flush_plan(const PT *plane, int64_t seg0, int64_t n, int half, int tid) {
     FlushPlan f;
     constexpr uintptr_t kChunkBytes = 4 * sizeof(PT);   // 4 elements: 8 B (bf16) or 16 B (fp32)
     const bool rows_aligned = (n % 4) == 0;             // every row start keeps the chunk alignment
+    f.lo = half;
+    f.hi = (int)min((int64_t)(kL - half), n - seg0);    // columns >= n are outside the plane
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int t0 = 2048 * h + 4 * tid;
-        const int64_t col = seg0 + t0;
-        f.t0[h] = t0;
-        f.vec[h] = rows_aligned && (reinterpret_cast<uintptr_t>(plane + col) % kChunkBytes) == 0 && t0 >= half &&
-                   t0 + 4 <= kL - half && (full || col + 4 <= n);
+    for (int h = 0; h < kFlushChunks; ++h) {
+        const int t0 = 4 * (tid + h * kThr);
+        f.vec[h] = rows_aligned && (reinterpret_cast<uintptr_t>(plane + seg0 + t0) % kChunkBytes) == 0 &&
+                   t0 >= f.lo && t0 + 4 <= f.hi;
     }
     return f;
 }
 
-// Write the staged powers of one template row.
 template <class PT>
-__device__ __forceinline__ void flush(const float *stage, PT *row, int64_t seg0, int64_t n, int half,
-                                      const FlushPlan &f) {
+__device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const FlushPlan &f, int tid) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int t0 = f.t0[h];
-        const float4 v = *reinterpret_cast<const float4 *>(stage + stage_idx(t0));
-        const int64_t col = seg0 + t0;
-        if (f.vec[h]) {
-            flush_chunk<PT>::vec(row + col, v);
-        } else {
-            const float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int t = t0 + i;
-                if (t >= half && t < kL - half && col + i < n) plane_store<PT>::put(row + col + i, vv[i]);
-            }
-        }
+    for (int h = 0; h < kFlushChunks; ++h) {
+        const int t0 = 4 * (tid + h * kThr);
+        Stage<PT>::flush4(stage, t0, row_seg, f.vec[h], f.lo, f.hi);
     }
 }
 
@@ -135,25 +160,32 @@ template <class PT>
 __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_t n, const uint32_t *__restrict__ bank,
                                          const uint32_t *__restrict__ tab, PT *__restrict__ plane, int32_t M,
                                          int32_t V, int64_t s, int j0, int j1, uint32_t *bufA, uint32_t *bufB,
-                                         float *stage) {
+                                         uint32_t *stage) {
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, c = lane & 15, g = lane >> 4;
     const int half = M / 2;
     const int64_t seg0 = s * (int64_t)V - half;   // plane column of time index t is seg0 + t
-    const bool full = seg0 + (kL - half) <= n;
     // ---------------- forward transform ----------------
     // F1: n2 = Q, column n3 = c, K: n1 = 4 g + p  ->  rows k1 = 4 g + e  -> buffer B
+    const bool inside = seg0 >= 0 && seg0 + kL <= n;   // no window sample falls outside [0, n)
+    const float2 *win = spec + seg0;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int Q = 2 * w + q;
+    for (int q = 0; q < kGpw; ++q) {
+        const int Q = kGpw * w + q;
         Op b;
+        float2 v[4];
+        if (inside) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int64_t idx = seg0 + 256 * (4 * g + p) + 16 * Q + c;
-            float2 v = make_float2(0.f, 0.f);
-            if (idx >= 0 && idx < n) v = spec[idx];
-            b.w[p] = bf16_pack(v.x, v.y);
+            for (int p = 0; p < 4; ++p) v[p] = win[256 * (4 * g + p) + 16 * Q + c];
+        } else {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int64_t idx = seg0 + 256 * (4 * g + p) + 16 * Q + c;
+                v[p] = (idx >= 0 && idx < n) ? spec[idx] : make_float2(0.f, 0.f);
+            }
         }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) b.w[p] = bf16_pack(v[p].x, v[p].y);
         const f32x4_t dre = mma(load_op(tab, OP_F12 + 2 * Q, lane), b);
         const f32x4_t dim = mma(load_op(tab, OP_F12 + 2 * Q + 1, lane), b);
         uint4 o;
@@ -166,8 +198,8 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
     __syncthreads();
     // F2: n3 = Q, column k1 = c, K: n2 = 4 g + p  ->  rows k2 = 4 g + e  -> buffer A
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int Q = 2 * w + q;
+    for (int q = 0; q < kGpw; ++q) {
+        const int Q = kGpw * w + q;
         Op b;
 #pragma unroll
         for (int p = 0; p < 4; ++p) b.w[p] = bufB[addrB(c, 4 * g + p, Q)];
@@ -184,10 +216,10 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
     // F3: k1 = Q, column k2 = c, K: n3 = 4 g + p -> X[Q, c, 4 g + e] in registers.
     // Each wave reads exactly the buffer-A words its own I1 writes later, so
     // no barrier is needed before the template loop.
-    uint32_t sA[2][4], sB[2][4];
+    uint32_t sA[kGpw][4], sB[kGpw][4];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int Q = 2 * w + q;
+    for (int q = 0; q < kGpw; ++q) {
+        const int Q = kGpw * w + q;
         Op b;
 #pragma unroll
         for (int p = 0; p < 4; ++p) b.w[p] = bufA[addrA(Q, c, 4 * g + p)];
@@ -201,25 +233,25 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
     }
 
     // ---------------- per-group inverse operators ----------------
-    Op a1re[2], a1im[2], a23re[2], a23im[2];
+    Op a1re[kGpw], a1im[kGpw], a23re[kGpw], a23im[kGpw];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int Q = 2 * w + q;
+    for (int q = 0; q < kGpw; ++q) {
+        const int Q = kGpw * w + q;
         a1re[q] = load_op(tab, OP_I1 + 2 * Q, lane);
         a1im[q] = load_op(tab, OP_I1 + 2 * Q + 1, lane);
         a23re[q] = load_op(tab, OP_I23 + 2 * Q, lane);
         a23im[q] = load_op(tab, OP_I23 + 2 * Q + 1, lane);
     }
 
-    const FlushPlan fp = flush_plan<PT>(plane, seg0, n, half, full, tid);
-    const uint4 *bank4 = reinterpret_cast<const uint4 *>(bank) + (2 * w) * 64 + lane;
+    const FlushPlan fp = flush_plan<PT>(plane, seg0, n, half, tid);
+    const uint4 *bank4 = reinterpret_cast<const uint4 *>(bank) + (kGpw * w) * 64 + lane;
 
     // One template: I1 (group k1 = Q) on X * H_j, I2 (group n3), I3 (group n2).
-    auto one_template = [&](int j, const uint4 (&hc)[2]) {
+    auto one_template = [&](int j, const uint4 (&hc)[kGpw]) {
         // I1: DFT16 over k3 with e(n3 k1); rows n3 = 4 g + e -> buffer A
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int Q = 2 * w + q;
+        for (int q = 0; q < kGpw; ++q) {
+            const int Q = kGpw * w + q;
             const uint32_t hw[4] = {hc[q].x, hc[q].y, hc[q].z, hc[q].w};
             Op b;
 #pragma unroll
@@ -229,11 +261,11 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
             for (int e = 0; e < 4; ++e) bufA[addrA(Q, c, 4 * g + e)] = bf16_pack(dre[e], dim[e]);
         }
         __syncthreads();
-        if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n, seg0, n, half, fp);
+        if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n + seg0, fp, tid);
         // I2: DFT16 over k2 with e(16 n3 k2); rows n2 = 4 g + e -> buffer B
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int Q = 2 * w + q;
+        for (int q = 0; q < kGpw; ++q) {
+            const int Q = kGpw * w + q;
             const uint4 v = *reinterpret_cast<const uint4 *>(&bufA[addrA(c, 4 * g, Q)]);   // 4 consecutive k2
             const Op b = {{v.x, v.y, v.z, v.w}};
             const f32x4_t dre = mma(a23re[q], b), dim = mma(a23im[q], b);
@@ -243,37 +275,37 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
         __syncthreads();
         // I3: DFT16 over k1 with e(16 n2 k1); rows n1 = 4 g + e; |y|^2 -> staging
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int Q = 2 * w + q;
+        for (int q = 0; q < kGpw; ++q) {
+            const int Q = kGpw * w + q;
             const uint4 v = *reinterpret_cast<const uint4 *>(&bufB[addrB(4 * g, Q, c)]);   // 4 consecutive k1
             const Op b = {{v.x, v.y, v.z, v.w}};
-            const f32x4_t dre = mma(a23re[q], b), dim = mma(a23im[q], b);
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                stage[stage_idx(256 * (4 * g + e) + 16 * Q + c)] = dre[e] * dre[e] + dim[e] * dim[e];
+            const f32x4_t dre = mma(b, a23re[q]), dim = mma(b, a23im[q]);
+            Stage<PT>::put4(stage, 256 * c + 16 * Q + 4 * g, dre[0] * dre[0] + dim[0] * dim[0],
+                            dre[1] * dre[1] + dim[1] * dim[1], dre[2] * dre[2] + dim[2] * dim[2],
+                            dre[3] * dre[3] + dim[3] * dim[3]);
         }
     };
 
     // templates in pairs with two statically assigned bank registers: the
     // next template's bank entry is in flight while the current one runs
-    uint4 hA[2], hB[2];
+    uint4 hA[kGpw], hB[kGpw];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) hA[q] = bank4[(size_t)j0 * (kL / 4) + q * 64];
+    for (int q = 0; q < kGpw; ++q) hA[q] = bank4[(size_t)j0 * (kL / 4) + q * 64];
     for (int j = j0; j < j1; j += 2) {
         if (j + 1 < j1) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q) hB[q] = bank4[(size_t)(j + 1) * (kL / 4) + q * 64];
+            for (int q = 0; q < kGpw; ++q) hB[q] = bank4[(size_t)(j + 1) * (kL / 4) + q * 64];
         }
         one_template(j, hA);
         if (j + 1 >= j1) break;
         if (j + 2 < j1) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q) hA[q] = bank4[(size_t)(j + 2) * (kL / 4) + q * 64];
+            for (int q = 0; q < kGpw; ++q) hA[q] = bank4[(size_t)(j + 2) * (kL / 4) + q * 64];
         }
         one_template(j + 1, hB);
     }
     __syncthreads();
-    flush<PT>(stage, plane + (int64_t)(j1 - 1) * n, seg0, n, half, fp);
+    flush<PT>(stage, plane + (int64_t)(j1 - 1) * n + seg0, fp, tid);
 }
 
 // Out-of-line copy for the persistent kernel: inlined into its tile loop the
@@ -283,11 +315,11 @@ template <class PT>
 __device__ __noinline__ void m4k_tile_call(const float2 *__restrict__ spec, int64_t n,
                                            const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
                                            PT *__restrict__ plane, int32_t M, int32_t V, int64_t s, int j0, int j1,
-                                           uint32_t *bufA, uint32_t *bufB, float *stage) {
+                                           uint32_t *bufA, uint32_t *bufB, uint32_t *stage) {
     m4k_tile<PT>(spec, n, bank, tab, plane, M, V, s, j0, j1, bufA, bufB, stage);
 }
 
-#define M4K_ATTR __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(4)))
+#define M4K_ATTR __attribute__((amdgpu_flat_work_group_size(kThr, kThr), amdgpu_waves_per_eu(kWavesPerEU)))
 
 // One spectrum: workgroup b takes template chunk b mod n_chunks of segment b / n_chunks.
 template <class PT>
@@ -297,7 +329,7 @@ __global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int
                                             int32_t z_chunk, int32_t n_chunks) {
     __shared__ __align__(16) uint32_t bufA[kBufWords];
     __shared__ __align__(16) uint32_t bufB[kBufWords];
-    __shared__ __align__(16) float stage[kStageWords];
+    __shared__ __align__(16) uint32_t stage[Stage<PT>::kWords];
     const int chunk = blockIdx.x % n_chunks;
     const int64_t s = blockIdx.x / n_chunks;
     const int j0 = chunk * z_chunk;
@@ -319,7 +351,7 @@ __global__ void M4K_ATTR correlate_mfma4096_batch(const float2 *__restrict__ spe
                                                   int32_t z_chunk, int32_t n_chunks) {
     __shared__ __align__(16) uint32_t bufA[kBufWords];
     __shared__ __align__(16) uint32_t bufB[kBufWords];
-    __shared__ __align__(16) float stage[kStageWords];
+    __shared__ __align__(16) uint32_t stage[Stage<PT>::kWords];
     __shared__ int s_tile;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
@@ -358,7 +390,7 @@ hipError_t launch(const fdas_plan_s &p, const void *spec, int64_t n, void *plane
     const int64_t blocks = n_seg * p.n_chunks;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const auto *ws = static_cast<const unsigned char *>(p.ws);
-    hipLaunchKernelGGL(correlate_mfma4096<PT>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL(correlate_mfma4096<PT>, dim3((unsigned)blocks), dim3(kThr), 0, st,
                        static_cast<const float2 *>(spec), n, reinterpret_cast<const uint32_t *>(ws + p.off_bank),
                        reinterpret_cast<const uint32_t *>(ws + p.off_tab), static_cast<PT *>(plane), p.M, p.V,
                        p.cfg.n_z, p.z_chunk, p.n_chunks);
@@ -376,7 +408,7 @@ hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes,
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>((int64_t)cus * 2, std::max<int64_t>(p.batch_tiles, 1));
-    hipLaunchKernelGGL(correlate_mfma4096_batch<PT>, dim3((unsigned)grid), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL(correlate_mfma4096_batch<PT>, dim3((unsigned)grid), dim3(kThr), 0, st,
                        static_cast<const float2 *>(spectra), jobs, p.batch_jobs, p.batch_tiles, counter,
                        reinterpret_cast<const uint32_t *>(ws + p.off_bank),
                        reinterpret_cast<const uint32_t *>(ws + p.off_tab), static_cast<PT *>(planes), p.M, p.V,

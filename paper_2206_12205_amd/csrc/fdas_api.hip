@@ -108,9 +108,10 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     p->mfma = mfma_ok && c.algo != FDAS_ALGO_VALU;
     int zc = c.z_chunk;
     if (zc == 0) {
-        // vector-ALU kernel: eight chunks, one per XCD; matrix-core kernel:
-        // four chunks (its per-segment forward transform costs about one template)
-        zc = p->mfma ? (c.n_z + 3) / 4 : (c.n_z + 7) / 8;
+        // vector-ALU kernel: eight chunks, one per XCD; matrix-core kernels:
+        // two (L = 4096) or four (L = 8192) chunks, since each chunk repeats
+        // the segment's forward transform (measured best on the single-DM plane)
+        zc = !p->mfma ? (c.n_z + 7) / 8 : L == fdas::m4k::kL ? (c.n_z + 1) / 2 : (c.n_z + 3) / 4;
     }
     if (zc > c.n_z) zc = c.n_z;
     p->z_chunk = zc;

@@ -23,7 +23,7 @@
 //   A[i][k]: i = c, k = 8 g + e     B[k][j]: j = c, k = 8 g + e     D[i][j]: j = c, i = 4 g + e
 // with K slot 8 g + 2 p + part holding part (re / im) of complex input 4 g + p.
 //
-// Work split: 8 waves per workgroup, wave w owns MFMA groups Q = 2 w + q (q < 2):
+// Groups and columns per stage (group Q < 16, column c = lane & 15):
 //   stage k3 (I1 / F3): k1 = Q, column c -> k2 = c
 //   stage k2 (I2 / F2): n3 = Q, column c -> k1 = c
 //   stage k1 (I3 / F1): n2 = Q, column c -> n3 = c
@@ -44,8 +44,6 @@ namespace fdas {
 namespace m4k {
 
 constexpr int kL = 4096;
-constexpr int kWaves = 8;
-constexpr int kThreads = 64 * kWaves;
 constexpr int kBufWords = 5184;   // last index 15*324 + 15 + 15*20 = 5175, rounded up
 
 __host__ __device__ constexpr int addrA(int k1, int x, int n3) { return k1 * 324 + x + 20 * n3; }
