@@ -91,6 +91,49 @@ def cpu_baseline(spec, cfg, r_center, target_s=15.0):
                       f"({cells} cells, {dt:.1f} s), {cfg['n_taps']} taps"}
 
 
+def batched_search(args, cfg, dev, n_spec=256, seed=2206):
+    """Many-spectra workload: 256 spectra with log-uniform lengths in
+    [2^19, 2^22] bins (mean 1.76e6), the single-DM template grid, BF16 form,
+    autotuned plan per length class, planes chunked through a 16 GB buffer
+    and thresholded peaks of every plane.  Spectra are seeded unit-power
+    complex noise generated on the device (the statistics of a normalised
+    noise spectrum)."""
+    import numpy as np
+    import torch
+    from paper_2206_12205_amd.pipeline import BatchSearch
+    g = np.random.default_rng(seed)
+    lengths = np.exp(g.uniform(np.log(2 ** 19), np.log(2 ** 22), n_spec)).astype(np.int64).tolist()
+    total = int(sum(lengths))
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    spectra = torch.randn(total, dtype=torch.complex64, device=dev, generator=gen)
+    t0 = time.perf_counter()
+    bs = BatchSearch(lengths, cfg["z_min"], cfg["z_step"], cfg["n_z"], cfg["n_taps"], compute="bf16",
+                     plane_dtype="bf16", buffer_bytes=16 << 30, tune=True, device=dev)
+    setup_s = time.perf_counter() - t0
+    res = {}
+    for name, fp in (("correlate", False), ("correlate_and_peaks", True)):
+        bs.run(spectra, cfg["threshold"], find_peaks=fp)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        steps = max(1, min(args.steps, 3))
+        e0.record()
+        for _ in range(steps):
+            bs.run(spectra, cfg["threshold"], find_peaks=fp)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"ms_per_pass": ms, "cells_per_s": bs.cells / (ms * 1e-3)}
+    n_found = int(bs.n_found.sum().item())
+    out = {"workload": f"{n_spec} spectra, lengths log-uniform in [2^19, 2^22] bins (total {total}), "
+                       f"{cfg['n_z']} templates, {cfg['n_taps']} taps, BF16 form, raw BF16 planes "
+                       f"chunked through a 16 GB buffer, peaks above {cfg['threshold']}",
+           "cells": bs.cells, "chunks": len(bs.chunks), "setup_s": setup_s,
+           "tuned": {f"2^{k}": v for k, v in bs.tuned.items()}, "peaks_found": n_found, **res}
+    del bs, spectra
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +141,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched many-spectra search (256 dedispersion trials)")
     ap.add_argument("--trials", type=int, default=8,
                     help="seeded single-DM trials in the accuracy ensemble (outside the timed region)")
     ap.add_argument("--seg-len", type=int, default=None,
@@ -157,6 +202,7 @@ def main():
     pl_8 = Plan(compute="bf16", plane_dtype="bf16", algo="mfma", **common)  # the stated segment 8192
     pl_v = Plan(compute="bf16", plane_dtype="bf16", algo="valu", **common)
     pl_f = Plan(compute="fp32", plane_dtype="fp32", **common)
+    pl_q = Plan(compute="fp8", plane_dtype="bf16", **cm_auto)               # FP8 e4m3 form
     plane_b = pl_b.empty_plane(n)
     plane_f = pl_f.empty_plane(n)
     torch.cuda.synchronize()
@@ -165,6 +211,8 @@ def main():
     ms_8, _ = time_correlate(pl_8, x, pl_8.empty_plane(n), args.steps, args.warmup)
     ms_v, _ = time_correlate(pl_v, x, pl_v.empty_plane(n), args.steps, args.warmup)
     ms_f, wall_f = time_correlate(pl_f, x, plane_f, args.steps, args.warmup)
+    plane_q = pl_q.empty_plane(n)
+    ms_q, _ = time_correlate(pl_q, x, plane_q, args.steps, args.warmup)
     del pl_v, pl_8
 
     # algorithmic HBM bytes per launch: the plane store plus one read of the
@@ -202,6 +250,8 @@ def main():
                  "hbm_frac": bytes_f / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "bf16_seg8192": {"value": cells / (ms_8 * 1e-3), "unit": "cells/s", "ms_per_step": ms_8},
         "bf16_valu": {"value": cells / (ms_v * 1e-3), "unit": "cells/s", "ms_per_step": ms_v},
+        "fp8": {"value": cells / (ms_q * 1e-3), "unit": "cells/s", "ms_per_step": ms_q,
+                "kernel": f"correlate_valu_fp8 (e4m3 stages, segment {pl_q.seg_len}, raw BF16 plane)"},
         "speedup_bf16_over_fp32": ms_f / ms_b,
         "wall_s": {"bf16": wall_b, "fp32": wall_f},
     }
@@ -211,35 +261,46 @@ def main():
         # harmonic bands (Table 3) of each trial's injected pulsar, over a
         # seeded ensemble; SNR differences by Eq. 2 (SNR = power / plane std)
         pl_d = Plan(compute="fp64", plane_dtype="fp64", **common)
-        n_bright = same_b = same_f = 0
-        dsnr, err_b, err_f = [], 0.0, 0.0
+        n_bright = same_b = same_f = same_q = 0
+        dsnr, dsnr_q, err_b, err_f, err_q = [], [], 0.0, 0.0, 0.0
         for trial in range(args.trials):
             spt = sp if trial == 0 else synth.config2(trial)
             xt = torch.from_numpy(spt.spec).to(dev)
             pd = pl_d.correlate(xt)
             pb = pl_b.correlate(xt, plane_b).to(torch.float32)
             pf = pl_f.correlate(xt, plane_f)
+            pq = pl_q.correlate(xt, plane_q).to(torch.float32)
             psr = spt.pulsars[0]
             bands = metrics.harmonic_bands(psr.f, spt.T, n, 8)
             md = metrics.band_maxima(pd, bands)
             mb = metrics.band_maxima(pb, bands)
             mf = metrics.band_maxima(pf, bands)
-            sb, sf = float(pb.std()), float(pf.std())
+            mq = metrics.band_maxima(pq, bands)
+            sb, sf, sq = float(pb.std()), float(pf.std()), float(pq.std())
             bright = [i for i, m in enumerate(mf) if m[2] > cfg["threshold"]]
             n_bright += len(bright)
             same_b += sum((mb[i][0], mb[i][1]) == (md[i][0], md[i][1]) for i in bright)
             same_f += sum((mf[i][0], mf[i][1]) == (md[i][0], md[i][1]) for i in bright)
+            same_q += sum((mq[i][0], mq[i][1]) == (md[i][0], md[i][1]) for i in bright)
             dsnr += [float(metrics.rel_diff_pct(mb[i][2] / sb, mf[i][2] / sf)) for i in bright]
+            dsnr_q += [float(metrics.rel_diff_pct(mq[i][2] / sq, mf[i][2] / sf)) for i in bright]
             # max relative power error vs FP64 (floor 1: the noise mean)
             err_b = max(err_b, ((pb.to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item())
             err_f = max(err_f, ((pf.to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item())
-            del pd, pb, xt
+            err_q = max(err_q, ((pq.to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item())
+            del pd, pb, pq, xt
         out["accuracy"] = {"trials": args.trials, "bright_band_maxima": n_bright,
                            "bf16_same_bin_vs_fp64": same_b, "fp32_same_bin_vs_fp64": same_f,
                            "bf16_same_bin_frac": same_b / n_bright if n_bright else None,
                            "bf16_max_abs_dsnr_pct": max(map(abs, dsnr)) if dsnr else None,
-                           "bf16_max_rel_power_err": err_b, "fp32_max_rel_power_err": err_f}
+                           "bf16_max_rel_power_err": err_b, "fp32_max_rel_power_err": err_f,
+                           "fp8_same_bin_vs_fp64": same_q,
+                           "fp8_max_abs_dsnr_pct": max(map(abs, dsnr_q)) if dsnr_q else None,
+                           "fp8_max_rel_power_err": err_q}
         del pl_d
+
+    if not args.no_batched:
+        out["batched"] = batched_search(args, cfg, dev)
 
     if not args.no_cpu_baseline:
         r_c = int(round(sp.pulsars[0].r_bar(sp.T)))

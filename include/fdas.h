@@ -33,6 +33,15 @@
  *              bfloat16 (round to nearest even), arithmetic accumulated in
  *              single precision.  The spectrum input stays single precision
  *              (the paper keeps its real FFT in single precision).
+ *   FDAS_FP8E4M3  one step below bfloat16 (no FP8 form in the paper): the
+ *              stored transform stages, the segment spectrum and the templates
+ *              are OCP e4m3 (3 mantissa bits, largest 448) with power-of-two
+ *              scales; each stored stage takes the largest scale that keeps the
+ *              workgroup's largest component within 448, each template its
+ *              own.  Arithmetic is single precision; the window is read in
+ *              single precision.  Vector-ALU kernel, L in {1024, 2048, 4096}
+ *              (0 chooses 4096); the e4m3 format has no infinities, so an Inf
+ *              input turns its segments' outputs into NaN.
  *   FDAS_FP64  double precision throughout: the gold-standard plane.
  * Plane dtypes: FDAS_FP32 (4 B/cell), FDAS_BF16 (2 B/cell raw bfloat16; a
  * consumer widens it exactly to single precision by placing the two bytes in
@@ -71,7 +80,7 @@ typedef struct fdas_plan_s *fdas_plan_t;
 typedef enum {
     FDAS_FP32 = 0,
     FDAS_BF16 = 1,
-    FDAS_FP8E4M3 = 2,   /* reserved: rejected with FDAS_E_UNSUPPORTED */
+    FDAS_FP8E4M3 = 2,   /* OCP e4m3 storage form (vector-ALU kernel, L <= 4096) */
     FDAS_FP64 = 3
 } fdas_dtype;
 
@@ -92,8 +101,9 @@ typedef struct {
     int32_t n_z;          /* number of templates, >= 1 */
     int32_t n_taps;       /* M: even, >= 2; the overlap between segments */
     int32_t seg_len;      /* L: power of two in [1024, 16384], L > M; 0 = choose (BF16: 4096 for
-                             M <= 512, 8192 for M <= 2048; otherwise the power of two >= 32 M) */
-    int32_t compute;      /* FDAS_FP32 | FDAS_BF16 | FDAS_FP64 */
+                             M <= 512, 8192 for M <= 2048; FP8: 4096; otherwise the power of
+                             two >= 32 M, at most 8192 for FP64) */
+    int32_t compute;      /* FDAS_FP32 | FDAS_BF16 | FDAS_FP8E4M3 | FDAS_FP64 */
     int32_t plane_dtype;  /* FDAS_FP32 | FDAS_BF16 (not with FP64 compute) | FDAS_FP64 (FP64 compute only) */
     int32_t z_chunk;      /* templates per workgroup; 0 = choose */
     int32_t algo;         /* FDAS_ALGO_AUTO | FDAS_ALGO_VALU | FDAS_ALGO_MFMA */
@@ -193,14 +203,41 @@ int fdas_correlate(fdas_plan_t plan, const void *spectrum, int64_t n_bins,
  *
  * fdas_correlate_batch enqueues the batch on stream: a counter reset kernel
  * and one persistent launch whose workgroups pull (job, segment, template
- * chunk) tiles until none is left (BF16 matrix-core plans), or one
- * correlation launch per job (other plans).  It records only kernels, so it
+ * chunk) tiles until none is left, each workgroup starting on the template
+ * chunk of its XCD so that an XCD's L2 holds only part of the bank (BF16
+ * matrix-core plans with L = 4096), or one correlation launch per job (other
+ * plans).  It records only kernels, so it
  * can be captured in a HIP graph and replayed; each job's plane is exactly
  * what fdas_correlate writes for that spectrum.  FDAS_E_STATE without
  * templates or a batch. */
 int fdas_set_batch(fdas_plan_t plan, const fdas_job *jobs, int32_t n_jobs, int64_t spectra_bins,
                    int64_t plane_cells, void *stream);
 int fdas_correlate_batch(fdas_plan_t plan, const void *spectra, void *planes, void *stream);
+
+/* Measured choice of the kernel knobs (segment length, kernel family,
+ * templates per workgroup) for a workload: the batched mode serves spectra of
+ * several length classes, and the fastest segment length and template chunk
+ * depend on the length and the template count.  Synchronous on stream.
+ *
+ * cfg fixes the workload (max_bins, z grid, taps, compute, plane dtype); each
+ * of seg_len, algo and z_chunk that is 0 / FDAS_ALGO_AUTO is searched, a
+ * non-zero value is kept.  Candidates: every supported L in [1024, 16384]
+ * with L > M (BF16 also on the matrix-core kernels where they exist) and
+ * template chunks n_z, ceil(n_z/2), ceil(n_z/4), ceil(n_z/8).  Each one gets
+ * a plan on the caller's workspace, its template bank, one warm-up and reps
+ * timed fdas_correlate launches on spectrum (n_bins bins) into plane (n_z x
+ * n_bins of the plane dtype), timed with HIP events.
+ *
+ * fdas_tune_workspace gives the workspace size that covers every candidate.
+ * fdas_tune writes the fastest configuration (all knobs explicit) to *best
+ * and its mean launch time in milliseconds to *best_ms; the workspace content
+ * is overwritten (a plan that used it must call fdas_make_templates again).
+ * FDAS_E_WORKSPACE if workspace_bytes is below fdas_tune_workspace's value,
+ * FDAS_E_UNSUPPORTED if no candidate is valid, FDAS_E_INVALID for bad
+ * arguments (reps in [1, 1000]). */
+int fdas_tune_workspace(const fdas_config *cfg, size_t *workspace_bytes);
+int fdas_tune(const fdas_config *cfg, const void *spectrum, int64_t n_bins, void *plane, void *workspace,
+              size_t workspace_bytes, int32_t reps, fdas_config *best, float *best_ms, void *stream);
 
 /* Thresholded peaks of a plane written by fdas_correlate with the same plan
  * (Sections "Detailed explanation" and "Peakfinding methodology").  A cell is
@@ -211,7 +248,9 @@ int fdas_correlate_batch(fdas_plan_t plan, const void *spectra, void *planes, vo
  * order with job = 0; the true count goes to *n_found (device int64).  When
  * the count exceeds capacity the first capacity peaks are written and the
  * caller sees it by comparing *n_found with capacity (the call itself cannot
- * know without a device synchronisation and returns FDAS_OK). */
+ * know without a device synchronisation and returns FDAS_OK).  The plane
+ * pointer needs only the alignment of its element type (a job's plane inside
+ * a batch buffer may start anywhere); out 16-byte, n_found 8-byte aligned. */
 int fdas_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, float threshold,
                fdas_peak *out, int64_t capacity, int64_t *n_found, void *stream);
 

@@ -43,3 +43,58 @@ def bf16_truncate(x) -> np.ndarray:
     paper's statistics reject it."""
     f = np.ascontiguousarray(x, dtype=np.float32)
     return ((f.view(np.uint32) >> 16) << 16).view(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# FP8 e4m3 (the OCP "e4m3fn" encoding: 1 sign, 4 exponent bits with bias 7,
+# 3 mantissa bits, no infinities, S.1111.111 is NaN, largest finite 448,
+# smallest normal 2^-6, subnormals in steps of 2^-9).  The paper has no FP8
+# form; this is the reduced-precision form below bfloat16 that gfx950 stores
+# natively.  Defined by its value table, rounded to nearest with ties to the
+# even code, by exhaustive search (plain, slow, obviously correct).
+# ---------------------------------------------------------------------------
+
+def e4m3_value(code: int) -> float:
+    """Value of one e4m3 code (NaN for the two NaN codes)."""
+    code = int(code) & 0xFF
+    s = -1.0 if code & 0x80 else 1.0
+    e = (code >> 3) & 0xF
+    m = code & 0x7
+    if e == 15 and m == 7:
+        return float("nan")
+    if e == 0:
+        return s * (m / 8.0) * 2.0 ** -6
+    return s * (1.0 + m / 8.0) * 2.0 ** (e - 7)
+
+
+E4M3_TABLE = np.array([e4m3_value(c) for c in range(256)])
+E4M3_MAX = 448.0
+
+
+def e4m3_bits(x) -> np.ndarray:
+    """Nearest e4m3 code of each value (ties to the even code); |x| above the
+    rounding range of 448 and NaN give the NaN code 0x7F (sign kept)."""
+    xs = np.asarray(x, dtype=np.float64).ravel()
+    pos = np.array([c for c in range(0x7F)])          # finite non-negative codes 0x00..0x7E
+    vals = E4M3_TABLE[pos]
+    out = np.empty(xs.size, dtype=np.uint8)
+    for i, v in enumerate(xs):
+        sign = 0x80 if (np.signbit(v) and not np.isnan(v)) else 0
+        a = abs(v)
+        if np.isnan(v) or a >= 464.0:                 # 464 = midpoint of 448 and the next step
+            out[i] = 0x7F | sign
+            continue
+        d = np.abs(vals - a)
+        best = np.flatnonzero(d == d.min())
+        c = best[0] if best.size == 1 else [b for b in best if b % 2 == 0][0]
+        out[i] = int(pos[c]) | sign
+    return out.reshape(np.shape(x))
+
+
+def e4m3_decode(bits) -> np.ndarray:
+    return E4M3_TABLE[np.asarray(bits, dtype=np.uint8)]
+
+
+def to_e4m3(x) -> np.ndarray:
+    """Round to the nearest e4m3 value (float64 result)."""
+    return e4m3_decode(e4m3_bits(x))

@@ -1,10 +1,10 @@
-// Batched launches: the tile counter reset kernel.
+// Batched launches: reset of the per-chunk segment counters.
 #include "internal.hpp"
 
 namespace fdas {
 
-__global__ void k_batch_reset(int32_t *counter) {
-    if (threadIdx.x == 0) counter[0] = 0;
+__global__ void k_batch_reset(int32_t *counters, int32_t n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counters[i] = 0;
 }
 
 }  // namespace fdas

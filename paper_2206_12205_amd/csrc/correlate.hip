@@ -132,6 +132,7 @@ hipError_t dispatch_dtype(const fdas_plan_s &p, const void *spec, int64_t n, voi
 }  // namespace
 
 hipError_t launch_correlate(const fdas_plan_s &p, const void *spec, int64_t n, void *plane, hipStream_t st) {
+    if (p.cfg.compute == FDAS_FP8E4M3) return launch_correlate_fp8(p, spec, n, plane, st);
     switch (p.log2L) {
         case 10: return dispatch_dtype<10>(p, spec, n, plane, st);
         case 11: return dispatch_dtype<11>(p, spec, n, plane, st);

@@ -338,40 +338,55 @@ __global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int
     m4k_tile<PT>(spec, n, bank, tab, plane, M, V, s, j0, j1, bufA, bufB, stage);
 }
 
-// Many spectra in one persistent launch: every workgroup pulls tiles
-// (job, segment, template chunk) from a device counter until none is left,
-// so ragged lengths balance across the CUs.  Tile t belongs to the last job
-// whose tile_base is <= t.
+// Many spectra in one persistent launch.  Tiles are (job, segment, template
+// chunk); each chunk has its own queue of segments (all jobs' segments in
+// order, job by binary search over the segment prefix seg_base).  Workgroups
+// are dispatched round-robin over the eight XCDs, so a workgroup starts on
+// chunk (XCD mod n_chunks): each XCD's L2 then holds only its chunks' part of
+// the template bank.  A workgroup whose queue is empty moves on to the next
+// chunk's queue, so ragged lengths still balance across the CUs.
+constexpr int kXcds = 8;
+
 template <class PT>
 __global__ void M4K_ATTR correlate_mfma4096_batch(const float2 *__restrict__ spectra,
                                                   const fdas_batch_job *__restrict__ jobs, int32_t n_jobs,
-                                                  int64_t n_tiles, int32_t *__restrict__ counter,
+                                                  int32_t n_segs, int32_t *__restrict__ counters,
                                                   const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
                                                   PT *__restrict__ planes, int32_t M, int32_t V, int32_t n_z,
                                                   int32_t z_chunk, int32_t n_chunks) {
     __shared__ __align__(16) uint32_t bufA[kBufWords];
     __shared__ __align__(16) uint32_t bufB[kBufWords];
     __shared__ __align__(16) uint32_t stage[Stage<PT>::kWords];
-    __shared__ int s_tile;
+    __shared__ int s_chunk, s_seg;
+    const int c0 = (int)(blockIdx.x % kXcds) % n_chunks;
+    int c_off = 0;   // used by thread 0 only
     for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+        if (threadIdx.x == 0) {
+            int sg = n_segs;
+            while (c_off < n_chunks) {
+                sg = atomicAdd(&counters[(c0 + c_off) % n_chunks], 1);
+                if (sg < n_segs) break;
+                ++c_off;
+            }
+            s_chunk = c_off < n_chunks ? (c0 + c_off) % n_chunks : -1;
+            s_seg = sg;
+        }
         __syncthreads();
         // the tile and everything derived from it are the same on every lane:
         // keep them in scalar registers
-        const int t = __builtin_amdgcn_readfirstlane((int)s_tile);
-        if (t >= n_tiles) return;                 // uniform: every wave leaves together
-        int lo = 0, hi = n_jobs - 1;              // last job with tile_base <= t
+        const int chunk = __builtin_amdgcn_readfirstlane(s_chunk);
+        if (chunk < 0) return;                    // uniform: every wave leaves together
+        const int sg = __builtin_amdgcn_readfirstlane(s_seg);
+        int lo = 0, hi = n_jobs - 1;              // last job with seg_base <= sg
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].tile_base <= t) lo = mid;
+            if (jobs[mid].seg_base <= sg) lo = mid;
             else hi = mid - 1;
         }
         lo = __builtin_amdgcn_readfirstlane(lo);
         const int64_t spec_off = jobs[lo].spec_off, nb = jobs[lo].n_bins;
         const int64_t plane_off = jobs[lo].plane_off;
-        const int local = t - (int)jobs[lo].tile_base;
-        const int chunk = local % n_chunks;
-        const int s = local / n_chunks;
+        const int s = sg - (int)jobs[lo].seg_base;
         const int j0 = chunk * z_chunk;
         const int j1 = min(j0 + z_chunk, n_z);
         // an opaque zero keeps the per-tile operator loads inside the loop, so
@@ -399,9 +414,9 @@ hipError_t launch(const fdas_plan_s &p, const void *spec, int64_t n, void *plane
 template <class PT>
 hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes, hipStream_t st) {
     auto *ws = static_cast<unsigned char *>(p.ws);
-    int32_t *counter = reinterpret_cast<int32_t *>(ws + p.off_batch);
-    const auto *jobs = reinterpret_cast<const fdas_batch_job *>(ws + p.off_batch + 256);
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, counter);
+    int32_t *counters = reinterpret_cast<int32_t *>(ws + p.off_batch);
+    const auto *jobs = reinterpret_cast<const fdas_batch_job *>(ws + p.off_batch + p.batch_hdr);
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, st, counters, p.n_chunks);
     int dev = 0, cus = 256;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -409,7 +424,8 @@ hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes,
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>((int64_t)cus * 2, std::max<int64_t>(p.batch_tiles, 1));
     hipLaunchKernelGGL(correlate_mfma4096_batch<PT>, dim3((unsigned)grid), dim3(kThr), 0, st,
-                       static_cast<const float2 *>(spectra), jobs, p.batch_jobs, p.batch_tiles, counter,
+                       static_cast<const float2 *>(spectra), jobs, p.batch_jobs,
+                       (int32_t)(p.batch_tiles / p.n_chunks), counters,
                        reinterpret_cast<const uint32_t *>(ws + p.off_bank),
                        reinterpret_cast<const uint32_t *>(ws + p.off_tab), static_cast<PT *>(planes), p.M, p.V,
                        p.cfg.n_z, p.z_chunk, p.n_chunks);

@@ -8,14 +8,20 @@
 #include "mfma8192.hpp"
 
 namespace {
-
 thread_local int g_last_hip = 0;
+}  // namespace
 
-int hip_status(hipError_t e) {
+namespace fdas {
+int hip_status_of(hipError_t e) {
     if (e == hipSuccess) return FDAS_OK;
     g_last_hip = (int)e;
     return FDAS_E_HIP;
 }
+}  // namespace fdas
+
+namespace {
+
+int hip_status(hipError_t e) { return fdas::hip_status_of(e); }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -32,6 +38,7 @@ int elem_bytes(int dtype) {
         case FDAS_FP32: return 8;
         case FDAS_BF16: return 4;
         case FDAS_FP64: return 16;
+        case FDAS_FP8E4M3: return 2;
         default: return 0;
     }
 }
@@ -61,15 +68,15 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     if (!cfg || !out || !workspace_bytes) return FDAS_E_INVALID;
     *out = nullptr;
     const fdas_config c = *cfg;
-    if (c.compute == FDAS_FP8E4M3) return FDAS_E_UNSUPPORTED;
-    if (c.compute != FDAS_FP32 && c.compute != FDAS_BF16 && c.compute != FDAS_FP64) return FDAS_E_INVALID;
+    if (c.compute != FDAS_FP32 && c.compute != FDAS_BF16 && c.compute != FDAS_FP64 && c.compute != FDAS_FP8E4M3)
+        return FDAS_E_INVALID;
     if (c.n_z < 1 || c.max_bins < 1 || c.n_taps < 2 || (c.n_taps & 1) || c.n_taps > 4096) return FDAS_E_INVALID;
     if (!std::isfinite(c.z_min) || !std::isfinite(c.z_step)) return FDAS_E_INVALID;
     if (c.n_z > 1 && !(c.z_step > 0.0)) return FDAS_E_INVALID;
     if (c.z_chunk < 0) return FDAS_E_INVALID;
     if (c.algo < FDAS_ALGO_AUTO || c.algo > FDAS_ALGO_MFMA) return FDAS_E_INVALID;
     if (c.max_jobs < 0 || c.max_jobs > (1 << 24)) return FDAS_E_INVALID;
-    // plane dtype: FP64 compute writes FP64 only; FP32/BF16 compute write FP32 or BF16
+    // plane dtype: FP64 compute writes FP64 only; FP32/BF16/FP8 compute write FP32 or BF16
     if (c.compute == FDAS_FP64) {
         if (c.plane_dtype != FDAS_FP64) return FDAS_E_INVALID;
     } else if (c.plane_dtype != FDAS_FP32 && c.plane_dtype != FDAS_BF16) {
@@ -81,6 +88,8 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
             L = 4096;   // the 16x16x16 matrix-core kernel; overlap waste M / L <= 12.5 %
         } else if (c.compute == FDAS_BF16 && c.algo != FDAS_ALGO_VALU && c.n_taps <= 2048) {
             L = 8192;
+        } else if (c.compute == FDAS_FP8E4M3) {
+            L = 4096;   // the longest FP8 segment (three scaled stages)
         } else {
             L = int64_t(1) << ilog2(32 * (int64_t)c.n_taps);
             if (L < 1024) L = 1024;
@@ -91,6 +100,8 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     if (L < 1024 || L > 16384 || (L & (L - 1))) return FDAS_E_INVALID;
     if (c.n_taps >= L) return FDAS_E_INVALID;
     if (c.compute == FDAS_FP64 && L > 8192) return FDAS_E_UNSUPPORTED;
+    // FP8: vector-ALU kernel only, at most three radix-16 stages
+    if (c.compute == FDAS_FP8E4M3 && (L > 4096 || c.algo == FDAS_ALGO_MFMA)) return FDAS_E_UNSUPPORTED;
 
     fdas_plan_s *p = new (std::nothrow) fdas_plan_s();
     if (!p) return FDAS_E_INVALID;
@@ -135,10 +146,14 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     p->sz_scr = fdas::peak_scratch_bytes(p->peak_tile_cap);
     off = align_up(off + p->sz_scr, 256);
     p->off_tab = off;
-    p->sz_tab = !p->mfma ? 0 : (L == fdas::m8k::kL ? fdas::m8k::kTableBytes : fdas::m4k::kTableBytes);
+    if (c.compute == FDAS_FP8E4M3)   // FP32 staging of the bank, then one exponent per template
+        p->sz_tab = fdas::fp8_staging_bytes(*p) + (size_t)c.n_z * sizeof(int32_t);
+    else
+        p->sz_tab = !p->mfma ? 0 : (L == fdas::m8k::kL ? fdas::m8k::kTableBytes : fdas::m4k::kTableBytes);
     off = align_up(off + p->sz_tab, 256);
     p->off_batch = off;
-    p->sz_batch = c.max_jobs > 0 ? 256 + (size_t)c.max_jobs * sizeof(fdas_batch_job) : 0;
+    p->batch_hdr = align_up((size_t)p->n_chunks * sizeof(int32_t), 256);   // one counter per template chunk
+    p->sz_batch = c.max_jobs > 0 ? p->batch_hdr + (size_t)c.max_jobs * sizeof(fdas_batch_job) : 0;
     off = align_up(off + p->sz_batch, 256);
     p->ws_bytes = off;
     p->cfg.algo = p->mfma ? FDAS_ALGO_MFMA : FDAS_ALGO_VALU;
@@ -205,7 +220,11 @@ int fdas_correlate(fdas_plan_t p, const void *spectrum, int64_t n_bins, void *pl
 int fdas_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, float threshold, fdas_peak *out,
                int64_t capacity, int64_t *n_found, void *stream) {
     if (!p || !plane || !n_found || capacity < 0 || (capacity > 0 && !out)) return FDAS_E_INVALID;
-    if (!aligned16(plane) || (out && !aligned16(out)) || (reinterpret_cast<uintptr_t>(n_found) & 7u))
+    // the plane is read element by element: element alignment suffices (a
+    // job's plane inside a batch buffer starts anywhere)
+    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
+    if ((reinterpret_cast<uintptr_t>(plane) % pe) != 0 || (out && !aligned16(out)) ||
+        (reinterpret_cast<uintptr_t>(n_found) & 7u))
         return FDAS_E_INVALID;
     if (n_bins < 1 || n_bins > p->cfg.max_bins) return FDAS_E_INVALID;
     if (!p->ws) return FDAS_E_WORKSPACE;
@@ -220,26 +239,26 @@ int fdas_set_batch(fdas_plan_t p, const fdas_job *jobs, int32_t n_jobs, int64_t 
     p->batch_jobs = 0;
     if (n_jobs > p->cfg.max_jobs) return FDAS_E_INVALID;
     std::vector<fdas_batch_job> tab((size_t)n_jobs);
-    int64_t tiles = 0;
+    int64_t segs = 0;
     for (int32_t i = 0; i < n_jobs; ++i) {
         const fdas_job &j = jobs[i];
         if (j.n_bins < 1 || j.n_bins > p->cfg.max_bins || j.spec_off < 0 || j.plane_off < 0) return FDAS_E_INVALID;
         if (j.spec_off > spectra_bins - j.n_bins) return FDAS_E_INVALID;
         if (j.n_bins > (plane_cells - j.plane_off) / p->cfg.n_z || j.plane_off > plane_cells) return FDAS_E_INVALID;
-        tab[i] = {j.spec_off, j.n_bins, j.plane_off, tiles};
-        tiles += (j.n_bins + p->V - 1) / p->V * p->n_chunks;
-        // tile indices are 32-bit on the device, and the counter runs one past
-        // the last tile per workgroup
-        if (tiles > 0x7fffffffLL - (1 << 20)) return FDAS_E_INVALID;
+        tab[i] = {j.spec_off, j.n_bins, j.plane_off, segs};
+        segs += (j.n_bins + p->V - 1) / p->V;
+        // segment and tile indices are 32-bit on the device; each chunk's
+        // counter overshoots the segment count by at most one per workgroup
+        if (segs * p->n_chunks > 0x7fffffffLL - (1 << 20)) return FDAS_E_INVALID;
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(static_cast<unsigned char *>(p->ws) + p->off_batch + 256, tab.data(),
+    hipError_t e = hipMemcpyAsync(static_cast<unsigned char *>(p->ws) + p->off_batch + p->batch_hdr, tab.data(),
                                   tab.size() * sizeof(fdas_batch_job), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_status(e);
     p->batch_host = std::move(tab);
     p->batch_jobs = n_jobs;
-    p->batch_tiles = tiles;
+    p->batch_tiles = segs * p->n_chunks;
     return FDAS_OK;
 }
 

@@ -11,6 +11,9 @@
 
 namespace fdas {
 
+// FDAS_OK for hipSuccess, else FDAS_E_HIP with the code kept for fdas_last_hip_error.
+int hip_status_of(hipError_t e);
+
 constexpr int kPointsPerThread = 16;   // complex points each thread keeps in registers
 constexpr int kMinLog2L = 10;
 constexpr int kMaxLog2L = 14;
@@ -22,7 +25,7 @@ struct fdas_batch_job {
     int64_t spec_off;     // first bin of the job's spectrum in the spectra buffer
     int64_t n_bins;       // its length N
     int64_t plane_off;    // first cell of its n_z x N plane in the planes buffer
-    int64_t tile_base;    // index of its first (segment, template chunk) tile
+    int64_t seg_base;     // index of its first segment among all jobs' segments
 };
 
 struct fdas_plan_s {
@@ -38,7 +41,8 @@ struct fdas_plan_s {
     size_t off_scr = 0, sz_scr = 0;        // peak counters
     size_t off_tab = 0, sz_tab = 0;        // matrix-core operator/twiddle tables
     bool mfma = false;                     // matrix-core correlation kernel (L = 4096 or 8192)
-    size_t off_batch = 0, sz_batch = 0;    // batch counter (256 B) + job table
+    size_t off_batch = 0, sz_batch = 0;    // per-chunk segment counters (batch_hdr B) + job table
+    size_t batch_hdr = 0;
     int32_t batch_jobs = 0;                // jobs set by fdas_set_batch (0: none)
     int64_t batch_tiles = 0;
     std::vector<fdas_batch_job> batch_host;   // host copy of the job table
@@ -63,10 +67,17 @@ hipError_t launch_correlate_m4k(const fdas_plan_s &p, const void *spec, int64_t 
 
 hipError_t launch_correlate_m4k_batch(const fdas_plan_s &p, const void *spectra, void *planes, hipStream_t s);
 
-// Resets the batch tile counter (batch.hip); a kernel, so graph capture records no memset.
-__global__ void k_batch_reset(int32_t *counter);
+// Resets the n per-chunk segment counters of a batch (batch.hip); a kernel,
+// so graph capture records no memset.
+__global__ void k_batch_reset(int32_t *counters, int32_t n);
 
 // Correlation (correlate.hip).
+// FP8 (e4m3) form: bytes of the FP32 bank staging at the start of the tables
+// region (the per-template exponents follow it), the bank conversion and the
+// correlation.
+size_t fp8_staging_bytes(const fdas_plan_s &p);
+hipError_t launch_fp8_bank(const fdas_plan_s &p, hipStream_t st);
+hipError_t launch_correlate_fp8(const fdas_plan_s &p, const void *spec, int64_t n, void *plane, hipStream_t st);
 hipError_t launch_correlate(const fdas_plan_s &p, const void *spec, int64_t n,
                             void *plane, hipStream_t s);
 

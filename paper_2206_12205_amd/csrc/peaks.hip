@@ -10,11 +10,15 @@
 //
 // Deterministic three-kernel scheme with one tile = one plane row x
 // kPeakTileCols columns, tiles numbered in (z_idx, column block) order:
-//   count  every workgroup counts the peaks of its tile;
+//   count  every tile counts its peaks (a tile whose row has no cell above
+//          the threshold is settled by that one read);
 //   scan   one workgroup turns the counts into exclusive offsets and the total;
-//   write  every workgroup recomputes its peaks and writes them at its offset
+//   write  every tile with peaks recomputes them and writes them at its offset
 //          in column order, dropping those at or beyond the capacity.
+// Each workgroup of the count and write kernels takes 16 consecutive tiles.
 // The list is therefore sorted by (z_idx, r) with no sort pass.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace fdas {
@@ -39,16 +43,23 @@ __device__ __forceinline__ double plane_val<unsigned short>(const unsigned short
 
 // Stage rows z-1..z+1, columns c0-1 .. c0+kPeakTileCols into LDS (-inf outside
 // the plane) and flag this thread's kCellsPerThread consecutive cells.
+// Neighbourhood values are compared in the plane's own precision widened to
+// float (BF16, FP32: exact) or double (FP64); the threshold is a float.
 template <class PT>
-__device__ __forceinline__ int tile_flags(const PT *plane, int64_t n, int n_z, int z, int64_t c0, double thr,
-                                          double (*buf)[kPeakTileCols + 2], bool *flag) {
+using peak_val_t = typename std::conditional<sizeof(PT) == 8, double, float>::type;
+
+template <class PT>
+__device__ __forceinline__ int tile_flags(const PT *plane, int64_t n, int n_z, int z, int64_t c0, float thr_f,
+                                          peak_val_t<PT> (*buf)[kPeakTileCols + 2], bool *flag) {
+    using V = peak_val_t<PT>;
+    const V thr = (V)thr_f;
     for (int i = threadIdx.x; i < 3 * (kPeakTileCols + 2); i += kPeakThreads) {
         const int row = i / (kPeakTileCols + 2);
         const int col = i % (kPeakTileCols + 2);
         const int zz = z + row - 1;
         const int64_t cc = c0 + col - 1;
-        double v = -INFINITY;
-        if (zz >= 0 && zz < n_z && cc >= 0 && cc < n) v = plane_val<PT>(plane, (int64_t)zz * n + cc);
+        V v = -INFINITY;
+        if (zz >= 0 && zz < n_z && cc >= 0 && cc < n) v = (V)plane_val<PT>(plane, (int64_t)zz * n + cc);
         buf[row][col] = v;
     }
     __syncthreads();
@@ -57,7 +68,7 @@ __device__ __forceinline__ int tile_flags(const PT *plane, int64_t n, int n_z, i
     for (int q = 0; q < kCellsPerThread; ++q) {
         const int col = threadIdx.x * kCellsPerThread + q + 1;
         const int64_t cc = c0 + col - 1;
-        const double c = buf[1][col];
+        const V c = buf[1][col];
         bool ok = cc < n && c > thr;
         // preceding neighbours (strict), following neighbours (non-strict)
         ok = ok && c > buf[0][col - 1] && c > buf[0][col] && c > buf[0][col + 1] && c > buf[1][col - 1];
@@ -68,20 +79,58 @@ __device__ __forceinline__ int tile_flags(const PT *plane, int64_t n, int n_z, i
     return cnt;
 }
 
+// Does any of this thread's kCellsPerThread cells of row z exceed thr?  A
+// cheap pre-test: in a noise plane almost no tile holds a cell above the
+// threshold, and such tiles need no neighbourhood.  Same comparison as the
+// full test (values widened to double).
+template <class PT>
+__device__ __forceinline__ bool cells_above(const PT *plane, int64_t n, int z, int64_t c0, float thr) {
+    const PT *row = plane + (int64_t)z * n;
+    const int64_t c = c0 + (int64_t)threadIdx.x * kCellsPerThread;
+    bool any = false;
+    if (c + kCellsPerThread <= n && (reinterpret_cast<uintptr_t>(row + c) % (kCellsPerThread * sizeof(PT))) == 0) {
+        PT v[kCellsPerThread];
+        if constexpr (sizeof(PT) == 2) {
+            *reinterpret_cast<uint2 *>(v) = *reinterpret_cast<const uint2 *>(row + c);
+        } else if constexpr (sizeof(PT) == 4) {
+            *reinterpret_cast<uint4 *>(v) = *reinterpret_cast<const uint4 *>(row + c);
+        } else {
+#pragma unroll
+            for (int q = 0; q < kCellsPerThread; ++q) v[q] = row[c + q];
+        }
+#pragma unroll
+        for (int q = 0; q < kCellsPerThread; ++q) any |= plane_val<PT>(v, q) > (double)thr;
+    } else {
+        for (int q = 0; q < kCellsPerThread; ++q)
+            if (c + q < n) any |= plane_val<PT>(row, c + q) > (double)thr;
+    }
+    return any;
+}
+
+// Each workgroup takes kTilesPerBlock consecutive tiles.
+constexpr int kTilesPerBlock = 16;
+
 template <class PT>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, double thr, int32_t *counts) {
-    __shared__ double buf[3][kPeakTileCols + 2];
-    const int64_t tile = blockIdx.x;
-    const int z = (int)(tile / n_cb);
-    const int64_t c0 = (tile % n_cb) * kPeakTileCols;
+k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, int32_t *counts) {
+    __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
     __shared__ int sum;
-    if (threadIdx.x == 0) sum = 0;   // visible after the barrier inside tile_flags
-    bool flag[kCellsPerThread];
-    const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
-    if (cnt) atomicAdd(&sum, cnt);
-    __syncthreads();
-    if (threadIdx.x == 0) counts[tile] = sum;
+    for (int i = 0; i < kTilesPerBlock; ++i) {
+        const int64_t tile = (int64_t)blockIdx.x * kTilesPerBlock + i;
+        if (tile >= n_tiles) break;
+        const int z = (int)(tile / n_cb);
+        const int64_t c0 = (tile % n_cb) * kPeakTileCols;
+        if (!__syncthreads_or(cells_above<PT>(plane, n, z, c0, thr))) {
+            if (threadIdx.x == 0) counts[tile] = 0;
+            continue;
+        }
+        if (threadIdx.x == 0) sum = 0;   // visible after the barrier inside tile_flags
+        bool flag[kCellsPerThread];
+        const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
+        if (cnt) atomicAdd(&sum, cnt);
+        __syncthreads();
+        if (threadIdx.x == 0) counts[tile] = sum;
+    }
 }
 
 // Single workgroup: exclusive scan of counts -> offsets, total -> *n_found.
@@ -110,13 +159,12 @@ __global__ void __launch_bounds__(1024) k_peak_scan(const int32_t *counts, int64
     if (threadIdx.x == 1023) *n_found = part[1023];
 }
 
+// Recompute the flags of one tile that holds peaks and write them at the
+// tile's offset in column order, dropping those at or beyond the capacity.
 template <class PT>
-__global__ void __launch_bounds__(kPeakThreads)
-k_peak_write(const PT *plane, int64_t n, int n_z, int64_t n_cb, double thr, const int64_t *offsets,
-             fdas_peak *out, int64_t capacity) {
-    __shared__ double buf[3][kPeakTileCols + 2];
-    __shared__ int pre[kPeakThreads];
-    const int64_t tile = blockIdx.x;
+__device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t tile,
+                                           float thr, const int64_t *offsets, fdas_peak *out, int64_t capacity,
+                                           peak_val_t<PT> (*buf)[kPeakTileCols + 2], int *pre) {
     const int z = (int)(tile / n_cb);
     const int64_t c0 = (tile % n_cb) * kPeakTileCols;
     bool flag[kCellsPerThread];
@@ -147,6 +195,21 @@ k_peak_write(const PT *plane, int64_t n, int n_z, int64_t n_cb, double thr, cons
     }
 }
 
+template <class PT>
+__global__ void __launch_bounds__(kPeakThreads)
+k_peak_write(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, const int32_t *counts,
+             const int64_t *offsets, fdas_peak *out, int64_t capacity) {
+    __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
+    __shared__ int pre[kPeakThreads];
+    for (int i = 0; i < kTilesPerBlock; ++i) {
+        const int64_t tile = (int64_t)blockIdx.x * kTilesPerBlock + i;
+        if (tile >= n_tiles) break;
+        if (counts[tile] == 0) continue;   // uniform: no peak in this tile
+        write_tile<PT>(plane, n, n_z, n_cb, tile, thr, offsets, out, capacity, buf, pre);
+        __syncthreads();                   // buf and pre are reused by the next tile
+    }
+}
+
 namespace {
 template <class PT>
 hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, fdas_peak *out, int64_t cap,
@@ -157,11 +220,12 @@ hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, fdas
     unsigned char *scr = static_cast<unsigned char *>(p.ws) + p.off_scr;
     int64_t *offsets = reinterpret_cast<int64_t *>(scr);
     int32_t *counts = reinterpret_cast<int32_t *>(scr + (size_t)n_tiles * sizeof(int64_t));
-    hipLaunchKernelGGL(k_peak_count<PT>, dim3((unsigned)n_tiles), dim3(kPeakThreads), 0, st, plane, n,
-                       p.cfg.n_z, n_cb, (double)thr, counts);
+    const unsigned blocks = (unsigned)((n_tiles + kTilesPerBlock - 1) / kTilesPerBlock);
+    hipLaunchKernelGGL(k_peak_count<PT>, dim3(blocks), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb,
+                       n_tiles, thr, counts);
     hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, st, counts, offsets, n_tiles, n_found);
-    hipLaunchKernelGGL(k_peak_write<PT>, dim3((unsigned)n_tiles), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z,
-                       n_cb, (double)thr, offsets, out, cap);
+    hipLaunchKernelGGL(k_peak_write<PT>, dim3(blocks), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb,
+                       n_tiles, thr, counts, offsets, out, cap);
     return hipGetLastError();
 }
 }  // namespace

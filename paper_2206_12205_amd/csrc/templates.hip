@@ -221,6 +221,8 @@ hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st) {
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
         case FDAS_FP64: e = hipFuncSetAttribute((const void *)k_spectrum<cpx<double>>,
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
+        case FDAS_FP8E4M3: e = hipFuncSetAttribute((const void *)k_spectrum<cpx<float>>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); break;
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -243,6 +245,15 @@ hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st) {
                 hipLaunchKernelGGL(k_m4k_tables, dim3((nthreads + 255) / 256), dim3(256), 0, st,
                                    reinterpret_cast<uint32_t *>(ws + p.off_tab));
             }
+            hipLaunchKernelGGL(k_twiddles<float>, dim3((p.L + 255) / 256), dim3(256), 0, st,
+                               reinterpret_cast<cpx<float> *>(ws + p.off_tw), p.L);
+            break;
+        case FDAS_FP8E4M3:
+            // FP32 spectrum into the staging area, then per-template scaled e4m3
+            hipLaunchKernelGGL(k_spectrum<cpx<float>>, grid, dim3(256), lds, st, taps,
+                               reinterpret_cast<cpx<float> *>(ws + p.off_tab), p.M, p.L, 0);
+            e = launch_fp8_bank(p, st);
+            if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_twiddles<float>, dim3((p.L + 255) / 256), dim3(256), 0, st,
                                reinterpret_cast<cpx<float> *>(ws + p.off_tw), p.L);
             break;

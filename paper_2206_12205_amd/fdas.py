@@ -82,6 +82,9 @@ def lib() -> ctypes.CDLL:
         L.fdas_get_layout.argtypes = [P, ctypes.POINTER(FdasLayout)]
         L.fdas_make_templates.argtypes = [P, P]
         L.fdas_correlate.argtypes = [P, P, I64, P, P]
+        L.fdas_tune_workspace.argtypes = [ctypes.POINTER(FdasConfig), ctypes.POINTER(ctypes.c_size_t)]
+        L.fdas_tune.argtypes = [ctypes.POINTER(FdasConfig), P, I64, P, P, ctypes.c_size_t, I32,
+                                ctypes.POINTER(FdasConfig), ctypes.POINTER(ctypes.c_float), P]
         L.fdas_set_batch.argtypes = [P, ctypes.POINTER(FdasJob), I32, I64, I64, P]
         L.fdas_correlate_batch.argtypes = [P, P, P, P]
         L.fdas_peaks.argtypes = [P, P, I64, ctypes.c_float, P, I64, P, P]
@@ -257,8 +260,8 @@ class Plan:
                 "power": rec["power"].copy(), "n_found": found}
 
     def bank(self):
-        """Template bank as a complex tensor view (FP32/FP64) or raw uint16
-        pairs (BF16), shape (n_z, L[, 2])."""
+        """Template bank as a complex tensor view (FP32/FP64), raw bfloat16
+        pairs (BF16) or e4m3 code pairs (FP8), shape (n_z, L, 2)."""
         import torch
         L = self.seg_len
         b = self.workspace[self.layout.bank_offset:self.layout.bank_offset + self.layout.bank_bytes]
@@ -266,7 +269,39 @@ class Plan:
             return b.view(torch.float32).view(self.n_z, L, 2)
         if self.cfg.compute == FP64:
             return b.view(torch.float64).view(self.n_z, L, 2)
+        if self.cfg.compute == FP8E4M3:
+            return b.view(self.n_z, L, 2)          # e4m3 codes (re, im)
         return b.view(torch.int16).view(self.n_z, L, 2)
+
+    def fp8_exponents(self):
+        """Per-template power-of-two exponents t_j of the FP8 bank (bank = e4m3(H 2^t_j))."""
+        import torch
+        if self.cfg.compute != FP8E4M3:
+            raise ValueError("only FP8 plans have bank exponents")
+        off = self.layout.tables_offset + self.n_z * self.seg_len * 8
+        return self.workspace[off:off + 4 * self.n_z].view(torch.int32)
+
+
+def tune(spectrum, z_min, z_step, n_z, n_taps, compute="bf16", plane_dtype=None, max_bins=None,
+         seg_len=0, algo="auto", z_chunk=0, reps=5, stream=None):
+    """Measured choice of seg_len / algo / z_chunk (fdas_tune) on a device
+    spectrum; knobs given as non-zero are kept.  Returns a dict with the
+    chosen knobs and the mean launch time in ms."""
+    import torch
+    n = spectrum.numel()
+    cfg = make_config(max_bins or n, z_min, z_step, n_z, n_taps, seg_len, compute, plane_dtype, z_chunk, algo)
+    nbytes = ctypes.c_size_t()
+    _check(lib().fdas_tune_workspace(ctypes.byref(cfg), ctypes.byref(nbytes)), "fdas_tune_workspace")
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=spectrum.device)
+    pdt = {FP32: torch.float32, BF16: torch.bfloat16, FP64: torch.float64}[cfg.plane_dtype]
+    plane = torch.empty((int(n_z), n), dtype=pdt, device=spectrum.device)
+    best = FdasConfig()
+    ms = ctypes.c_float()
+    _check(lib().fdas_tune(ctypes.byref(cfg), ctypes.c_void_p(spectrum.data_ptr()), n,
+                           ctypes.c_void_p(plane.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nbytes.value,
+                           int(reps), ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)), "fdas_tune")
+    return {"seg_len": int(best.seg_len), "algo": {ALGO_VALU: "valu", ALGO_MFMA: "mfma"}[int(best.algo)],
+            "z_chunk": int(best.z_chunk), "ms": float(ms.value)}
 
 
 def _ptr(t):

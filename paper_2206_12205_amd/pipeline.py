@@ -1,0 +1,132 @@
+"""Batched acceleration search over many spectra (dedispersion trials).
+
+Orchestration only: every step runs in libfdas kernels through the C ABI.
+Spectra of uneven length share one template grid.  They are grouped into
+length classes (powers of two); each class gets the kernel configuration the
+autotuner (fdas_tune) measures fastest for its longest member, and its jobs
+are packed into chunks whose planes fit one reusable plane buffer.  A pass
+over the batch runs, per chunk, one persistent fdas_correlate_batch launch and
+the thresholded peak finder on every job's plane, so the full set of planes
+(tens of GB in BF16 for hundreds of trials) is never held at once.
+"""
+from __future__ import annotations
+
+import math
+
+from . import fdas as F
+
+
+class BatchSearch:
+    """Peaks of the f-fdot planes of a batch of packed spectra.
+
+    lengths      bins of each spectrum; spectra are packed back to back in a
+                 complex64 device tensor in this order
+    buffer_bytes size of the reused plane buffer
+    tune         measure the kernel configuration per length class (else the
+                 library's defaults)
+    """
+
+    def __init__(self, lengths, z_min, z_step, n_z, n_taps, compute="bf16", plane_dtype="bf16",
+                 buffer_bytes=8 << 30, tune=True, tune_reps=3, device="cuda:0", peak_capacity=1 << 12):
+        import torch
+        self.lengths = [int(v) for v in lengths]
+        if not self.lengths or min(self.lengths) < 1:
+            raise ValueError("every spectrum needs at least one bin")
+        self.n_z = int(n_z)
+        self.device = torch.device(device)
+        self.spec_off = [0]
+        for v in self.lengths[:-1]:
+            self.spec_off.append(self.spec_off[-1] + v)
+        self.total_bins = sum(self.lengths)
+        self.cells = self.n_z * self.total_bins
+        elem = {"bf16": 2, "fp32": 4, "fp64": 8}[plane_dtype]
+        self.plane_dtype = plane_dtype
+        self.peak_capacity = int(peak_capacity)
+        common = dict(z_min=z_min, z_step=z_step, n_z=n_z, n_taps=n_taps, compute=compute,
+                      plane_dtype=plane_dtype)
+        max_job = max(self.lengths)
+        if self.n_z * max_job * elem > buffer_bytes:
+            raise ValueError("the plane buffer cannot hold the longest spectrum's plane")
+        # length classes: ceil(log2(n))
+        classes = {}
+        for i, v in enumerate(self.lengths):
+            classes.setdefault(max(int(math.ceil(math.log2(v))), 0), []).append(i)
+        self.tuned = {}
+        self.chunks = []          # (plan, job indices, plane offsets in the buffer)
+        for cls in sorted(classes):
+            jobs = classes[cls]
+            cmax = max(self.lengths[i] for i in jobs)
+            knobs = dict(seg_len=0, algo="auto", z_chunk=0)
+            if tune:
+                # timed on one spectrum as long as the whole class (capped), so
+                # the candidate sees the amount of work of the class's launch
+                n_probe = min(sum(self.lengths[i] for i in jobs), max(cmax, 1 << 24))
+                probe = torch.randn(n_probe, dtype=torch.complex64, device=self.device,
+                                    generator=torch.Generator(device=self.device).manual_seed(cls))
+                t = F.tune(probe, max_bins=n_probe, reps=tune_reps, **common)
+                knobs = dict(seg_len=t["seg_len"], algo=t["algo"], z_chunk=t["z_chunk"])
+                self.tuned[cls] = t
+                del probe
+            # pack the class's jobs into buffer-sized chunks
+            cur, used = [], 0
+            for i in jobs:
+                need = self.n_z * self.lengths[i] * elem
+                if cur and used + need > buffer_bytes:
+                    self.chunks.append(self._chunk(cur, cmax, knobs, common))
+                    cur, used = [], 0
+                cur.append(i)
+                used += need
+            if cur:
+                self.chunks.append(self._chunk(cur, cmax, knobs, common))
+        cells_max = max(sum(self.n_z * self.lengths[i] for i in ch[1]) for ch in self.chunks)
+        self.buffer = torch.empty(cells_max, dtype=self.chunks[0][0].torch_plane_dtype(), device=self.device)
+        self.peaks_raw = torch.empty((len(self.lengths), self.peak_capacity, 24), dtype=torch.uint8,
+                                     device=self.device)
+        self.n_found = torch.zeros(len(self.lengths), dtype=torch.int64, device=self.device)
+
+    def _chunk(self, jobs, cmax, knobs, common):
+        pl = F.Plan(max_bins=cmax, max_jobs=len(jobs), device=self.device, **knobs, **common)
+        table = (F.FdasJob * len(jobs))()
+        po = 0
+        for k, i in enumerate(jobs):
+            table[k] = F.FdasJob(self.spec_off[i], self.lengths[i], po)
+            po += self.n_z * self.lengths[i]
+        F._check(F.lib().fdas_set_batch(pl._h, table, len(jobs), self.total_bins, po, F._stream_ptr(None)),
+                 "fdas_set_batch")
+        offs = []
+        po = 0
+        for i in jobs:
+            offs.append(po)
+            po += self.n_z * self.lengths[i]
+        return pl, list(jobs), offs
+
+    def run(self, spectra, threshold, stream=None, find_peaks=True):
+        """One pass: planes chunk by chunk into the buffer, peaks of every
+        job's plane into the per-job peak lists (asynchronous on stream).
+        find_peaks=False runs the correlations only (for timing)."""
+        import ctypes
+        import torch
+        if spectra.dtype != torch.complex64 or not spectra.is_contiguous() or spectra.numel() < self.total_bins:
+            raise ValueError("spectra must be a contiguous complex64 tensor holding every packed spectrum")
+        s = F._stream_ptr(stream)
+        L = F.lib()
+        esz = self.buffer.element_size()
+        for pl, jobs, offs in self.chunks:
+            F._check(L.fdas_correlate_batch(pl._h, ctypes.c_void_p(spectra.data_ptr()),
+                                            ctypes.c_void_p(self.buffer.data_ptr()), s), "fdas_correlate_batch")
+            for i, po in zip(jobs, offs) if find_peaks else ():
+                F._check(L.fdas_peaks(pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz), self.lengths[i],
+                                      float(threshold), ctypes.c_void_p(self.peaks_raw[i].data_ptr()),
+                                      self.peak_capacity, ctypes.c_void_p(self.n_found[i:i + 1].data_ptr()), s),
+                         "fdas_peaks")
+
+    def peaks(self, i):
+        """Peak list of job i after run() (host copy): dict of z_idx, r, power, n_found."""
+        import numpy as np
+        found = int(self.n_found[i].item())
+        k = min(found, self.peak_capacity)
+        raw = self.peaks_raw[i, :k].cpu().numpy()
+        rec = raw.view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
+                                 ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
+        return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(), "power": rec["power"].copy(),
+                "n_found": found}

@@ -50,7 +50,12 @@ def test_struct_sizes():
     (dict(max_bins=0), F.E_INVALID),
     (dict(z_step=0.0), F.E_INVALID),
     (dict(n_z=1, z_step=0.0), F.OK),         # a single template needs no step
-    (dict(compute="fp8"), F.E_UNSUPPORTED),
+    (dict(compute="fp8"), F.OK),
+    (dict(compute="fp8", seg_len=8192, n_taps=256), F.E_UNSUPPORTED),   # FP8: L <= 4096
+    (dict(compute="fp8", seg_len=4096, n_taps=256, algo="mfma"), F.E_UNSUPPORTED),
+    (dict(compute="fp8", plane_dtype="fp64"), F.E_INVALID),
+    (dict(compute="fp8", seg_len=0, n_taps=256), F.OK),
+    (dict(compute=7), F.E_INVALID),
     (dict(compute="fp64", plane_dtype="fp32"), F.E_INVALID),
     (dict(compute="fp32", plane_dtype="fp64"), F.E_INVALID),
     (dict(compute="fp64", seg_len=16384, n_taps=512), F.E_UNSUPPORTED),
@@ -167,5 +172,51 @@ def test_batch_argument_checks_on_host():
         assert L.fdas_set_workspace(h, ctypes.c_void_p(0x10000), n.value) == F.OK
         jobs = (F.FdasJob * 1)(F.FdasJob(0, 100, 0))
         assert L.fdas_set_batch(h, jobs, 1, 100, 500, None) == F.E_INVALID
+    finally:
+        L.fdas_destroy(h)
+
+
+def test_tune_argument_checks_on_host():
+    L = F.lib()
+    cfg = make(max_bins=4096, seg_len=0, n_taps=256, n_z=5, z_min=-4.0, compute="bf16")
+    n = ctypes.c_size_t()
+    assert L.fdas_tune_workspace(ctypes.byref(cfg), ctypes.byref(n)) == F.OK
+    # covers the largest candidate: L = 16384 on the vector-ALU kernel
+    big = make(max_bins=4096, seg_len=16384, n_taps=256, n_z=5, z_min=-4.0, compute="bf16", algo="valu")
+    assert n.value >= plan_status(big)[1] > 0
+    need = n.value
+    fixed = ctypes.c_size_t()
+    c4 = make(max_bins=4096, seg_len=4096, n_taps=256, n_z=5, z_min=-4.0, compute="bf16", algo="mfma", z_chunk=5)
+    assert L.fdas_tune_workspace(ctypes.byref(c4), ctypes.byref(fixed)) == F.OK
+    assert fixed.value == plan_status(c4)[1]
+    bad = make(n_z=0)
+    assert L.fdas_tune_workspace(ctypes.byref(bad), ctypes.byref(n)) == F.E_INVALID
+    assert L.fdas_tune_workspace(None, ctypes.byref(n)) == F.E_INVALID
+    c64 = make(compute="fp64", seg_len=16384, n_taps=512)
+    assert L.fdas_tune_workspace(ctypes.byref(c64), ctypes.byref(n)) == F.E_UNSUPPORTED
+    fake = ctypes.c_void_p(0x10000)
+    best = F.FdasConfig()
+    ms = ctypes.c_float()
+    args = lambda **kw: [ctypes.byref(kw.get("cfg", cfg)), fake, kw.get("nb", 100), fake, fake,
+                         kw.get("ws", 1 << 40), kw.get("reps", 3), ctypes.byref(best), ctypes.byref(ms), None]
+    assert L.fdas_tune(*args(reps=0)) == F.E_INVALID
+    assert L.fdas_tune(*args(reps=1001)) == F.E_INVALID
+    assert L.fdas_tune(*args(nb=0)) == F.E_INVALID
+    assert L.fdas_tune(*args(nb=4097)) == F.E_INVALID
+    assert L.fdas_tune(*args(ws=need - 1)) == F.E_WORKSPACE
+
+
+def test_fp8_layout_on_host():
+    L = F.lib()
+    cfg = make(max_bins=100000, seg_len=0, n_taps=256, n_z=9, z_min=-8.0, compute="fp8")
+    h = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    assert L.fdas_plan(ctypes.byref(cfg), ctypes.byref(h), ctypes.byref(n)) == F.OK
+    try:
+        lay = F.FdasLayout()
+        assert L.fdas_get_layout(h, ctypes.byref(lay)) == F.OK
+        assert lay.seg_len == 4096 and lay.algo == F.ALGO_VALU and lay.bank_elem_bytes == 2
+        assert lay.bank_bytes == 9 * 4096 * 2
+        assert lay.tables_bytes == 9 * 4096 * 8 + 9 * 4      # FP32 staging + exponents
     finally:
         L.fdas_destroy(h)

@@ -123,3 +123,29 @@ def test_bands_table3():
     mx = metrics.band_maxima(P, b)
     assert mx == [(2, 150, 5.0), (0, 151, 7.0), (0, 300, 7.0)]
     assert metrics.bin_match(mx, mx) == 1.0
+
+
+def test_e4m3_table_and_rounding():
+    """OCP e4m3fn: spot values of the format definition, round-trip of every
+    finite code, ties to even, subnormals, NaN."""
+    from oracle import casts as C
+    v = C.E4M3_TABLE
+    assert v[0x7E] == 448.0 and v[0x38] == 1.0 and v[0x40] == 2.0
+    assert v[0x08] == 2.0 ** -6 and v[0x01] == 2.0 ** -9 and v[0x00] == 0.0
+    assert np.isnan(v[0x7F]) and np.isnan(v[0xFF]) and v[0xB8] == -1.0
+    finite = [c for c in range(256) if not np.isnan(v[c]) and c != 0x80]
+    assert np.array_equal(C.e4m3_bits(v[finite]), np.array(finite, dtype=np.uint8))
+    # monotone over the non-negative codes
+    assert np.all(np.diff(v[:0x7F]) > 0)
+    # ties to even: 1 + 1/16 lies between codes 0x38 (1.0) and 0x39 (1.125)
+    assert C.e4m3_bits(1.0625) == 0x38 and C.e4m3_bits(1.1875) == 0x3A
+    assert C.e4m3_bits(1.0626) == 0x39 and C.e4m3_bits(-1.0625) == 0xB8
+    # subnormal ties: 1.5 * 2^-9 lies between 0x01 and 0x02 -> 0x02 (even)
+    assert C.e4m3_bits(1.5 * 2.0 ** -9) == 0x02 and C.e4m3_bits(0.5 * 2.0 ** -9) == 0x00
+    assert C.e4m3_bits(460.0) == 0x7E and C.e4m3_bits(464.0) == 0x7F
+    assert C.e4m3_bits(float("nan")) == 0x7F
+    # nearest: relative error at most 2^-4 over the normal range
+    g = np.random.default_rng(3)
+    x = np.exp(g.uniform(np.log(2.0 ** -6), np.log(448.0), 2000))
+    r = C.to_e4m3(x)
+    assert np.max(np.abs(r - x) / x) <= 2.0 ** -4 + 1e-15
