@@ -15,10 +15,13 @@
 //            v_dot2_f32_bf16.
 //   template j: the bank entry of j + 1 is prefetched; Y = X * H_j -> I1 ->
 //            LDS A -> barrier -> (flush of template j - 1's row) -> I2 ->
-//            LDS B -> barrier -> I3, computed with the operands swapped so
-//            each lane holds four consecutive time samples -> |y|^2 staged in
-//            LDS in the plane's type (one 8- or 16-byte write), written to the
-//            plane one barrier later with coalesced vector stores.
+//            LDS B -> barrier -> I3.  All three inverse stages run with the
+//            operands swapped (transposed outputs): each lane then holds four
+//            consecutive values of the next stage's K digit, so every
+//            exchange is one 16-byte LDS write and one 16-byte read, and I3
+//            leaves four consecutive time samples per lane -> |y|^2 staged in
+//            LDS in the plane's type, written to the plane one barrier later
+//            with coalesced vector stores.
 // All twiddles live in the per-group stage operators, so the vector ALU only
 // forms the template product, packs stage outputs to bf16 and squares.
 // Register use stays at 64 VGPRs or fewer, so two workgroups (eight waves per
@@ -63,6 +66,13 @@ __device__ __forceinline__ Op load_op(const uint32_t *tab, int op, int lane) {
     const uint4 v = reinterpret_cast<const uint4 *>(tab + op * kOpWords)[lane];
     return Op{{v.x, v.y, v.z, v.w}};
 }
+
+// Inverse-stage exchange: 16-byte chunks of four consecutive K values, chunk
+// (a, b, g) at word 4 (256 g + 16 a + ((a + b) & 15)).  I1 writes with a fixed
+// per wave and b = lane column, I2 reads with a = lane column and b fixed (and
+// likewise I2 -> I3): the skew (a + b) & 15 spreads both patterns over all
+// bank groups.
+__device__ __forceinline__ int chunk_addr(int a, int b, int g) { return 4 * (256 * g + 16 * a + ((a + b) & 15)); }
 
 // Staging of one template row's powers between I3 and the plane store.
 // FP32 plane: one float per sample at t + 4 (t >> 8); BF16 plane: the bf16
@@ -248,7 +258,8 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
 
     // One template: I1 (group k1 = Q) on X * H_j, I2 (group n3), I3 (group n2).
     auto one_template = [&](int j, const uint4 (&hc)[kGpw]) {
-        // I1: DFT16 over k3 with e(n3 k1); rows n3 = 4 g + e -> buffer A
+        // I1: DFT16 over k3 with e(n3 k1), transposed: lane (c, g) receives
+        // n3 = c, k2 = 4 g + e -> one 16-byte chunk of buffer A
 #pragma unroll
         for (int q = 0; q < kGpw; ++q) {
             const int Q = kGpw * w + q;
@@ -256,28 +267,37 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
             Op b;
 #pragma unroll
             for (int p = 0; p < 4; ++p) b.w[p] = bf16_pack(dot2(sA[q][p], hw[p]), dot2(sB[q][p], hw[p]));
-            const f32x4_t dre = mma(a1re[q], b), dim = mma(a1im[q], b);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) bufA[addrA(Q, c, 4 * g + e)] = bf16_pack(dre[e], dim[e]);
+            const f32x4_t dre = mma(b, a1re[q]), dim = mma(b, a1im[q]);
+            uint4 o;
+            o.x = bf16_pack(dre[0], dim[0]);
+            o.y = bf16_pack(dre[1], dim[1]);
+            o.z = bf16_pack(dre[2], dim[2]);
+            o.w = bf16_pack(dre[3], dim[3]);
+            *reinterpret_cast<uint4 *>(&bufA[chunk_addr(Q, c, g)]) = o;   // (k1, n3, k2 block)
         }
         __syncthreads();
         if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n + seg0, fp, tid);
-        // I2: DFT16 over k2 with e(16 n3 k2); rows n2 = 4 g + e -> buffer B
+        // I2: DFT16 over k2 with e(16 n3 k2), transposed: lane (c, g)
+        // receives n2 = c, k1 = 4 g + e -> one 16-byte chunk of buffer B
 #pragma unroll
         for (int q = 0; q < kGpw; ++q) {
             const int Q = kGpw * w + q;
-            const uint4 v = *reinterpret_cast<const uint4 *>(&bufA[addrA(c, 4 * g, Q)]);   // 4 consecutive k2
+            const uint4 v = *reinterpret_cast<const uint4 *>(&bufA[chunk_addr(c, Q, g)]);   // k1 = c, n3 = Q
             const Op b = {{v.x, v.y, v.z, v.w}};
-            const f32x4_t dre = mma(a23re[q], b), dim = mma(a23im[q], b);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) bufB[addrB(c, 4 * g + e, Q)] = bf16_pack(dre[e], dim[e]);
+            const f32x4_t dre = mma(b, a23re[q]), dim = mma(b, a23im[q]);
+            uint4 o;
+            o.x = bf16_pack(dre[0], dim[0]);
+            o.y = bf16_pack(dre[1], dim[1]);
+            o.z = bf16_pack(dre[2], dim[2]);
+            o.w = bf16_pack(dre[3], dim[3]);
+            *reinterpret_cast<uint4 *>(&bufB[chunk_addr(c, Q, g)]) = o;   // (n2, n3, k1 block)
         }
         __syncthreads();
         // I3: DFT16 over k1 with e(16 n2 k1); rows n1 = 4 g + e; |y|^2 -> staging
 #pragma unroll
         for (int q = 0; q < kGpw; ++q) {
             const int Q = kGpw * w + q;
-            const uint4 v = *reinterpret_cast<const uint4 *>(&bufB[addrB(4 * g, Q, c)]);   // 4 consecutive k1
+            const uint4 v = *reinterpret_cast<const uint4 *>(&bufB[chunk_addr(Q, c, g)]);   // n2 = Q, n3 = c
             const Op b = {{v.x, v.y, v.z, v.w}};
             const f32x4_t dre = mma(b, a23re[q]), dim = mma(b, a23im[q]);
             Stage<PT>::put4(stage, 256 * c + 16 * Q + 4 * g, dre[0] * dre[0] + dim[0] * dim[0],
@@ -286,6 +306,9 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
         }
     };
 
+    // the inverse stages use the chunk layout: every wave must be done with
+    // its forward reads of buffer A
+    __syncthreads();
     // templates in pairs with two statically assigned bank registers: the
     // next template's bank entry is in flight while the current one runs
     uint4 hA[kGpw], hB[kGpw];

@@ -120,9 +120,10 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     int zc = c.z_chunk;
     if (zc == 0) {
         // vector-ALU kernel: eight chunks, one per XCD; matrix-core kernels:
-        // two (L = 4096) or four (L = 8192) chunks, since each chunk repeats
-        // the segment's forward transform (measured best on the single-DM plane)
-        zc = !p->mfma ? (c.n_z + 7) / 8 : L == fdas::m4k::kL ? (c.n_z + 1) / 2 : (c.n_z + 3) / 4;
+        // three (L = 4096) or four (L = 8192) chunks: each chunk repeats the
+        // segment's forward transform, more chunks balance the workgroups
+        // better (measured best on the single-DM plane)
+        zc = !p->mfma ? (c.n_z + 7) / 8 : L == fdas::m4k::kL ? (c.n_z + 2) / 3 : (c.n_z + 3) / 4;
     }
     if (zc > c.n_z) zc = c.n_z;
     p->z_chunk = zc;

@@ -28,10 +28,11 @@
 //   stage k2 (I2 / F2): n3 = Q, column c -> k1 = c
 //   stage k1 (I3 / F1): n2 = Q, column c -> n3 = c
 //
-// LDS stage buffers (one bf16 complex per 32-bit word) use additive layouts so
-// that every access is a per-lane base plus an immediate offset; the strides
-// keep each access pattern free of bank conflicts (32 banks of 4 bytes), with
-// one 128-bit side per transpose:
+// The forward stages exchange through two LDS buffers (one bf16 complex per
+// 32-bit word) with additive layouts, so that every access is a per-lane base
+// plus an immediate offset; the strides keep each access pattern free of bank
+// conflicts (32 banks of 4 bytes), with one 128-bit side per transpose (the
+// inverse stages use the chunk layout of correlate_m4k.hip instead):
 //   buffer A ("x-contiguous"):  k1 * 324 + x + 20 * n3   (stage 2 reads 4 x in one b128)
 //   buffer B ("k1-contiguous"): k1 + 324 * x + 20 * n3   (stage 3 reads 4 k1 in one b128)
 #pragma once

@@ -1,9 +1,9 @@
 """GPU checks of the FP8 (OCP e4m3) precision form.
 
-Bars.  The bank must equal the oracle's e4m3 codes of the FP32-rounded
-template spectra scaled by the same power of two (codes may differ by one in
-rare cases where the GPU's and the oracle's FP64 spectra round to different
-FP32 values).  The plane is held against the FP64 oracle with bars from the
+Bars.  The bank must hold the oracle's e4m3 values of the FP32-rounded
+template spectra scaled by the same power of two (one e4m3 step apart in rare
+cases where the GPU's and the oracle's FP64 spectra round to different FP32
+values; the sign of an exact zero is not compared).  The plane is held against the FP64 oracle with bars from the
 e4m3 rounding: each rounding is at most 2^-4 of the value; along the path
 there are six (two forward stages, the segment spectrum, the template, two
 inverse stages) with power-of-two scales set from each stage's largest
@@ -37,9 +37,6 @@ def plan(dev, **kw):
     return Plan(device=dev, **kw)
 
 
-@pytest.mark.xfail(strict=False, reason="1.5 % of the L = 1024 e4m3 codes differ by one code from the "
-                                       "oracle's; the hardware conversion itself matches the oracle on "
-                                       "ties, subnormals and midpoints, the cause is being traced")
 def test_fp8_bank_matches_oracle(dev):
     import torch
     say("[fp8] bank")
@@ -56,8 +53,14 @@ def test_fp8_bank_matches_oracle(dev):
         t_ref = np.floor(np.log2(448.0 / hmax)).astype(np.int64)
         assert np.array_equal(texp, t_ref)
         want = casts.e4m3_bits(h32 * np.ldexp(1.0, t_ref)[:, None, None])
-        d = codes.astype(np.int64) - want.astype(np.int64)
-        assert np.abs(d).max() <= 1 and np.mean(d != 0) < 1e-3, f"L={L}: {np.mean(d != 0)}"
+        # compare values, not codes: +0 and -0 are the same value (the z = 0
+        # template's imaginary parts are exact zeros on the GPU and +-1e-17
+        # rounding noise in the oracle's FFT)
+        got_v, want_v = casts.e4m3_decode(codes), casts.e4m3_decode(want)
+        step = np.spacing(np.maximum(np.abs(want_v), 2.0 ** -6).astype(np.float32)) * 2.0 ** 20   # one e4m3 step
+        d = np.abs(got_v - want_v)
+        assert np.all(d <= step), f"L={L}: {d.max()}"
+        assert np.mean(d != 0) < 1e-3, f"L={L}: {np.mean(d != 0)}"
 
 
 def fp8_plane_vs_oracle(dev, x, zmin, zstep, nz, M, L, pd="fp32"):
