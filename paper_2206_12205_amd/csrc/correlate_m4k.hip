@@ -166,13 +166,21 @@ __device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const 
 // One tile: segment s of the spectrum (n bins) against templates [j0, j1),
 // writing plane rows j0 .. j1 - 1 (row stride n).  Called by the whole
 // workgroup; contains barriers.
-template <class PT>
+template <class PT, bool kOpaqueLane = false>
 __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_t n, const uint32_t *__restrict__ bank,
                                          const uint32_t *__restrict__ tab, PT *__restrict__ plane, int32_t M,
                                          int32_t V, int64_t s, int j0, int j1, uint32_t *bufA, uint32_t *bufB,
                                          uint32_t *stage) {
-    const int tid = threadIdx.x;
-    const int w = tid >> 6, lane = tid & 63, c = lane & 15, g = lane >> 4;
+    int tid = (int)threadIdx.x, w = tid >> 6, lane = tid & 63;
+    if constexpr (kOpaqueLane) {
+        // per-tile copies the compiler cannot prove loop-invariant, so that a
+        // persistent caller does not keep every lane address live across tiles
+        w = __builtin_amdgcn_readfirstlane(w);
+        asm volatile("" : "+s"(w));
+        asm volatile("" : "+v"(lane));
+        tid = 64 * w + lane;
+    }
+    const int c = lane & 15, g = lane >> 4;
     const int half = M / 2;
     const int64_t seg0 = s * (int64_t)V - half;   // plane column of time index t is seg0 + t
     // ---------------- forward transform ----------------
@@ -331,17 +339,6 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
     flush<PT>(stage, plane + (int64_t)(j1 - 1) * n + seg0, fp, tid);
 }
 
-// Out-of-line copy for the persistent kernel: inlined into its tile loop the
-// body spills; called, it keeps every value in registers (the call saves a few
-// registers once per tile).
-template <class PT>
-__device__ __noinline__ void m4k_tile_call(const float2 *__restrict__ spec, int64_t n,
-                                           const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
-                                           PT *__restrict__ plane, int32_t M, int32_t V, int64_t s, int j0, int j1,
-                                           uint32_t *bufA, uint32_t *bufB, uint32_t *stage) {
-    m4k_tile<PT>(spec, n, bank, tab, plane, M, V, s, j0, j1, bufA, bufB, stage);
-}
-
 #define M4K_ATTR __attribute__((amdgpu_flat_work_group_size(kThr, kThr), amdgpu_waves_per_eu(kWavesPerEU)))
 
 // One spectrum: workgroup b takes template chunk b mod n_chunks of segment b / n_chunks.
@@ -416,8 +413,8 @@ __global__ void M4K_ATTR correlate_mfma4096_batch(const float2 *__restrict__ spe
         // they are not hoisted out and held in registers across tiles
         int opaque = 0;
         asm volatile("" : "+s"(opaque));
-        m4k_tile_call<PT>(spectra + spec_off + opaque, nb, bank + opaque, tab + opaque, planes + plane_off + opaque, M,
-                          V + opaque, s, j0, j1, bufA, bufB, stage);
+        m4k_tile<PT, true>(spectra + spec_off + opaque, nb, bank + opaque, tab + opaque, planes + plane_off + opaque,
+                           M, V + opaque, s, j0, j1, bufA, bufB, stage);
     }
 }
 

@@ -12,7 +12,8 @@
 // kPeakTileCols columns, tiles numbered in (z_idx, column block) order:
 //   count  every tile counts its peaks (a tile whose row has no cell above
 //          the threshold is settled by that one read);
-//   scan   one workgroup turns the counts into exclusive offsets and the total;
+//   scan   one workgroup turns the per-workgroup totals into exclusive offsets
+//          and the total;
 //   write  every tile with peaks recomputes them and writes them at its offset
 //          in column order, dropping those at or beyond the capacity.
 // Each workgroup of the count and write kernels takes 16 consecutive tiles.
@@ -112,15 +113,62 @@ constexpr int kTilesPerBlock = 16;
 
 template <class PT>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, int32_t *counts) {
+k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, int32_t *counts,
+             int32_t *block_counts) {
     __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
     __shared__ int sum;
+    __shared__ unsigned int s_mask;
+    // Pre-test of all the workgroup's tiles first, so that their loads are in
+    // flight together: bit i of mask = tile i has a cell above the threshold.
+    const int64_t t0 = (int64_t)blockIdx.x * kTilesPerBlock;
+    const int z0 = (int)(t0 / n_cb);
+    const int64_t cb0 = t0 % n_cb;
+    const PT *row0 = plane + (int64_t)z0 * n + cb0 * kPeakTileCols;
+    unsigned int mine = 0;
+    if (t0 + kTilesPerBlock <= n_tiles && (cb0 + kTilesPerBlock) * kPeakTileCols <= n &&
+        (reinterpret_cast<uintptr_t>(row0) % (kCellsPerThread * sizeof(PT))) == 0) {
+        // all tiles full and in one row: unconditional loads
+        PT v[kTilesPerBlock][kCellsPerThread];
+#pragma unroll
+        for (int i = 0; i < kTilesPerBlock; ++i) {
+            const PT *src = row0 + i * kPeakTileCols + threadIdx.x * kCellsPerThread;
+            if constexpr (sizeof(PT) == 2) {
+                *reinterpret_cast<uint2 *>(v[i]) = *reinterpret_cast<const uint2 *>(src);
+            } else if constexpr (sizeof(PT) == 4) {
+                *reinterpret_cast<uint4 *>(v[i]) = *reinterpret_cast<const uint4 *>(src);
+            } else {
+#pragma unroll
+                for (int q = 0; q < kCellsPerThread; ++q) v[i][q] = src[q];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kTilesPerBlock; ++i) {
+            bool any = false;
+#pragma unroll
+            for (int q = 0; q < kCellsPerThread; ++q) any |= plane_val<PT>(v[i], q) > (double)thr;
+            mine |= any ? 1u << i : 0u;
+        }
+    } else {
+        for (int i = 0; i < kTilesPerBlock; ++i) {
+            const int64_t tile = t0 + i;
+            if (tile >= n_tiles) break;
+            if (cells_above<PT>(plane, n, (int)(tile / n_cb), (tile % n_cb) * kPeakTileCols, thr)) mine |= 1u << i;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mine |= (unsigned int)__shfl_xor((int)mine, o, 64);
+    if (threadIdx.x == 0) s_mask = 0u;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0 && mine) atomicOr(&s_mask, mine);
+    __syncthreads();
+    const unsigned int mask = s_mask;
+    int total = 0;   // thread 0: peaks of this workgroup's tiles
     for (int i = 0; i < kTilesPerBlock; ++i) {
-        const int64_t tile = (int64_t)blockIdx.x * kTilesPerBlock + i;
+        const int64_t tile = t0 + i;
         if (tile >= n_tiles) break;
         const int z = (int)(tile / n_cb);
         const int64_t c0 = (tile % n_cb) * kPeakTileCols;
-        if (!__syncthreads_or(cells_above<PT>(plane, n, z, c0, thr))) {
+        if (!((mask >> i) & 1u)) {
             if (threadIdx.x == 0) counts[tile] = 0;
             continue;
         }
@@ -129,11 +177,16 @@ k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles,
         const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
         if (cnt) atomicAdd(&sum, cnt);
         __syncthreads();
-        if (threadIdx.x == 0) counts[tile] = sum;
+        if (threadIdx.x == 0) {
+            counts[tile] = sum;
+            total += sum;
+        }
     }
+    if (threadIdx.x == 0) block_counts[blockIdx.x] = total;
 }
 
-// Single workgroup: exclusive scan of counts -> offsets, total -> *n_found.
+// Single workgroup: exclusive scan of the per-workgroup totals -> offsets,
+// total -> *n_found (kTilesPerBlock times fewer entries than tiles).
 __global__ void __launch_bounds__(1024) k_peak_scan(const int32_t *counts, int64_t *offsets, int64_t n_tiles,
                                                     int64_t *n_found) {
     __shared__ int64_t part[1024];
@@ -163,7 +216,7 @@ __global__ void __launch_bounds__(1024) k_peak_scan(const int32_t *counts, int64
 // tile's offset in column order, dropping those at or beyond the capacity.
 template <class PT>
 __device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t tile,
-                                           float thr, const int64_t *offsets, fdas_peak *out, int64_t capacity,
+                                           float thr, int64_t tile_off, fdas_peak *out, int64_t capacity,
                                            peak_val_t<PT> (*buf)[kPeakTileCols + 2], int *pre) {
     const int z = (int)(tile / n_cb);
     const int64_t c0 = (tile % n_cb) * kPeakTileCols;
@@ -177,7 +230,7 @@ __device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, 
         pre[threadIdx.x] += v;
         __syncthreads();
     }
-    int64_t pos = offsets[tile] + pre[threadIdx.x] - cnt;
+    int64_t pos = tile_off + pre[threadIdx.x] - cnt;
 #pragma unroll
     for (int q = 0; q < kCellsPerThread; ++q) {
         if (!flag[q]) continue;
@@ -198,14 +251,17 @@ __device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, 
 template <class PT>
 __global__ void __launch_bounds__(kPeakThreads)
 k_peak_write(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, const int32_t *counts,
-             const int64_t *offsets, fdas_peak *out, int64_t capacity) {
+             const int64_t *block_offsets, fdas_peak *out, int64_t capacity) {
     __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
     __shared__ int pre[kPeakThreads];
+    int64_t off = block_offsets[blockIdx.x];
     for (int i = 0; i < kTilesPerBlock; ++i) {
         const int64_t tile = (int64_t)blockIdx.x * kTilesPerBlock + i;
         if (tile >= n_tiles) break;
-        if (counts[tile] == 0) continue;   // uniform: no peak in this tile
-        write_tile<PT>(plane, n, n_z, n_cb, tile, thr, offsets, out, capacity, buf, pre);
+        const int cnt = counts[tile];
+        if (cnt == 0) continue;            // uniform: no peak in this tile
+        write_tile<PT>(plane, n, n_z, n_cb, tile, thr, off, out, capacity, buf, pre);
+        off += cnt;
         __syncthreads();                   // buf and pre are reused by the next tile
     }
 }
@@ -218,12 +274,14 @@ hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, fdas
     const int64_t n_tiles = n_cb * p.cfg.n_z;
     if (n_tiles > p.peak_tile_cap || n_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
     unsigned char *scr = static_cast<unsigned char *>(p.ws) + p.off_scr;
-    int64_t *offsets = reinterpret_cast<int64_t *>(scr);
-    int32_t *counts = reinterpret_cast<int32_t *>(scr + (size_t)n_tiles * sizeof(int64_t));
-    const unsigned blocks = (unsigned)((n_tiles + kTilesPerBlock - 1) / kTilesPerBlock);
+    const int64_t n_blocks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
+    int64_t *offsets = reinterpret_cast<int64_t *>(scr);                           // per workgroup
+    int32_t *counts = reinterpret_cast<int32_t *>(scr + (size_t)n_blocks * sizeof(int64_t));   // per tile
+    int32_t *block_counts = counts + n_tiles;                                       // per workgroup
+    const unsigned blocks = (unsigned)n_blocks;
     hipLaunchKernelGGL(k_peak_count<PT>, dim3(blocks), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb,
-                       n_tiles, thr, counts);
-    hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, st, counts, offsets, n_tiles, n_found);
+                       n_tiles, thr, counts, block_counts);
+    hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, st, block_counts, offsets, n_blocks, n_found);
     hipLaunchKernelGGL(k_peak_write<PT>, dim3(blocks), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb,
                        n_tiles, thr, counts, offsets, out, cap);
     return hipGetLastError();
