@@ -10,14 +10,16 @@
 //
 // Deterministic three-kernel scheme with one tile = one plane row x
 // kPeakTileCols columns, tiles numbered in (z_idx, column block) order:
-//   count  every tile counts its peaks (a tile whose row has no cell above
-//          the threshold is settled by that one read);
+//   mark   one streaming pass flags the tiles that hold a cell above the
+//          threshold;
+//   count  every flagged tile counts its peaks (unflagged tiles count zero);
 //   scan   one workgroup turns the per-workgroup totals into exclusive offsets
 //          and the total;
 //   write  every tile with peaks recomputes them and writes them at its offset
 //          in column order, dropping those at or beyond the capacity.
 // Each workgroup of the count and write kernels takes 16 consecutive tiles.
 // The list is therefore sorted by (z_idx, r) with no sort pass.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -27,6 +29,8 @@ namespace fdas {
 constexpr int kPeakThreads = 256;
 constexpr int kCellsPerThread = kPeakTileCols / kPeakThreads;   // 4
 
+// offsets (int64) and totals (int32) per workgroup of 16 tiles, counts
+// (int32) and flags (uint8) per tile
 size_t peak_scratch_bytes(int64_t n_tiles) {
     return (size_t)n_tiles * (sizeof(int32_t) + sizeof(int64_t)) + 256;
 }
@@ -80,95 +84,73 @@ __device__ __forceinline__ int tile_flags(const PT *plane, int64_t n, int n_z, i
     return cnt;
 }
 
-// Does any of this thread's kCellsPerThread cells of row z exceed thr?  A
-// cheap pre-test: in a noise plane almost no tile holds a cell above the
-// threshold, and such tiles need no neighbourhood.  Same comparison as the
-// full test (values widened to double).
-template <class PT>
-__device__ __forceinline__ bool cells_above(const PT *plane, int64_t n, int z, int64_t c0, float thr) {
-    const PT *row = plane + (int64_t)z * n;
-    const int64_t c = c0 + (int64_t)threadIdx.x * kCellsPerThread;
-    bool any = false;
-    if (c + kCellsPerThread <= n && (reinterpret_cast<uintptr_t>(row + c) % (kCellsPerThread * sizeof(PT))) == 0) {
-        PT v[kCellsPerThread];
-        if constexpr (sizeof(PT) == 2) {
-            *reinterpret_cast<uint2 *>(v) = *reinterpret_cast<const uint2 *>(row + c);
-        } else if constexpr (sizeof(PT) == 4) {
-            *reinterpret_cast<uint4 *>(v) = *reinterpret_cast<const uint4 *>(row + c);
-        } else {
-#pragma unroll
-            for (int q = 0; q < kCellsPerThread; ++q) v[q] = row[c + q];
-        }
-#pragma unroll
-        for (int q = 0; q < kCellsPerThread; ++q) any |= plane_val<PT>(v, q) > (double)thr;
-    } else {
-        for (int q = 0; q < kCellsPerThread; ++q)
-            if (c + q < n) any |= plane_val<PT>(row, c + q) > (double)thr;
-    }
-    return any;
-}
-
 // Each workgroup takes kTilesPerBlock consecutive tiles.
 constexpr int kTilesPerBlock = 16;
 
+// Tile flags: flag[tile] = 1 iff the tile's row segment holds a cell above
+// the threshold (only such tiles can hold a peak).  k_peak_mark streams the
+// whole plane as one flat array in 16-byte vectors (any alignment of the
+// plane pointer: a head and a tail of single cells), so the common empty
+// tile costs one read of its cells and no neighbourhood.  k_peak_clear
+// zeroes the flags at the start of every call (a kernel, not a memset, so
+// the call can be captured in a graph).
+__global__ void k_peak_clear(uint8_t *flags, int64_t n_tiles) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_tiles; i += (int64_t)gridDim.x * blockDim.x)
+        flags[i] = 0;
+}
+
 template <class PT>
-__global__ void __launch_bounds__(kPeakThreads)
-k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, int32_t *counts,
-             int32_t *block_counts) {
-    __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
-    __shared__ int sum;
-    __shared__ unsigned int s_mask;
-    // Pre-test of all the workgroup's tiles first, so that their loads are in
-    // flight together: bit i of mask = tile i has a cell above the threshold.
-    const int64_t t0 = (int64_t)blockIdx.x * kTilesPerBlock;
-    const int z0 = (int)(t0 / n_cb);
-    const int64_t cb0 = t0 % n_cb;
-    const PT *row0 = plane + (int64_t)z0 * n + cb0 * kPeakTileCols;
-    unsigned int mine = 0;
-    if (t0 + kTilesPerBlock <= n_tiles && (cb0 + kTilesPerBlock) * kPeakTileCols <= n &&
-        (reinterpret_cast<uintptr_t>(row0) % (kCellsPerThread * sizeof(PT))) == 0) {
-        // all tiles full and in one row: unconditional loads
-        PT v[kTilesPerBlock][kCellsPerThread];
+__device__ __forceinline__ void mark_cell(const PT *plane, int64_t f, int64_t n, int64_t n_cb, double thr,
+                                          uint8_t *flags) {
+    if (plane_val<PT>(plane, f) > thr) {
+        const int64_t z = f / n, col = f - z * n;
+        flags[z * n_cb + col / kPeakTileCols] = 1;
+    }
+}
+
+template <class PT>
+__global__ void __launch_bounds__(256) k_peak_mark(const PT *plane, int64_t n, int64_t total, int64_t n_cb, float thr_f,
+                                                   uint8_t *flags) {
+    constexpr int kVec = 16 / sizeof(PT);   // cells per 16-byte vector
+    const double thr = (double)thr_f;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(plane);
+    int64_t head = (int64_t)(((16 - (addr & 15)) & 15) / sizeof(PT));
+    if (head > total) head = total;
+    const int64_t n_vec = (total - head) / kVec;
+    const int64_t tail0 = head + n_vec * kVec;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (gid < head) mark_cell<PT>(plane, gid, n, n_cb, thr, flags);
+    if (gid < total - tail0) mark_cell<PT>(plane, tail0 + gid, n, n_cb, thr, flags);
+    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+    const u32x4_t *vp = reinterpret_cast<const u32x4_t *>(plane + head);
+    for (int64_t v = gid; v < n_vec; v += stride) {
+        const u32x4_t u = __builtin_nontemporal_load(vp + v);
+        const PT *cells = reinterpret_cast<const PT *>(&u);
+        bool any = false;
 #pragma unroll
-        for (int i = 0; i < kTilesPerBlock; ++i) {
-            const PT *src = row0 + i * kPeakTileCols + threadIdx.x * kCellsPerThread;
-            if constexpr (sizeof(PT) == 2) {
-                *reinterpret_cast<uint2 *>(v[i]) = *reinterpret_cast<const uint2 *>(src);
-            } else if constexpr (sizeof(PT) == 4) {
-                *reinterpret_cast<uint4 *>(v[i]) = *reinterpret_cast<const uint4 *>(src);
-            } else {
+        for (int q = 0; q < kVec; ++q) any |= plane_val<PT>(cells, q) > thr;
+        if (any) {   // rare: locate the cells
 #pragma unroll
-                for (int q = 0; q < kCellsPerThread; ++q) v[i][q] = src[q];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < kTilesPerBlock; ++i) {
-            bool any = false;
-#pragma unroll
-            for (int q = 0; q < kCellsPerThread; ++q) any |= plane_val<PT>(v[i], q) > (double)thr;
-            mine |= any ? 1u << i : 0u;
-        }
-    } else {
-        for (int i = 0; i < kTilesPerBlock; ++i) {
-            const int64_t tile = t0 + i;
-            if (tile >= n_tiles) break;
-            if (cells_above<PT>(plane, n, (int)(tile / n_cb), (tile % n_cb) * kPeakTileCols, thr)) mine |= 1u << i;
+            for (int q = 0; q < kVec; ++q) mark_cell<PT>(plane, head + v * kVec + q, n, n_cb, thr, flags);
         }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mine |= (unsigned int)__shfl_xor((int)mine, o, 64);
-    if (threadIdx.x == 0) s_mask = 0u;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0 && mine) atomicOr(&s_mask, mine);
-    __syncthreads();
-    const unsigned int mask = s_mask;
+}
+
+template <class PT>
+__global__ void __launch_bounds__(kPeakThreads)
+k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, uint8_t *flags,
+             int32_t *counts, int32_t *block_counts) {
+    __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
+    __shared__ int sum;
+    const int64_t t0 = (int64_t)blockIdx.x * kTilesPerBlock;
     int total = 0;   // thread 0: peaks of this workgroup's tiles
     for (int i = 0; i < kTilesPerBlock; ++i) {
         const int64_t tile = t0 + i;
         if (tile >= n_tiles) break;
         const int z = (int)(tile / n_cb);
         const int64_t c0 = (tile % n_cb) * kPeakTileCols;
-        if (!((mask >> i) & 1u)) {
+        if (flags[tile] == 0) {                  // uniform: no cell above the threshold
             if (threadIdx.x == 0) counts[tile] = 0;
             continue;
         }
@@ -278,9 +260,14 @@ hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, fdas
     int64_t *offsets = reinterpret_cast<int64_t *>(scr);                           // per workgroup
     int32_t *counts = reinterpret_cast<int32_t *>(scr + (size_t)n_blocks * sizeof(int64_t));   // per tile
     int32_t *block_counts = counts + n_tiles;                                       // per workgroup
+    uint8_t *flags = reinterpret_cast<uint8_t *>(block_counts + n_blocks);            // per tile
     const unsigned blocks = (unsigned)n_blocks;
+    const int64_t total = n_tiles / n_cb * n;                                       // cells of the plane
+    hipLaunchKernelGGL(k_peak_clear, dim3((unsigned)std::min<int64_t>((n_tiles + 255) / 256, 4096)), dim3(256), 0, st,
+                       flags, n_tiles);
+    hipLaunchKernelGGL(k_peak_mark<PT>, dim3(8192), dim3(256), 0, st, plane, n, total, n_cb, thr, flags);
     hipLaunchKernelGGL(k_peak_count<PT>, dim3(blocks), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb,
-                       n_tiles, thr, counts, block_counts);
+                       n_tiles, thr, flags, counts, block_counts);
     hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, st, block_counts, offsets, n_blocks, n_found);
     hipLaunchKernelGGL(k_peak_write<PT>, dim3(blocks), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb,
                        n_tiles, thr, counts, offsets, out, cap);
