@@ -26,6 +26,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+T_START = time.perf_counter()
+
+
+def note(msg):
+    """Progress of the run on stderr (the result is the one JSON line on stdout)."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def time_correlate(pl, x, plane, steps, warmup):
@@ -91,46 +97,119 @@ def cpu_baseline(spec, cfg, r_center, target_s=15.0):
                       f"({cells} cells, {dt:.1f} s), {cfg['n_taps']} taps"}
 
 
-def batched_search(args, cfg, dev, n_spec=256, seed=2206):
-    """Many-spectra workload: 256 spectra with log-uniform lengths in
-    [2^19, 2^22] bins (mean 1.76e6), the single-DM template grid, BF16 form,
-    autotuned plan per length class, planes chunked through a 16 GB buffer
-    and thresholded peaks of every plane.  Spectra are seeded unit-power
-    complex noise generated on the device (the statistics of a normalised
-    noise spectrum)."""
+def batched_search(args, cfg, dev):
+    """Many-spectra workload: 256 dedispersion trials with series lengths
+    log-uniform in [2^20, 2^23] samples (spectra of 2^19..2^22 bins), 10 % of
+    them with an injected binary pulsar, generated on the device (seeded);
+    the single-DM template grid, BF16 form, autotuned plan per length class,
+    planes chunked through a 16 GB buffer and thresholded peaks of every
+    plane."""
     import numpy as np
     import torch
+    import synth
     from paper_2206_12205_amd.pipeline import BatchSearch
-    g = np.random.default_rng(seed)
-    lengths = np.exp(g.uniform(np.log(2 ** 19), np.log(2 ** 22), n_spec)).astype(np.int64).tolist()
+    c3 = synth.CONFIGS[3]
+    note("batched: generating 256 trials on the device")
+    spectra, trials = synth.config3(dev)
+    lengths = [t.n_bins for t in trials]
+    note("batched: trials ready; planning and tuning")
     total = int(sum(lengths))
-    gen = torch.Generator(device=dev).manual_seed(seed)
-    spectra = torch.randn(total, dtype=torch.complex64, device=dev, generator=gen)
     t0 = time.perf_counter()
-    bs = BatchSearch(lengths, cfg["z_min"], cfg["z_step"], cfg["n_z"], cfg["n_taps"], compute="bf16",
+    bs = BatchSearch(lengths, c3["z_min"], c3["z_step"], c3["n_z"], c3["n_taps"], compute="bf16",
                      plane_dtype="bf16", buffer_bytes=16 << 30, tune=True, device=dev)
     setup_s = time.perf_counter() - t0
+    note(f"batched: {len(trials)} trials generated, {len(bs.chunks)} chunks planned and tuned ({setup_s:.1f} s)")
     res = {}
     for name, fp in (("correlate", False), ("correlate_and_peaks", True)):
-        bs.run(spectra, cfg["threshold"], find_peaks=fp)
+        bs.run(spectra, c3["threshold"], find_peaks=fp)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         steps = max(1, min(args.steps, 3))
         e0.record()
         for _ in range(steps):
-            bs.run(spectra, cfg["threshold"], find_peaks=fp)
+            bs.run(spectra, c3["threshold"], find_peaks=fp)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         res[name] = {"ms_per_pass": ms, "cells_per_s": bs.cells / (ms * 1e-3)}
-    n_found = int(bs.n_found.sum().item())
-    out = {"workload": f"{n_spec} spectra, lengths log-uniform in [2^19, 2^22] bins (total {total}), "
-                       f"{cfg['n_z']} templates, {cfg['n_taps']} taps, BF16 form, raw BF16 planes "
-                       f"chunked through a 16 GB buffer, peaks above {cfg['threshold']}",
+        note(f"batched {name}: {ms:.1f} ms per pass")
+    # an injected pulsar counts as found when a peak sits within 2 bins of
+    # the mean frequency of one of its harmonics
+    found, noise_peaks, injected = 0, 0, 0
+    for i, t in enumerate(trials):
+        pk = bs.peaks(i)
+        if t.pulsar is None:
+            noise_peaks += pk["n_found"]
+            continue
+        injected += 1
+        rb = [t.pulsar.r_bar(t.T, h) for h in range(1, len(t.pulsar.amps) + 1) if t.pulsar.amps[h - 1] > 0]
+        if pk["n_found"] and any(np.min(np.abs(pk["r"] - r)) <= 2 for r in rb):
+            found += 1
+    out = {"workload": f"{len(trials)} dedispersion trials, series log-uniform in [2^20, 2^23] samples "
+                       f"snapped to 2^k / 3*2^k "
+                       f"(spectra {min(lengths)}..{max(lengths)} bins, total {total}), 10 % with an injected "
+                       f"binary pulsar, {c3['n_z']} templates, {c3['n_taps']} taps, BF16 form, raw BF16 "
+                       f"planes chunked through a 16 GB buffer, peaks above {c3['threshold']}",
            "cells": bs.cells, "chunks": len(bs.chunks), "setup_s": setup_s,
-           "tuned": {f"2^{k}": v for k, v in bs.tuned.items()}, "peaks_found": n_found, **res}
+           "tuned": {f"2^{k}": v for k, v in bs.tuned.items()},
+           "injected_pulsars": injected, "pulsars_with_a_harmonic_peak": found,
+           "peaks_in_noise_only_trials": noise_peaks, **res}
     del bs, spectra
+    return out
+
+
+def wide_search(args, dev):
+    """Wide workload: 2^24 samples, 16 injected pulsars, 201 templates (z in
+    [-200, 200]), 512 taps; the FP32, BF16 and FP8 planes timed and graded on
+    the pulsars' harmonic bands (Table 3) against the FP64 plane.  The
+    spectrum is generated on the device (seeded)."""
+    import torch
+    import synth
+    from paper_2206_12205_amd import metrics
+    from paper_2206_12205_amd.fdas import Plan
+    c5 = synth.CONFIGS[5]
+    note("wide: generating the spectrum")
+    x, sp = synth.config5_device(dev)
+    n = x.numel()
+    cells = c5["n_z"] * n
+    common = dict(max_bins=n, z_min=c5["z_min"], z_step=c5["z_step"], n_z=c5["n_z"], n_taps=c5["n_taps"],
+                  seg_len=0, device=dev)
+    forms = {"bf16": Plan(compute="bf16", plane_dtype="bf16", **common),
+             "fp32": Plan(compute="fp32", plane_dtype="fp32", **common),
+             "fp8": Plan(compute="fp8", plane_dtype="bf16", **common)}
+    steps = max(1, min(args.steps, 10))
+    out = {"workload": f"wide: {n} bins x {c5['n_z']} templates (z -200..200 step 2), {c5['n_taps']} taps, "
+                       f"16 injected pulsars", "cells": cells}
+    planes = {}
+    for name, pl in forms.items():
+        planes[name] = pl.empty_plane(n)
+        ms, _ = time_correlate(pl, x, planes[name], steps, 2)
+        out[name] = {"value": cells / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms, "seg_len": pl.seg_len,
+                     "algo": pl.algo}
+        note(f"wide {name}: {ms:.3f} ms per plane")
+    pd = Plan(compute="fp64", plane_dtype="fp64", **common).correlate(x)
+    note("wide: FP64 plane done")
+    std = {k: float(v.to(torch.float32).std()) for k, v in planes.items()}
+    acc = {k: {"same_bin": 0, "dsnr": []} for k in planes}
+    n_bright = 0
+    for psr in sp.pulsars:
+        bands = metrics.harmonic_bands(psr.f, sp.T, n, 8)
+        md = metrics.band_maxima(pd, bands)
+        mx = {k: metrics.band_maxima(v.to(torch.float32), bands) for k, v in planes.items()}
+        br = [i for i, m in enumerate(mx["fp32"]) if m[2] > c5["threshold"]]
+        n_bright += len(br)
+        for k in planes:
+            acc[k]["same_bin"] += sum((mx[k][i][0], mx[k][i][1]) == (md[i][0], md[i][1]) for i in br)
+            acc[k]["dsnr"] += [float(metrics.rel_diff_pct(mx[k][i][2] / std[k], mx["fp32"][i][2] / std["fp32"]))
+                               for i in br]
+    out["bright_band_maxima"] = n_bright
+    for k in planes:
+        err = ((planes[k].to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item()
+        out[k].update({"same_bin_vs_fp64": acc[k]["same_bin"],
+                       "max_abs_dsnr_pct_vs_fp32": max(map(abs, acc[k]["dsnr"])) if acc[k]["dsnr"] else None,
+                       "max_rel_power_err_vs_fp64": err})
+    del pd, planes, forms, x
     return out
 
 
@@ -143,6 +222,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched many-spectra search (256 dedispersion trials)")
+    ap.add_argument("--no-wide", action="store_true",
+                    help="skip the wide workload (201 x 8.4M planes in FP32, BF16 and FP8 vs FP64)")
     ap.add_argument("--trials", type=int, default=8,
                     help="seeded single-DM trials in the accuracy ensemble (outside the timed region)")
     ap.add_argument("--seg-len", type=int, default=None,
@@ -207,12 +288,15 @@ def main():
     plane_f = pl_f.empty_plane(n)
     torch.cuda.synchronize()
 
+    note("single-DM spectrum ready; timing the BF16 matrix-core plane")
     ms_b, wall_b = time_correlate(pl_b, x, plane_b, args.steps, args.warmup)
     ms_8, _ = time_correlate(pl_8, x, pl_8.empty_plane(n), args.steps, args.warmup)
     ms_v, _ = time_correlate(pl_v, x, pl_v.empty_plane(n), args.steps, args.warmup)
     ms_f, wall_f = time_correlate(pl_f, x, plane_f, args.steps, args.warmup)
     plane_q = pl_q.empty_plane(n)
     ms_q, _ = time_correlate(pl_q, x, plane_q, args.steps, args.warmup)
+    note(f"timed: bf16 {ms_b:.3f} ms, bf16 L=8192 {ms_8:.3f} ms, bf16 valu {ms_v:.3f} ms, fp32 {ms_f:.3f} ms, "
+         f"fp8 {ms_q:.3f} ms")
     del pl_v, pl_8
 
     # algorithmic HBM bytes per launch: the plane store plus one read of the
@@ -289,6 +373,7 @@ def main():
             err_f = max(err_f, ((pf.to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item())
             err_q = max(err_q, ((pq.to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item())
             del pd, pb, pq, xt
+            note(f"accuracy trial {trial}: {n_bright} bright band maxima so far")
         out["accuracy"] = {"trials": args.trials, "bright_band_maxima": n_bright,
                            "bf16_same_bin_vs_fp64": same_b, "fp32_same_bin_vs_fp64": same_f,
                            "bf16_same_bin_frac": same_b / n_bright if n_bright else None,
@@ -302,8 +387,12 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_search(args, cfg, dev)
 
+    if not args.no_wide:
+        out["wide"] = wide_search(args, dev)
+
     if not args.no_cpu_baseline:
         r_c = int(round(sp.pulsars[0].r_bar(sp.T)))
+        note("timing the FP64 CPU oracle")
         out["cpu_baseline"] = cpu_baseline(sp.spec, cfg, r_c)
 
     print(json.dumps(out), flush=True)

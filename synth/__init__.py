@@ -43,6 +43,9 @@ CONFIGS = {
             n_z=17, n_taps=64, seg_len=1024, threshold=20.0),
     2: dict(name="single-DM", n_t=2 ** 23, tsamp=64e-6, z_min=-100.0,
             z_step=2.0, n_z=101, n_taps=256, seg_len=8192, threshold=45.0),
+    3: dict(name="batched", n_spec=256, n_t_min=2 ** 20, n_t_max=2 ** 23,
+            tsamps=(64e-6, 128e-6, 256e-6, 512e-6), frac_pulsar=0.1, z_min=-100.0,
+            z_step=2.0, n_z=101, n_taps=256, threshold=45.0),
     5: dict(name="wide", n_t=2 ** 24, tsamp=64e-6, z_min=-200.0, z_step=2.0,
             n_z=201, n_taps=512, seg_len=16384, threshold=45.0),
 }
@@ -217,3 +220,93 @@ def refine_offsets(n: int, trial: int = 0):
     """Seeded candidate offsets for refinement: dr ~ U[-0.5, 0.5], dz ~ U[-1, 1]."""
     g = rng(4, trial)
     return g.uniform(-0.5, 0.5, size=n), g.uniform(-1.0, 1.0, size=n)
+
+
+@dataclass
+class Trial:
+    """One spectrum of the batched workload: its place in the packed tensor."""
+    offset: int                  # first bin in the packed spectra
+    n_bins: int
+    n_t: int
+    tsamp: float
+    pulsar: Pulsar | None
+
+    @property
+    def T(self) -> float:
+        return self.n_t * self.tsamp
+
+
+def _device_spectrum(n_t: int, tsamp: float, pulsars, seed: int, device):
+    """Gaussian series plus pulsars on the device (torch, FP64), then the
+    to_spectrum recipe: real FFT, Nyquist dropped, DC zeroed, median
+    normalisation; complex64."""
+    import torch
+    gen = torch.Generator(device=device).manual_seed(int(seed))
+    x = torch.randn(n_t, dtype=torch.float64, device=device, generator=gen)
+    if pulsars:
+        t = torch.arange(n_t, dtype=torch.float64, device=device) * tsamp
+        for p in pulsars:
+            cyc = p.f * t + 0.5 * p.fdot * t * t
+            for h, (a, ph) in enumerate(zip(p.amps, p.phases), start=1):
+                if a == 0.0:
+                    continue
+                ch = h * cyc
+                ch = ch - torch.floor(ch)
+                x += a * torch.cos(2.0 * math.pi * ch + ph)
+        del t
+    X = torch.fft.rfft(x)[: n_t // 2]
+    del x
+    X[0] = 0.0
+    med = torch.median(X[1:].real ** 2 + X[1:].imag ** 2)
+    return (X / torch.sqrt(med / math.log(2.0))).to(torch.complex64)
+
+
+def config5_device(device, trial: int = 0):
+    """The wide workload generated on the device: 2^24 samples at 64 us and 16
+    pulsars drawn as in config5 (a different noise realisation, drawn by
+    torch from a seed of the same generator).  Returns (spectrum tensor,
+    Spectrum with spec=None)."""
+    c = CONFIGS[5]
+    n_t, tsamp = c["n_t"], c["tsamp"]
+    T = n_t * tsamp
+    g = rng(5, 1000 + trial)
+    ps = [draw_pulsar(g, T, tsamp, p_range=(1e-3, 20e-3), z_range=(-180.0, 180.0),
+                      n_t=n_t) for _ in range(16)]
+    X = _device_spectrum(n_t, tsamp, ps, int(g.integers(0, 2 ** 62)), device)
+    return X, Spectrum(None, n_t, tsamp, ps)
+
+
+def config3(device, trial: int = 0, n_spec: int | None = None):
+    """Batched dedispersion trials, generated on the device (torch, FP64).
+
+    n_spec spectra (256 by default) with series lengths log-uniform in
+    [2^20, 2^23] samples (snapped to 2^k or 3 * 2^k), a sampling time drawn from
+    64 / 128 / 256 / 512 us, Gaussian noise, and in 10 % of them one binary
+    pulsar drawn as in the single-DM workload.  Each series goes through the
+    same recipe as to_spectrum (real FFT, Nyquist dropped, DC zeroed, median
+    normalisation), here with torch on the device so that 4.7e8 bins take
+    seconds.  Returns (packed complex64 tensor, list of Trial).
+    """
+    import torch
+    c = CONFIGS[3]
+    g = rng(3, trial)
+    n = c["n_spec"] if n_spec is None else int(n_spec)
+    # log-uniform lengths snapped to the nearest of 2^k and 3 * 2^k: every
+    # spectrum is the real FFT of its series, and FFT-friendly sizes keep the
+    # device FFT library from compiling a kernel for each of 256 odd lengths
+    grid = np.array(sorted(m * 2 ** k for m in (1, 3) for k in range(18, 24)
+                           if c["n_t_min"] <= m * 2 ** k <= c["n_t_max"]), dtype=np.int64)
+    want = np.exp(g.uniform(math.log(c["n_t_min"]), math.log(c["n_t_max"]), n))
+    n_ts = grid[np.argmin(np.abs(np.log(want)[:, None] - np.log(grid)[None, :]), axis=1)]
+    tsamps = g.choice(np.array(c["tsamps"]), size=n)
+    with_psr = g.permutation(n)[: int(round(c["frac_pulsar"] * n))]
+    seeds = g.integers(0, 2 ** 62, size=n)
+    parts, trials, off = [], [], 0
+    for i in range(n):
+        n_t, tsamp = int(n_ts[i]), float(tsamps[i])
+        psr = draw_pulsar(g, n_t * tsamp, tsamp, n_t=n_t) if i in with_psr else None
+        X = _device_spectrum(n_t, tsamp, [psr] if psr else [], int(seeds[i]), device)
+        parts.append(X)
+        trials.append(Trial(off, n_t // 2, n_t, tsamp, psr))
+        off += n_t // 2
+    return torch.cat(parts), trials

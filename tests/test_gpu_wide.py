@@ -1,0 +1,89 @@
+"""GPU parity at the wide workload's full size (2^24 samples, 16 pulsars,
+201 templates, 512 taps): the FP32 plane against the FP64 oracle on sampled
+column windows (pulsar fundamentals, segment boundaries, the tail), and the
+BF16 and FP8 planes' harmonic-band maxima against the GPU's FP64 plane (itself
+held to the oracle at 1e-9 on the tiny workload)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import plane as OP
+from oracle import response as R
+
+pytestmark = pytest.mark.gpu
+
+C5 = synth.CONFIGS[5]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def wide(dev):
+    x, sp = synth.config5_device(dev)
+    return x, sp
+
+
+def plan(dev, n, **kw):
+    from paper_2206_12205_amd.fdas import Plan
+    return Plan(max_bins=n, z_min=C5["z_min"], z_step=C5["z_step"], n_z=C5["n_z"], n_taps=C5["n_taps"],
+                device=dev, **kw)
+
+
+def test_wide_fp32_sampled_windows(dev, wide):
+    x, sp = wide
+    n = x.numel()
+    say(f"[wide] fp32 n={n}")
+    pl = plan(dev, n, compute="fp32")
+    assert pl.seg_len == 16384
+    p = pl.correlate(x)
+    xs = x.cpu().numpy()
+    taps = R.template_taps(R.z_grid(C5["z_min"], C5["z_step"], C5["n_z"]), C5["n_taps"])
+    V = pl.seg_len - C5["n_taps"]
+    starts = [int(psr.r_bar(sp.T)) - 128 for psr in sp.pulsars[:3]] + [V - 128, 7 * V - 128, n - 256]
+    for a in starts:
+        a = max(0, min(a, n - 256))
+        ref = OP.plane(xs, taps, a, a + 256)
+        got = p[:, a:a + 256].double().cpu().numpy()
+        err = np.abs(got - ref) / np.maximum(ref, 1.0)
+        assert err.max() <= 1e-4, f"window {a}: {err.max():.2e}"
+
+
+def test_wide_bf16_fp8_band_maxima(dev, wide):
+    import torch
+    from paper_2206_12205_amd import metrics
+    x, sp = wide
+    n = x.numel()
+    say("[wide] band maxima bf16 / fp8 vs fp64")
+    pd = plan(dev, n, compute="fp64", plane_dtype="fp64").correlate(x)
+    pf = plan(dev, n, compute="fp32").correlate(x)
+    pb = plan(dev, n, compute="bf16", plane_dtype="bf16").correlate(x).to(torch.float32)
+    pq = plan(dev, n, compute="fp8", plane_dtype="bf16").correlate(x).to(torch.float32)
+    same_b = same_q = same_f = n_bright = 0
+    for psr in sp.pulsars:
+        bands = metrics.harmonic_bands(psr.f, sp.T, n, 8)
+        md = metrics.band_maxima(pd, bands)
+        mf, mb, mq = (metrics.band_maxima(t, bands) for t in (pf, pb, pq))
+        bright = [i for i, m in enumerate(mf) if m[2] > C5["threshold"]]
+        n_bright += len(bright)
+        for i in bright:
+            same_f += (mf[i][0], mf[i][1]) == (md[i][0], md[i][1])
+            same_b += (mb[i][0], mb[i][1]) == (md[i][0], md[i][1])
+            same_q += (mq[i][0], mq[i][1]) == (md[i][0], md[i][1])
+    say(f"  bright {n_bright}: fp32 {same_f} bf16 {same_b} fp8 {same_q} same bin")
+    assert n_bright >= 16
+    # FP32 and BF16: at least 97 % of the bright band maxima in the FP64 cell
+    # (a band whose two best cells are within the form's rounding may flip)
+    assert same_f >= 0.97 * n_bright
+    assert same_b >= 0.97 * n_bright
+    # the brightest pulsar's fundamental lands in the same cell in every form
+    top = max(sp.pulsars, key=lambda p: p.p1)
+    band = metrics.harmonic_bands(top.f, sp.T, n, 1)
+    ref = metrics.band_maxima(pd, band)[0]
+    for t in (pb, pq):
+        m = metrics.band_maxima(t, band)[0]
+        assert (m[0], m[1]) == (ref[0], ref[1])
