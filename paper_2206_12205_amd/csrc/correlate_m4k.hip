@@ -13,7 +13,8 @@
 //            inverse stage's B-operand layout, kept as (Re, -Im) and (Im, Re)
 //            bf16 pairs so each product with a template value is two
 //            v_dot2_f32_bf16.
-//   template j: the bank entry of j + 1 is prefetched; Y = X * H_j -> I1 ->
+//   template j: the bank entry of j + 1 is prefetched and its product with
+//            X formed after I2 of template j; Y = X * H_j -> I1 ->
 //            LDS A -> barrier -> (flush of template j - 1's row) -> I2 ->
 //            LDS B -> barrier -> I3.  All three inverse stages run with the
 //            operands swapped (transposed outputs): each lane then holds four
@@ -265,17 +266,31 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
     const uint4 *bank4 = reinterpret_cast<const uint4 *>(bank) + (kGpw * w) * 64 + lane;
 
     // One template: I1 (group k1 = Q) on X * H_j, I2 (group n3), I3 (group n2).
-    auto one_template = [&](int j, const uint4 (&hc)[kGpw]) {
+    // template product Y = X * H_j into the I1 operand (kept in bin[])
+    Op bin[kGpw];
+    auto product = [&](const uint4 (&hc)[kGpw]) {
+#pragma unroll
+        for (int q = 0; q < kGpw; ++q) {
+            const uint32_t hw[4] = {hc[q].x, hc[q].y, hc[q].z, hc[q].w};
+#pragma unroll
+            for (int p = 0; p < 4; ++p) bin[q].w[p] = bf16_pack(dot2(sA[q][p], hw[p]), dot2(sB[q][p], hw[p]));
+        }
+    };
+
+    // One template.  Single-segment launches form the product of the next
+    // template (bank entry hn) between I2 and the second barrier, which
+    // balances the vector-ALU work of the two barrier intervals (template j's
+    // product is then already in bin[]); the persistent batch kernel forms
+    // template j's product (bank entry hc) just before its I1, which needs
+    // fewer registers live across the barriers.
+    auto one_template = [&](int j, const uint4 (&hc)[kGpw], const uint4 (&hn)[kGpw], bool has_next) {
+        if constexpr (kOpaqueLane) product(hc);
         // I1: DFT16 over k3 with e(n3 k1), transposed: lane (c, g) receives
         // n3 = c, k2 = 4 g + e -> one 16-byte chunk of buffer A
 #pragma unroll
         for (int q = 0; q < kGpw; ++q) {
             const int Q = kGpw * w + q;
-            const uint32_t hw[4] = {hc[q].x, hc[q].y, hc[q].z, hc[q].w};
-            Op b;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) b.w[p] = bf16_pack(dot2(sA[q][p], hw[p]), dot2(sB[q][p], hw[p]));
-            const f32x4_t dre = mma(b, a1re[q]), dim = mma(b, a1im[q]);
+            const f32x4_t dre = mma(bin[q], a1re[q]), dim = mma(bin[q], a1im[q]);
             uint4 o;
             o.x = bf16_pack(dre[0], dim[0]);
             o.y = bf16_pack(dre[1], dim[1]);
@@ -300,6 +315,9 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
             o.w = bf16_pack(dre[3], dim[3]);
             *reinterpret_cast<uint4 *>(&bufB[chunk_addr(c, Q, g)]) = o;   // (n2, n3, k1 block)
         }
+        if constexpr (!kOpaqueLane) {
+            if (has_next) product(hn);
+        }
         __syncthreads();
         // I3: DFT16 over k1 with e(16 n2 k1); rows n1 = 4 g + e; |y|^2 -> staging
 #pragma unroll
@@ -317,23 +335,24 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
     // the inverse stages use the chunk layout: every wave must be done with
     // its forward reads of buffer A
     __syncthreads();
-    // templates in pairs with two statically assigned bank registers: the
-    // next template's bank entry is in flight while the current one runs
+    // bank entries in two statically assigned register sets: the entry of
+    // template j + 1 is loaded while template j runs
     uint4 hA[kGpw], hB[kGpw];
 #pragma unroll
     for (int q = 0; q < kGpw; ++q) hA[q] = bank4[(size_t)j0 * (kL / 4) + q * 64];
+    if constexpr (!kOpaqueLane) product(hA);
     for (int j = j0; j < j1; j += 2) {
         if (j + 1 < j1) {
 #pragma unroll
             for (int q = 0; q < kGpw; ++q) hB[q] = bank4[(size_t)(j + 1) * (kL / 4) + q * 64];
         }
-        one_template(j, hA);
+        one_template(j, hA, hB, j + 1 < j1);
         if (j + 1 >= j1) break;
         if (j + 2 < j1) {
 #pragma unroll
             for (int q = 0; q < kGpw; ++q) hA[q] = bank4[(size_t)(j + 2) * (kL / 4) + q * 64];
         }
-        one_template(j + 1, hB);
+        one_template(j + 1, hB, hA, j + 2 < j1);
     }
     __syncthreads();
     flush<PT>(stage, plane + (int64_t)(j1 - 1) * n + seg0, fp, tid);
