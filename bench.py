@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import statistics
 import os
 import sys
 import time
@@ -51,6 +52,62 @@ def time_correlate(pl, x, plane, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / steps, wall
+
+
+def launch_stats(pl, x, plane, n=256):
+    """Mean, standard deviation and median of n individually timed launches
+    (HIP events around each launch on the launch stream), in ms."""
+    import statistics
+    import torch
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record(st)
+        pl.correlate(x, plane)
+        b.record(st)
+    torch.cuda.synchronize()
+    t = [a.elapsed_time(b) for a, b in ev]
+    return {"mean": statistics.fmean(t), "std": statistics.pstdev(t), "median": statistics.median(t), "n": n}
+
+
+def copy_bandwidth(dev, nbytes=4 << 30, reps=10):
+    """Achieved HBM bandwidth of a plain device-to-device copy (read + write
+    bytes over time), the practical ceiling next to the 8 TB/s peak."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def measured_counts(kernel_sources):
+    """Per-launch instruction counts from the committed counter summary (same
+    source-hash guard as the traffic), or None."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "correlate_mfma4096_single_dm_hbm_counters.md")
+    try:
+        txt = open(path).read()
+        h = hashlib.sha1()
+        for f in kernel_sources:
+            with open(os.path.join(ROOT, "paper_2206_12205_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if re.search(r"kernel_source_sha1: ([0-9a-f]+)", txt).group(1) != h.hexdigest():
+            return None
+        return {k: float(re.search(rf"{k}: ([0-9.e+]+)", txt).group(1))
+                for k in ("mfma_insts_per_launch", "valu_insts_per_launch")}
+    except (OSError, AttributeError):
+        return None
 
 
 def measured_traffic(kernel_sources):
@@ -162,8 +219,8 @@ def batched_search(args, cfg, dev):
 def wide_search(args, dev):
     """Wide workload: 2^24 samples, 16 injected pulsars, 201 templates (z in
     [-200, 200]), 512 taps; the FP32, BF16 and FP8 planes timed and graded on
-    the pulsars' harmonic bands (Table 3) against the FP64 plane.  The
-    spectrum is generated on the device (seeded)."""
+    windows around each pulsar's harmonics (r_h +- 32, z_h +- 4) against the
+    FP64 plane.  The spectrum is generated on the device (seeded)."""
     import torch
     import synth
     from paper_2206_12205_amd import metrics
@@ -194,16 +251,17 @@ def wide_search(args, dev):
     acc = {k: {"same_bin": 0, "dsnr": []} for k in planes}
     n_bright = 0
     for psr in sp.pulsars:
-        bands = metrics.harmonic_bands(psr.f, sp.T, n, 8)
-        md = metrics.band_maxima(pd, bands)
-        mx = {k: metrics.band_maxima(v.to(torch.float32), bands) for k, v in planes.items()}
+        # windows around each harmonic (Table 3 bands of 16 pulsars overlap)
+        wins = metrics.pulsar_windows(psr, sp.T, n, c5["z_min"], c5["z_step"], c5["n_z"])
+        md = metrics.window_maxima(pd, wins)
+        mx = {k: metrics.window_maxima(v.to(torch.float32), wins) for k, v in planes.items()}
         br = [i for i, m in enumerate(mx["fp32"]) if m[2] > c5["threshold"]]
         n_bright += len(br)
         for k in planes:
             acc[k]["same_bin"] += sum((mx[k][i][0], mx[k][i][1]) == (md[i][0], md[i][1]) for i in br)
             acc[k]["dsnr"] += [float(metrics.rel_diff_pct(mx[k][i][2] / std[k], mx["fp32"][i][2] / std["fp32"]))
                                for i in br]
-    out["bright_band_maxima"] = n_bright
+    out["bright_harmonic_windows"] = n_bright
     for k in planes:
         err = ((planes[k].to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item()
         out[k].update({"same_bin_vs_fp64": acc[k]["same_bin"],
@@ -224,7 +282,7 @@ def main():
                     help="skip the batched many-spectra search (256 dedispersion trials)")
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the wide workload (201 x 8.4M planes in FP32, BF16 and FP8 vs FP64)")
-    ap.add_argument("--trials", type=int, default=8,
+    ap.add_argument("--trials", type=int, default=256,
                     help="seeded single-DM trials in the accuracy ensemble (outside the timed region)")
     ap.add_argument("--seg-len", type=int, default=None,
                     help="segment length of the BF16 matrix-core plan (default: the workload's 8192)")
@@ -299,6 +357,10 @@ def main():
          f"fp8 {ms_q:.3f} ms")
     del pl_v, pl_8
 
+    st_b = launch_stats(pl_b, x, plane_b)
+    copy_gbs = copy_bandwidth(dev)
+    note(f"per-launch BF16 {st_b['mean']:.4f} +- {st_b['std']:.4f} ms (median {st_b['median']:.4f}); "
+         f"device copy {copy_gbs:.0f} GB/s")
     # algorithmic HBM bytes per launch: the plane store plus one read of the
     # complex64 spectrum (templates are served from cache)
     bytes_b = cells * 2 + n * 8
@@ -329,16 +391,29 @@ def main():
                      "traffic": (measured_traffic(["correlate_m4k.hip", "mfma4096.hpp"])
                                  if pl_b.algo == "mfma" and pl_b.seg_len == 4096 else None),
                      "kernel": f"correlate_{pl_b.algo}{pl_b.seg_len} (BF16 form, raw BF16 plane)",
-                     "bytes_per_launch": bytes_b},
+                     "bytes_per_launch": bytes_b, "copy_frac": ach_b / copy_gbs},
         "fp32": {"value": cells / (ms_f * 1e-3), "unit": "cells/s", "ms_per_step": ms_f,
                  "hbm_frac": bytes_f / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "bf16_seg8192": {"value": cells / (ms_8 * 1e-3), "unit": "cells/s", "ms_per_step": ms_8},
         "bf16_valu": {"value": cells / (ms_v * 1e-3), "unit": "cells/s", "ms_per_step": ms_v},
         "fp8": {"value": cells / (ms_q * 1e-3), "unit": "cells/s", "ms_per_step": ms_q,
                 "kernel": f"correlate_valu_fp8 (e4m3 stages, segment {pl_q.seg_len}, raw BF16 plane)"},
+        "per_launch_ms": st_b,
+        "copy_gbs": copy_gbs,
         "speedup_bf16_over_fp32": ms_f / ms_b,
         "wall_s": {"bf16": wall_b, "fp32": wall_f},
     }
+
+    cnt = measured_counts(["correlate_m4k.hip", "mfma4096.hpp"]) if pl_b.algo == "mfma" and pl_b.seg_len == 4096 \
+        else None
+    if cnt:
+        # MFMA: 16x16x32 bf16 = 16,384 flops per instruction against the dense
+        # bf16 peak; VALU: wave64 instructions at 4 cycles on a 16-lane SIMD
+        # against 1,024 SIMDs at the 2.4 GHz peak clock
+        out["utilisation"] = {
+            "mfma_frac_of_bf16_peak": cnt["mfma_insts_per_launch"] * 16384 / (ms_b * 1e-3) / 2.5e15,
+            "valu_issue_frac_at_peak_clock": cnt["valu_insts_per_launch"] * 4 / (ms_b * 1e-3) / (1024 * 2.4e9),
+            "source": "instruction counts of profiles/correlate_mfma4096_single_dm_hbm_counters.md"}
 
     if not args.no_accuracy:
         # peak-bin match of BF16 and FP32 against the FP64 gold plane on the
@@ -348,8 +423,7 @@ def main():
         n_bright = same_b = same_f = same_q = 0
         dsnr, dsnr_q, err_b, err_f, err_q = [], [], 0.0, 0.0, 0.0
         for trial in range(args.trials):
-            spt = sp if trial == 0 else synth.config2(trial)
-            xt = torch.from_numpy(spt.spec).to(dev)
+            xt, spt = synth.config2_device(dev, trial)
             pd = pl_d.correlate(xt)
             pb = pl_b.correlate(xt, plane_b).to(torch.float32)
             pf = pl_f.correlate(xt, plane_f)
@@ -373,14 +447,19 @@ def main():
             err_f = max(err_f, ((pf.to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item())
             err_q = max(err_q, ((pq.to(torch.float64) - pd).abs() / pd.clamp(min=1.0)).max().item())
             del pd, pb, pq, xt
-            note(f"accuracy trial {trial}: {n_bright} bright band maxima so far")
+            if trial % 32 == 31 or trial == args.trials - 1:
+                note(f"accuracy trial {trial}: {n_bright} bright band maxima so far")
         out["accuracy"] = {"trials": args.trials, "bright_band_maxima": n_bright,
                            "bf16_same_bin_vs_fp64": same_b, "fp32_same_bin_vs_fp64": same_f,
                            "bf16_same_bin_frac": same_b / n_bright if n_bright else None,
                            "bf16_max_abs_dsnr_pct": max(map(abs, dsnr)) if dsnr else None,
+                           "bf16_dsnr_pct_mean": statistics.fmean(dsnr) if dsnr else None,
+                           "bf16_dsnr_pct_sigma": statistics.pstdev(dsnr) if dsnr else None,
+                           "bf16_bright_within_3pct": sum(abs(v) <= 3.0 for v in dsnr),
                            "bf16_max_rel_power_err": err_b, "fp32_max_rel_power_err": err_f,
                            "fp8_same_bin_vs_fp64": same_q,
                            "fp8_max_abs_dsnr_pct": max(map(abs, dsnr_q)) if dsnr_q else None,
+                           "fp8_dsnr_pct_sigma": statistics.pstdev(dsnr_q) if dsnr_q else None,
                            "fp8_max_rel_power_err": err_q}
         del pl_d
 

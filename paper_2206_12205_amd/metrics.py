@@ -92,3 +92,46 @@ def bin_match(a, b):
         return float("nan")
     same = sum(1 for x, y in zip(a, b) if x[0] == y[0] and x[1] == y[1])
     return same / len(a)
+
+
+def pulsar_windows(psr, t_obs: float, n_bins: int, z_min: float, z_step: float, n_z: int,
+                   dr: int = 32, dz: float = 4.0):
+    """Plane windows around one pulsar's harmonics: rows with |z - z_h| <= dz,
+    columns with |r - r_h| <= dr, where r_h and z_h = h fdot T^2 are the mean
+    Fourier frequency and drift of harmonic h (used where Table 3 bands of
+    several pulsars overlap).  Returns (j_lo, j_hi, r_lo, r_hi), half-open."""
+    out = []
+    for h in range(1, len(psr.amps) + 1):
+        if psr.amps[h - 1] == 0.0:
+            continue
+        rh, zh = psr.r_bar(t_obs, h), psr.z(t_obs, h)
+        j_lo = max(int(math.ceil((zh - dz - z_min) / z_step)), 0)
+        j_hi = min(int(math.floor((zh + dz - z_min) / z_step)) + 1, n_z)
+        r_lo = max(int(math.floor(rh - dr)), 0)
+        r_hi = min(int(math.floor(rh + dr)) + 1, n_bins)
+        if j_lo < j_hi and r_lo < r_hi:
+            out.append((j_lo, j_hi, r_lo, r_hi))
+    return out
+
+
+def window_maxima(plane, windows):
+    """For each window (j_lo, j_hi, r_lo, r_hi): (z_idx, r, power) of its
+    highest cell; ties resolve to the first cell in (z_idx, r) order."""
+    res = []
+    for j_lo, j_hi, r_lo, r_hi in windows:
+        blk = plane[j_lo:j_hi, r_lo:r_hi]
+        w = r_hi - r_lo
+        try:
+            import torch
+            if isinstance(blk, torch.Tensor):
+                flat = blk.contiguous().view(-1)
+                mx = flat.max()
+                idx = int(torch.nonzero(flat == mx)[0, 0])
+                res.append((j_lo + idx // w, r_lo + idx % w, float(mx)))
+                continue
+        except ImportError:
+            pass
+        b = np.asarray(blk)
+        idx = int(np.argmax(b))
+        res.append((j_lo + idx // w, r_lo + idx % w, float(b.flat[idx])))
+    return res

@@ -276,6 +276,20 @@ def config5_device(device, trial: int = 0):
     return X, Spectrum(None, n_t, tsamp, ps)
 
 
+def config2_device(device, trial: int = 0):
+    """A single-DM trial generated on the device (the config2 recipe, a
+    different realisation: pulsar drawn from generator (2, 1000 + trial),
+    noise by torch from a seed of it).  Returns (spectrum tensor, Spectrum
+    with spec=None)."""
+    c = CONFIGS[2]
+    n_t, tsamp = c["n_t"], c["tsamp"]
+    T = n_t * tsamp
+    g = rng(2, 1000 + trial)
+    p = draw_pulsar(g, T, tsamp, n_t=n_t)
+    X = _device_spectrum(n_t, tsamp, [p], int(g.integers(0, 2 ** 62)), device)
+    return X, Spectrum(None, n_t, tsamp, [p])
+
+
 def config3(device, trial: int = 0, n_spec: int | None = None):
     """Batched dedispersion trials, generated on the device (torch, FP64).
 

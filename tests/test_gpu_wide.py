@@ -1,8 +1,9 @@
 """GPU parity at the wide workload's full size (2^24 samples, 16 pulsars,
 201 templates, 512 taps): the FP32 plane against the FP64 oracle on sampled
 column windows (pulsar fundamentals, segment boundaries, the tail), and the
-BF16 and FP8 planes' harmonic-band maxima against the GPU's FP64 plane (itself
-held to the oracle at 1e-9 on the tiny workload)."""
+BF16 and FP8 planes' maxima in windows around each pulsar's harmonics
+(r_h +- 32, z_h +- 4; the Table 3 bands of 16 pulsars overlap) against the
+GPU's FP64 plane (itself held to the oracle at 1e-9 on the tiny workload)."""
 import sys
 
 import numpy as np
@@ -53,7 +54,7 @@ def test_wide_fp32_sampled_windows(dev, wide):
         assert err.max() <= 1e-4, f"window {a}: {err.max():.2e}"
 
 
-def test_wide_bf16_fp8_band_maxima(dev, wide):
+def test_wide_bf16_fp8_harmonic_maxima(dev, wide):
     import torch
     from paper_2206_12205_amd import metrics
     x, sp = wide
@@ -65,9 +66,9 @@ def test_wide_bf16_fp8_band_maxima(dev, wide):
     pq = plan(dev, n, compute="fp8", plane_dtype="bf16").correlate(x).to(torch.float32)
     same_b = same_q = same_f = n_bright = 0
     for psr in sp.pulsars:
-        bands = metrics.harmonic_bands(psr.f, sp.T, n, 8)
-        md = metrics.band_maxima(pd, bands)
-        mf, mb, mq = (metrics.band_maxima(t, bands) for t in (pf, pb, pq))
+        wins = metrics.pulsar_windows(psr, sp.T, n, C5["z_min"], C5["z_step"], C5["n_z"])
+        md = metrics.window_maxima(pd, wins)
+        mf, mb, mq = (metrics.window_maxima(t, wins) for t in (pf, pb, pq))
         bright = [i for i, m in enumerate(mf) if m[2] > C5["threshold"]]
         n_bright += len(bright)
         for i in bright:
@@ -76,14 +77,14 @@ def test_wide_bf16_fp8_band_maxima(dev, wide):
             same_q += (mq[i][0], mq[i][1]) == (md[i][0], md[i][1])
     say(f"  bright {n_bright}: fp32 {same_f} bf16 {same_b} fp8 {same_q} same bin")
     assert n_bright >= 16
-    # FP32 and BF16: at least 97 % of the bright band maxima in the FP64 cell
+    # FP32 and BF16: at least 97 % of the bright window maxima in the FP64 cell
     # (a band whose two best cells are within the form's rounding may flip)
     assert same_f >= 0.97 * n_bright
     assert same_b >= 0.97 * n_bright
     # the brightest pulsar's fundamental lands in the same cell in every form
     top = max(sp.pulsars, key=lambda p: p.p1)
-    band = metrics.harmonic_bands(top.f, sp.T, n, 1)
-    ref = metrics.band_maxima(pd, band)[0]
+    win = metrics.pulsar_windows(top, sp.T, n, C5["z_min"], C5["z_step"], C5["n_z"])[:1]
+    ref = metrics.window_maxima(pd, win)[0]
     for t in (pb, pq):
-        m = metrics.band_maxima(t, band)[0]
+        m = metrics.window_maxima(t, win)[0]
         assert (m[0], m[1]) == (ref[0], ref[1])

@@ -69,3 +69,26 @@ def test_peak_curvature_and_ascent_converge_on_chirp():
     pz = refine.power(x, [r[0]] * 3, [z[0] - hz, z[0], z[0] + hz])[0]
     d2z = (pz[0] - 2 * pz[1] + pz[2]) / hz ** 2
     assert d2z / (-math.pi ** 2 * pz[1] / 90) == pytest.approx(1.0, abs=0.1)
+
+
+def test_window_maxima_brute_force():
+    """window_maxima against a plain scan, and pulsar_windows' geometry."""
+    import numpy as np
+    import synth
+    from paper_2206_12205_amd import metrics
+    g = np.random.default_rng(4)
+    P = g.exponential(size=(21, 500))
+    P[7, 123] = 99.0
+    wins = [(5, 10, 100, 150), (0, 21, 0, 500), (20, 21, 499, 500)]
+    got = metrics.window_maxima(P, wins)
+    for (j0, j1, r0, r1), (j, r, p) in zip(wins, got):
+        blk = P[j0:j1, r0:r1]
+        jj, rr = np.unravel_index(np.argmax(blk), blk.shape)
+        assert (j, r, p) == (j0 + jj, r0 + rr, blk[jj, rr])
+    psr = synth.Pulsar(f=100.0, fdot=2.0 / 100.0 ** 2, amps=[1.0, 0.0, 0.5], phases=[0, 0, 0], p1=100.0)
+    w = metrics.pulsar_windows(psr, 100.0, 100000, -20.0, 2.0, 21, dr=32, dz=4.0)
+    assert len(w) == 2                                  # harmonic 2 has zero amplitude
+    # harmonic 1: r = 10000 + 1, z = 2 -> rows z in [-2, 6] -> j 9..13
+    assert w[0] == (9, 14, int(np.floor(10001 - 32)), int(np.floor(10001 + 32)) + 1)
+    # harmonic 3: z = 6 -> rows z in [2, 10] -> j 11..15
+    assert w[1][:2] == (11, 16)
