@@ -274,8 +274,10 @@ def wide_search(args, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed launches before each timed window; the GPU clock needs ~100 "
+                         "back-to-back launches (~30 ms) to reach its steady state")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
@@ -340,7 +342,9 @@ def main():
     pl_b = Plan(compute="bf16", plane_dtype="bf16", **cm_auto)             # matrix-core kernel
     pl_8 = Plan(compute="bf16", plane_dtype="bf16", algo="mfma", **common)  # the stated segment 8192
     pl_v = Plan(compute="bf16", plane_dtype="bf16", algo="valu", **common)
-    pl_f = Plan(compute="fp32", plane_dtype="fp32", **common)
+    cm_f = dict(common)
+    cm_f["seg_len"] = 0                                                    # the library's choice
+    pl_f = Plan(compute="fp32", plane_dtype="fp32", **cm_f)
     pl_q = Plan(compute="fp8", plane_dtype="bf16", **cm_auto)               # FP8 e4m3 form
     plane_b = pl_b.empty_plane(n)
     plane_f = pl_f.empty_plane(n)
@@ -392,7 +396,7 @@ def main():
                                  if pl_b.algo == "mfma" and pl_b.seg_len == 4096 else None),
                      "kernel": f"correlate_{pl_b.algo}{pl_b.seg_len} (BF16 form, raw BF16 plane)",
                      "bytes_per_launch": bytes_b, "copy_frac": ach_b / copy_gbs},
-        "fp32": {"value": cells / (ms_f * 1e-3), "unit": "cells/s", "ms_per_step": ms_f,
+        "fp32": {"value": cells / (ms_f * 1e-3), "unit": "cells/s", "ms_per_step": ms_f, "seg_len": pl_f.seg_len,
                  "hbm_frac": bytes_f / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "bf16_seg8192": {"value": cells / (ms_8 * 1e-3), "unit": "cells/s", "ms_per_step": ms_8},
         "bf16_valu": {"value": cells / (ms_v * 1e-3), "unit": "cells/s", "ms_per_step": ms_v},

@@ -102,7 +102,7 @@ typedef struct {
     int32_t n_taps;       /* M: even, >= 2; the overlap between segments */
     int32_t seg_len;      /* L: power of two in [1024, 16384], L > M; 0 = choose (BF16: 4096 for
                              M <= 512, 8192 for M <= 2048; FP8: 4096; otherwise the power of
-                             two >= 32 M, at most 8192 for FP64) */
+                             two >= 8 M, at least 1024, at most 8192 for FP64) */
     int32_t compute;      /* FDAS_FP32 | FDAS_BF16 | FDAS_FP8E4M3 | FDAS_FP64 */
     int32_t plane_dtype;  /* FDAS_FP32 | FDAS_BF16 (not with FP64 compute) | FDAS_FP64 (FP64 compute only) */
     int32_t z_chunk;      /* templates per workgroup; 0 = choose */

@@ -91,7 +91,11 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
         } else if (c.compute == FDAS_FP8E4M3) {
             L = 4096;   // the longest FP8 segment (three scaled stages)
         } else {
-            L = int64_t(1) << ilog2(32 * (int64_t)c.n_taps);
+            // vector-ALU kernel: the shortest power of two >= 8 M (overlap
+            // waste M / L <= 12.5 %); longer segments only add a pass
+            // (measured: FP32, M = 256: L = 2048 / 4096 / 8192 / 16384 ->
+            // 0.74 / 0.77 / 1.20 / 3.0 ms per single-DM plane)
+            L = int64_t(1) << ilog2(8 * (int64_t)c.n_taps);
             if (L < 1024) L = 1024;
             const int64_t lmax = c.compute == FDAS_FP64 ? 8192 : 16384;
             if (L > lmax) L = lmax;

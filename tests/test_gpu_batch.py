@@ -24,7 +24,8 @@ def say(msg):
     sys.stdout.flush()
 
 
-# segment 4096 with 256 taps keeps V = 3840 valid bins per segment
+# BF16's segment 4096 with 256 taps keeps V = 3840 valid bins per segment
+# (FP32's automatic 2048 keeps V = 1792; 3839..3841 straddle its third segment)
 LENGTHS = [70001, 1, 3839, 3840, 3841, 12345, 200000, 517]
 ZMIN, ZSTEP, NZ, M = -20.0, 2.0, 21, 256
 

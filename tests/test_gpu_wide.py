@@ -40,7 +40,7 @@ def test_wide_fp32_sampled_windows(dev, wide):
     n = x.numel()
     say(f"[wide] fp32 n={n}")
     pl = plan(dev, n, compute="fp32")
-    assert pl.seg_len == 16384
+    assert pl.seg_len == 4096          # the automatic choice: the power of two >= 8 M
     p = pl.correlate(x)
     xs = x.cpu().numpy()
     taps = R.template_taps(R.z_grid(C5["z_min"], C5["z_step"], C5["n_z"]), C5["n_taps"])
