@@ -57,11 +57,21 @@ __device__ __forceinline__ f32x4_t mma(const Op &a, const Op &b) {
                                                    0, 0, 0);
 }
 
-// a.lo * b.lo + a.hi * b.hi of two bf16 pairs, accumulated in FP32
-__device__ __forceinline__ float dot2(uint32_t a, uint32_t b) {
-    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), 0.0f,
-                                           false);
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// a.lo * b.lo + a.hi * b.hi of two bf16 pairs plus c, in FP32
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
 }
+
+// Two FP32 zeros in one 64-bit register pair (one 64-bit move instead of two
+// 32-bit ones for the accumulators of v_dot2c; the empty asm emits nothing)
+__device__ __forceinline__ f32x2_t zero_pair() {
+    uint64_t z = 0;
+    asm volatile("" : "+v"(z));
+    return __builtin_bit_cast(f32x2_t, z);
+}
+
 
 __device__ __forceinline__ Op load_op(const uint32_t *tab, int op, int lane) {
     const uint4 v = reinterpret_cast<const uint4 *>(tab + op * kOpWords)[lane];
@@ -77,8 +87,12 @@ __device__ __forceinline__ int chunk_addr(int a, int b, int g) { return 4 * (256
 
 // Staging of one template row's powers between I3 and the plane store.
 // FP32 plane: one float per sample at t + 4 (t >> 8); BF16 plane: the bf16
-// value, two samples per word, at word t / 2 + 2 (t >> 8).  The pads keep the
-// I3 writes (lanes 256 samples apart) and the flush reads conflict-free.
+// value, two samples per word, at word t / 2 + 4 (t >> 8), so runs of 8
+// samples are 16-byte aligned for the flush reads.  The FP32 pad keeps the
+// I3 writes (lanes 256 samples apart) and the flush reads conflict-free; the
+// BF16 pad leaves a two-way conflict in the I3 writes (lanes c and c + 8),
+// cheaper than the conflict of reading 8 samples as two 8-byte halves under
+// a 2-word pad (measured).
 template <class PT>
 struct Stage;
 template <>
@@ -103,39 +117,41 @@ struct Stage<float> {
 };
 template <>
 struct Stage<__bf16> {
-    static constexpr int kWords = kL / 2 + 2 * 16;
+    static constexpr int kWords = kL / 2 + 4 * 16;
     static __device__ __forceinline__ void put4(uint32_t *st, int t0, float a, float b, float c, float d) {
         uint2 u;
         u.x = bf16_pack(a, b);
         u.y = bf16_pack(c, d);
-        *reinterpret_cast<uint2 *>(&st[t0 / 2 + 2 * (t0 >> 8)]) = u;
+        *reinterpret_cast<uint2 *>(&st[t0 / 2 + 4 * (t0 >> 8)]) = u;
     }
-    static __device__ __forceinline__ void flush4(const uint32_t *st, int t0, __bf16 *row, bool vec, int lo, int hi) {
-        const uint2 u = *reinterpret_cast<const uint2 *>(&st[t0 / 2 + 2 * (t0 >> 8)]);
+    // samples t0 .. t0 + 7 (t0 a multiple of 8): one 16-byte read, one 16-byte store
+    static __device__ __forceinline__ void flush8(const uint32_t *st, int t0, __bf16 *row, bool vec, int lo, int hi) {
+        const uint4 u = *reinterpret_cast<const uint4 *>(&st[t0 / 2 + 4 * (t0 >> 8)]);
         if (vec) {
-            typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
-            u32x2_t w;
-            w.x = u.x;
-            w.y = u.y;
-            __builtin_nontemporal_store(w, reinterpret_cast<u32x2_t *>(row + t0));
+            const u32x4_t w = {u.x, u.y, u.z, u.w};
+            __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t *>(row + t0));
         } else {
-            const uint32_t ww[2] = {u.x, u.y};
+            const uint32_t ww[4] = {u.x, u.y, u.z, u.w};
             uint16_t *r16 = reinterpret_cast<uint16_t *>(row);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 8; ++i)
                 if (t0 + i >= lo && t0 + i < hi) r16[t0 + i] = (uint16_t)(ww[i >> 1] >> (16 * (i & 1)));
         }
     }
 };
 
-// Per-thread flush plan: thread tid owns time samples [t0, t0 + 4) with
-// t0 = 4 (tid + h kThr), h < kFlushChunks (consecutive lanes take
-// consecutive chunks).  vec[h]: the chunk is entirely kept, inside the plane
-// and aligned for one vector store in every template row.  Samples
-// [lo, hi) of a row are kept.
+// Per-thread flush plan.  FP32 rows: thread tid owns time samples
+// [t0, t0 + 4) with t0 = 4 (tid + h kThr), h < kFlushChunks (consecutive
+// lanes take consecutive chunks).  BF16 rows: the threads of one half of the
+// workgroup own 8 samples each, t0 = 8 (tid mod 512), so every store is 16
+// bytes (1 KB per wave); the halves take even and odd templates in turn.
+// vec[h] / vec8: the chunk is entirely kept, inside the plane and aligned
+// for one vector store in every template row.  Samples [lo, hi) of a row are
+// kept.
 constexpr int kFlushChunks = kL / (4 * kThr);
 struct FlushPlan {
     bool vec[kFlushChunks];
+    bool vec8;
     int lo, hi;
 };
 
@@ -152,15 +168,25 @@ __device__ __forceinline__ FlushPlan flush_plan(const PT *plane, int64_t seg0, i
         f.vec[h] = rows_aligned && (reinterpret_cast<uintptr_t>(plane + seg0 + t0) % kChunkBytes) == 0 &&
                    t0 >= f.lo && t0 + 4 <= f.hi;
     }
+    {
+        const int t0 = 8 * (tid & 511);
+        f.vec8 = (n % 8) == 0 && (reinterpret_cast<uintptr_t>(plane + seg0 + t0) % 16) == 0 && t0 >= f.lo &&
+                 t0 + 8 <= f.hi;
+    }
     return f;
 }
 
 template <class PT>
-__device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const FlushPlan &f, int tid) {
+__device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const FlushPlan &f, int tid, int jpar) {
+    if constexpr (sizeof(PT) == 2) {
+        // lower half of the workgroup: even templates, upper half: odd ones
+        if ((tid >> 9) == jpar) Stage<PT>::flush8(stage, 8 * (tid & 511), row_seg, f.vec8, f.lo, f.hi);
+    } else {
 #pragma unroll
-    for (int h = 0; h < kFlushChunks; ++h) {
-        const int t0 = 4 * (tid + h * kThr);
-        Stage<PT>::flush4(stage, t0, row_seg, f.vec[h], f.lo, f.hi);
+        for (int h = 0; h < kFlushChunks; ++h) {
+            const int t0 = 4 * (tid + h * kThr);
+            Stage<PT>::flush4(stage, t0, row_seg, f.vec[h], f.lo, f.hi);
+        }
     }
 }
 
@@ -273,7 +299,10 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
         for (int q = 0; q < kGpw; ++q) {
             const uint32_t hw[4] = {hc[q].x, hc[q].y, hc[q].z, hc[q].w};
 #pragma unroll
-            for (int p = 0; p < 4; ++p) bin[q].w[p] = bf16_pack(dot2(sA[q][p], hw[p]), dot2(sB[q][p], hw[p]));
+            for (int p = 0; p < 4; ++p) {
+                const f32x2_t z = zero_pair();
+                bin[q].w[p] = bf16_pack(dot2(sA[q][p], hw[p], z.x), dot2(sB[q][p], hw[p], z.y));
+            }
         }
     };
 
@@ -299,7 +328,7 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
             *reinterpret_cast<uint4 *>(&bufA[chunk_addr(Q, c, g)]) = o;   // (k1, n3, k2 block)
         }
         __syncthreads();
-        if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n + seg0, fp, tid);
+        if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n + seg0, fp, tid, (j - 1) & 1);
         // I2: DFT16 over k2 with e(16 n3 k2), transposed: lane (c, g)
         // receives n2 = c, k1 = 4 g + e -> one 16-byte chunk of buffer B
 #pragma unroll
@@ -355,7 +384,7 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
         one_template(j + 1, hB, hA, j + 2 < j1);
     }
     __syncthreads();
-    flush<PT>(stage, plane + (int64_t)(j1 - 1) * n + seg0, fp, tid);
+    flush<PT>(stage, plane + (int64_t)(j1 - 1) * n + seg0, fp, tid, (j1 - 1) & 1);
 }
 
 #define M4K_ATTR __attribute__((amdgpu_flat_work_group_size(kThr, kThr), amdgpu_waves_per_eu(kWavesPerEU)))
