@@ -70,6 +70,25 @@ def launch_stats(pl, x, plane, n=256):
     return {"mean": statistics.fmean(t), "std": statistics.pstdev(t), "median": statistics.median(t), "n": n}
 
 
+def fill_bandwidth(dev, nbytes=4 << 30, reps=10):
+    """Achieved HBM bandwidth of a plain device fill (write bytes only over
+    time): the ceiling for a path whose traffic is almost all plane writes."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        a.fill_(1.0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        a.fill_(1.0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a
+    return nbytes / (ms * 1e-3) / 1e9
+
+
 def copy_bandwidth(dev, nbytes=4 << 30, reps=10):
     """Achieved HBM bandwidth of a plain device-to-device copy (read + write
     bytes over time), the practical ceiling next to the 8 TB/s peak."""
@@ -363,8 +382,9 @@ def main():
 
     st_b = launch_stats(pl_b, x, plane_b)
     copy_gbs = copy_bandwidth(dev)
+    fill_gbs = fill_bandwidth(dev)
     note(f"per-launch BF16 {st_b['mean']:.4f} +- {st_b['std']:.4f} ms (median {st_b['median']:.4f}); "
-         f"device copy {copy_gbs:.0f} GB/s")
+         f"device copy {copy_gbs:.0f} GB/s, fill {fill_gbs:.0f} GB/s")
     # algorithmic HBM bytes per launch: the plane store plus one read of the
     # complex64 spectrum (templates are served from cache)
     bytes_b = cells * 2 + n * 8
@@ -395,7 +415,7 @@ def main():
                      "traffic": (measured_traffic(["correlate_m4k.hip", "mfma4096.hpp"])
                                  if pl_b.algo == "mfma" and pl_b.seg_len == 4096 else None),
                      "kernel": f"correlate_{pl_b.algo}{pl_b.seg_len} (BF16 form, raw BF16 plane)",
-                     "bytes_per_launch": bytes_b, "copy_frac": ach_b / copy_gbs},
+                     "bytes_per_launch": bytes_b, "copy_frac": ach_b / copy_gbs, "fill_frac": ach_b / fill_gbs},
         "fp32": {"value": cells / (ms_f * 1e-3), "unit": "cells/s", "ms_per_step": ms_f, "seg_len": pl_f.seg_len,
                  "hbm_frac": bytes_f / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "bf16_seg8192": {"value": cells / (ms_8 * 1e-3), "unit": "cells/s", "ms_per_step": ms_8},
@@ -404,6 +424,7 @@ def main():
                 "kernel": f"correlate_valu_fp8 (e4m3 stages, segment {pl_q.seg_len}, raw BF16 plane)"},
         "per_launch_ms": st_b,
         "copy_gbs": copy_gbs,
+        "fill_gbs": fill_gbs,
         "speedup_bf16_over_fp32": ms_f / ms_b,
         "wall_s": {"bf16": wall_b, "fp32": wall_f},
     }
