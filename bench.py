@@ -210,6 +210,23 @@ def batched_search(args, cfg, dev):
         ms = e0.elapsed_time(e1) / steps
         res[name] = {"ms_per_pass": ms, "cells_per_s": bs.cells / (ms * 1e-3)}
         note(f"batched {name}: {ms:.1f} ms per pass")
+    # the same pass recorded once as a HIP graph and replayed
+    g = bs.capture(spectra, c3["threshold"], find_peaks=True)
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    steps = max(1, min(args.steps, 3))
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res["correlate_and_peaks_graph"] = {"ms_per_pass": ms, "cells_per_s": bs.cells / (ms * 1e-3),
+                                        "launches_per_pass": len(bs.chunks) + len(lengths) * 5}
+    note(f"batched correlate_and_peaks as one HIP graph: {ms:.1f} ms per pass")
+    del g
     # an injected pulsar counts as found when a peak sits within 2 bins of
     # the mean frequency of one of its harmonics
     found, noise_peaks, injected = 0, 0, 0

@@ -8,17 +8,21 @@
 // row-major (z_idx, r) order and P >= each one that follows it.  Comparisons
 // are exact (values widened to double), NaN never qualifies.
 //
-// Deterministic three-kernel scheme with one tile = one plane row x
-// kPeakTileCols columns, tiles numbered in (z_idx, column block) order:
-//   mark   one streaming pass flags the tiles that hold a cell above the
-//          threshold;
-//   count  every flagged tile counts its peaks (unflagged tiles count zero);
-//   scan   one workgroup turns the per-workgroup totals into exclusive offsets
+// Deterministic scheme with one tile = one plane row x kPeakTileCols
+// columns, tiles numbered in (z_idx, column block) order and grouped in
+// chunks of 16 consecutive tiles:
+//   mark   one streaming pass flags the tiles (and their chunks) that hold a
+//          cell above the threshold;
+//   count  every flagged tile counts its peaks; per chunk the total (zero for
+//          a chunk without flags);
+//   scan   one workgroup turns the per-chunk totals into exclusive offsets
 //          and the total;
 //   write  every tile with peaks recomputes them and writes them at its offset
 //          in column order, dropping those at or beyond the capacity.
-// Each workgroup of the count and write kernels takes 16 consecutive tiles.
-// The list is therefore sorted by (z_idx, r) with no sort pass.
+// The count and write kernels run a fixed grid that strides over the chunks
+// and skips unflagged chunks after one byte read, so a plane with few peaks
+// costs one streaming read plus a few thousand workgroups.  The list is
+// sorted by (z_idx, r) with no sort pass.
 #include <algorithm>
 #include <type_traits>
 
@@ -29,8 +33,8 @@ namespace fdas {
 constexpr int kPeakThreads = 256;
 constexpr int kCellsPerThread = kPeakTileCols / kPeakThreads;   // 4
 
-// offsets (int64) and totals (int32) per workgroup of 16 tiles, counts
-// (int32) and flags (uint8) per tile
+// offsets (int64), totals (int32) and flags (uint8) per chunk of 16 tiles,
+// counts (int32) and flags (uint8) per tile
 size_t peak_scratch_bytes(int64_t n_tiles) {
     return (size_t)n_tiles * (sizeof(int32_t) + sizeof(int64_t)) + 256;
 }
@@ -84,35 +88,75 @@ __device__ __forceinline__ int tile_flags(const PT *plane, int64_t n, int n_z, i
     return cnt;
 }
 
-// Each workgroup takes kTilesPerBlock consecutive tiles.
+// Tiles per chunk (the unit of the per-chunk totals and offsets).
 constexpr int kTilesPerBlock = 16;
+// Workgroups of the count and write kernels (they stride over the chunks).
+constexpr int kPeakGrid = 2048;
 
 // Tile flags: flag[tile] = 1 iff the tile's row segment holds a cell above
-// the threshold (only such tiles can hold a peak).  k_peak_mark streams the
-// whole plane as one flat array in 16-byte vectors (any alignment of the
-// plane pointer: a head and a tail of single cells), so the common empty
+// the threshold (only such tiles can hold a peak), and the chunk flag
+// cflag[tile / 16] = 1 with it.  k_peak_mark streams the whole plane as one
+// flat array in 16-byte vectors, four per thread in flight (any alignment of
+// the plane pointer: a head and a tail of single cells), so the common empty
 // tile costs one read of its cells and no neighbourhood.  k_peak_clear
-// zeroes the flags at the start of every call (a kernel, not a memset, so
-// the call can be captured in a graph).
-__global__ void k_peak_clear(uint8_t *flags, int64_t n_tiles) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_tiles; i += (int64_t)gridDim.x * blockDim.x)
+// zeroes both flag arrays (n entries, stored back to back) at the start of
+// every call (a kernel, not a memset, so the call can be captured in a
+// graph).
+__global__ void k_peak_clear(uint8_t *flags, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         flags[i] = 0;
 }
 
 template <class PT>
 __device__ __forceinline__ void mark_cell(const PT *plane, int64_t f, int64_t n, int64_t n_cb, double thr,
-                                          uint8_t *flags) {
+                                          uint8_t *flags, uint8_t *cflags) {
     if (plane_val<PT>(plane, f) > thr) {
         const int64_t z = f / n, col = f - z * n;
-        flags[z * n_cb + col / kPeakTileCols] = 1;
+        const int64_t tile = z * n_cb + col / kPeakTileCols;
+        flags[tile] = 1;
+        cflags[tile / kTilesPerBlock] = 1;
     }
+}
+
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
+
+// Could the 16-byte vector u hold a cell above the threshold?  A superset
+// test (exact test in mark_cell).  Raw bfloat16 with thr >= 0: a cell above
+// thr has a bit pattern above tb, the pattern of thr truncated to bfloat16
+// (patterns of non-negative values order like the values; negative values
+// and NaN have larger patterns and are rechecked), four packed 16-bit
+// maxima.  Other types, or thr < 0 / NaN: the exact comparison.
+template <class PT>
+__device__ __forceinline__ bool maybe_above(const u32x4_t &u, double thr, unsigned short tb, bool use_bits) {
+    constexpr int kVec = 16 / sizeof(PT);
+    if constexpr (sizeof(PT) == 2) {
+        if (use_bits) {
+            // words copied to scalars first: a bit cast of a vector element
+            // expression (u.y) reads the vector's first element with this
+            // compiler
+            const uint32_t w0 = u.x, w1 = u.y, w2 = u.z, w3 = u.w;
+            const u16x2_t m = __builtin_elementwise_max(
+                __builtin_elementwise_max(__builtin_bit_cast(u16x2_t, w0), __builtin_bit_cast(u16x2_t, w1)),
+                __builtin_elementwise_max(__builtin_bit_cast(u16x2_t, w2), __builtin_bit_cast(u16x2_t, w3)));
+            return (m.x > tb) | (m.y > tb);
+        }
+    }
+    const PT *cells = reinterpret_cast<const PT *>(&u);
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < kVec; ++q) any |= plane_val<PT>(cells, q) > thr;
+    return any;
 }
 
 template <class PT>
 __global__ void __launch_bounds__(256) k_peak_mark(const PT *plane, int64_t n, int64_t total, int64_t n_cb, float thr_f,
-                                                   uint8_t *flags) {
+                                                   uint8_t *flags, uint8_t *cflags) {
     constexpr int kVec = 16 / sizeof(PT);   // cells per 16-byte vector
+    constexpr int kUnroll = 4;              // vectors in flight per thread
     const double thr = (double)thr_f;
+    const bool use_bits = thr_f >= 0.0f;    // false for NaN too
+    const unsigned short tb = (unsigned short)(__float_as_uint(thr_f) >> 16);
     const uintptr_t addr = reinterpret_cast<uintptr_t>(plane);
     int64_t head = (int64_t)(((16 - (addr & 15)) & 15) / sizeof(PT));
     if (head > total) head = total;
@@ -120,51 +164,60 @@ __global__ void __launch_bounds__(256) k_peak_mark(const PT *plane, int64_t n, i
     const int64_t tail0 = head + n_vec * kVec;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (gid < head) mark_cell<PT>(plane, gid, n, n_cb, thr, flags);
-    if (gid < total - tail0) mark_cell<PT>(plane, tail0 + gid, n, n_cb, thr, flags);
-    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+    if (gid < head) mark_cell<PT>(plane, gid, n, n_cb, thr, flags, cflags);
+    if (gid < total - tail0) mark_cell<PT>(plane, tail0 + gid, n, n_cb, thr, flags, cflags);
     const u32x4_t *vp = reinterpret_cast<const u32x4_t *>(plane + head);
-    for (int64_t v = gid; v < n_vec; v += stride) {
-        const u32x4_t u = __builtin_nontemporal_load(vp + v);
-        const PT *cells = reinterpret_cast<const PT *>(&u);
-        bool any = false;
+    for (int64_t v0 = gid; v0 < n_vec; v0 += kUnroll * stride) {
+        u32x4_t u[kUnroll];
 #pragma unroll
-        for (int q = 0; q < kVec; ++q) any |= plane_val<PT>(cells, q) > thr;
-        if (any) {   // rare: locate the cells
+        for (int k = 0; k < kUnroll; ++k) {
+            const int64_t v = v0 + k * stride;
+            u[k] = v < n_vec ? __builtin_nontemporal_load(vp + v) : u32x4_t{0u, 0u, 0u, 0u};
+        }
 #pragma unroll
-            for (int q = 0; q < kVec; ++q) mark_cell<PT>(plane, head + v * kVec + q, n, n_cb, thr, flags);
+        for (int k = 0; k < kUnroll; ++k) {
+            const int64_t v = v0 + k * stride;
+            if (v < n_vec && maybe_above<PT>(u[k], thr, tb, use_bits)) {   // rare: locate the cells
+#pragma unroll
+                for (int q = 0; q < kVec; ++q)
+                    mark_cell<PT>(plane, head + v * kVec + q, n, n_cb, thr, flags, cflags);
+            }
         }
     }
 }
 
 template <class PT>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, uint8_t *flags,
-             int32_t *counts, int32_t *block_counts) {
+k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, const uint8_t *flags,
+             const uint8_t *cflags, int32_t *counts, int32_t *block_counts) {
     __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
     __shared__ int sum;
-    const int64_t t0 = (int64_t)blockIdx.x * kTilesPerBlock;
-    int total = 0;   // thread 0: peaks of this workgroup's tiles
-    for (int i = 0; i < kTilesPerBlock; ++i) {
-        const int64_t tile = t0 + i;
-        if (tile >= n_tiles) break;
-        const int z = (int)(tile / n_cb);
-        const int64_t c0 = (tile % n_cb) * kPeakTileCols;
-        if (flags[tile] == 0) {                  // uniform: no cell above the threshold
-            if (threadIdx.x == 0) counts[tile] = 0;
+    const int64_t n_chunks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
+    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+        if (cflags[ch] == 0) {                   // uniform: no cell above the threshold in the chunk
+            if (threadIdx.x == 0) block_counts[ch] = 0;
             continue;
         }
-        if (threadIdx.x == 0) sum = 0;   // visible after the barrier inside tile_flags
-        bool flag[kCellsPerThread];
-        const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
-        if (cnt) atomicAdd(&sum, cnt);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            counts[tile] = sum;
-            total += sum;
+        int total = 0;   // thread 0: peaks of this chunk's tiles
+        for (int i = 0; i < kTilesPerBlock; ++i) {
+            const int64_t tile = ch * kTilesPerBlock + i;
+            if (tile >= n_tiles) break;
+            if (flags[tile] == 0) continue;      // uniform; its count is never read
+            const int z = (int)(tile / n_cb);
+            const int64_t c0 = (tile % n_cb) * kPeakTileCols;
+            if (threadIdx.x == 0) sum = 0;       // visible after the barrier inside tile_flags
+            bool flag[kCellsPerThread];
+            const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
+            if (cnt) atomicAdd(&sum, cnt);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                counts[tile] = sum;
+                total += sum;
+            }
+            __syncthreads();                     // buf and sum are reused by the next tile
         }
+        if (threadIdx.x == 0) block_counts[ch] = total;
     }
-    if (threadIdx.x == 0) block_counts[blockIdx.x] = total;
 }
 
 // Single workgroup: exclusive scan of the per-workgroup totals -> offsets,
@@ -232,19 +285,25 @@ __device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, 
 
 template <class PT>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_write(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, const int32_t *counts,
-             const int64_t *block_offsets, fdas_peak *out, int64_t capacity) {
+k_peak_write(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, const uint8_t *flags,
+             const int32_t *counts, const int32_t *block_counts, const int64_t *block_offsets, fdas_peak *out,
+             int64_t capacity) {
     __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
     __shared__ int pre[kPeakThreads];
-    int64_t off = block_offsets[blockIdx.x];
-    for (int i = 0; i < kTilesPerBlock; ++i) {
-        const int64_t tile = (int64_t)blockIdx.x * kTilesPerBlock + i;
-        if (tile >= n_tiles) break;
-        const int cnt = counts[tile];
-        if (cnt == 0) continue;            // uniform: no peak in this tile
-        write_tile<PT>(plane, n, n_z, n_cb, tile, thr, off, out, capacity, buf, pre);
-        off += cnt;
-        __syncthreads();                   // buf and pre are reused by the next tile
+    const int64_t n_chunks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
+    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+        if (block_counts[ch] == 0) continue;     // uniform: no peak in the chunk
+        int64_t off = block_offsets[ch];
+        for (int i = 0; i < kTilesPerBlock; ++i) {
+            const int64_t tile = ch * kTilesPerBlock + i;
+            if (tile >= n_tiles) break;
+            if (flags[tile] == 0) continue;      // uniform: counts[tile] was not written
+            const int cnt = counts[tile];
+            if (cnt == 0) continue;              // uniform: no peak in this tile
+            write_tile<PT>(plane, n, n_z, n_cb, tile, thr, off, out, capacity, buf, pre);
+            off += cnt;
+            __syncthreads();                     // buf and pre are reused by the next tile
+        }
     }
 }
 
@@ -256,21 +315,22 @@ hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, fdas
     const int64_t n_tiles = n_cb * p.cfg.n_z;
     if (n_tiles > p.peak_tile_cap || n_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
     unsigned char *scr = static_cast<unsigned char *>(p.ws) + p.off_scr;
-    const int64_t n_blocks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
-    int64_t *offsets = reinterpret_cast<int64_t *>(scr);                           // per workgroup
+    const int64_t n_blocks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;     // chunks
+    int64_t *offsets = reinterpret_cast<int64_t *>(scr);                           // per chunk
     int32_t *counts = reinterpret_cast<int32_t *>(scr + (size_t)n_blocks * sizeof(int64_t));   // per tile
-    int32_t *block_counts = counts + n_tiles;                                       // per workgroup
+    int32_t *block_counts = counts + n_tiles;                                       // per chunk
     uint8_t *flags = reinterpret_cast<uint8_t *>(block_counts + n_blocks);            // per tile
-    const unsigned blocks = (unsigned)n_blocks;
+    uint8_t *cflags = flags + n_tiles;                                              // per chunk
+    const unsigned grid = (unsigned)std::min<int64_t>(n_blocks, kPeakGrid);
     const int64_t total = n_tiles / n_cb * n;                                       // cells of the plane
-    hipLaunchKernelGGL(k_peak_clear, dim3((unsigned)std::min<int64_t>((n_tiles + 255) / 256, 4096)), dim3(256), 0, st,
-                       flags, n_tiles);
-    hipLaunchKernelGGL(k_peak_mark<PT>, dim3(8192), dim3(256), 0, st, plane, n, total, n_cb, thr, flags);
-    hipLaunchKernelGGL(k_peak_count<PT>, dim3(blocks), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb,
-                       n_tiles, thr, flags, counts, block_counts);
+    hipLaunchKernelGGL(k_peak_clear, dim3((unsigned)std::min<int64_t>((n_tiles + n_blocks + 255) / 256, 4096)),
+                       dim3(256), 0, st, flags, n_tiles + n_blocks);
+    hipLaunchKernelGGL(k_peak_mark<PT>, dim3(8192), dim3(256), 0, st, plane, n, total, n_cb, thr, flags, cflags);
+    hipLaunchKernelGGL(k_peak_count<PT>, dim3(grid), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb, n_tiles,
+                       thr, flags, cflags, counts, block_counts);
     hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, st, block_counts, offsets, n_blocks, n_found);
-    hipLaunchKernelGGL(k_peak_write<PT>, dim3(blocks), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb,
-                       n_tiles, thr, counts, offsets, out, cap);
+    hipLaunchKernelGGL(k_peak_write<PT>, dim3(grid), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb, n_tiles,
+                       thr, flags, counts, block_counts, offsets, out, cap);
     return hipGetLastError();
 }
 }  // namespace

@@ -7,7 +7,9 @@ autotuner (fdas_tune) measures fastest for its longest member, and its jobs
 are packed into chunks whose planes fit one reusable plane buffer.  A pass
 over the batch runs, per chunk, one persistent fdas_correlate_batch launch and
 the thresholded peak finder on every job's plane, so the full set of planes
-(tens of GB in BF16 for hundreds of trials) is never held at once.
+(tens of GB in BF16 for hundreds of trials) is never held at once.  A pass
+issues kernels only, so it can be recorded once as a HIP graph (capture) and
+replayed.
 """
 from __future__ import annotations
 
@@ -119,6 +121,25 @@ class BatchSearch:
                                       float(threshold), ctypes.c_void_p(self.peaks_raw[i].data_ptr()),
                                       self.peak_capacity, ctypes.c_void_p(self.n_found[i:i + 1].data_ptr()), s),
                          "fdas_peaks")
+
+    def capture(self, spectra, threshold, find_peaks=True):
+        """Record one pass (run) into a HIP graph and return it
+        (torch.cuda.CUDAGraph).  Every launch of a pass has fixed arguments
+        (each chunk has its own plan and job table, set at construction), and
+        the library records only kernels (counters and peak counts are
+        cleared by kernels, not memsets), so g.replay() runs a whole pass on
+        the current contents of spectra and refreshes the peak lists."""
+        import torch
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            self.run(spectra, threshold, find_peaks=find_peaks)      # warm-up on the capture stream
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run(spectra, threshold, find_peaks=find_peaks)
+        return g
 
     def peaks(self, i):
         """Peak list of job i after run() (host copy): dict of z_idx, r, power, n_found."""

@@ -115,3 +115,44 @@ def test_batch_search_strong_peak_vs_oracle(dev):
     assert (got["z_idx"][k], got["r"][k]) == (jz, jr)
     _, ro_r, _ = OPK.peaks(ref, 20.0)
     assert abs(got["n_found"] - len(ro_r)) <= max(2, len(ro_r) // 10)
+
+
+def test_batch_search_graph_replays_match_eager(dev):
+    """A whole pass (several chunks, every job's peaks) recorded once as a HIP
+    graph: each replay, on new spectra with eager work and synchronisation in
+    between, gives exactly the eager pass's peak lists."""
+    import torch
+    from paper_2206_12205_amd.pipeline import BatchSearch
+    lengths = [20000, 70001, 3001, 150000, 9000, 40000, 1, 131072]
+    n_z, M = 9, 128
+    say("[pipeline] graph capture of a pass")
+    xa = torch.from_numpy(np.concatenate(batch_spectra(lengths, seed=21))).to(dev)
+    xb = torch.from_numpy(np.concatenate(batch_spectra(lengths, seed=22))).to(dev)
+    bs = BatchSearch(lengths, -8.0, 2.0, n_z, M, compute="bf16", plane_dtype="bf16",
+                     buffer_bytes=n_z * 160000 * 2 * 2, tune=False, device=dev, peak_capacity=256)
+    assert len(bs.chunks) >= 3
+    thr = 20.0
+
+    def lists():
+        return [bs.peaks(i) for i in range(len(lengths))]
+
+    want = {}
+    for name, src in (("a", xa), ("b", xb)):
+        bs.run(src, thr)
+        torch.cuda.synchronize()
+        want[name] = lists()
+    spectra = xa.clone()
+    g = bs.capture(spectra, thr)
+    for rep, name in enumerate("abab"):
+        spectra.copy_(xa if name == "a" else xb)     # eager work between replays
+        bs.n_found.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = lists()
+        for i, (gi, wi) in enumerate(zip(got, want[name])):
+            assert gi["n_found"] == wi["n_found"], f"replay {rep} job {i}"
+            for k in ("z_idx", "r", "power"):
+                assert np.array_equal(gi[k], wi[k]), f"replay {rep} job {i} {k}"
+        _ = float(bs.buffer.float().sum().item())     # more eager work on the same stream
+    del g
