@@ -252,6 +252,37 @@ def batched_search(args, cfg, dev):
     return out
 
 
+def harmonic_timing(pl, plane, steps):
+    """fdas_harmonic_sum on the headline BF16 plane for H = 2, 4, 8, 16:
+    time per call, summed cells per second and HBM fraction of the
+    algorithmic bytes (the plane read once plus the summed plane written)."""
+    import torch
+    n_z, n = plane.shape
+    elem = plane.element_size()
+    res = {}
+    for H in (2, 4, 8, 16):
+        out = pl.harmonic_sum(plane, H)
+        for _ in range(10):
+            pl.harmonic_sum(plane, H, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(10, min(steps, 100))
+        e0.record()
+        for _ in range(reps):
+            pl.harmonic_sum(plane, H, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nh = (n - 1) // H + 1
+        alg = n_z * n * elem + n_z * nh * elem
+        res[f"H{H}"] = {"ms": ms, "summed_cells_per_s": n_z * nh / (ms * 1e-3),
+                        "algorithmic_GBs": alg / (ms * 1e-3) / 1e9,
+                        "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        note(f"harmonic sum H={H}: {ms:.3f} ms")
+        del out
+    return res
+
+
 def wide_search(args, dev):
     """Wide workload: 2^24 samples, 16 injected pulsars, 201 templates (z in
     [-200, 200]), 512 taps; the FP32, BF16 and FP8 planes timed and graded on
@@ -318,6 +349,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched many-spectra search (256 dedispersion trials)")
+    ap.add_argument("--no-harmonic", action="store_true", help="skip the harmonic-sum timing")
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the wide workload (201 x 8.4M planes in FP32, BF16 and FP8 vs FP64)")
     ap.add_argument("--trials", type=int, default=256,
@@ -397,6 +429,8 @@ def main():
          f"fp8 {ms_q:.3f} ms")
     del pl_v, pl_8
 
+    if not args.no_harmonic:
+        harm = harmonic_timing(pl_b, plane_b, args.steps)
     st_b = launch_stats(pl_b, x, plane_b)
     copy_gbs = copy_bandwidth(dev)
     fill_gbs = fill_bandwidth(dev)
@@ -504,6 +538,9 @@ def main():
                            "fp8_dsnr_pct_sigma": statistics.pstdev(dsnr_q) if dsnr_q else None,
                            "fp8_max_rel_power_err": err_q}
         del pl_d
+
+    if not args.no_harmonic:
+        out["harmonic_sum"] = {"workload": "the single-DM BF16 plane, BF16 sums out", **harm}
 
     if not args.no_batched:
         out["batched"] = batched_search(args, cfg, dev)

@@ -254,6 +254,27 @@ int fdas_tune(const fdas_config *cfg, const void *spectrum, int64_t n_bins, void
 int fdas_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, float threshold,
                fdas_peak *out, int64_t capacity, int64_t *n_found, void *stream);
 
+/* Incoherent harmonic sum of a plane written by fdas_correlate with the same
+ * plan.  Harmonic h of a periodic signal at (r, z) lies at (h r, h z)
+ * (Section "Detailed explanation"); the sum gathers the powers of the first
+ * n_harm harmonics onto the fundamental's cell:
+ *   S[j, r] = sum_{h=1..n_harm} P[j_h, h r],  r in [0, N_H),  N_H = (n_bins - 1) / n_harm + 1,
+ *   j_h = floor((h z_j - z_min) / z_step + 1/2)   (nearest template row of h z_j,
+ *         a tie going to the upper row; each step one IEEE double operation
+ *         in this order, z_j = z_min + j z_step),
+ * a term whose row j_h lies outside [0, n_z) being left out (one template:
+ * its row is kept for every h when z_min = 0, only for h = 1 otherwise).
+ *   plane    device, n_z x n_bins of the plan's plane dtype (element alignment)
+ *   n_harm   H, 1..32
+ *   out      device, n_z x N_H cells of the plan's plane dtype, row stride N_H
+ *            (element alignment); sums in single precision (double for an
+ *            FP64 plane), bfloat16 output rounded to nearest even.  fdas_peaks
+ *            on out with n_bins = N_H thresholds the summed plane.
+ * Needs no workspace.  FDAS_E_INVALID for bad pointers or sizes,
+ * FDAS_E_UNSUPPORTED for more than 65535 templates. */
+int fdas_harmonic_sum(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_harm, void *out,
+                      void *stream);
+
 /* Candidate refinement: matched-filter power at continuous (r, z) and its
  * gradient (no plan needed).  The plane samples the power on integer r and a
  * z grid, and quantisation in both axes moves peaks into adjacent bins

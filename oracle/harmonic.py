@@ -54,17 +54,18 @@ def harmonic_rows(z_min: float, z_step: float, n_z: int, n_harm: int) -> np.ndar
     return rows
 
 
-def harmonic_sum(P: np.ndarray, z_min: float, z_step: float, n_harm: int) -> np.ndarray:
-    """S_H (float64, n_z x N_H) of the plane P (n_z x N)."""
-    P = np.asarray(P, dtype=np.float64)
+def harmonic_sum(P: np.ndarray, z_min: float, z_step: float, n_harm: int, out_rows=None) -> np.ndarray:
+    """S_H (float64, n_z x N_H) of the plane P (n_z x N); with out_rows, only
+    those output rows (len(out_rows) x N_H), for sampling large planes."""
     n_z, n = P.shape
     nh = n_fundamentals(n, n_harm)
     rows = harmonic_rows(z_min, z_step, n_z, n_harm)
     r = np.arange(nh)
-    S = np.zeros((n_z, nh))
-    for j in range(n_z):
+    want = range(n_z) if out_rows is None else list(out_rows)
+    S = np.zeros((len(want), nh))
+    for k, j in enumerate(want):
         for h in range(1, n_harm + 1):
             jh = rows[j, h - 1]
             if jh >= 0:
-                S[j] += P[jh, h * r]
+                S[k] += np.asarray(P[jh, h * r], dtype=np.float64)
     return S

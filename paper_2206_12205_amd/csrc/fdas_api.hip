@@ -237,6 +237,17 @@ int fdas_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, float threshold
         fdas::launch_peaks(*p, plane, n_bins, threshold, out, capacity, n_found, static_cast<hipStream_t>(stream)));
 }
 
+int fdas_harmonic_sum(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_harm, void *out, void *stream) {
+    if (!p || !plane || !out) return FDAS_E_INVALID;
+    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
+    if ((reinterpret_cast<uintptr_t>(plane) % pe) != 0 || (reinterpret_cast<uintptr_t>(out) % pe) != 0)
+        return FDAS_E_INVALID;
+    if (n_bins < 1 || n_bins > p->cfg.max_bins || n_harm < 1 || n_harm > fdas::kMaxHarmonics)
+        return FDAS_E_INVALID;
+    if (p->cfg.n_z > 65535) return FDAS_E_UNSUPPORTED;
+    return hip_status(fdas::launch_harmonic_sum(*p, plane, n_bins, n_harm, out, static_cast<hipStream_t>(stream)));
+}
+
 int fdas_set_batch(fdas_plan_t p, const fdas_job *jobs, int32_t n_jobs, int64_t spectra_bins, int64_t plane_cells,
                    void *stream) {
     if (!p || !jobs || n_jobs < 1) return FDAS_E_INVALID;

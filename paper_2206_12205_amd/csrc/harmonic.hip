@@ -1,0 +1,122 @@
+// Incoherent harmonic summing over the f-fdot plane.
+//
+// Harmonic h of a periodic signal at (r, z) sits at (h r, h z) (Section
+// "Detailed explanation"), so summing the powers of the first H harmonics
+// onto the fundamental's cell gathers a pulsar's power spread over its
+// harmonics into one cell:
+//   S_H[j, r] = sum_{h=1..H} P[j_h, h r],  r < N_H = floor((N - 1) / H) + 1,
+//   j_h = floor((h z_j - z_min) / z_step + 1/2), z_j = z_min + j z_step,
+// terms with j_h outside the grid left out (one template: row 0 kept when
+// h z_0 = z_0).  The row of each harmonic is a decision taken in double
+// precision from the z grid; each step is one IEEE double operation in the
+// order written (no fused multiply-add), so the rows are exactly those of
+// that definition.
+//
+// One workgroup per (template row, block of 1024 fundamentals), 4 consecutive
+// fundamentals per thread; the workgroup's harmonic rows are computed once
+// into LDS.  Harmonic h of consecutive fundamentals is h bins apart, so the
+// reads of harmonic h touch every cache line of an h-times wider span: the
+// kernel reads about (H + 1) / 2 planes' worth of cache lines, held in part
+// by the L2 and the last-level cache.  Sums in FP32 (FP64 for an FP64
+// plane); the output has the plane's dtype (bfloat16 rounded to nearest
+// even), so fdas_peaks thresholds it directly.
+#include "internal.hpp"
+#include "plane_io.hpp"
+
+namespace fdas {
+
+namespace {
+
+constexpr int kHsThreads = 256;
+constexpr int kHsPerThread = 4;
+
+__device__ int harmonic_row(double z_min, double z_step, int n_z, int j, int h) {
+#pragma clang fp contract(off)
+    if (n_z == 1) return ((double)h * z_min == z_min) ? 0 : -1;
+    const double t = z_min + (double)j * z_step;
+    const double u = (double)h * t;
+    const double v = u - z_min;
+    const double x = v / z_step;
+    const double f = floor(x + 0.5);
+    if (!(f >= 0.0 && f < (double)n_z)) return -1;   // outside the grid (or NaN)
+    return (int)f;
+}
+
+// plane element -> accumulation type
+template <class PT>
+struct hs_io;
+template <>
+struct hs_io<float> {
+    using acc = float;
+    static __device__ __forceinline__ float get(const float *p, int64_t i) { return p[i]; }
+    static __device__ __forceinline__ void put(float *p, float v) { plane_store<float>::put(p, v); }
+};
+template <>
+struct hs_io<double> {
+    using acc = double;
+    static __device__ __forceinline__ double get(const double *p, int64_t i) { return p[i]; }
+    static __device__ __forceinline__ void put(double *p, double v) { plane_store<double>::put(p, v); }
+};
+template <>
+struct hs_io<__bf16> {
+    using acc = float;
+    static __device__ __forceinline__ float get(const __bf16 *p, int64_t i) {
+        return __uint_as_float((uint32_t)reinterpret_cast<const unsigned short *>(p)[i] << 16);   // exact
+    }
+    static __device__ __forceinline__ void put(__bf16 *p, float v) { plane_store<__bf16>::put(p, v); }
+};
+
+template <class PT>
+__global__ void __launch_bounds__(kHsThreads)
+k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, double z_step, int n_harm, int64_t nh,
+               PT *__restrict__ out) {
+    using A = typename hs_io<PT>::acc;
+    __shared__ int rows[kMaxHarmonics];
+    const int j = blockIdx.y;
+    if ((int)threadIdx.x < n_harm) rows[threadIdx.x] = harmonic_row(z_min, z_step, n_z, j, threadIdx.x + 1);
+    __syncthreads();
+    const int64_t r0 = ((int64_t)blockIdx.x * kHsThreads + threadIdx.x) * kHsPerThread;
+    if (r0 >= nh) return;
+    A acc[kHsPerThread];
+#pragma unroll
+    for (int i = 0; i < kHsPerThread; ++i) acc[i] = 0;
+    // h r <= H (N_H - 1) <= N - 1 for every kept fundamental r < N_H
+    for (int h = 1; h <= n_harm; ++h) {
+        const int jh = rows[h - 1];
+        if (jh < 0) continue;
+        const PT *row = plane + (int64_t)jh * n;
+#pragma unroll
+        for (int i = 0; i < kHsPerThread; ++i)
+            if (r0 + i < nh) acc[i] += hs_io<PT>::get(row, (int64_t)h * (r0 + i));
+    }
+    PT *o = out + (int64_t)j * nh;
+#pragma unroll
+    for (int i = 0; i < kHsPerThread; ++i)
+        if (r0 + i < nh) hs_io<PT>::put(o + r0 + i, acc[i]);
+}
+
+template <class PT>
+hipError_t run(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out, hipStream_t st) {
+    const int64_t nh = (n - 1) / n_harm + 1;
+    const int64_t per_block = (int64_t)kHsThreads * kHsPerThread;
+    const int64_t bx = (nh + per_block - 1) / per_block;
+    if (bx > 0x7fffffffLL || p.cfg.n_z > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_harmonic_sum<PT>, dim3((unsigned)bx, (unsigned)p.cfg.n_z), dim3(kHsThreads), 0, st,
+                       static_cast<const PT *>(plane), n, p.cfg.n_z, p.cfg.z_min, p.cfg.z_step, n_harm, nh,
+                       static_cast<PT *>(out));
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_harmonic_sum(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,
+                               hipStream_t st) {
+    switch (p.cfg.plane_dtype) {
+        case FDAS_FP32: return run<float>(p, plane, n, n_harm, out, st);
+        case FDAS_BF16: return run<__bf16>(p, plane, n, n_harm, out, st);
+        case FDAS_FP64: return run<double>(p, plane, n, n_harm, out, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fdas

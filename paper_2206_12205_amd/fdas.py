@@ -88,6 +88,7 @@ def lib() -> ctypes.CDLL:
         L.fdas_set_batch.argtypes = [P, ctypes.POINTER(FdasJob), I32, I64, I64, P]
         L.fdas_correlate_batch.argtypes = [P, P, P, P]
         L.fdas_peaks.argtypes = [P, P, I64, ctypes.c_float, P, I64, P, P]
+        L.fdas_harmonic_sum.argtypes = [P, P, I64, I32, P, P]
         D = ctypes.c_double
         L.fdas_refine.argtypes = [P, I64, I32, P, P, P, P, P, I32, I32, D, D, P]
         L.fdas_refine_backward.argtypes = [P, I64, I32, P, P, P, P, P, I32, P]
@@ -258,6 +259,23 @@ class Plan:
                                  ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
         return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(),
                 "power": rec["power"].copy(), "n_found": found}
+
+    def harmonic_sum(self, plane, n_harm, out=None, stream=None):
+        """Incoherent sum of the first n_harm harmonics of a plane (fdas_harmonic_sum):
+        an (n_z, (n - 1) // n_harm + 1) tensor of the plane dtype."""
+        import torch
+        if plane.dim() != 2 or plane.shape[0] != self.n_z or plane.dtype != self.torch_plane_dtype() \
+                or not plane.is_contiguous():
+            raise ValueError("plane must be a contiguous (n_z, n) tensor of the plan's plane dtype")
+        n = plane.shape[1]
+        nh = (n - 1) // int(n_harm) + 1 if n > 0 else 0
+        if out is None:
+            out = torch.empty((self.n_z, nh), dtype=plane.dtype, device=self.device)
+        elif out.shape != (self.n_z, nh) or out.dtype != plane.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous (n_z, N_H) tensor of the plane dtype")
+        _check(lib().fdas_harmonic_sum(self._h, ctypes.c_void_p(plane.data_ptr()), n, int(n_harm),
+                                       ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "fdas_harmonic_sum")
+        return out
 
     def bank(self):
         """Template bank as a complex tensor view (FP32/FP64), raw bfloat16

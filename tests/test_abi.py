@@ -101,6 +101,15 @@ def test_layout_and_workspace_checks_on_host():
         assert L.fdas_peaks(h, fake, 100, 1.0, None, 5, nf, None) == F.E_INVALID   # capacity>0, no out
         assert L.fdas_peaks(h, fake, 100, 1.0, fake, -1, nf, None) == F.E_INVALID
         assert L.fdas_peaks(h, fake, 100, 1.0, fake, 5, ctypes.c_void_p(0x20004), None) == F.E_INVALID
+        # harmonic sum: argument checks only (each returns before any launch)
+        assert L.fdas_harmonic_sum(h, fake, 100, 0, fake, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum(h, fake, 100, 33, fake, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum(h, fake, 0, 4, fake, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum(h, fake, 4097, 4, fake, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum(h, None, 100, 4, fake, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum(h, fake, 100, 4, None, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum(h, ctypes.c_void_p(0x10001), 100, 4, fake, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum(None, fake, 100, 4, fake, None) == F.E_INVALID
     finally:
         L.fdas_destroy(h)
     L.fdas_destroy(None)

@@ -1,0 +1,154 @@
+"""GPU parity of the harmonic sum (fdas_harmonic_sum) with the oracle.
+
+Both sides sum the same GPU plane (copied to the host), so the comparison
+isolates the summing: FP64 planes must agree exactly (both add the harmonics
+in order h = 1..H in double precision); FP32 sums within H 2^-23 relative
+(sequential single-precision additions); BF16 outputs, rounded from single
+precision, within one bfloat16 step of the oracle's double sum rounded the
+same way.  Peaks of the summed plane must be the oracle's peaks of the oracle
+sum.  The full single-DM BF16 plane is checked on sampled rows.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import harmonic as HS
+from oracle import peaks as OK_PEAKS
+from oracle import response as R
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def plan(dev, **kw):
+    from paper_2206_12205_amd.fdas import Plan
+    return Plan(device=dev, **kw)
+
+
+def host(t):
+    import torch
+    return t.to(torch.float64).cpu().numpy()
+
+
+def bf16_round(x):
+    """Round float64 values to bfloat16 (nearest even) through float32, as float64."""
+    import torch
+    return torch.from_numpy(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def check(got, want, dtype, n_harm, what):
+    assert got.shape == want.shape, what
+    if dtype == "fp64":
+        assert np.array_equal(got, want), what
+    elif dtype == "fp32":
+        err = np.abs(got - want) / np.maximum(np.abs(want), 1e-30)
+        assert err.max() <= n_harm * 2.0 ** -23, f"{what}: {err.max():.3e}"
+    else:
+        w = bf16_round(want)
+        # one bfloat16 step: 2^-7 of the value's binade
+        step = np.exp2(np.floor(np.log2(np.maximum(np.abs(w), 1e-30))) - 7)
+        d = np.abs(got - w)
+        assert np.all(d <= step), f"{what}: {np.max(d / step):.2f} steps"
+        assert np.mean(d != 0) < 0.01, what
+
+
+C1 = synth.CONFIGS[1]
+
+
+@pytest.mark.parametrize("pd", ["fp32", "bf16", "fp64"])
+@pytest.mark.parametrize("n_harm", [1, 2, 3, 8, 32])
+def test_harmonic_sum_tiny_workload(dev, pd, n_harm):
+    import torch
+    say(f"[harmonic] tiny {pd} H={n_harm}")
+    sp = synth.config1(0)
+    compute = "fp64" if pd == "fp64" else "fp32"
+    pl = plan(dev, max_bins=sp.spec.size, z_min=C1["z_min"], z_step=C1["z_step"], n_z=C1["n_z"],
+              n_taps=C1["n_taps"], seg_len=C1["seg_len"], compute=compute, plane_dtype=pd)
+    P = pl.correlate(torch.from_numpy(sp.spec).to(dev))
+    S = pl.harmonic_sum(P, n_harm)
+    want = HS.harmonic_sum(host(P), C1["z_min"], C1["z_step"], n_harm)
+    check(host(S), want, pd, n_harm, f"{pd} H={n_harm}")
+
+
+@pytest.mark.parametrize("z_min,z_step,n_z", [(-3.0, 2.0, 12), (0.0, 0.0, 1), (3.0, 0.0, 1), (-7.5, 1.25, 13)])
+@pytest.mark.parametrize("n", [1, 5, 1023, 4097])
+def test_harmonic_sum_grids_and_lengths(dev, z_min, z_step, n_z, n):
+    """Grids with ties (h z_j halfway between rows), single templates with and
+    without z = 0, lengths shorter than H and ragged block tails (FP64: exact)."""
+    import torch
+    say(f"[harmonic] grid z_min={z_min} step={z_step} n_z={n_z} n={n}")
+    rng = np.random.default_rng(n + n_z)
+    Ph = rng.exponential(size=(n_z, n))
+    pl = plan(dev, max_bins=max(n, 2), z_min=z_min, z_step=z_step, n_z=n_z, n_taps=16, compute="fp64",
+              plane_dtype="fp64")
+    P = torch.from_numpy(Ph).to(dev)
+    for H in (1, 2, 7, 32):
+        S = pl.harmonic_sum(P, H)
+        want = HS.harmonic_sum(Ph, z_min, z_step, H)
+        assert np.array_equal(host(S), want), f"H={H}"
+
+
+def test_peaks_of_the_summed_plane(dev):
+    """fdas_peaks on the summed FP64 plane = the oracle's peaks of the oracle sum."""
+    import torch
+    say("[harmonic] peaks of the sum")
+    sp = synth.config1(0)
+    pl = plan(dev, max_bins=sp.spec.size, z_min=C1["z_min"], z_step=C1["z_step"], n_z=C1["n_z"],
+              n_taps=C1["n_taps"], seg_len=C1["seg_len"], compute="fp64", plane_dtype="fp64")
+    P = pl.correlate(torch.from_numpy(sp.spec).to(dev))
+    for H in (2, 4):
+        S = pl.harmonic_sum(P, H)
+        want = HS.harmonic_sum(host(P), C1["z_min"], C1["z_step"], H)
+        thr = 2.0 * H + 6.0
+        got = pl.peaks(S, thr, capacity=4096)
+        j, r, pw = OK_PEAKS.peaks(want, thr)
+        assert got["n_found"] == len(j) > 0
+        assert np.array_equal(got["z_idx"], j) and np.array_equal(got["r"], r)
+
+
+def test_harmonic_series_of_chirps_on_the_gpu(dev):
+    """The sum at the fundamental's cell of a noise-free harmonic series of
+    chirps is the sum of their matched powers (the oracle pin's physics),
+    through the GPU plane and the GPU sum."""
+    import torch
+    say("[harmonic] chirp series")
+    n_t, r_bar, z, m, H = 1 << 14, 1000, 2.0, 64, 4
+    amps = [1.0, 0.7, 0.5, 0.3]
+    x = np.zeros(n_t // 2, dtype=np.complex128)
+    for h in range(1, H + 1):
+        x += synth.complex_chirp_spectrum(n_t, h * r_bar - h * z / 2, h * z, amps[h - 1])
+    pl = plan(dev, max_bins=x.size, z_min=-12.0, z_step=2.0, n_z=13, n_taps=m, seg_len=1024, compute="fp32")
+    S = host(pl.harmonic_sum(pl.correlate(torch.from_numpy(x.astype(np.complex64)).to(dev)), H))
+    e_ret = R.retained_energy([h * z for h in range(1, H + 1)], m)
+    want = sum(amps[h - 1] ** 2 * n_t * e_ret[h - 1] for h in range(1, H + 1))
+    j = 7                                                   # z = 2 on the grid -12, -10, ..., 12
+    assert np.unravel_index(np.argmax(S), S.shape) == (j, r_bar)
+    assert abs(S[j, r_bar] / want - 1.0) < 2e-3
+
+
+def test_single_dm_bf16_plane_sampled_rows(dev):
+    """Full single-DM size (101 x 4,194,304 BF16 plane, H = 8): the GPU sum on
+    sampled output rows (both ends, the z = 0 row and rows whose harmonics run
+    off the grid) against the oracle's sum of the same plane."""
+    import torch
+    c = synth.CONFIGS[2]
+    say("[harmonic] single-DM bf16 H=8")
+    x, _ = synth.config2_device(dev, 0)
+    n = x.numel()
+    pl = plan(dev, max_bins=n, z_min=c["z_min"], z_step=c["z_step"], n_z=c["n_z"], n_taps=c["n_taps"],
+              compute="bf16", plane_dtype="bf16")
+    P = pl.correlate(x)
+    S = pl.harmonic_sum(P, 8)
+    torch.cuda.synchronize()
+    Ph = P.view(torch.int16).cpu().numpy().view(np.uint16)    # raw bfloat16
+    Pf = (Ph.astype(np.uint32) << 16).view(np.float32)        # exact widening
+    rows = [0, 3, 44, 49, 50, 51, 56, 57, 100]
+    want = HS.harmonic_sum(Pf, c["z_min"], c["z_step"], 8, out_rows=rows)
+    got = host(S[rows])
+    check(got, want, "bf16", 8, "single-DM rows")
