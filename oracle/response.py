@@ -40,6 +40,12 @@ and the plane is P[z, r] = |sum_m X[r - m] g_z[m]|^2 (X = 0 outside [0, N)).
 The overlap-save form needs the length-L spectrum of the circularly placed
 taps, H_z = FFT_L(h_z) / L with h_z[m mod L] = g_z[m]; the 1/L folds the
 inverse transform's normalisation into the template.
+
+Jerk.  A third search axis (not in the paper, which searches z only): a
+sinusoid whose drift changes by w bins over the observation has response
+A(q, z, w) = integral_0^1 exp(i pi (2 q u + z u^2 + w u^3 / 3)) du, taken
+here by the composite Simpson rule (response_jerk), and templates
+g[m] = conj(A(m - z/2 - w/6, z, w)) / ||.||.
 """
 from __future__ import annotations
 
@@ -145,33 +151,64 @@ def response_grad(q, z):
     return dq, dz
 
 
+def response_jerk(q, z, w, phase_step: float = 0.02) -> np.ndarray:
+    """A(q, z, w) = integral_0^1 exp(i pi (2 q u + z u^2 + w u^3 / 3)) du.
+
+    A sinusoid whose frequency runs r0 + z u + w u^2 / 2 over the observation
+    (w: the change of the drift, the jerk search's third axis).  No closed
+    form: composite Simpson rule on an even number of intervals, each at most
+    phase_step radians of phase (|phase'| <= pi (2|q| + 2|z| + |w|)), so the
+    rule's error (h phase')^4 / 180 stays near 1e-9."""
+    q = np.atleast_1d(np.asarray(q, dtype=np.float64))
+    z = np.atleast_1d(np.asarray(z, dtype=np.float64))
+    w = np.atleast_1d(np.asarray(w, dtype=np.float64))
+    q, z, w = np.broadcast_arrays(q, z, w)
+    out = np.empty(q.shape, dtype=np.complex128)
+    for idx in np.ndindex(q.shape):
+        qq, zz, ww = q[idx], z[idx], w[idx]
+        rate = math.pi * (2.0 * abs(qq) + 2.0 * abs(zz) + abs(ww))
+        n = max(64, 2 * int(math.ceil(rate / phase_step / 2.0)))
+        u = np.linspace(0.0, 1.0, n + 1)
+        f = np.exp(1j * math.pi * (2.0 * qq * u + zz * u * u + ww * u ** 3 / 3.0))
+        coef = np.ones(n + 1)
+        coef[1:-1:2] = 4.0
+        coef[2:-1:2] = 2.0
+        out[idx] = np.dot(coef, f) / (3.0 * n)
+    return out
+
+
 def z_grid(z_min: float, z_step: float, n_z: int) -> np.ndarray:
     return z_min + z_step * np.arange(n_z, dtype=np.float64)
 
 
-def template_taps(zs, n_taps: int, normalise: bool = True) -> np.ndarray:
-    """g_z[m] for m in [-M/2, M/2), rows per z, column i = m + M/2 (complex128)."""
+def template_taps(zs, n_taps: int, normalise: bool = True, w: float = 0.0) -> np.ndarray:
+    """g_z[m] for m in [-M/2, M/2), rows per z, column i = m + M/2 (complex128).
+    With a jerk w: g_z[m] = conj(A(m - z/2 - w/6, z, w)) / ||.|| (r stays the
+    mean frequency r0 + z/2 + w/6)."""
     if n_taps % 2:
         raise ValueError("n_taps must be even")
     zs = np.atleast_1d(np.asarray(zs, dtype=np.float64))
     m = np.arange(-n_taps // 2, n_taps // 2, dtype=np.float64)
-    g = np.conj(response(m[None, :] - 0.5 * zs[:, None], zs[:, None]))
+    if w == 0.0:
+        g = np.conj(response(m[None, :] - 0.5 * zs[:, None], zs[:, None]))
+    else:
+        g = np.conj(response_jerk(m[None, :] - 0.5 * zs[:, None] - w / 6.0, zs[:, None], w))
     if normalise:
         g /= np.linalg.norm(g, axis=1, keepdims=True)
     return g
 
 
-def retained_energy(zs, n_taps: int) -> np.ndarray:
-    """sum over the M taps of |A(m - z/2, z)|^2 (Parseval: 1 over all m)."""
-    g = template_taps(zs, n_taps, normalise=False)
+def retained_energy(zs, n_taps: int, w: float = 0.0) -> np.ndarray:
+    """sum over the M taps of |A(m - z/2 - w/6, z, w)|^2 (Parseval: 1 over all m)."""
+    g = template_taps(zs, n_taps, normalise=False, w=w)
     return np.sum(np.abs(g) ** 2, axis=1)
 
 
-def template_spectra(zs, n_taps: int, seg_len: int) -> np.ndarray:
+def template_spectra(zs, n_taps: int, seg_len: int, w: float = 0.0) -> np.ndarray:
     """H_z = FFT_L(h_z) / L with h_z[m mod L] = g_z[m]; rows per z, complex128."""
     if seg_len <= n_taps:
         raise ValueError("segment length must exceed the tap count")
-    g = template_taps(zs, n_taps)
+    g = template_taps(zs, n_taps, w=w)
     h = np.zeros((g.shape[0], seg_len), dtype=np.complex128)
     m = np.arange(-n_taps // 2, n_taps // 2)
     h[:, np.mod(m, seg_len)] = g

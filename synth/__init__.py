@@ -202,14 +202,14 @@ def random_spectrum(n_bins: int, seed: int) -> np.ndarray:
     return s.astype(np.complex64)
 
 
-def complex_chirp_spectrum(n_t: int, r0: float, z: float, amp: float = 1.0):
-    """Noise-free spectrum of amp * exp(2 pi i (r0 u + z u^2 / 2)), u = n / n_t.
+def complex_chirp_spectrum(n_t: int, r0: float, z: float, amp: float = 1.0, w: float = 0.0):
+    """Noise-free spectrum of amp * exp(2 pi i (r0 u + z u^2 / 2 + w u^3 / 6)), u = n / n_t.
 
     Full complex FFT (a complex chirp has no mirror image), divided by sqrt(n_t)
     (declared sigma 1), first n_t / 2 bins kept, complex64.
     """
     u = np.arange(n_t, dtype=np.float64) / n_t
-    cyc = r0 * u + 0.5 * z * u * u
+    cyc = r0 * u + 0.5 * z * u * u + w * u * u * u / 6.0
     cyc -= np.floor(cyc)
     x = amp * np.exp(2j * np.pi * cyc)
     X = np.fft.fft(x)[: n_t // 2] / math.sqrt(n_t)
