@@ -283,6 +283,50 @@ def harmonic_timing(pl, plane, steps):
     return res
 
 
+def jerk_volume(args, cfg, dev, x, plane):
+    """Jerk search on the single-DM spectrum: five planes w = -60, -30, 0, 30,
+    60 (BF16 form, matrix-core kernel), one plan (and template bank) per w,
+    built once; the volume time is the five correlations.  The bank build per
+    w (quadrature of the cubic-phase response in FP64) is timed apart."""
+    import torch
+    from paper_2206_12205_amd.fdas import Plan
+    ws = (-60.0, -30.0, 0.0, 30.0, 60.0)
+    n = x.numel()
+    common = dict(max_bins=n, z_min=cfg["z_min"], z_step=cfg["z_step"], n_z=cfg["n_z"], n_taps=cfg["n_taps"],
+                  compute="bf16", plane_dtype="bf16", device=dev)
+    plans = []
+    for w in ws:
+        pl = Plan(**common)
+        pl.make_templates(w=w)
+        plans.append(pl)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        plans[-1].make_templates(w=ws[-1])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_bank = e0.elapsed_time(e1) / 3
+    for _ in range(20):
+        for pl in plans:
+            pl.correlate(x, plane)
+    torch.cuda.synchronize()
+    reps = max(5, min(args.steps, 50))
+    e0.record()
+    for _ in range(reps):
+        for pl in plans:
+            pl.correlate(x, plane)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    cells = len(ws) * cfg["n_z"] * n
+    note(f"jerk volume: {len(ws)} w planes in {ms:.3f} ms; bank build {ms_bank:.2f} ms per w")
+    del plans
+    return {"workload": f"single-DM spectrum, w in {list(ws)} x {cfg['n_z']} z x {n} r, BF16 form, one plan "
+                        f"per w", "cells": cells, "ms_per_volume": ms, "cells_per_s": cells / (ms * 1e-3),
+            "bank_build_ms_per_w": ms_bank}
+
+
 def wide_search(args, dev):
     """Wide workload: 2^24 samples, 16 injected pulsars, 201 templates (z in
     [-200, 200]), 512 taps; the FP32, BF16 and FP8 planes timed and graded on
@@ -350,6 +394,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched many-spectra search (256 dedispersion trials)")
     ap.add_argument("--no-harmonic", action="store_true", help="skip the harmonic-sum timing")
+    ap.add_argument("--no-jerk", action="store_true", help="skip the jerk-volume timing")
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the wide workload (201 x 8.4M planes in FP32, BF16 and FP8 vs FP64)")
     ap.add_argument("--trials", type=int, default=256,
@@ -541,6 +586,9 @@ def main():
 
     if not args.no_harmonic:
         out["harmonic_sum"] = {"workload": "the single-DM BF16 plane, BF16 sums out", **harm}
+
+    if not args.no_jerk:
+        out["jerk"] = jerk_volume(args, cfg, dev, x, plane_b)
 
     if not args.no_batched:
         out["batched"] = batched_search(args, cfg, dev)

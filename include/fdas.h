@@ -182,6 +182,22 @@ int fdas_get_layout(fdas_plan_t plan, fdas_layout *out);
  * stream; FDAS_E_WORKSPACE without a workspace. */
 int fdas_make_templates(fdas_plan_t plan, void *stream);
 
+/* Template bank of one plane of a jerk search: the same z grid, the taps
+ * of a sinusoid whose drift itself changes by w bins over the observation
+ * (frequency r0 + z u + w u^2 / 2, u in [0, 1)):
+ *   A(q, z, w) = int_0^1 exp(i pi (2 q u + z u^2 + w u^3 / 3)) du,
+ *   g_j[m] = conj(A(m - z_j/2 - w/6, z_j, w)) / ||.||_2
+ * (r stays the mean frequency).  The paper searches z only (Section
+ * "Introduction" cites the method); w extends the same correlation to the
+ * f-fdot-fddot volume one plane per w.  The response has no closed form and
+ * is integrated on the GPU by composite 16-point Gauss-Legendre quadrature in
+ * double precision (panels of at most half a turn of phase); w = 0 is
+ * exactly fdas_make_templates (closed form).  The rest as
+ * fdas_make_templates: asynchronous on stream, FDAS_E_WORKSPACE without a
+ * workspace, FDAS_E_INVALID for a non-finite w; fdas_correlate then writes
+ * the plane of this w. */
+int fdas_make_templates_jerk(fdas_plan_t plan, double w, void *stream);
+
 /* The f-fdot plane of one spectrum.
  *   spectrum  device, n_bins complex64 values (interleaved re, im floats)
  *   n_bins    N, 1 <= N <= max_bins

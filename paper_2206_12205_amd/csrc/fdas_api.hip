@@ -210,6 +210,15 @@ int fdas_make_templates(fdas_plan_t p, void *stream) {
     return s;
 }
 
+int fdas_make_templates_jerk(fdas_plan_t p, double w, void *stream) {
+    if (!p || !std::isfinite(w)) return FDAS_E_INVALID;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    p->templates_ready = false;
+    const int s = hip_status(fdas::launch_make_templates(*p, static_cast<hipStream_t>(stream), w));
+    if (s == FDAS_OK) p->templates_ready = true;
+    return s;
+}
+
 int fdas_correlate(fdas_plan_t p, const void *spectrum, int64_t n_bins, void *plane, void *stream) {
     if (!p || !spectrum || !plane) return FDAS_E_INVALID;
     if (!aligned16(spectrum) || !aligned16(plane)) return FDAS_E_INVALID;

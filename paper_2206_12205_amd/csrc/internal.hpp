@@ -55,7 +55,7 @@ struct fdas_plan_s {
 namespace fdas {
 
 // Template bank + twiddle table (templates.hip).
-hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t s);
+hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t s, double w = 0.0);
 
 // Matrix-core correlation, L = 8192, BF16 form (correlate_mfma.hip).
 hipError_t launch_correlate_mfma(const fdas_plan_s &p, const void *spec, int64_t n,

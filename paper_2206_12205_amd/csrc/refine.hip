@@ -33,17 +33,6 @@
 
 namespace fdas {
 
-__device__ constexpr double kGLx[16] = {
-    0.0052995325041750307, 0.0277124884633837,  0.067184398806084122, 0.1222977958224985,
-    0.19106187779867811,   0.27099161117138632, 0.35919822461037054,  0.45249374508118129,
-    0.54750625491881877,   0.64080177538962946, 0.72900838882861363,  0.80893812220132189,
-    0.87770220417750155,   0.93281560119391593, 0.9722875115366163,   0.99470046749582497};
-__device__ constexpr double kGLw[16] = {
-    0.013576229705877019, 0.031126761969323853, 0.047579255841246296, 0.062314485627767015,
-    0.074797994408288382, 0.08457825969750131,  0.091301707522461806, 0.094725305227534293,
-    0.094725305227534293, 0.091301707522461806, 0.08457825969750131,  0.074797994408288382,
-    0.062314485627767015, 0.047579255841246296, 0.031126761969323853, 0.013576229705877019};
-
 // A, A_q, A_z at (q, z).
 __device__ void response_d(double q, double z, cd &A, cd &Aq, cd &Az) {
     const double twopi = 2.0 * M_PI;

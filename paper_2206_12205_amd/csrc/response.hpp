@@ -145,6 +145,36 @@ __device__ inline cd moment2(double q) {
     return ea * (ia - 2.0 * ia2 + 2.0 * ia3) - 2.0 * ia3;
 }
 
+// 16-point Gauss-Legendre nodes and weights on [0, 1].
+__device__ constexpr double kGLx[16] = {
+    0.0052995325041750307, 0.0277124884633837,  0.067184398806084122, 0.1222977958224985,
+    0.19106187779867811,   0.27099161117138632, 0.35919822461037054,  0.45249374508118129,
+    0.54750625491881877,   0.64080177538962946, 0.72900838882861363,  0.80893812220132189,
+    0.87770220417750155,   0.93281560119391593, 0.9722875115366163,   0.99470046749582497};
+__device__ constexpr double kGLw[16] = {
+    0.013576229705877019, 0.031126761969323853, 0.047579255841246296, 0.062314485627767015,
+    0.074797994408288382, 0.08457825969750131,  0.091301707522461806, 0.094725305227534293,
+    0.094725305227534293, 0.091301707522461806, 0.08457825969750131,  0.074797994408288382,
+    0.062314485627767015, 0.047579255841246296, 0.031126761969323853, 0.013576229705877019};
+
+// Response with a jerk term, A(q, z, w) = int_0^1 exp(i pi (2 q u + z u^2 +
+// w u^3 / 3)) du: a sinusoid whose frequency (bins) runs r0 + z u + w u^2 / 2
+// over the observation (w the change of the drift; w = 0 is A(q, z)).  No
+// closed form: composite 16-point Gauss-Legendre quadrature with panels of
+// at most half a turn of phase (|phase'| <= pi (2|q| + 2|z| + |w|) on [0, 1]).
+__device__ inline cd response_jerk(double q, double z, double w) {
+    const int npan = (int)ceil(2.0 * fabs(q) + 2.0 * fabs(z) + fabs(w)) + 2;
+    cd s = {0.0, 0.0};
+    for (int pn = 0; pn < npan; ++pn) {
+        for (int i = 0; i < 16; ++i) {
+            const double u = (pn + kGLx[i]) / npan;
+            const double wt = kGLw[i] / npan;
+            s = s + wt * expipi(2.0 * q * u + z * u * u + w * u * u * u / 3.0);
+        }
+    }
+    return s;
+}
+
 // A(q, z) for any real q, z.
 __device__ inline cd response(double q, double z) {
     if (fabs(z) < 1e-6) {

@@ -3,7 +3,8 @@
 // The paper generates its templates in a higher precision and converts them
 // to the reduced one with a GPU kernel (Section "Template conversion"; the
 // bfloat16 conversion statistics are Table 1).  Here:
-//   taps      g_j[m] = conj(A(m - z_j/2, z_j)),  m in [-M/2, M/2)   (FP64)
+//   taps      g_j[m] = conj(A(m - z_j/2, z_j)),  m in [-M/2, M/2)   (FP64);
+//             with a jerk w: conj(A(m - z_j/2 - w/6, z_j, w)) (response.hpp)
 //   norm      g_j /= ||g_j||_2                                       (FP64)
 //   spectrum  H_j[k] = (1/L) sum_m g_j[m] exp(-2 pi i k m / L),  k in [0, L)
 //             i.e. the length-L DFT of the circularly placed taps h[m mod L],
@@ -29,6 +30,17 @@ __global__ void k_taps(cd *taps, int32_t n_z, int32_t M, double z_min, double z_
     const int m = (int)(i % M) - M / 2;
     const double z = z_min + z_step * j;
     taps[i] = conj(response((double)m - 0.5 * z, z));
+}
+
+// Taps of a jerk search plane: g_j[m] = conj(A(m - z_j/2 - w/6, z_j, w)),
+// m - z_j/2 - w/6 being the offset from the mean frequency r0 + z/2 + w/6.
+__global__ void k_taps_jerk(cd *taps, int32_t n_z, int32_t M, double z_min, double z_step, double w) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_z * M) return;
+    const int j = (int)(i / M);
+    const int m = (int)(i % M) - M / 2;
+    const double z = z_min + z_step * j;
+    taps[i] = conj(response_jerk((double)m - 0.5 * z - w / 6.0, z, w));
 }
 
 // One workgroup per template: l2 norm by a fixed-order tree reduction.
@@ -203,12 +215,16 @@ __global__ void k_twiddles(cpx<R> *tw, int32_t L) {
     tw[e] = {(R)cs, (R)sn};
 }
 
-hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st) {
+hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st, double w) {
     unsigned char *ws = static_cast<unsigned char *>(p.ws);
     cd *taps = reinterpret_cast<cd *>(ws + p.off_taps);
     const int64_t nt = (int64_t)p.cfg.n_z * p.M;
-    hipLaunchKernelGGL(k_taps, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, taps, p.cfg.n_z, p.M,
-                       p.cfg.z_min, p.cfg.z_step);
+    if (w == 0.0)
+        hipLaunchKernelGGL(k_taps, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, taps, p.cfg.n_z, p.M,
+                           p.cfg.z_min, p.cfg.z_step);
+    else
+        hipLaunchKernelGGL(k_taps_jerk, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, taps, p.cfg.n_z, p.M,
+                           p.cfg.z_min, p.cfg.z_step, w);
     hipLaunchKernelGGL(k_normalise, dim3(p.cfg.n_z), dim3(256), 0, st, taps, p.M);
     const dim3 grid((unsigned)((p.L + 255) / 256), (unsigned)p.cfg.n_z);
     const size_t lds = (size_t)p.M * sizeof(cd);

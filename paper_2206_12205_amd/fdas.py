@@ -90,6 +90,7 @@ def lib() -> ctypes.CDLL:
         L.fdas_peaks.argtypes = [P, P, I64, ctypes.c_float, P, I64, P, P]
         L.fdas_harmonic_sum.argtypes = [P, P, I64, I32, P, P]
         D = ctypes.c_double
+        L.fdas_make_templates_jerk.argtypes = [P, D, P]
         L.fdas_refine.argtypes = [P, I64, I32, P, P, P, P, P, I32, I32, D, D, P]
         L.fdas_refine_backward.argtypes = [P, I64, I32, P, P, P, P, P, I32, P]
         L.fdas_strerror.argtypes = [ctypes.c_int]
@@ -170,8 +171,14 @@ class Plan:
     def algo(self) -> str:
         return {ALGO_VALU: "valu", ALGO_MFMA: "mfma"}[int(self.layout.algo)]
 
-    def make_templates(self, stream=None):
-        _check(lib().fdas_make_templates(self._h, _stream_ptr(stream)), "fdas_make_templates")
+    def make_templates(self, stream=None, w=0.0):
+        """Template bank of the plan's z grid; w != 0: the plane of jerk w
+        (fdas_make_templates_jerk)."""
+        if w == 0.0:
+            _check(lib().fdas_make_templates(self._h, _stream_ptr(stream)), "fdas_make_templates")
+        else:
+            _check(lib().fdas_make_templates_jerk(self._h, float(w), _stream_ptr(stream)),
+                   "fdas_make_templates_jerk")
 
     def torch_plane_dtype(self):
         import torch

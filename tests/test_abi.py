@@ -88,6 +88,9 @@ def test_layout_and_workspace_checks_on_host():
         assert lay.bank_offset % 256 == 0 and lay.twiddle_offset % 256 == 0
         fake = ctypes.c_void_p(0x10000)           # never dereferenced on these paths
         assert L.fdas_correlate(h, fake, 100, fake, None) == F.E_WORKSPACE
+        assert L.fdas_make_templates_jerk(h, 12.0, None) == F.E_WORKSPACE
+        assert L.fdas_make_templates_jerk(h, float("nan"), None) == F.E_INVALID
+        assert L.fdas_make_templates_jerk(None, 12.0, None) == F.E_INVALID
         assert L.fdas_set_workspace(h, fake, n.value - 1) == F.E_WORKSPACE
         assert L.fdas_set_workspace(h, ctypes.c_void_p(0x10008), n.value) == F.E_INVALID
         assert L.fdas_set_workspace(h, None, n.value) == F.E_WORKSPACE
