@@ -78,3 +78,31 @@ def margins(P, j, r, threshold: float):
                     gap = min(gap, abs(c - float(P[a, b])))
         out[i] = gap / max(c, 1.0)
     return out
+
+
+def band_max(P, windows):
+    """Highest cell of each window (z_lo, z_hi, r_lo, r_hi), half-open and
+    clipped to the plane: the paper's peak-finding method takes the highest
+    point of each harmonic band (Section "Peakfinding methodology", Table 3).
+    NaN cells are skipped; ties go to the first cell in (z_idx, r) order.
+    Returns (z_idx int64, r int64, power float64); a window with no
+    non-NaN cell gives (-1, -1, nan)."""
+    n_z, n = P.shape
+    zs, rs, ps = [], [], []
+    for z_lo, z_hi, r_lo, r_hi in windows:
+        a, b = max(int(z_lo), 0), min(int(z_hi), n_z)
+        c, d = max(int(r_lo), 0), min(int(r_hi), n)
+        best = None
+        if a < b and c < d:
+            blk = np.asarray(P[a:b, c:d], dtype=np.float64)
+            ok = ~np.isnan(blk)
+            if ok.any():
+                m = np.max(blk[ok])
+                jj, rr = np.nonzero(ok & (blk == m))      # row-major order: the first is the tie winner
+                best = (a + int(jj[0]), c + int(rr[0]), float(m))
+        if best is None:
+            best = (-1, -1, float("nan"))
+        zs.append(best[0])
+        rs.append(best[1])
+        ps.append(best[2])
+    return np.array(zs, np.int64), np.array(rs, np.int64), np.array(ps)

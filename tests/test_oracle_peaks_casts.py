@@ -149,3 +149,29 @@ def test_e4m3_table_and_rounding():
     x = np.exp(g.uniform(np.log(2.0 ** -6), np.log(448.0), 2000))
     r = C.to_e4m3(x)
     assert np.max(np.abs(r - x) / x) <= 2.0 ** -4 + 1e-15
+
+
+def test_band_max_against_brute_force_with_ties_nan_and_clipping():
+    """Band maxima vs a pure-Python scan in (z, r) order (ties: first cell;
+    NaN skipped; windows clipped at the plane's edges; empty windows)."""
+    from oracle import peaks as OPK
+    rng = np.random.default_rng(7)
+    P = np.round(rng.uniform(0, 4, size=(9, 57)))          # few distinct values: many ties
+    P[3, 10:20] = np.nan
+    P[0:2, 50:57] = np.nan
+    windows = [(0, 9, 0, 57), (2, 5, 8, 22), (-3, 2, 48, 70), (0, 2, 50, 57), (4, 4, 0, 10),
+               (7, 20, -5, 3), (3, 4, 10, 20), (1, 8, 30, 31)]
+    z, r, p = OPK.band_max(P, windows)
+    for k, (z_lo, z_hi, r_lo, r_hi) in enumerate(windows):
+        best = None
+        for zz in range(max(z_lo, 0), min(z_hi, 9)):
+            for cc in range(max(r_lo, 0), min(r_hi, 57)):
+                v = P[zz, cc]
+                if v != v:
+                    continue
+                if best is None or v > best[2]:
+                    best = (zz, cc, v)
+        if best is None:
+            assert (z[k], r[k]) == (-1, -1) and np.isnan(p[k])
+        else:
+            assert (z[k], r[k], p[k]) == best
