@@ -270,6 +270,25 @@ int fdas_tune(const fdas_config *cfg, const void *spectrum, int64_t n_bins, void
 int fdas_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, float threshold,
                fdas_peak *out, int64_t capacity, int64_t *n_found, void *stream);
 
+/* Band maxima of a plane written by fdas_correlate with the same plan: the
+ * paper's own peak finding takes the highest point of each harmonic band
+ * (Section "Peakfinding methodology", band bounds in Table 3), and the same
+ * reduction over noise-only planes measures the noise canopy (Section
+ * "Extreme bin drifts").
+ *   windows  device, n_windows x 4 int64 (z_lo, z_hi, r_lo, r_hi): template
+ *            rows [z_lo, z_hi) x bins [r_lo, r_hi), clipped to the plane
+ *            (8-byte aligned)
+ *   out      device, n_windows entries (16-byte aligned): r, z_idx and power
+ *            (the plane value as single precision) of the window's highest
+ *            cell, job = 0; NaN cells are skipped, ties go to the first cell
+ *            in (z_idx, r) order; a window with no non-NaN cell gives
+ *            r = z_idx = -1 and power NaN
+ * Deterministic (order-independent reductions).  Needs no workspace; out is
+ * also the accumulator while the call runs.  FDAS_E_INVALID for bad
+ * pointers, n_bins outside [1, max_bins] or n_windows outside [1, 65535]. */
+int fdas_band_max(fdas_plan_t plan, const void *plane, int64_t n_bins, const int64_t *windows,
+                  int32_t n_windows, fdas_peak *out, void *stream);
+
 /* Incoherent harmonic sum of a plane written by fdas_correlate with the same
  * plan.  Harmonic h of a periodic signal at (r, z) lies at (h r, h z)
  * (Section "Detailed explanation"); the sum gathers the powers of the first

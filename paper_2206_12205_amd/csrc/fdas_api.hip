@@ -246,6 +246,18 @@ int fdas_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, float threshold
         fdas::launch_peaks(*p, plane, n_bins, threshold, out, capacity, n_found, static_cast<hipStream_t>(stream)));
 }
 
+int fdas_band_max(fdas_plan_t p, const void *plane, int64_t n_bins, const int64_t *windows, int32_t n_windows,
+                  fdas_peak *out, void *stream) {
+    if (!p || !plane || !windows || !out) return FDAS_E_INVALID;
+    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
+    if ((reinterpret_cast<uintptr_t>(plane) % pe) != 0 || (reinterpret_cast<uintptr_t>(windows) & 7u) ||
+        !aligned16(out))
+        return FDAS_E_INVALID;
+    if (n_bins < 1 || n_bins > p->cfg.max_bins || n_windows < 1 || n_windows > 65535) return FDAS_E_INVALID;
+    return hip_status(
+        fdas::launch_band_max(*p, plane, n_bins, windows, n_windows, out, static_cast<hipStream_t>(stream)));
+}
+
 int fdas_harmonic_sum(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_harm, void *out, void *stream) {
     if (!p || !plane || !out) return FDAS_E_INVALID;
     const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value

@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
         L.fdas_correlate_batch.argtypes = [P, P, P, P]
         L.fdas_peaks.argtypes = [P, P, I64, ctypes.c_float, P, I64, P, P]
         L.fdas_harmonic_sum.argtypes = [P, P, I64, I32, P, P]
+        L.fdas_band_max.argtypes = [P, P, I64, P, I32, P, P]
         D = ctypes.c_double
         L.fdas_make_templates_jerk.argtypes = [P, D, P]
         L.fdas_refine.argtypes = [P, I64, I32, P, P, P, P, P, I32, I32, D, D, P]
@@ -266,6 +267,23 @@ class Plan:
                                  ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
         return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(),
                 "power": rec["power"].copy(), "n_found": found}
+
+    def band_max(self, plane, windows, stream=None):
+        """Highest cell of each window (z_lo, z_hi, r_lo, r_hi) of a plane
+        (fdas_band_max) -> dict of numpy arrays z_idx, r, power."""
+        import numpy as np
+        import torch
+        if plane.dim() != 2 or plane.shape[0] != self.n_z or plane.dtype != self.torch_plane_dtype() \
+                or not plane.is_contiguous():
+            raise ValueError("plane must be a contiguous (n_z, n) tensor of the plan's plane dtype")
+        win = torch.as_tensor(np.asarray(windows, dtype=np.int64).reshape(-1, 4), device=self.device).contiguous()
+        out = torch.empty((win.shape[0], 24), dtype=torch.uint8, device=self.device)
+        _check(lib().fdas_band_max(self._h, ctypes.c_void_p(plane.data_ptr()), plane.shape[1],
+                                   ctypes.c_void_p(win.data_ptr()), int(win.shape[0]),
+                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "fdas_band_max")
+        rec = out.cpu().numpy().view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
+                                              ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
+        return {"z_idx": rec["z_idx"].astype(np.int64), "r": rec["r"].copy(), "power": rec["power"].copy()}
 
     def harmonic_sum(self, plane, n_harm, out=None, stream=None):
         """Incoherent sum of the first n_harm harmonics of a plane (fdas_harmonic_sum):

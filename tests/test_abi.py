@@ -104,6 +104,13 @@ def test_layout_and_workspace_checks_on_host():
         assert L.fdas_peaks(h, fake, 100, 1.0, None, 5, nf, None) == F.E_INVALID   # capacity>0, no out
         assert L.fdas_peaks(h, fake, 100, 1.0, fake, -1, nf, None) == F.E_INVALID
         assert L.fdas_peaks(h, fake, 100, 1.0, fake, 5, ctypes.c_void_p(0x20004), None) == F.E_INVALID
+        # band maxima: argument checks only
+        assert L.fdas_band_max(h, fake, 100, fake, 0, fake, None) == F.E_INVALID
+        assert L.fdas_band_max(h, fake, 100, fake, 65536, fake, None) == F.E_INVALID
+        assert L.fdas_band_max(h, fake, 0, fake, 4, fake, None) == F.E_INVALID
+        assert L.fdas_band_max(h, fake, 100, ctypes.c_void_p(0x10004), 4, fake, None) == F.E_INVALID
+        assert L.fdas_band_max(h, fake, 100, fake, 4, ctypes.c_void_p(0x10008), None) == F.E_INVALID
+        assert L.fdas_band_max(h, fake, 100, None, 4, fake, None) == F.E_INVALID
         # harmonic sum: argument checks only (each returns before any launch)
         assert L.fdas_harmonic_sum(h, fake, 100, 0, fake, None) == F.E_INVALID
         assert L.fdas_harmonic_sum(h, fake, 100, 33, fake, None) == F.E_INVALID
