@@ -327,6 +327,62 @@ def jerk_volume(args, cfg, dev, x, plane):
             "bank_build_ms_per_w": ms_bank}
 
 
+def noise_canopy(args, cfg, dev):
+    """The paper's noise-canopy experiment on synthetic noise-only planes:
+    eight single-DM noise spectra (no pulsar), their FP32 and BF16 planes,
+    and 48 bands per plane of width 1.5 f T bins (f drawn as the pulsar
+    population's fundamental, P ~ U[1, 10] ms) at seeded positions, all rows;
+    the highest cell of each band by fdas_band_max.  Reported: the canopy
+    (the range of the band maxima per width class), and how often BF16 and
+    FP32 pick different cells for the same band (a flip) and by how far."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2206_12205_amd.fdas import Plan
+    n_t, tsamp = cfg["n_t"], cfg["tsamp"]
+    T = n_t * tsamp
+    n = n_t // 2
+    common = dict(max_bins=n, z_min=cfg["z_min"], z_step=cfg["z_step"], n_z=cfg["n_z"], n_taps=cfg["n_taps"],
+                  device=dev)
+    pl_f = Plan(compute="fp32", plane_dtype="fp32", **common)
+    pl_b = Plan(compute="bf16", plane_dtype="bf16", **common)
+    pf, pb = pl_f.empty_plane(n), pl_b.empty_plane(n)
+    g = np.random.default_rng(np.random.SeedSequence([12205, 6]))
+    maxima = {"narrow": [], "wide": []}
+    flips = drift_r = drift_z = extreme = n_bands = 0
+    ms_band = 0.0
+    for trial in range(8):
+        x = synth._device_spectrum(n_t, tsamp, [], 7000 + trial, dev)
+        pl_f.correlate(x, pf)
+        pl_b.correlate(x, pb)
+        periods = g.uniform(1e-3, 10e-3, size=48)
+        widths = np.floor(1.5 * T / periods).astype(np.int64)
+        starts = np.array([g.integers(0, n - w) for w in widths], dtype=np.int64)
+        windows = [(0, cfg["n_z"], int(s0), int(s0 + w)) for s0, w in zip(starts, widths)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bf = pl_f.band_max(pf, windows)
+        ms_band += (time.perf_counter() - t0) * 1e3
+        bb = pl_b.band_max(pb, windows)
+        for k, w in enumerate(widths):
+            maxima["narrow" if w < np.median(widths) else "wide"].append(float(bf["power"][k]))
+            dz, dr = abs(int(bb["z_idx"][k]) - int(bf["z_idx"][k])), abs(int(bb["r"][k]) - int(bf["r"][k]))
+            if dz or dr:
+                flips += 1
+                drift_r = max(drift_r, dr)
+                drift_z = max(drift_z, dz)
+                extreme += dz > 1 or dr > 1
+        n_bands += len(widths)
+    del pl_f, pl_b, pf, pb
+    note(f"noise canopy: {n_bands} bands, {flips} BF16/FP32 flips ({extreme} extreme)")
+    return {"workload": f"8 single-DM noise-only spectra, FP32 and BF16 planes, {n_bands} bands of width "
+                        f"1.5 f T (P ~ U[1, 10] ms), all {cfg['n_z']} rows",
+            "canopy_fp32": {k: {"min": min(v), "median": float(np.median(v)), "max": max(v), "bands": len(v)}
+                            for k, v in maxima.items()},
+            "bf16_vs_fp32_flips": flips, "flips_extreme": extreme, "max_drift_r": drift_r, "max_drift_z": drift_z,
+            "bands": n_bands, "band_max_ms_per_plane_host_timed": ms_band / 8}
+
+
 def wide_search(args, dev):
     """Wide workload: 2^24 samples, 16 injected pulsars, 201 templates (z in
     [-200, 200]), 512 taps; the FP32, BF16 and FP8 planes timed and graded on
@@ -395,6 +451,7 @@ def main():
                     help="skip the batched many-spectra search (256 dedispersion trials)")
     ap.add_argument("--no-harmonic", action="store_true", help="skip the harmonic-sum timing")
     ap.add_argument("--no-jerk", action="store_true", help="skip the jerk-volume timing")
+    ap.add_argument("--no-canopy", action="store_true", help="skip the noise-canopy experiment")
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the wide workload (201 x 8.4M planes in FP32, BF16 and FP8 vs FP64)")
     ap.add_argument("--trials", type=int, default=256,
@@ -589,6 +646,9 @@ def main():
 
     if not args.no_jerk:
         out["jerk"] = jerk_volume(args, cfg, dev, x, plane_b)
+
+    if not args.no_canopy:
+        out["noise_canopy"] = noise_canopy(args, cfg, dev)
 
     if not args.no_batched:
         out["batched"] = batched_search(args, cfg, dev)
