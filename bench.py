@@ -283,6 +283,35 @@ def harmonic_timing(pl, plane, steps):
     return res
 
 
+def prep_timing(args, cfg, dev):
+    """fdas_prepare on a single-DM-length series (2^23 FP32 samples, seeded
+    noise on the device): real FFT, DC, median normalisation.  Algorithmic
+    bytes: the series read once and the spectrum written once."""
+    import torch
+    from paper_2206_12205_amd.fdas import prepare
+    n_t = cfg["n_t"]
+    g = torch.Generator(device=dev).manual_seed(12205)
+    xs = torch.randn(n_t, dtype=torch.float32, device=dev, generator=g)
+    out = prepare(xs)
+    for _ in range(10):
+        prepare(xs, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(10, min(args.steps, 100))
+    e0.record()
+    for _ in range(reps):
+        prepare(xs, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = n_t * 4 + (n_t // 2) * 8
+    note(f"spectrum preparation (2^{n_t.bit_length() - 1} samples): {ms:.3f} ms")
+    return {"workload": f"{n_t} FP32 samples -> {n_t // 2} normalised bins", "ms": ms,
+            "algorithmic_GBs": alg / (ms * 1e-3) / 1e9,
+            "fft_passes": ((n_t // 2).bit_length() - 1) // 2 + ((n_t // 2).bit_length() - 1) % 2,
+            "note": "the workspace comes from torch's caching allocator per call (inside the timed loop)"}
+
+
 def jerk_volume(args, cfg, dev, x, plane):
     """Jerk search on the single-DM spectrum: five planes w = -60, -30, 0, 30,
     60 (BF16 form, matrix-core kernel), one plan (and template bank) per w,
@@ -452,6 +481,7 @@ def main():
     ap.add_argument("--no-harmonic", action="store_true", help="skip the harmonic-sum timing")
     ap.add_argument("--no-jerk", action="store_true", help="skip the jerk-volume timing")
     ap.add_argument("--no-canopy", action="store_true", help="skip the noise-canopy experiment")
+    ap.add_argument("--no-prep", action="store_true", help="skip the spectrum-preparation timing")
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the wide workload (201 x 8.4M planes in FP32, BF16 and FP8 vs FP64)")
     ap.add_argument("--trials", type=int, default=256,
@@ -646,6 +676,9 @@ def main():
 
     if not args.no_jerk:
         out["jerk"] = jerk_volume(args, cfg, dev, x, plane_b)
+
+    if not args.no_prep:
+        out["spectrum_preparation"] = prep_timing(args, cfg, dev)
 
     if not args.no_canopy:
         out["noise_canopy"] = noise_canopy(args, cfg, dev)

@@ -182,6 +182,27 @@ int fdas_get_layout(fdas_plan_t plan, fdas_layout *out);
  * stream; FDAS_E_WORKSPACE without a workspace. */
 int fdas_make_templates(fdas_plan_t plan, void *stream);
 
+/* Spectrum preparation upstream of fdas_correlate (no plan needed): the
+ * normalised spectrum of a real time series, with the real FFT in single
+ * precision as the paper keeps it (Section "Casting between single-precision
+ * and bfloat16"):
+ *   X[k] = sum_t x[t] exp(-2 pi i k t / N_t),  k in [0, N_t / 2)  (Nyquist dropped),
+ *   X[0] = 0,   X[k] /= sqrt(median_{k >= 1} |X[k]|^2 / ln 2)
+ * so that white-noise powers become Exp(1).  The FFT runs as radix-4/2
+ * Stockham passes over global memory on N_t / 2 complex points, twiddles
+ * from double precision; the median is an exact selection.
+ *   series     device, n_t floats (8-byte aligned)
+ *   n_t        a power of two in [4, 2^28] (FDAS_E_UNSUPPORTED otherwise;
+ *              FDAS_E_INVALID below 4)
+ *   spectrum   device, n_t / 2 complex64 (16-byte aligned): the result
+ *   workspace  device, at least fdas_prepare_workspace's bytes (16-byte
+ *              aligned), FDAS_E_WORKSPACE otherwise
+ * Asynchronous on stream; records kernels only (graph-capturable).  An
+ * all-zero series has median 0 and gives non-finite values. */
+int fdas_prepare_workspace(int64_t n_t, size_t *workspace_bytes);
+int fdas_prepare(const float *series, int64_t n_t, void *spectrum, void *workspace, size_t workspace_bytes,
+                 void *stream);
+
 /* Template bank of one plane of a jerk search: the same z grid, the taps
  * of a sinusoid whose drift itself changes by w bins over the observation
  * (frequency r0 + z u + w u^2 / 2, u in [0, 1)):

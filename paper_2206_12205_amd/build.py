@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["fdas_api.hip", "templates.hip", "correlate.hip", "correlate_mfma.hip", "correlate_m4k.hip", "peaks.hip",
            "refine.hip", "batch.hip", "tune.hip",
-           "correlate_fp8.hip", "harmonic.hip", "bands.hip"]
+           "correlate_fp8.hip", "harmonic.hip", "bands.hip", "prep.hip"]
 
 # packed-FP32 instructions are disabled for every HIP translation unit
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",

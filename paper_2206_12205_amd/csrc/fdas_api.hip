@@ -246,6 +246,26 @@ int fdas_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, float threshold
         fdas::launch_peaks(*p, plane, n_bins, threshold, out, capacity, n_found, static_cast<hipStream_t>(stream)));
 }
 
+static bool prep_length_ok(int64_t n_t) { return n_t >= 4 && n_t <= ((int64_t)1 << 28) && (n_t & (n_t - 1)) == 0; }
+
+int fdas_prepare_workspace(int64_t n_t, size_t *workspace_bytes) {
+    if (!workspace_bytes) return FDAS_E_INVALID;
+    if (n_t < 4) return FDAS_E_INVALID;
+    if (!prep_length_ok(n_t)) return FDAS_E_UNSUPPORTED;
+    *workspace_bytes = fdas::prep_workspace_bytes(n_t);
+    return FDAS_OK;
+}
+
+int fdas_prepare(const float *series, int64_t n_t, void *spectrum, void *workspace, size_t workspace_bytes,
+                 void *stream) {
+    if (!series || !spectrum || n_t < 4) return FDAS_E_INVALID;
+    if ((reinterpret_cast<uintptr_t>(series) & 7u) || !aligned16(spectrum)) return FDAS_E_INVALID;
+    if (!prep_length_ok(n_t)) return FDAS_E_UNSUPPORTED;
+    if (!workspace || workspace_bytes < fdas::prep_workspace_bytes(n_t) || !aligned16(workspace))
+        return FDAS_E_WORKSPACE;
+    return hip_status(fdas::launch_prepare(series, n_t, spectrum, workspace, static_cast<hipStream_t>(stream)));
+}
+
 int fdas_band_max(fdas_plan_t p, const void *plane, int64_t n_bins, const int64_t *windows, int32_t n_windows,
                   fdas_peak *out, void *stream) {
     if (!p || !plane || !windows || !out) return FDAS_E_INVALID;

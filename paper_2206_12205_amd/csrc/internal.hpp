@@ -94,6 +94,10 @@ size_t peak_scratch_bytes(int64_t n_tiles);
 hipError_t launch_peaks(const fdas_plan_s &p, const void *plane, int64_t n, float thr,
                         fdas_peak *out, int64_t capacity, int64_t *n_found, hipStream_t s);
 
+// Spectrum preparation (prep.hip).
+size_t prep_workspace_bytes(int64_t n_t);
+hipError_t launch_prepare(const float *series, int64_t n_t, void *out, void *ws, hipStream_t st);
+
 // Band maxima (bands.hip).
 hipError_t launch_band_max(const fdas_plan_s &p, const void *plane, int64_t n, const int64_t *windows,
                            int32_t n_windows, fdas_peak *out, hipStream_t st);

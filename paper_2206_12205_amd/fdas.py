@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
         L.fdas_peaks.argtypes = [P, P, I64, ctypes.c_float, P, I64, P, P]
         L.fdas_harmonic_sum.argtypes = [P, P, I64, I32, P, P]
         L.fdas_band_max.argtypes = [P, P, I64, P, I32, P, P]
+        L.fdas_prepare_workspace.argtypes = [I64, ctypes.POINTER(ctypes.c_size_t)]
+        L.fdas_prepare.argtypes = [P, I64, P, P, ctypes.c_size_t, P]
         D = ctypes.c_double
         L.fdas_make_templates_jerk.argtypes = [P, D, P]
         L.fdas_refine.argtypes = [P, I64, I32, P, P, P, P, P, I32, I32, D, D, P]
@@ -349,6 +351,26 @@ def tune(spectrum, z_min, z_step, n_z, n_taps, compute="bf16", plane_dtype=None,
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def prepare(series, out=None, stream=None):
+    """Normalised spectrum of a real FP32 time series (fdas_prepare): the
+    single-precision real FFT, Nyquist dropped, DC zeroed, median-power
+    normalisation; returns an (n_t / 2,) complex64 tensor."""
+    import torch
+    if series.dtype != torch.float32 or series.dim() != 1 or not series.is_contiguous() or not series.is_cuda:
+        raise ValueError("series must be a contiguous 1-D float32 device tensor")
+    n_t = series.numel()
+    nb = ctypes.c_size_t(0)
+    _check(lib().fdas_prepare_workspace(n_t, ctypes.byref(nb)), "fdas_prepare_workspace")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=series.device)
+    if out is None:
+        out = torch.empty(n_t // 2, dtype=torch.complex64, device=series.device)
+    elif out.dtype != torch.complex64 or out.numel() != n_t // 2 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous complex64 tensor of n_t / 2 bins")
+    _check(lib().fdas_prepare(ctypes.c_void_p(series.data_ptr()), n_t, ctypes.c_void_p(out.data_ptr()),
+                              ctypes.c_void_p(ws.data_ptr()), nb.value, _stream_ptr(stream)), "fdas_prepare")
+    return out
 
 
 def refine(spectrum, r, z, taps=32, n_steps=0, eta_r_scale=1.0, eta_z_scale=1.0, stream=None):

@@ -146,8 +146,9 @@ def draw_pulsar(g: np.random.Generator, T: float, tsamp: float,
     return Pulsar(f=f, fdot=fdot, amps=amps, phases=phases, p1=p1)
 
 
-def config1(trial: int = 0) -> Spectrum:
-    """Tiny workload: 2^17 samples at 64 us, one sinusoid f = 137.3 Hz, z = +6.4.
+def config1_series(trial: int = 0):
+    """The tiny workload's time series (float64) and its pulsar: 2^17 samples
+    at 64 us, one sinusoid f = 137.3 Hz, z = +6.4.
 
     Amplitude reading: noise-free matched power 200 (matched-filter amplitude
     SNR sqrt(2 * 200) = 20), i.e. a = sqrt(4 * 200 / N_t) for unit-sigma noise.
@@ -160,11 +161,19 @@ def config1(trial: int = 0) -> Spectrum:
     p = Pulsar(f=137.3, fdot=6.4 / (T * T), amps=[math.sqrt(4.0 * 200.0 / n_t)],
                phases=[float(g.uniform(0.0, 2.0 * math.pi))], p1=200.0)
     add_signal(x, tsamp, p)
-    return Spectrum(to_spectrum(x), n_t, tsamp, [p])
+    return x, p
 
 
-def config2(trial: int = 0, noise: bool = True) -> Spectrum:
-    """Single-DM workload: 2^23 samples at 64 us, one 8-harmonic binary pulsar."""
+def config1(trial: int = 0) -> Spectrum:
+    """Tiny workload spectrum (config1_series through to_spectrum)."""
+    c = CONFIGS[1]
+    x, p = config1_series(trial)
+    return Spectrum(to_spectrum(x), c["n_t"], c["tsamp"], [p])
+
+
+def config2_series(trial: int = 0, noise: bool = True):
+    """The single-DM workload's time series (float64) and its pulsar: 2^23
+    samples at 64 us, one 8-harmonic binary pulsar."""
     c = CONFIGS[2]
     n_t, tsamp = c["n_t"], c["tsamp"]
     T = n_t * tsamp
@@ -172,7 +181,14 @@ def config2(trial: int = 0, noise: bool = True) -> Spectrum:
     x = g.standard_normal(n_t) if noise else np.zeros(n_t)
     p = draw_pulsar(g, T, tsamp, n_t=n_t)
     add_signal(x, tsamp, p)
-    return Spectrum(to_spectrum(x, None if noise else 1.0), n_t, tsamp, [p])
+    return x, p
+
+
+def config2(trial: int = 0, noise: bool = True) -> Spectrum:
+    """Single-DM workload spectrum (config2_series through to_spectrum)."""
+    c = CONFIGS[2]
+    x, p = config2_series(trial, noise)
+    return Spectrum(to_spectrum(x, None if noise else 1.0), c["n_t"], c["tsamp"], [p])
 
 
 def config5(trial: int = 0) -> Spectrum:

@@ -126,6 +126,23 @@ def test_layout_and_workspace_checks_on_host():
     assert L.fdas_strerror(F.E_CAPACITY).decode() == "peak capacity exceeded"
 
 
+def test_prepare_argument_checks():
+    L = F.lib()
+    nb = ctypes.c_size_t(0)
+    assert L.fdas_prepare_workspace(1 << 20, ctypes.byref(nb)) == F.OK
+    assert nb.value >= (1 << 19) * 16
+    assert L.fdas_prepare_workspace(3 << 10, ctypes.byref(nb)) == F.E_UNSUPPORTED
+    assert L.fdas_prepare_workspace(2, ctypes.byref(nb)) == F.E_INVALID
+    assert L.fdas_prepare_workspace(1024, None) == F.E_INVALID
+    fake = ctypes.c_void_p(0x10000)
+    assert L.fdas_prepare(None, 1024, fake, fake, 1 << 20, None) == F.E_INVALID
+    assert L.fdas_prepare(ctypes.c_void_p(0x10004), 1024, fake, fake, 1 << 20, None) == F.E_INVALID
+    assert L.fdas_prepare(fake, 1024, ctypes.c_void_p(0x10008), fake, 1 << 20, None) == F.E_INVALID
+    assert L.fdas_prepare(fake, 1000, fake, fake, 1 << 20, None) == F.E_UNSUPPORTED
+    assert L.fdas_prepare(fake, 1024, fake, fake, 16, None) == F.E_WORKSPACE
+    assert L.fdas_prepare(fake, 1024, fake, None, 1 << 20, None) == F.E_WORKSPACE
+
+
 def test_null_arguments():
     L = F.lib()
     assert L.fdas_plan(None, None, None) == F.E_INVALID
