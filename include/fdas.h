@@ -208,11 +208,12 @@ int fdas_prepare(const float *series, int64_t n_t, void *spectrum, void *workspa
  * (frequency r0 + z u + w u^2 / 2, u in [0, 1)):
  *   A(q, z, w) = int_0^1 exp(i pi (2 q u + z u^2 + w u^3 / 3)) du,
  *   g_j[m] = conj(A(m - z_j/2 - w/6, z_j, w)) / ||.||_2
- * (r stays the mean frequency).  The paper searches z only (Section
- * "Introduction" cites the method); w extends the same correlation to the
- * f-fdot-fddot volume one plane per w.  The response has no closed form and
- * is integrated on the GPU by composite 16-point Gauss-Legendre quadrature in
- * double precision (panels of at most half a turn of phase); w = 0 is
+ * (r stays the mean frequency).  The paper studies the z search only and
+ * describes the jerk search as the same template correlation over an
+ * f-fdot-fddot volume (Section "FDAS vs Jerk Search"): one plane per w.
+ * The response has no closed form and is integrated on the GPU by composite
+ * 16-point Gauss-Legendre quadrature in double precision (panels of at most
+ * half a turn of phase); w = 0 is
  * exactly fdas_make_templates (closed form).  The rest as
  * fdas_make_templates: asynchronous on stream, FDAS_E_WORKSPACE without a
  * workspace, FDAS_E_INVALID for a non-finite w; fdas_correlate then writes

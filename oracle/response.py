@@ -41,7 +41,8 @@ The overlap-save form needs the length-L spectrum of the circularly placed
 taps, H_z = FFT_L(h_z) / L with h_z[m mod L] = g_z[m]; the 1/L folds the
 inverse transform's normalisation into the template.
 
-Jerk.  A third search axis (not in the paper, which searches z only): a
+Jerk.  A third search axis (Section "FDAS vs Jerk Search" describes it; the
+paper studies z only): a
 sinusoid whose drift changes by w bins over the observation has response
 A(q, z, w) = integral_0^1 exp(i pi (2 q u + z u^2 + w u^3 / 3)) du, taken
 here by the composite Simpson rule (response_jerk), and templates
