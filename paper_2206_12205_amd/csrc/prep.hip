@@ -132,21 +132,34 @@ __global__ void __launch_bounds__(kPrepThreads) k_sel_hist(const float2 *__restr
         if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-// One workgroup: the bin holding the remaining rank; prefix extended by it;
-// histogram cleared for the next pass.
+// One workgroup of 1024 threads, two bins each: an inclusive scan of the
+// counts finds the bin holding the remaining rank (the one bin with
+// exclusive sum <= rank < inclusive sum); the prefix is extended by it and
+// the histogram cleared for the next pass.
 __global__ void __launch_bounds__(1024) k_sel_pick(SelState *st, uint32_t *hist, int bits) {
-    __shared__ uint32_t cnt[2048];
+    __shared__ uint32_t part[1024];
     const int nb = 1 << bits;
-    for (int i = threadIdx.x; i < nb; i += 1024) cnt[i] = hist[i];
+    const int t = threadIdx.x;
+    const uint32_t c0 = 2 * t < nb ? hist[2 * t] : 0u, c1 = 2 * t + 1 < nb ? hist[2 * t + 1] : 0u;
+    part[t] = c0 + c1;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t rank = st->rank, b = 0;
-        while (b < (uint32_t)nb - 1 && rank >= cnt[b]) rank -= cnt[b++];
-        st->prefix = (st->prefix << bits) | b;
-        st->rank = rank;
+    for (int w = 1; w < 1024; w <<= 1) {
+        const uint32_t v = t >= w ? part[t - w] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2048; i += 1024) hist[i] = 0;
+    const uint32_t rank = st->rank;
+    const uint32_t excl = part[t] - c0 - c1;   // counts of the bins before 2t
+    __syncthreads();                             // every thread has read st->rank
+    if (excl <= rank && rank < excl + c0) {
+        st->prefix = (st->prefix << bits) | (uint32_t)(2 * t);
+        st->rank = rank - excl;
+    } else if (excl + c0 <= rank && rank < excl + c0 + c1) {
+        st->prefix = (st->prefix << bits) | (uint32_t)(2 * t + 1);
+        st->rank = rank - excl - c0;
+    }
+    for (int i = t; i < 2048; i += 1024) hist[i] = 0;
 }
 
 __global__ void __launch_bounds__(kPrepThreads) k_prep_scale(float2 *X, int64_t N, const SelState *st) {
