@@ -196,15 +196,16 @@ def batched_search(args, cfg, dev):
     setup_s = time.perf_counter() - t0
     note(f"batched: {len(trials)} trials generated, {len(bs.chunks)} chunks planned and tuned ({setup_s:.1f} s)")
     res = {}
-    for name, fp in (("correlate", False), ("correlate_and_peaks", True)):
-        bs.run(spectra, c3["threshold"], find_peaks=fp)
+    for name, fp, fu in (("correlate", False, True), ("correlate_and_peaks_per_job", True, False),
+                         ("correlate_and_peaks", True, True)):
+        bs.run(spectra, c3["threshold"], find_peaks=fp, fused=fu)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         steps = max(1, min(args.steps, 3))
         e0.record()
         for _ in range(steps):
-            bs.run(spectra, c3["threshold"], find_peaks=fp)
+            bs.run(spectra, c3["threshold"], find_peaks=fp, fused=fu)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
@@ -224,7 +225,7 @@ def batched_search(args, cfg, dev):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     res["correlate_and_peaks_graph"] = {"ms_per_pass": ms, "cells_per_s": bs.cells / (ms * 1e-3),
-                                        "launches_per_pass": len(bs.chunks) + len(lengths) * 5}
+                                        "launches_per_pass": len(bs.chunks) * 7}
     note(f"batched correlate_and_peaks as one HIP graph: {ms:.1f} ms per pass")
     del g
     # an injected pulsar counts as found when a peak sits within 2 bins of
@@ -250,6 +251,52 @@ def batched_search(args, cfg, dev):
            "peaks_in_noise_only_trials": noise_peaks, **res}
     del bs, spectra
     return out
+
+
+def peaks_timing(pl, x, plane, thr, steps, ms_plane):
+    """Plane plus thresholded peaks of the headline spectrum: fdas_correlate
+    then fdas_peaks (a streaming pass over the plane flags the tiles) against
+    fdas_correlate_peaks (the correlation kernel flags them while storing the
+    plane); the same list either way."""
+    import ctypes
+    import torch
+    from paper_2206_12205_amd import fdas as F
+    L = F.lib()
+    n = x.numel()
+    cap = 1 << 16
+    out = torch.empty((cap, 24), dtype=torch.uint8, device=x.device)
+    nf = torch.zeros(1, dtype=torch.int64, device=x.device)
+    xs, pp = ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(plane.data_ptr())
+    op, np_ = ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(nf.data_ptr())
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+
+    def separate():
+        F._check(L.fdas_correlate(pl._h, xs, n, pp, sp), "fdas_correlate")
+        F._check(L.fdas_peaks(pl._h, pp, n, float(thr), op, cap, np_, sp), "fdas_peaks")
+
+    def fused():
+        F._check(L.fdas_correlate_peaks(pl._h, xs, n, pp, float(thr), op, cap, np_, sp), "fdas_correlate_peaks")
+
+    res = {}
+    for name, fn in (("correlate_then_peaks", separate), ("correlate_peaks_fused", fused)):
+        for _ in range(max(steps // 4, 5)):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"ms": ms, "cells_per_s": pl.n_z * n / (ms * 1e-3), "peak_finding_ms": ms - ms_plane,
+                     "n_found": int(nf.item())}
+    res["threshold"] = thr
+    note(f"plane + peaks: separate {res['correlate_then_peaks']['ms']:.4f} ms, "
+         f"fused {res['correlate_peaks_fused']['ms']:.4f} ms ({res['correlate_peaks_fused']['n_found']} peaks)")
+    return res
 
 
 def harmonic_timing(pl, plane, steps):
@@ -561,6 +608,7 @@ def main():
          f"fp8 {ms_q:.3f} ms")
     del pl_v, pl_8
 
+    fused_pk = peaks_timing(pl_b, x, plane_b, cfg["threshold"], args.steps, ms_b)
     if not args.no_harmonic:
         harm = harmonic_timing(pl_b, plane_b, args.steps)
     st_b = launch_stats(pl_b, x, plane_b)
@@ -670,6 +718,8 @@ def main():
                            "fp8_dsnr_pct_sigma": statistics.pstdev(dsnr_q) if dsnr_q else None,
                            "fp8_max_rel_power_err": err_q}
         del pl_d
+
+    out["plane_and_peaks"] = {"workload": "the single-DM BF16 plane and its thresholded peaks", **fused_pk}
 
     if not args.no_harmonic:
         out["harmonic_sum"] = {"workload": "the single-DM BF16 plane, BF16 sums out", **harm}

@@ -292,6 +292,39 @@ int fdas_tune(const fdas_config *cfg, const void *spectrum, int64_t n_bins, void
 int fdas_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, float threshold,
                fdas_peak *out, int64_t capacity, int64_t *n_found, void *stream);
 
+/* Plane and peaks of one spectrum in one call: the plane fdas_correlate
+ * writes and exactly the list and count fdas_peaks then gives for it (same
+ * arguments, alignment and error rules as the two calls; spectrum and plane
+ * 16-byte aligned).  With a BF16 matrix-core plan of L = 4096 the correlation
+ * kernel flags the peak finder's tiles (one row x 1024 bins) that hold a
+ * stored cell above the threshold while it writes the plane, so the finder
+ * reads the plane only around those tiles instead of streaming all of it
+ * (peak finding fused into the plane store); other plans run fdas_correlate
+ * then fdas_peaks.  Asynchronous on stream, kernels only. */
+int fdas_correlate_peaks(fdas_plan_t plan, const void *spectrum, int64_t n_bins, void *plane, float threshold,
+                         fdas_peak *out, int64_t capacity, int64_t *n_found, void *stream);
+
+/* Batched form over the batch set by fdas_set_batch: every job's plane, as
+ * fdas_correlate_batch writes it, and the peaks of every job's plane.  Job
+ * i's list goes to out + i * capacity (capacity entries each, job = i; the
+ * list fdas_peaks gives for that plane otherwise) and its true count to
+ * n_found[i] (device, n_jobs int64, 8-byte aligned).  The tiles of all jobs'
+ * planes share one index space, so one count, one scan and one write launch
+ * serve the whole batch; with a BF16 matrix-core plan of L = 4096 the tiles
+ * are flagged by the persistent correlation launch itself, other plans add
+ * one flagging pass per job.
+ *   scratch  caller device memory, 16-byte aligned, at least the bytes
+ *            fdas_batch_peaks_workspace gives for the current batch (flags,
+ *            counts and offsets: about 6 bytes per 1024 plane cells)
+ * fdas_batch_peaks_workspace: FDAS_E_STATE without a batch.
+ * fdas_correlate_batch_peaks: asynchronous on stream, kernels only
+ * (graph-capturable); FDAS_E_WORKSPACE for a missing or short scratch,
+ * FDAS_E_STATE without templates or a batch. */
+int fdas_batch_peaks_workspace(fdas_plan_t plan, size_t *scratch_bytes);
+int fdas_correlate_batch_peaks(fdas_plan_t plan, const void *spectra, void *planes, float threshold,
+                               fdas_peak *out, int64_t capacity, int64_t *n_found, void *scratch,
+                               size_t scratch_bytes, void *stream);
+
 /* Band maxima of a plane written by fdas_correlate with the same plan: the
  * paper's own peak finding takes the highest point of each harmonic band
  * (Section "Peakfinding methodology", band bounds in Table 3), and the same

@@ -27,8 +27,12 @@
 // forms the template product, packs stage outputs to bf16 and squares.
 // Register use stays at 64 VGPRs or fewer, so two workgroups (eight waves per
 // SIMD) share a CU.
+// A marking instance (kMark) also sets the peak finder's tile flags for the
+// cells it stores above a threshold, so a fused peak search need not read
+// the plane back to find the tiles worth examining.
 #include "fft_valu.hpp"
 #include "internal.hpp"
+#include "marks.hpp"
 #include "mfma4096.hpp"
 #include "plane_io.hpp"
 
@@ -101,17 +105,30 @@ struct Stage<float> {
     static __device__ __forceinline__ void put4(uint32_t *st, int t0, float a, float b, float c, float d) {
         *reinterpret_cast<float4 *>(&st[t0 + 4 * (t0 >> 8)]) = make_float4(a, b, c, d);
     }
-    // samples t0 .. t0 + 3 -> plane, vector or element-wise
-    static __device__ __forceinline__ void flush4(const uint32_t *st, int t0, float *row, bool vec, int lo, int hi) {
+    // samples t0 .. t0 + 3 -> plane, vector or element-wise; kMark: the
+    // peak tiles of the kept samples flagged when one of the four is above
+    // the threshold (plane row z, column seg0 + t)
+    template <bool kMark>
+    static __device__ __forceinline__ void flush4(const uint32_t *st, int t0, float *row, bool vec, int lo, int hi,
+                                                  const PeakMarks &m, int64_t z, int64_t seg0) {
         const float4 v = *reinterpret_cast<const float4 *>(&st[t0 + 4 * (t0 >> 8)]);
+        const float vv[4] = {v.x, v.y, v.z, v.w};
         if (vec) {
             const f32x4_t u = {v.x, v.y, v.z, v.w};
             __builtin_nontemporal_store(u, reinterpret_cast<f32x4_t *>(row + t0));
         } else {
-            const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 if (t0 + i >= lo && t0 + i < hi) row[t0 + i] = vv[i];
+        }
+        if constexpr (kMark) {
+            if ((vv[0] > m.thr) | (vv[1] > m.thr) | (vv[2] > m.thr) | (vv[3] > m.thr)) {   // rare
+                // an opaque copy keeps the run bounds (loop-invariant per
+                // lane) from being hoisted and held across the template loop
+                int t = t0;
+                asm volatile("" : "+v"(t));
+                mark_run(m, (uint32_t)z * (uint32_t)m.n_cb, (int32_t)seg0, max(t, lo), min(t + 3, hi - 1));
+            }
         }
     }
 };
@@ -124,8 +141,11 @@ struct Stage<__bf16> {
         u.y = bf16_pack(c, d);
         *reinterpret_cast<uint2 *>(&st[t0 / 2 + 4 * (t0 >> 8)]) = u;
     }
-    // samples t0 .. t0 + 7 (t0 a multiple of 8): one 16-byte read, one 16-byte store
-    static __device__ __forceinline__ void flush8(const uint32_t *st, int t0, __bf16 *row, bool vec, int lo, int hi) {
+    // samples t0 .. t0 + 7 (t0 a multiple of 8): one 16-byte read, one
+    // 16-byte store; kMark: as for FP32, when the packed prefilter passes
+    template <bool kMark>
+    static __device__ __forceinline__ void flush8(const uint32_t *st, int t0, __bf16 *row, bool vec, int lo, int hi,
+                                                  const PeakMarks &m, int64_t z, int64_t seg0) {
         const uint4 u = *reinterpret_cast<const uint4 *>(&st[t0 / 2 + 4 * (t0 >> 8)]);
         if (vec) {
             const u32x4_t w = {u.x, u.y, u.z, u.w};
@@ -136,6 +156,14 @@ struct Stage<__bf16> {
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 if (t0 + i >= lo && t0 + i < hi) r16[t0 + i] = (uint16_t)(ww[i >> 1] >> (16 * (i & 1)));
+        }
+        if constexpr (kMark) {
+            const uint32_t w0 = u.x, w1 = u.y, w2 = u.z, w3 = u.w;
+            if (bf16x8_maybe_above(w0, w1, w2, w3, m)) {   // rare
+                int t = t0;   // opaque copy, as for FP32
+                asm volatile("" : "+v"(t));
+                mark_run(m, (uint32_t)z * (uint32_t)m.n_cb, (int32_t)seg0, max(t, lo), min(t + 7, hi - 1));
+            }
         }
     }
 };
@@ -176,28 +204,33 @@ __device__ __forceinline__ FlushPlan flush_plan(const PT *plane, int64_t seg0, i
     return f;
 }
 
-template <class PT>
-__device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const FlushPlan &f, int tid, int jpar) {
+// Row z of the plane (its segment starts at column seg0) from the staging
+// buffer; kMark: with its peak tiles marked.
+template <class PT, bool kMark>
+__device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const FlushPlan &f, int tid, int jpar,
+                                      const PeakMarks &m, int64_t z, int64_t seg0) {
     if constexpr (sizeof(PT) == 2) {
         // lower half of the workgroup: even templates, upper half: odd ones
-        if ((tid >> 9) == jpar) Stage<PT>::flush8(stage, 8 * (tid & 511), row_seg, f.vec8, f.lo, f.hi);
+        if ((tid >> 9) == jpar)
+            Stage<PT>::template flush8<kMark>(stage, 8 * (tid & 511), row_seg, f.vec8, f.lo, f.hi, m, z, seg0);
     } else {
 #pragma unroll
         for (int h = 0; h < kFlushChunks; ++h) {
             const int t0 = 4 * (tid + h * kThr);
-            Stage<PT>::flush4(stage, t0, row_seg, f.vec[h], f.lo, f.hi);
+            Stage<PT>::template flush4<kMark>(stage, t0, row_seg, f.vec[h], f.lo, f.hi, m, z, seg0);
         }
     }
 }
 
 // One tile: segment s of the spectrum (n bins) against templates [j0, j1),
-// writing plane rows j0 .. j1 - 1 (row stride n).  Called by the whole
+// writing plane rows j0 .. j1 - 1 (row stride n); kMark: marking the peak
+// tiles (m) of the cells it stores above the threshold.  Called by the whole
 // workgroup; contains barriers.
-template <class PT, bool kOpaqueLane = false>
+template <class PT, bool kOpaqueLane = false, bool kMark = false>
 __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_t n, const uint32_t *__restrict__ bank,
                                          const uint32_t *__restrict__ tab, PT *__restrict__ plane, int32_t M,
                                          int32_t V, int64_t s, int j0, int j1, uint32_t *bufA, uint32_t *bufB,
-                                         uint32_t *stage) {
+                                         uint32_t *stage, const PeakMarks &m) {
     int tid = (int)threadIdx.x, w = tid >> 6, lane = tid & 63;
     if constexpr (kOpaqueLane) {
         // per-tile copies the compiler cannot prove loop-invariant, so that a
@@ -328,7 +361,7 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
             *reinterpret_cast<uint4 *>(&bufA[chunk_addr(Q, c, g)]) = o;   // (k1, n3, k2 block)
         }
         __syncthreads();
-        if (j > j0) flush<PT>(stage, plane + (int64_t)(j - 1) * n + seg0, fp, tid, (j - 1) & 1);
+        if (j > j0) flush<PT, kMark>(stage, plane + (int64_t)(j - 1) * n + seg0, fp, tid, (j - 1) & 1, m, j - 1, seg0);
         // I2: DFT16 over k2 with e(16 n3 k2), transposed: lane (c, g)
         // receives n2 = c, k1 = 4 g + e -> one 16-byte chunk of buffer B
 #pragma unroll
@@ -384,17 +417,18 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
         one_template(j + 1, hB, hA, j + 2 < j1);
     }
     __syncthreads();
-    flush<PT>(stage, plane + (int64_t)(j1 - 1) * n + seg0, fp, tid, (j1 - 1) & 1);
+    flush<PT, kMark>(stage, plane + (int64_t)(j1 - 1) * n + seg0, fp, tid, (j1 - 1) & 1, m, j1 - 1, seg0);
 }
 
 #define M4K_ATTR __attribute__((amdgpu_flat_work_group_size(kThr, kThr), amdgpu_waves_per_eu(kWavesPerEU)))
 
-// One spectrum: workgroup b takes template chunk b mod n_chunks of segment b / n_chunks.
-template <class PT>
+// One spectrum: workgroup b takes template chunk b mod n_chunks of segment
+// b / n_chunks.  kMark: the peak tiles of the plane (m) are marked as well.
+template <class PT, bool kMark>
 __global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int64_t n,
                                             const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
                                             PT *__restrict__ plane, int32_t M, int32_t V, int32_t n_z,
-                                            int32_t z_chunk, int32_t n_chunks) {
+                                            int32_t z_chunk, int32_t n_chunks, PeakMarks m) {
     __shared__ __align__(16) uint32_t bufA[kBufWords];
     __shared__ __align__(16) uint32_t bufB[kBufWords];
     __shared__ __align__(16) uint32_t stage[Stage<PT>::kWords];
@@ -403,7 +437,7 @@ __global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int
     const int j0 = chunk * z_chunk;
     const int j1 = min(j0 + z_chunk, n_z);
     if (j0 >= j1) return;
-    m4k_tile<PT>(spec, n, bank, tab, plane, M, V, s, j0, j1, bufA, bufB, stage);
+    m4k_tile<PT, false, kMark>(spec, n, bank, tab, plane, M, V, s, j0, j1, bufA, bufB, stage, m);
 }
 
 // Many spectra in one persistent launch.  Tiles are (job, segment, template
@@ -412,16 +446,19 @@ __global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int
 // are dispatched round-robin over the eight XCDs, so a workgroup starts on
 // chunk (XCD mod n_chunks): each XCD's L2 then holds only its chunks' part of
 // the template bank.  A workgroup whose queue is empty moves on to the next
-// chunk's queue, so ragged lengths still balance across the CUs.
+// chunk's queue, so ragged lengths still balance across the CUs.  kMark:
+// the peak tiles of every job's plane are marked as well (m.flags and
+// m.cflags are the batch's arrays, each job's part at its tile_base and
+// chunk_base).
 constexpr int kXcds = 8;
 
-template <class PT>
+template <class PT, bool kMark>
 __global__ void M4K_ATTR correlate_mfma4096_batch(const float2 *__restrict__ spectra,
                                                   const fdas_batch_job *__restrict__ jobs, int32_t n_jobs,
                                                   int32_t n_segs, int32_t *__restrict__ counters,
                                                   const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
                                                   PT *__restrict__ planes, int32_t M, int32_t V, int32_t n_z,
-                                                  int32_t z_chunk, int32_t n_chunks) {
+                                                  int32_t z_chunk, int32_t n_chunks, PeakMarks m) {
     __shared__ __align__(16) uint32_t bufA[kBufWords];
     __shared__ __align__(16) uint32_t bufB[kBufWords];
     __shared__ __align__(16) uint32_t stage[Stage<PT>::kWords];
@@ -461,26 +498,34 @@ __global__ void M4K_ATTR correlate_mfma4096_batch(const float2 *__restrict__ spe
         // they are not hoisted out and held in registers across tiles
         int opaque = 0;
         asm volatile("" : "+s"(opaque));
-        m4k_tile<PT, true>(spectra + spec_off + opaque, nb, bank + opaque, tab + opaque, planes + plane_off + opaque,
-                           M, V + opaque, s, j0, j1, bufA, bufB, stage);
+        PeakMarks mj = m;
+        if constexpr (kMark) {
+            mj.flags = m.flags + jobs[lo].tile_base;
+            mj.cflags = m.cflags + jobs[lo].chunk_base;
+            mj.n_cb = (int32_t)((nb + kPeakTileCols - 1) / kPeakTileCols);
+        }
+        m4k_tile<PT, true, kMark>(spectra + spec_off + opaque, nb, bank + opaque, tab + opaque,
+                                  planes + plane_off + opaque, M, V + opaque, s, j0, j1, bufA, bufB, stage, mj);
     }
 }
 
 namespace {
-template <class PT>
-hipError_t launch(const fdas_plan_s &p, const void *spec, int64_t n, void *plane, hipStream_t st) {
+template <class PT, bool kMark>
+hipError_t launch(const fdas_plan_s &p, const void *spec, int64_t n, void *plane, const PeakMarks &m,
+                  hipStream_t st) {
     const int64_t n_seg = (n + p.V - 1) / p.V;
     const int64_t blocks = n_seg * p.n_chunks;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const auto *ws = static_cast<const unsigned char *>(p.ws);
-    hipLaunchKernelGGL(correlate_mfma4096<PT>, dim3((unsigned)blocks), dim3(kThr), 0, st,
+    hipLaunchKernelGGL((correlate_mfma4096<PT, kMark>), dim3((unsigned)blocks), dim3(kThr), 0, st,
                        static_cast<const float2 *>(spec), n, reinterpret_cast<const uint32_t *>(ws + p.off_bank),
                        reinterpret_cast<const uint32_t *>(ws + p.off_tab), static_cast<PT *>(plane), p.M, p.V,
-                       p.cfg.n_z, p.z_chunk, p.n_chunks);
+                       p.cfg.n_z, p.z_chunk, p.n_chunks, m);
     return hipGetLastError();
 }
-template <class PT>
-hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes, hipStream_t st) {
+template <class PT, bool kMark>
+hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes, const PeakMarks &m,
+                        hipStream_t st) {
     auto *ws = static_cast<unsigned char *>(p.ws);
     int32_t *counters = reinterpret_cast<int32_t *>(ws + p.off_batch);
     const auto *jobs = reinterpret_cast<const fdas_batch_job *>(ws + p.off_batch + p.batch_hdr);
@@ -491,12 +536,12 @@ hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes,
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>((int64_t)cus * 2, std::max<int64_t>(p.batch_tiles, 1));
-    hipLaunchKernelGGL(correlate_mfma4096_batch<PT>, dim3((unsigned)grid), dim3(kThr), 0, st,
+    hipLaunchKernelGGL((correlate_mfma4096_batch<PT, kMark>), dim3((unsigned)grid), dim3(kThr), 0, st,
                        static_cast<const float2 *>(spectra), jobs, p.batch_jobs,
                        (int32_t)(p.batch_tiles / p.n_chunks), counters,
                        reinterpret_cast<const uint32_t *>(ws + p.off_bank),
                        reinterpret_cast<const uint32_t *>(ws + p.off_tab), static_cast<PT *>(planes), p.M, p.V,
-                       p.cfg.n_z, p.z_chunk, p.n_chunks);
+                       p.cfg.n_z, p.z_chunk, p.n_chunks, m);
     return hipGetLastError();
 }
 
@@ -506,15 +551,33 @@ hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes,
 
 hipError_t launch_correlate_m4k_batch(const fdas_plan_s &p, const void *spectra, void *planes, hipStream_t st) {
     if (p.L != m4k::kL || p.cfg.compute != FDAS_BF16) return hipErrorInvalidValue;
-    if (p.cfg.plane_dtype == FDAS_BF16) return m4k::launch_batch<__bf16>(p, spectra, planes, st);
-    if (p.cfg.plane_dtype == FDAS_FP32) return m4k::launch_batch<float>(p, spectra, planes, st);
+    const PeakMarks none{};
+    if (p.cfg.plane_dtype == FDAS_BF16) return m4k::launch_batch<__bf16, false>(p, spectra, planes, none, st);
+    if (p.cfg.plane_dtype == FDAS_FP32) return m4k::launch_batch<float, false>(p, spectra, planes, none, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_correlate_m4k_batch_marked(const fdas_plan_s &p, const void *spectra, void *planes,
+                                             const PeakMarks &marks, hipStream_t st) {
+    if (p.L != m4k::kL || p.cfg.compute != FDAS_BF16) return hipErrorInvalidValue;
+    if (p.cfg.plane_dtype == FDAS_BF16) return m4k::launch_batch<__bf16, true>(p, spectra, planes, marks, st);
+    if (p.cfg.plane_dtype == FDAS_FP32) return m4k::launch_batch<float, true>(p, spectra, planes, marks, st);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_correlate_m4k(const fdas_plan_s &p, const void *spec, int64_t n, void *plane, hipStream_t st) {
     if (p.L != m4k::kL || p.cfg.compute != FDAS_BF16) return hipErrorInvalidValue;
-    if (p.cfg.plane_dtype == FDAS_BF16) return m4k::launch<__bf16>(p, spec, n, plane, st);
-    if (p.cfg.plane_dtype == FDAS_FP32) return m4k::launch<float>(p, spec, n, plane, st);
+    const PeakMarks none{};
+    if (p.cfg.plane_dtype == FDAS_BF16) return m4k::launch<__bf16, false>(p, spec, n, plane, none, st);
+    if (p.cfg.plane_dtype == FDAS_FP32) return m4k::launch<float, false>(p, spec, n, plane, none, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_correlate_m4k_marked(const fdas_plan_s &p, const void *spec, int64_t n, void *plane,
+                                       const PeakMarks &marks, hipStream_t st) {
+    if (p.L != m4k::kL || p.cfg.compute != FDAS_BF16) return hipErrorInvalidValue;
+    if (p.cfg.plane_dtype == FDAS_BF16) return m4k::launch<__bf16, true>(p, spec, n, plane, marks, st);
+    if (p.cfg.plane_dtype == FDAS_FP32) return m4k::launch<float, true>(p, spec, n, plane, marks, st);
     return hipErrorInvalidValue;
 }
 

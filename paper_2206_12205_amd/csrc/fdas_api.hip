@@ -5,6 +5,7 @@
 #include <new>
 
 #include "internal.hpp"
+#include "marks.hpp"
 #include "mfma4096.hpp"
 #include "mfma8192.hpp"
 
@@ -308,14 +309,18 @@ int fdas_set_batch(fdas_plan_t p, const fdas_job *jobs, int32_t n_jobs, int64_t 
     p->batch_jobs = 0;
     if (n_jobs > p->cfg.max_jobs) return FDAS_E_INVALID;
     std::vector<fdas_batch_job> tab((size_t)n_jobs);
-    int64_t segs = 0;
+    int64_t segs = 0, tiles = 0, chunks = 0;
     for (int32_t i = 0; i < n_jobs; ++i) {
         const fdas_job &j = jobs[i];
         if (j.n_bins < 1 || j.n_bins > p->cfg.max_bins || j.spec_off < 0 || j.plane_off < 0) return FDAS_E_INVALID;
         if (j.spec_off > spectra_bins - j.n_bins) return FDAS_E_INVALID;
         if (j.n_bins > (plane_cells - j.plane_off) / p->cfg.n_z || j.plane_off > plane_cells) return FDAS_E_INVALID;
-        tab[i] = {j.spec_off, j.n_bins, j.plane_off, segs};
+        tab[i] = {j.spec_off, j.n_bins, j.plane_off, segs, tiles, chunks};
         segs += (j.n_bins + p->V - 1) / p->V;
+        // peak tiles of the job's plane, and their chunks (batched peak finding)
+        const int64_t jt = (int64_t)p->cfg.n_z * ((j.n_bins + fdas::kPeakTileCols - 1) / fdas::kPeakTileCols);
+        tiles += jt;
+        chunks += (jt + fdas::kPeakTilesPerChunk - 1) / fdas::kPeakTilesPerChunk;
         // segment and tile indices are 32-bit on the device; each chunk's
         // counter overshoots the segment count by at most one per workgroup
         if (segs * p->n_chunks > 0x7fffffffLL - (1 << 20)) return FDAS_E_INVALID;
@@ -328,6 +333,8 @@ int fdas_set_batch(fdas_plan_t p, const fdas_job *jobs, int32_t n_jobs, int64_t 
     p->batch_host = std::move(tab);
     p->batch_jobs = n_jobs;
     p->batch_tiles = segs * p->n_chunks;
+    p->batch_peak_tiles = tiles;
+    p->batch_peak_chunks = chunks;
     return FDAS_OK;
 }
 
@@ -350,6 +357,66 @@ int fdas_correlate_batch(fdas_plan_t p, const void *spectra, void *planes, void 
 }
 
 static bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+// The marking correlation indexes columns and tiles in 32 bits.
+static bool mark_fits(const fdas_plan_s &p, int64_t n_bins) {
+    const int64_t n_cb = (n_bins + fdas::kPeakTileCols - 1) / fdas::kPeakTileCols;
+    return p.mfma && p.L == fdas::m4k::kL && n_bins <= fdas::kMarkMaxBins && (int64_t)p.cfg.n_z * n_cb < 0x7fffffffLL;
+}
+
+int fdas_correlate_peaks(fdas_plan_t p, const void *spectrum, int64_t n_bins, void *plane, float threshold,
+                         fdas_peak *out, int64_t capacity, int64_t *n_found, void *stream) {
+    if (!p || !spectrum || !plane || !n_found || capacity < 0 || (capacity > 0 && !out)) return FDAS_E_INVALID;
+    if (!aligned16(spectrum) || !aligned16(plane) || (out && !aligned16(out)) || !aligned8(n_found))
+        return FDAS_E_INVALID;
+    if (n_bins < 1 || n_bins > p->cfg.max_bins) return FDAS_E_INVALID;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    if (!p->templates_ready) return FDAS_E_STATE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (mark_fits(*p, n_bins)) {
+        fdas::PeakMarks m;
+        hipError_t e = fdas::peak_marks(*p, n_bins, threshold, &m, st);
+        if (e == hipSuccess) e = fdas::launch_correlate_m4k_marked(*p, spectrum, n_bins, plane, m, st);
+        if (e == hipSuccess) e = fdas::launch_peaks(*p, plane, n_bins, threshold, out, capacity, n_found, st, true);
+        return hip_status(e);
+    }
+    const int s = fdas_correlate(p, spectrum, n_bins, plane, stream);
+    if (s != FDAS_OK) return s;
+    return hip_status(fdas::launch_peaks(*p, plane, n_bins, threshold, out, capacity, n_found, st));
+}
+
+int fdas_batch_peaks_workspace(fdas_plan_t p, size_t *scratch_bytes) {
+    if (!p || !scratch_bytes) return FDAS_E_INVALID;
+    if (p->batch_jobs < 1) return FDAS_E_STATE;
+    *scratch_bytes = fdas::batch_peak_scratch_bytes(*p);
+    return FDAS_OK;
+}
+
+int fdas_correlate_batch_peaks(fdas_plan_t p, const void *spectra, void *planes, float threshold, fdas_peak *out,
+                               int64_t capacity, int64_t *n_found, void *scratch, size_t scratch_bytes,
+                               void *stream) {
+    if (!p || !spectra || !planes || !n_found || capacity < 0 || (capacity > 0 && !out)) return FDAS_E_INVALID;
+    if (!aligned16(spectra) || !aligned16(planes) || (out && !aligned16(out)) || !aligned8(n_found))
+        return FDAS_E_INVALID;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    if (!p->templates_ready || p->batch_jobs < 1) return FDAS_E_STATE;
+    if (!scratch || !aligned16(scratch) || scratch_bytes < fdas::batch_peak_scratch_bytes(*p))
+        return FDAS_E_WORKSPACE;
+    if (capacity > 0 && p->batch_jobs > INT64_MAX / capacity) return FDAS_E_INVALID;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    fdas::PeakMarks m;
+    hipError_t e = fdas::batch_peak_marks(*p, scratch, threshold, &m, st);
+    if (e != hipSuccess) return hip_status(e);
+    if (mark_fits(*p, p->cfg.max_bins)) {
+        e = fdas::launch_correlate_m4k_batch_marked(*p, spectra, planes, m, st);
+    } else {
+        const int s = fdas_correlate_batch(p, spectra, planes, stream);
+        if (s != FDAS_OK) return s;
+        e = fdas::batch_peak_mark_pass(*p, planes, m, st);
+    }
+    if (e == hipSuccess) e = fdas::batch_peaks_finish(*p, planes, scratch, threshold, out, capacity, n_found, st);
+    return hip_status(e);
+}
 
 int fdas_refine(const void *spectrum, int64_t n_bins, int32_t n_cand, double *r, double *z, double *power,
                 double *dp_dr, double *dp_dz, int32_t taps, int32_t n_steps, double eta_r_scale, double eta_z_scale,

@@ -26,6 +26,8 @@ struct fdas_batch_job {
     int64_t n_bins;       // its length N
     int64_t plane_off;    // first cell of its n_z x N plane in the planes buffer
     int64_t seg_base;     // index of its first segment among all jobs' segments
+    int64_t tile_base;    // its first peak tile among all jobs' tiles (batched peak finding)
+    int64_t chunk_base;   // its first chunk of peak tiles among all jobs' chunks
 };
 
 struct fdas_plan_s {
@@ -45,6 +47,8 @@ struct fdas_plan_s {
     size_t batch_hdr = 0;
     int32_t batch_jobs = 0;                // jobs set by fdas_set_batch (0: none)
     int64_t batch_tiles = 0;
+    int64_t batch_peak_tiles = 0;          // peak tiles of all jobs' planes
+    int64_t batch_peak_chunks = 0;         // chunks of peak tiles of all jobs' planes
     std::vector<fdas_batch_job> batch_host;   // host copy of the job table
     int64_t peak_tile_cap = 0;             // number of peak tiles the scratch holds
     void *ws = nullptr;
@@ -71,6 +75,16 @@ hipError_t launch_correlate_m4k_batch(const fdas_plan_s &p, const void *spectra,
 // so graph capture records no memset.
 __global__ void k_batch_reset(int32_t *counters, int32_t n);
 
+struct PeakMarks;
+
+// L = 4096 matrix-core correlation that also marks the peak tiles of cells
+// above a threshold while storing the plane (marks: the flags of this plane;
+// batch: the flags of all jobs, each job at its tile_base / chunk_base).
+hipError_t launch_correlate_m4k_marked(const fdas_plan_s &p, const void *spec, int64_t n, void *plane,
+                                       const PeakMarks &marks, hipStream_t s);
+hipError_t launch_correlate_m4k_batch_marked(const fdas_plan_s &p, const void *spectra, void *planes,
+                                             const PeakMarks &marks, hipStream_t s);
+
 // Correlation (correlate.hip).
 // FP8 (e4m3) form: bytes of the FP32 bank staging at the start of the tables
 // region (the per-template exponents follow it), the bank conversion and the
@@ -89,10 +103,27 @@ hipError_t launch_refine_backward(const void *spec, int64_t n, int32_t n_cand, c
                                   const double *grad_p, double *grad_r, double *grad_z, int32_t taps, hipStream_t st);
 
 // Peaks (peaks.hip).
-constexpr int kPeakTileCols = 1024;   // columns per peak tile (one row per tile)
+constexpr int kPeakTileCols = 1024;     // columns per peak tile (one row per tile)
+constexpr int kPeakTilesPerChunk = 16;  // tiles per chunk (unit of the per-chunk totals and offsets)
 size_t peak_scratch_bytes(int64_t n_tiles);
+// premarked: the tile flags of this plane were set by peak_marks + a marking
+// correlation (the clear and the streaming mark pass are skipped)
 hipError_t launch_peaks(const fdas_plan_s &p, const void *plane, int64_t n, float thr,
-                        fdas_peak *out, int64_t capacity, int64_t *n_found, hipStream_t s);
+                        fdas_peak *out, int64_t capacity, int64_t *n_found, hipStream_t s,
+                        bool premarked = false);
+// Zeroes the tile flags of an n-bin plane in the plan's scratch and describes
+// them for a marking correlation.
+hipError_t peak_marks(const fdas_plan_s &p, int64_t n, float thr, PeakMarks *marks, hipStream_t s);
+// Batched peak finding over every job of the plan's batch, in a caller
+// scratch of batch_peak_scratch_bytes: zero the flags (batch_peak_marks),
+// mark them (a marking batch correlation, or batch_peak_mark_pass over the
+// planes), then batch_peaks_finish: job i's peaks at out + i * capacity
+// (job = i), its count at n_found[i].
+size_t batch_peak_scratch_bytes(const fdas_plan_s &p);
+hipError_t batch_peak_marks(const fdas_plan_s &p, void *scratch, float thr, PeakMarks *marks, hipStream_t s);
+hipError_t batch_peak_mark_pass(const fdas_plan_s &p, const void *planes, const PeakMarks &marks, hipStream_t s);
+hipError_t batch_peaks_finish(const fdas_plan_s &p, const void *planes, void *scratch, float thr, fdas_peak *out,
+                              int64_t capacity, int64_t *n_found, hipStream_t s);
 
 // Spectrum preparation (prep.hip).
 size_t prep_workspace_bytes(int64_t n_t);

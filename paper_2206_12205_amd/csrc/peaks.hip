@@ -13,30 +13,38 @@
 // chunks of 16 consecutive tiles:
 //   mark   one streaming pass flags the tiles (and their chunks) that hold a
 //          cell above the threshold;
-//   count  every flagged tile counts its peaks; per chunk the total (zero for
-//          a chunk without flags);
-//   scan   one workgroup turns the per-chunk totals into exclusive offsets
-//          and the total;
-//   write  every tile with peaks recomputes them and writes them at its offset
-//          in column order, dropping those at or beyond the capacity.
-// The count and write kernels run a fixed grid that strides over the chunks
-// and skips unflagged chunks after one byte read, so a plane with few peaks
-// costs one streaming read plus a few thousand workgroups.  The list is
+//   count  a fixed grid of workgroups, each owning a contiguous range of
+//          chunks: it reads 256 chunk flags at a time in one coalesced load,
+//          lists the flagged ones in order (wave ballots), counts the peaks
+//          of their flagged tiles and sums them into one total per workgroup;
+//   scan   one workgroup turns the (at most 2048) workgroup totals into
+//          exclusive offsets and the total;
+//   write  the same ranges again: each workgroup walks its flagged chunks in
+//          order from its offset, recomputes the peaks of tiles that have
+//          any and writes them in column order, dropping those at or beyond
+//          the capacity.
+// A plane with few peaks thus costs one streaming read plus two passes over
+// one byte per chunk, and no launch walks a long list serially.  The list is
 // sorted by (z_idx, r) with no sort pass.
+//
 #include <algorithm>
 #include <type_traits>
 
 #include "internal.hpp"
+#include "marks.hpp"
 
 namespace fdas {
 
 constexpr int kPeakThreads = 256;
 constexpr int kCellsPerThread = kPeakTileCols / kPeakThreads;   // 4
 
-// offsets (int64), totals (int32) and flags (uint8) per chunk of 16 tiles,
-// counts (int32) and flags (uint8) per tile
+// Workgroups of the count and write kernels (each owns a range of chunks).
+constexpr int kPeakGrid = 2048;
+
+// counts (int32) and flags (uint8) per tile, totals (int32) and flags per
+// chunk of 16 tiles, totals and offsets per workgroup, with padding
 size_t peak_scratch_bytes(int64_t n_tiles) {
-    return (size_t)n_tiles * (sizeof(int32_t) + sizeof(int64_t)) + 256;
+    return (size_t)n_tiles * 6 + (size_t)kPeakGrid * (sizeof(int32_t) + sizeof(int64_t)) + 4096;
 }
 
 template <class PT>
@@ -88,10 +96,8 @@ __device__ __forceinline__ int tile_flags(const PT *plane, int64_t n, int n_z, i
     return cnt;
 }
 
-// Tiles per chunk (the unit of the per-chunk totals and offsets).
-constexpr int kTilesPerBlock = 16;
-// Workgroups of the count and write kernels (they stride over the chunks).
-constexpr int kPeakGrid = 2048;
+// Tiles per chunk (the unit of the per-chunk totals).
+constexpr int kTilesPerBlock = kPeakTilesPerChunk;
 
 // Tile flags: flag[tile] = 1 iff the tile's row segment holds a cell above
 // the threshold (only such tiles can hold a peak), and the chunk flag
@@ -101,7 +107,8 @@ constexpr int kPeakGrid = 2048;
 // tile costs one read of its cells and no neighbourhood.  k_peak_clear
 // zeroes both flag arrays (n entries, stored back to back) at the start of
 // every call (a kernel, not a memset, so the call can be captured in a
-// graph).
+// graph).  A marking correlation sets the same flags while it stores the
+// plane (marks.hpp); the mark pass is then skipped.
 __global__ void k_peak_clear(uint8_t *flags, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         flags[i] = 0;
@@ -119,28 +126,16 @@ __device__ __forceinline__ void mark_cell(const PT *plane, int64_t f, int64_t n,
 }
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
 
 // Could the 16-byte vector u hold a cell above the threshold?  A superset
-// test (exact test in mark_cell).  Raw bfloat16 with thr >= 0: a cell above
-// thr has a bit pattern above tb, the pattern of thr truncated to bfloat16
-// (patterns of non-negative values order like the values; negative values
-// and NaN have larger patterns and are rechecked), four packed 16-bit
-// maxima.  Other types, or thr < 0 / NaN: the exact comparison.
+// test (exact test in mark_cell): raw bfloat16 through the packed bit-pattern
+// maximum of marks.hpp, other types the exact comparison.
 template <class PT>
-__device__ __forceinline__ bool maybe_above(const u32x4_t &u, double thr, unsigned short tb, bool use_bits) {
+__device__ __forceinline__ bool maybe_above(const u32x4_t &u, double thr, const PeakMarks &m) {
     constexpr int kVec = 16 / sizeof(PT);
     if constexpr (sizeof(PT) == 2) {
-        if (use_bits) {
-            // words copied to scalars first: a bit cast of a vector element
-            // expression (u.y) reads the vector's first element with this
-            // compiler
-            const uint32_t w0 = u.x, w1 = u.y, w2 = u.z, w3 = u.w;
-            const u16x2_t m = __builtin_elementwise_max(
-                __builtin_elementwise_max(__builtin_bit_cast(u16x2_t, w0), __builtin_bit_cast(u16x2_t, w1)),
-                __builtin_elementwise_max(__builtin_bit_cast(u16x2_t, w2), __builtin_bit_cast(u16x2_t, w3)));
-            return (m.x > tb) | (m.y > tb);
-        }
+        const uint32_t w0 = u.x, w1 = u.y, w2 = u.z, w3 = u.w;   // scalars first (see marks.hpp)
+        return bf16x8_maybe_above(w0, w1, w2, w3, m);
     }
     const PT *cells = reinterpret_cast<const PT *>(&u);
     bool any = false;
@@ -149,14 +144,12 @@ __device__ __forceinline__ bool maybe_above(const u32x4_t &u, double thr, unsign
     return any;
 }
 
+// total cells of the plane; m.flags / m.cflags / m.n_cb / m.thr describe it
 template <class PT>
-__global__ void __launch_bounds__(256) k_peak_mark(const PT *plane, int64_t n, int64_t total, int64_t n_cb, float thr_f,
-                                                   uint8_t *flags, uint8_t *cflags) {
+__global__ void __launch_bounds__(256) k_peak_mark(const PT *plane, int64_t n, int64_t total, PeakMarks m) {
     constexpr int kVec = 16 / sizeof(PT);   // cells per 16-byte vector
     constexpr int kUnroll = 4;              // vectors in flight per thread
-    const double thr = (double)thr_f;
-    const bool use_bits = thr_f >= 0.0f;    // false for NaN too
-    const unsigned short tb = (unsigned short)(__float_as_uint(thr_f) >> 16);
+    const double thr = (double)m.thr;
     const uintptr_t addr = reinterpret_cast<uintptr_t>(plane);
     int64_t head = (int64_t)(((16 - (addr & 15)) & 15) / sizeof(PT));
     if (head > total) head = total;
@@ -164,8 +157,8 @@ __global__ void __launch_bounds__(256) k_peak_mark(const PT *plane, int64_t n, i
     const int64_t tail0 = head + n_vec * kVec;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (gid < head) mark_cell<PT>(plane, gid, n, n_cb, thr, flags, cflags);
-    if (gid < total - tail0) mark_cell<PT>(plane, tail0 + gid, n, n_cb, thr, flags, cflags);
+    if (gid < head) mark_cell<PT>(plane, gid, n, m.n_cb, thr, m.flags, m.cflags);
+    if (gid < total - tail0) mark_cell<PT>(plane, tail0 + gid, n, m.n_cb, thr, m.flags, m.cflags);
     const u32x4_t *vp = reinterpret_cast<const u32x4_t *>(plane + head);
     for (int64_t v0 = gid; v0 < n_vec; v0 += kUnroll * stride) {
         u32x4_t u[kUnroll];
@@ -177,59 +170,150 @@ __global__ void __launch_bounds__(256) k_peak_mark(const PT *plane, int64_t n, i
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) {
             const int64_t v = v0 + k * stride;
-            if (v < n_vec && maybe_above<PT>(u[k], thr, tb, use_bits)) {   // rare: locate the cells
+            if (v < n_vec && maybe_above<PT>(u[k], thr, m)) {   // rare: locate the cells
 #pragma unroll
                 for (int q = 0; q < kVec; ++q)
-                    mark_cell<PT>(plane, head + v * kVec + q, n, n_cb, thr, flags, cflags);
+                    mark_cell<PT>(plane, head + v * kVec + q, n, m.n_cb, thr, m.flags, m.cflags);
             }
         }
     }
 }
 
+// Peaks of the flagged tiles of chunk ch of one plane (n_tiles tiles of
+// n_cb per row): counts[tile] for each flagged tile; returns the chunk's
+// total on thread 0.  Called by the whole workgroup; contains barriers.
+template <class PT>
+__device__ __forceinline__ int count_chunk(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles,
+                                           int64_t ch, float thr, const uint8_t *flags, int32_t *counts,
+                                           peak_val_t<PT> (*buf)[kPeakTileCols + 2], int *sum) {
+    int total = 0;   // thread 0: peaks of this chunk's tiles
+    for (int i = 0; i < kTilesPerBlock; ++i) {
+        const int64_t tile = ch * kTilesPerBlock + i;
+        if (tile >= n_tiles) break;
+        if (flags[tile] == 0) continue;      // uniform; its count is never read
+        const int z = (int)(tile / n_cb);
+        const int64_t c0 = (tile % n_cb) * kPeakTileCols;
+        if (threadIdx.x == 0) *sum = 0;      // visible after the barrier inside tile_flags
+        bool flag[kCellsPerThread];
+        const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
+        if (cnt) atomicAdd(sum, cnt);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            counts[tile] = *sum;
+            total += *sum;
+        }
+        __syncthreads();                     // buf and sum are reused by the next tile
+    }
+    return total;
+}
+
+// Flagged chunks among [c0, c0 + kPeakThreads) (below c_end), listed in
+// increasing order into list[] (offsets from c0); returns their number.
+// One coalesced byte load per thread and a ballot per wave.  Called by the
+// whole workgroup; contains barriers.
+__device__ __forceinline__ int flagged_chunks(const uint8_t *cflags, int64_t c0, int64_t c_end, int *list,
+                                              int *wave_cnt) {
+    constexpr int kWaves = kPeakThreads / 64;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const bool f = c0 + t < c_end && cflags[c0 + t] != 0;
+    const uint64_t bal = __ballot(f);
+    if (lane == 0) wave_cnt[w] = __popcll(bal);
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        base += i < w ? wave_cnt[i] : 0;
+        total += wave_cnt[i];
+    }
+    if (f) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+    __syncthreads();
+    return total;
+}
+
+// Chunk range of workgroup b: [b per, min((b + 1) per, n_chunks)).
+__device__ __forceinline__ void chunk_range(int64_t n_chunks, int64_t *r0, int64_t *r1) {
+    const int64_t per = (n_chunks + gridDim.x - 1) / gridDim.x;
+    *r0 = (int64_t)blockIdx.x * per;
+    *r1 = min(*r0 + per, n_chunks);
+}
+
+// Job of chunk ch of a batch: the last job whose first chunk is <= ch.
+__device__ __forceinline__ int job_of_chunk(const fdas_batch_job *jobs, int n_jobs, int64_t ch) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].chunk_base <= ch) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Where the chunks of a plane live: one plane, or a batch (chunk ch belongs
+// to job job_of_chunk(ch), whose tiles start at its tile_base).
+template <class PT>
+struct ChunkSource {
+    const PT *plane;                  // single plane / the batch's planes buffer
+    int64_t n, n_cb, n_tiles;         // single plane
+    const fdas_batch_job *jobs;       // batch (null for a single plane)
+    int n_jobs;
+
+    struct Local {
+        const PT *plane;
+        int64_t n, n_cb, n_tiles, ch, tile_base;
+        int job;
+    };
+    __device__ __forceinline__ Local at(int64_t ch, int n_z) const {
+        if (!jobs) return Local{plane, n, n_cb, n_tiles, ch, 0, 0};
+        const int jb = job_of_chunk(jobs, n_jobs, ch);
+        const int64_t nb = jobs[jb].n_bins;
+        const int64_t cb = (nb + kPeakTileCols - 1) / kPeakTileCols;
+        return Local{plane + jobs[jb].plane_off, nb, cb, cb * n_z, ch - jobs[jb].chunk_base, jobs[jb].tile_base,
+                     jb};
+    }
+};
+
+// Count: per flagged chunk its total (block_counts), per workgroup the sum
+// (wg_totals), per job the sum (job_totals, batch only: one atomic per
+// chunk with peaks, zeroed with the flags).
 template <class PT>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_count(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, const uint8_t *flags,
-             const uint8_t *cflags, int32_t *counts, int32_t *block_counts) {
+k_peak_count(ChunkSource<PT> src, int n_z, int64_t n_chunks, float thr, const uint8_t *flags, const uint8_t *cflags,
+             int32_t *counts, int32_t *block_counts, int32_t *wg_totals, unsigned long long *job_totals) {
     __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
-    __shared__ int sum;
-    const int64_t n_chunks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
-    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-        if (cflags[ch] == 0) {                   // uniform: no cell above the threshold in the chunk
-            if (threadIdx.x == 0) block_counts[ch] = 0;
-            continue;
-        }
-        int total = 0;   // thread 0: peaks of this chunk's tiles
-        for (int i = 0; i < kTilesPerBlock; ++i) {
-            const int64_t tile = ch * kTilesPerBlock + i;
-            if (tile >= n_tiles) break;
-            if (flags[tile] == 0) continue;      // uniform; its count is never read
-            const int z = (int)(tile / n_cb);
-            const int64_t c0 = (tile % n_cb) * kPeakTileCols;
-            if (threadIdx.x == 0) sum = 0;       // visible after the barrier inside tile_flags
-            bool flag[kCellsPerThread];
-            const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
-            if (cnt) atomicAdd(&sum, cnt);
-            __syncthreads();
+    __shared__ int sum, list[kPeakThreads], wave_cnt[kPeakThreads / 64];
+    int64_t r0, r1;
+    chunk_range(n_chunks, &r0, &r1);
+    int total = 0;   // thread 0
+    for (int64_t c0 = r0; c0 < r1; c0 += kPeakThreads) {
+        const int nf = flagged_chunks(cflags, c0, r1, list, wave_cnt);
+        for (int k = 0; k < nf; ++k) {
+            const int64_t ch = c0 + list[k];
+            const auto loc = src.at(ch, n_z);
+            const int t = count_chunk<PT>(loc.plane, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, thr,
+                                          flags + loc.tile_base, counts + loc.tile_base, buf, &sum);
             if (threadIdx.x == 0) {
-                counts[tile] = sum;
-                total += sum;
+                block_counts[ch] = t;
+                total += t;
+                if (job_totals && t) atomicAdd(&job_totals[loc.job], (unsigned long long)t);
             }
-            __syncthreads();                     // buf and sum are reused by the next tile
         }
-        if (threadIdx.x == 0) block_counts[ch] = total;
+        __syncthreads();                         // list is rewritten by the next group
     }
+    if (threadIdx.x == 0) wg_totals[blockIdx.x] = total;
 }
 
-// Single workgroup: exclusive scan of the per-workgroup totals -> offsets,
-// total -> *n_found (kTilesPerBlock times fewer entries than tiles).
-__global__ void __launch_bounds__(1024) k_peak_scan(const int32_t *counts, int64_t *offsets, int64_t n_tiles,
-                                                    int64_t *n_found) {
+// Single workgroup: exclusive scan of n values -> offsets (int64), the total
+// -> *total; with copy != null the values are also copied there (per-job
+// counts of a batch).
+template <class T>
+__global__ void __launch_bounds__(1024) k_peak_scan(const T *vals, int64_t n, int64_t *offsets, int64_t *total,
+                                                    int64_t *copy) {
     __shared__ int64_t part[1024];
-    const int64_t per = (n_tiles + 1023) / 1024;
+    const int64_t per = (n + 1023) / 1024;
     const int64_t b = threadIdx.x * per;
-    const int64_t e = min(b + per, n_tiles);
+    const int64_t e = min(b + per, n);
     int64_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += counts[i];
+    for (int64_t i = b; i < e; ++i) s += (int64_t)vals[i];
     part[threadIdx.x] = s;
     __syncthreads();
     // inclusive Hillis-Steele scan over the 1024 partial sums
@@ -242,16 +326,17 @@ __global__ void __launch_bounds__(1024) k_peak_scan(const int32_t *counts, int64
     int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
     for (int64_t i = b; i < e; ++i) {
         offsets[i] = run;
-        run += counts[i];
+        run += (int64_t)vals[i];
+        if (copy) copy[i] = (int64_t)vals[i];
     }
-    if (threadIdx.x == 1023) *n_found = part[1023];
+    if (threadIdx.x == 1023) *total = part[1023];
 }
 
 // Recompute the flags of one tile that holds peaks and write them at the
 // tile's offset in column order, dropping those at or beyond the capacity.
 template <class PT>
 __device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t tile,
-                                           float thr, int64_t tile_off, fdas_peak *out, int64_t capacity,
+                                           float thr, int64_t tile_off, fdas_peak *out, int64_t capacity, int job,
                                            peak_val_t<PT> (*buf)[kPeakTileCols + 2], int *pre) {
     const int z = (int)(tile / n_cb);
     const int64_t c0 = (tile % n_cb) * kPeakTileCols;
@@ -274,7 +359,7 @@ __device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, 
             fdas_peak pk;
             pk.r = c0 + col - 1;
             pk.z_idx = z;
-            pk.job = 0;
+            pk.job = job;
             pk.power = (float)buf[1][col];
             pk.reserved = 0.0f;
             out[pos] = pk;
@@ -283,66 +368,255 @@ __device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, 
     }
 }
 
+// The peaks of chunk ch of one plane, written from offset off on.  Called by
+// the whole workgroup; contains barriers.
+template <class PT>
+__device__ __forceinline__ void write_chunk(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles,
+                                            int64_t ch, float thr, const uint8_t *flags, const int32_t *counts,
+                                            int64_t off, fdas_peak *out, int64_t capacity, int job,
+                                            peak_val_t<PT> (*buf)[kPeakTileCols + 2], int *pre) {
+    for (int i = 0; i < kTilesPerBlock; ++i) {
+        const int64_t tile = ch * kTilesPerBlock + i;
+        if (tile >= n_tiles) break;
+        if (flags[tile] == 0) continue;      // uniform: counts[tile] was not written
+        const int cnt = counts[tile];
+        if (cnt == 0) continue;              // uniform: no peak in this tile
+        write_tile<PT>(plane, n, n_z, n_cb, tile, thr, off, out, capacity, job, buf, pre);
+        off += cnt;
+        __syncthreads();                     // buf and pre are reused by the next tile
+    }
+}
+
+// Write: each workgroup walks its flagged chunks in order from its offset;
+// a batch job's list starts at out + job * capacity and its offsets at the
+// job's prefix (job_prefix).
 template <class PT>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_write(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles, float thr, const uint8_t *flags,
-             const int32_t *counts, const int32_t *block_counts, const int64_t *block_offsets, fdas_peak *out,
-             int64_t capacity) {
+k_peak_write(ChunkSource<PT> src, int n_z, int64_t n_chunks, float thr, const uint8_t *flags, const uint8_t *cflags,
+             const int32_t *counts, const int32_t *block_counts, const int64_t *wg_offsets,
+             const int64_t *job_prefix, fdas_peak *out, int64_t capacity) {
     __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
-    __shared__ int pre[kPeakThreads];
-    const int64_t n_chunks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
-    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-        if (block_counts[ch] == 0) continue;     // uniform: no peak in the chunk
-        int64_t off = block_offsets[ch];
-        for (int i = 0; i < kTilesPerBlock; ++i) {
-            const int64_t tile = ch * kTilesPerBlock + i;
-            if (tile >= n_tiles) break;
-            if (flags[tile] == 0) continue;      // uniform: counts[tile] was not written
-            const int cnt = counts[tile];
-            if (cnt == 0) continue;              // uniform: no peak in this tile
-            write_tile<PT>(plane, n, n_z, n_cb, tile, thr, off, out, capacity, buf, pre);
-            off += cnt;
-            __syncthreads();                     // buf and pre are reused by the next tile
+    __shared__ int pre[kPeakThreads], list[kPeakThreads], wave_cnt[kPeakThreads / 64];
+    int64_t r0, r1;
+    chunk_range(n_chunks, &r0, &r1);
+    int64_t run = wg_offsets[blockIdx.x];   // peaks of all chunks before this one
+    for (int64_t c0 = r0; c0 < r1; c0 += kPeakThreads) {
+        const int nf = flagged_chunks(cflags, c0, r1, list, wave_cnt);
+        for (int k = 0; k < nf; ++k) {
+            const int64_t ch = c0 + list[k];
+            const int cnt = block_counts[ch];
+            if (cnt == 0) continue;              // uniform
+            const auto loc = src.at(ch, n_z);
+            const int64_t off = job_prefix ? run - job_prefix[loc.job] : run;
+            write_chunk<PT>(loc.plane, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, thr, flags + loc.tile_base,
+                            counts + loc.tile_base, off, out + (int64_t)loc.job * capacity, capacity, loc.job, buf,
+                            pre);
+            run += cnt;
         }
+        __syncthreads();                         // list is rewritten by the next group
     }
 }
 
 namespace {
+
+size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Scratch of the single-plane finder in the plan's workspace.
+struct PeakScratch {
+    int64_t n_cb, n_tiles, n_chunks;
+    int32_t *counts;         // per tile
+    int32_t *block_counts;   // per chunk
+    int32_t *wg_totals;      // per count workgroup
+    int64_t *wg_offsets;     // per count workgroup, then the total
+    uint8_t *flags;          // per tile
+    uint8_t *cflags;         // per chunk (right after flags: one clear covers both)
+};
+
+bool plane_scratch(const fdas_plan_s &p, int64_t n, PeakScratch *o) {
+    o->n_cb = (n + kPeakTileCols - 1) / kPeakTileCols;
+    o->n_tiles = o->n_cb * p.cfg.n_z;
+    if (o->n_tiles > p.peak_tile_cap || o->n_tiles > 0x7fffffffLL) return false;
+    o->n_chunks = (o->n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
+    unsigned char *b = static_cast<unsigned char *>(p.ws) + p.off_scr;
+    size_t off = 0;
+    o->wg_offsets = reinterpret_cast<int64_t *>(b + off);
+    off = up256(off + (kPeakGrid + 1) * sizeof(int64_t));
+    o->wg_totals = reinterpret_cast<int32_t *>(b + off);
+    off = up256(off + kPeakGrid * sizeof(int32_t));
+    o->counts = reinterpret_cast<int32_t *>(b + off);
+    off = up256(off + (size_t)o->n_tiles * sizeof(int32_t));
+    o->block_counts = reinterpret_cast<int32_t *>(b + off);
+    off = up256(off + (size_t)o->n_chunks * sizeof(int32_t));
+    o->flags = b + off;
+    o->cflags = o->flags + o->n_tiles;
+    return true;
+}
+
+void launch_clear(uint8_t *flags, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_peak_clear, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096))),
+                       dim3(256), 0, st, flags, n);
+}
+
+// Workgroups of a mark pass over `total` cells (16-byte vectors, four per thread).
+unsigned mark_grid(int64_t total, size_t elem) {
+    const int64_t vecs = total / (int64_t)(16 / elem);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (vecs + 1023) / 1024));
+}
+
+// Count, scan and write over n_chunks chunks (flags already set).
+template <class PT>
+void launch_finish(const ChunkSource<PT> &src, int n_z, int64_t n_chunks, float thr, const uint8_t *flags,
+                   const uint8_t *cflags, int32_t *counts, int32_t *block_counts, int32_t *wg_totals,
+                   int64_t *wg_offsets, unsigned long long *job_totals, int64_t *job_prefix, int64_t *n_found,
+                   fdas_peak *out, int64_t cap, hipStream_t st) {
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_chunks, kPeakGrid));
+    hipLaunchKernelGGL(k_peak_count<PT>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, thr, flags, cflags,
+                       counts, block_counts, wg_totals, job_totals);
+    // workgroup offsets; a single plane's total is its count
+    hipLaunchKernelGGL(k_peak_scan<int32_t>, dim3(1), dim3(1024), 0, st, wg_totals, (int64_t)grid, wg_offsets,
+                       job_totals ? wg_offsets + grid : n_found, (int64_t *)nullptr);
+    if (job_totals)   // per-job prefixes and counts
+        hipLaunchKernelGGL(k_peak_scan<unsigned long long>, dim3(1), dim3(1024), 0, st, job_totals,
+                           (int64_t)src.n_jobs, job_prefix, wg_offsets + grid, n_found);
+    hipLaunchKernelGGL(k_peak_write<PT>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, thr, flags, cflags,
+                       counts, block_counts, wg_offsets, job_prefix, out, cap);
+}
+
 template <class PT>
 hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, fdas_peak *out, int64_t cap,
-               int64_t *n_found, hipStream_t st) {
-    const int64_t n_cb = (n + kPeakTileCols - 1) / kPeakTileCols;
-    const int64_t n_tiles = n_cb * p.cfg.n_z;
-    if (n_tiles > p.peak_tile_cap || n_tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    unsigned char *scr = static_cast<unsigned char *>(p.ws) + p.off_scr;
-    const int64_t n_blocks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;     // chunks
-    int64_t *offsets = reinterpret_cast<int64_t *>(scr);                           // per chunk
-    int32_t *counts = reinterpret_cast<int32_t *>(scr + (size_t)n_blocks * sizeof(int64_t));   // per tile
-    int32_t *block_counts = counts + n_tiles;                                       // per chunk
-    uint8_t *flags = reinterpret_cast<uint8_t *>(block_counts + n_blocks);            // per tile
-    uint8_t *cflags = flags + n_tiles;                                              // per chunk
-    const unsigned grid = (unsigned)std::min<int64_t>(n_blocks, kPeakGrid);
-    const int64_t total = n_tiles / n_cb * n;                                       // cells of the plane
-    hipLaunchKernelGGL(k_peak_clear, dim3((unsigned)std::min<int64_t>((n_tiles + n_blocks + 255) / 256, 4096)),
-                       dim3(256), 0, st, flags, n_tiles + n_blocks);
-    hipLaunchKernelGGL(k_peak_mark<PT>, dim3(8192), dim3(256), 0, st, plane, n, total, n_cb, thr, flags, cflags);
-    hipLaunchKernelGGL(k_peak_count<PT>, dim3(grid), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb, n_tiles,
-                       thr, flags, cflags, counts, block_counts);
-    hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, st, block_counts, offsets, n_blocks, n_found);
-    hipLaunchKernelGGL(k_peak_write<PT>, dim3(grid), dim3(kPeakThreads), 0, st, plane, n, p.cfg.n_z, n_cb, n_tiles,
-                       thr, flags, counts, block_counts, offsets, out, cap);
+               int64_t *n_found, bool premarked, hipStream_t st) {
+    PeakScratch sc;
+    if (!plane_scratch(p, n, &sc)) return hipErrorInvalidValue;
+    if (!premarked) {
+        const int64_t total = (int64_t)p.cfg.n_z * n;   // cells of the plane
+        launch_clear(sc.flags, sc.n_tiles + sc.n_chunks, st);
+        hipLaunchKernelGGL(k_peak_mark<PT>, dim3(mark_grid(total, sizeof(PT))), dim3(256), 0, st, plane, n, total,
+                           make_peak_marks(sc.flags, sc.cflags, sc.n_cb, thr));
+    }
+    ChunkSource<PT> src{plane, n, sc.n_cb, sc.n_tiles, nullptr, 0};
+    launch_finish<PT>(src, p.cfg.n_z, sc.n_chunks, thr, sc.flags, sc.cflags, sc.counts, sc.block_counts,
+                      sc.wg_totals, sc.wg_offsets, nullptr, nullptr, n_found, out, cap, st);
     return hipGetLastError();
 }
+
+// Scratch of the batched finder (caller memory, 256-byte aligned regions).
+struct BatchScratch {
+    int32_t *counts;                 // per tile of all jobs
+    int32_t *block_counts;           // per chunk
+    int32_t *wg_totals;              // per count workgroup
+    int64_t *wg_offsets;             // per count workgroup, then the grand total
+    int64_t *job_prefix;             // per job
+    unsigned long long *job_totals;  // per job (zeroed with the flags, right before them)
+    uint8_t *flags;                  // per tile
+    uint8_t *cflags;                 // per chunk (right after flags)
+    size_t bytes;
+};
+
+BatchScratch batch_scratch(const fdas_plan_s &p, void *base) {
+    const size_t T = (size_t)p.batch_peak_tiles, C = (size_t)p.batch_peak_chunks, J = (size_t)p.batch_jobs;
+    unsigned char *b = static_cast<unsigned char *>(base);
+    BatchScratch o;
+    size_t off = 0;
+    o.counts = reinterpret_cast<int32_t *>(b + off);
+    off = up256(off + T * sizeof(int32_t));
+    o.block_counts = reinterpret_cast<int32_t *>(b + off);
+    off = up256(off + C * sizeof(int32_t));
+    o.wg_totals = reinterpret_cast<int32_t *>(b + off);
+    off = up256(off + kPeakGrid * sizeof(int32_t));
+    o.wg_offsets = reinterpret_cast<int64_t *>(b + off);
+    off = up256(off + (kPeakGrid + 1) * sizeof(int64_t));
+    o.job_prefix = reinterpret_cast<int64_t *>(b + off);
+    off = up256(off + J * sizeof(int64_t));
+    o.job_totals = reinterpret_cast<unsigned long long *>(b + off);
+    o.flags = b + off + J * sizeof(unsigned long long);
+    o.cflags = o.flags + T;
+    off = up256(off + J * sizeof(unsigned long long) + T + C);
+    o.bytes = off;
+    return o;
+}
+
+template <class PT>
+hipError_t run_batch_mark(const fdas_plan_s &p, const PT *planes, const PeakMarks &m, hipStream_t st) {
+    for (const fdas_batch_job &j : p.batch_host) {
+        const int64_t total = (int64_t)p.cfg.n_z * j.n_bins;
+        hipLaunchKernelGGL(k_peak_mark<PT>, dim3(mark_grid(total, sizeof(PT))), dim3(256), 0, st,
+                           planes + j.plane_off, j.n_bins, total,
+                           make_peak_marks(m.flags + j.tile_base, m.cflags + j.chunk_base,
+                                           (j.n_bins + kPeakTileCols - 1) / kPeakTileCols, m.thr));
+    }
+    return hipGetLastError();
+}
+
+template <class PT>
+hipError_t run_batch_finish(const fdas_plan_s &p, const PT *planes, void *scratch, float thr, fdas_peak *out,
+                            int64_t cap, int64_t *n_found, hipStream_t st) {
+    const BatchScratch sc = batch_scratch(p, scratch);
+    const auto *jobs = reinterpret_cast<const fdas_batch_job *>(static_cast<const unsigned char *>(p.ws) +
+                                                               p.off_batch + p.batch_hdr);
+    ChunkSource<PT> src{planes, 0, 0, 0, jobs, p.batch_jobs};
+    launch_finish<PT>(src, p.cfg.n_z, p.batch_peak_chunks, thr, sc.flags, sc.cflags, sc.counts, sc.block_counts,
+                      sc.wg_totals, sc.wg_offsets, sc.job_totals, sc.job_prefix, n_found, out, cap, st);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_peaks(const fdas_plan_s &p, const void *plane, int64_t n, float thr, fdas_peak *out,
-                        int64_t capacity, int64_t *n_found, hipStream_t st) {
+                        int64_t capacity, int64_t *n_found, hipStream_t st, bool premarked) {
     switch (p.cfg.plane_dtype) {
-        case FDAS_FP32: return run<float>(p, static_cast<const float *>(plane), n, thr, out, capacity, n_found, st);
+        case FDAS_FP32:
+            return run<float>(p, static_cast<const float *>(plane), n, thr, out, capacity, n_found, premarked, st);
         case FDAS_BF16:
             return run<unsigned short>(p, static_cast<const unsigned short *>(plane), n, thr, out, capacity,
-                                       n_found, st);
-        case FDAS_FP64: return run<double>(p, static_cast<const double *>(plane), n, thr, out, capacity, n_found, st);
+                                       n_found, premarked, st);
+        case FDAS_FP64:
+            return run<double>(p, static_cast<const double *>(plane), n, thr, out, capacity, n_found, premarked, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t peak_marks(const fdas_plan_s &p, int64_t n, float thr, PeakMarks *marks, hipStream_t st) {
+    PeakScratch sc;
+    if (!plane_scratch(p, n, &sc)) return hipErrorInvalidValue;
+    launch_clear(sc.flags, sc.n_tiles + sc.n_chunks, st);
+    *marks = make_peak_marks(sc.flags, sc.cflags, sc.n_cb, thr);
+    return hipGetLastError();
+}
+
+size_t batch_peak_scratch_bytes(const fdas_plan_s &p) { return batch_scratch(p, nullptr).bytes; }
+
+hipError_t batch_peak_marks(const fdas_plan_s &p, void *scratch, float thr, PeakMarks *marks, hipStream_t st) {
+    const BatchScratch sc = batch_scratch(p, scratch);
+    // per-job totals, tile flags and chunk flags, stored back to back
+    launch_clear(reinterpret_cast<uint8_t *>(sc.job_totals),
+                 (int64_t)(p.batch_jobs * sizeof(unsigned long long)) + p.batch_peak_tiles + p.batch_peak_chunks, st);
+    // n_cb differs per job: the marking kernels derive it from the job's length
+    *marks = make_peak_marks(sc.flags, sc.cflags, 0, thr);
+    return hipGetLastError();
+}
+
+hipError_t batch_peak_mark_pass(const fdas_plan_s &p, const void *planes, const PeakMarks &marks, hipStream_t st) {
+    switch (p.cfg.plane_dtype) {
+        case FDAS_FP32: return run_batch_mark<float>(p, static_cast<const float *>(planes), marks, st);
+        case FDAS_BF16:
+            return run_batch_mark<unsigned short>(p, static_cast<const unsigned short *>(planes), marks, st);
+        case FDAS_FP64: return run_batch_mark<double>(p, static_cast<const double *>(planes), marks, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_peaks_finish(const fdas_plan_s &p, const void *planes, void *scratch, float thr, fdas_peak *out,
+                              int64_t capacity, int64_t *n_found, hipStream_t st) {
+    switch (p.cfg.plane_dtype) {
+        case FDAS_FP32:
+            return run_batch_finish<float>(p, static_cast<const float *>(planes), scratch, thr, out, capacity,
+                                           n_found, st);
+        case FDAS_BF16:
+            return run_batch_finish<unsigned short>(p, static_cast<const unsigned short *>(planes), scratch, thr,
+                                                    out, capacity, n_found, st);
+        case FDAS_FP64:
+            return run_batch_finish<double>(p, static_cast<const double *>(planes), scratch, thr, out, capacity,
+                                            n_found, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -88,6 +88,9 @@ def lib() -> ctypes.CDLL:
         L.fdas_set_batch.argtypes = [P, ctypes.POINTER(FdasJob), I32, I64, I64, P]
         L.fdas_correlate_batch.argtypes = [P, P, P, P]
         L.fdas_peaks.argtypes = [P, P, I64, ctypes.c_float, P, I64, P, P]
+        L.fdas_correlate_peaks.argtypes = [P, P, I64, P, ctypes.c_float, P, I64, P, P]
+        L.fdas_batch_peaks_workspace.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        L.fdas_correlate_batch_peaks.argtypes = [P, P, P, ctypes.c_float, P, I64, P, P, ctypes.c_size_t, P]
         L.fdas_harmonic_sum.argtypes = [P, P, I64, I32, P, P]
         L.fdas_band_max.argtypes = [P, P, I64, P, I32, P, P]
         L.fdas_prepare_workspace.argtypes = [I64, ctypes.POINTER(ctypes.c_size_t)]
@@ -133,6 +136,17 @@ def make_config(max_bins, z_min, z_step, n_z, n_taps, seg_len=0, compute="fp32",
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
     return FdasConfig(int(max_bins), float(z_min), float(z_step), int(n_z), int(n_taps),
                       int(seg_len), c, pd, int(z_chunk), a, int(max_jobs))
+
+
+def peak_records(raw, found, capacity):
+    """Peak records (a (capacity, 24) uint8 tensor of fdas_peak entries) ->
+    dict of numpy arrays z_idx, r, power, job and the true count n_found."""
+    import numpy as np
+    k = min(int(found), int(capacity))
+    rec = raw[:k].cpu().numpy().view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
+                                              ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
+    return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(), "power": rec["power"].copy(),
+            "job": rec["job"].copy(), "n_found": int(found)}
 
 
 class Plan:
@@ -253,7 +267,6 @@ class Plan:
 
     def peaks(self, plane, threshold, capacity=1 << 16, stream=None):
         """Peaks of a plane -> dict of numpy arrays z_idx, r, power and n_found."""
-        import numpy as np
         import torch
         n = plane.shape[1]
         out = torch.empty((max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
@@ -262,13 +275,76 @@ class Plan:
                                 float(threshold), ctypes.c_void_p(out.data_ptr()),
                                 int(capacity), ctypes.c_void_p(nf.data_ptr()),
                                 _stream_ptr(stream)), "fdas_peaks")
-        found = int(nf.item())
-        k = min(found, int(capacity))
-        raw = out[:k].cpu().numpy()
-        rec = raw.view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
-                                 ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
-        return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(),
-                "power": rec["power"].copy(), "n_found": found}
+        return peak_records(out, int(nf.item()), capacity)
+
+    def correlate_peaks(self, spectrum, threshold, capacity=1 << 16, plane=None, stream=None):
+        """Plane and thresholded peaks of a spectrum in one call
+        (fdas_correlate_peaks) -> (plane, peaks dict as from peaks())."""
+        import torch
+        if spectrum.dtype != torch.complex64 or not spectrum.is_contiguous():
+            raise ValueError("spectrum must be a contiguous complex64 tensor")
+        n = spectrum.numel()
+        if plane is None:
+            plane = self.empty_plane(n)
+        if plane.dtype != self.torch_plane_dtype() or tuple(plane.shape) != (self.n_z, n) \
+                or not plane.is_contiguous():
+            raise ValueError("plane has the wrong dtype, shape or layout")
+        out = torch.empty((max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
+        nf = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().fdas_correlate_peaks(self._h, ctypes.c_void_p(spectrum.data_ptr()), n,
+                                          ctypes.c_void_p(plane.data_ptr()), float(threshold),
+                                          ctypes.c_void_p(out.data_ptr()), int(capacity),
+                                          ctypes.c_void_p(nf.data_ptr()), _stream_ptr(stream)),
+               "fdas_correlate_peaks")
+        return plane, peak_records(out, int(nf.item()), capacity)
+
+    def batch_peaks_scratch(self):
+        """Device scratch for fdas_correlate_batch_peaks on the stored batch
+        (a uint8 tensor, reused while large enough)."""
+        import torch
+        nb = ctypes.c_size_t(0)
+        _check(lib().fdas_batch_peaks_workspace(self._h, ctypes.byref(nb)), "fdas_batch_peaks_workspace")
+        cur = getattr(self, "_batch_scratch", None)
+        if cur is None or cur.numel() < nb.value:
+            cur = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=self.device)
+            self._batch_scratch = cur
+        return cur
+
+    def correlate_batch_peaks_async(self, spectra, planes, threshold, out, n_found, stream=None):
+        """Enqueue fdas_correlate_batch_peaks: out a (n_jobs, capacity, 24)
+        uint8 device tensor of peak records, n_found an int64 device tensor
+        of n_jobs counts.  No host synchronisation (graph-capturable)."""
+        import torch
+        if spectra.dtype != torch.complex64 or not spectra.is_contiguous() \
+                or spectra.numel() < self.batch_bins:
+            raise ValueError("spectra must be a contiguous complex64 tensor of the batch's size")
+        if planes.dtype != self.torch_plane_dtype() or not planes.is_contiguous() \
+                or planes.numel() < self.batch_cells:
+            raise ValueError("planes has the wrong dtype, size or layout")
+        n_jobs = len(self.batch_lengths)
+        if out.dim() != 3 or out.shape[0] != n_jobs or out.shape[2] != 24 or out.dtype != torch.uint8 \
+                or not out.is_contiguous() or n_found.numel() < n_jobs or n_found.dtype != torch.int64:
+            raise ValueError("out must be (n_jobs, capacity, 24) uint8, n_found n_jobs int64")
+        scr = self.batch_peaks_scratch()
+        _check(lib().fdas_correlate_batch_peaks(self._h, ctypes.c_void_p(spectra.data_ptr()),
+                                                ctypes.c_void_p(planes.data_ptr()), float(threshold),
+                                                ctypes.c_void_p(out.data_ptr()), int(out.shape[1]),
+                                                ctypes.c_void_p(n_found.data_ptr()),
+                                                ctypes.c_void_p(scr.data_ptr()), scr.numel(),
+                                                _stream_ptr(stream)), "fdas_correlate_batch_peaks")
+
+    def correlate_batch_peaks(self, spectra, threshold, capacity=1 << 12, planes=None, stream=None):
+        """Planes of the stored batch and every job's peaks
+        (fdas_correlate_batch_peaks) -> (planes, list of peaks dicts)."""
+        import torch
+        if planes is None:
+            planes = torch.empty(self.batch_cells, dtype=self.torch_plane_dtype(), device=self.device)
+        n_jobs = len(self.batch_lengths)
+        out = torch.empty((n_jobs, max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
+        nf = torch.zeros(n_jobs, dtype=torch.int64, device=self.device)
+        self.correlate_batch_peaks_async(spectra, planes, threshold, out, nf, stream)
+        found = nf.cpu().tolist()
+        return planes, [peak_records(out[i], found[i], capacity) for i in range(n_jobs)]
 
     def band_max(self, plane, windows, stream=None):
         """Highest cell of each window (z_lo, z_hi, r_lo, r_hi) of a plane

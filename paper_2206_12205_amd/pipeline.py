@@ -5,14 +5,17 @@ Spectra of uneven length share one template grid.  They are grouped into
 length classes (powers of two); each class gets the kernel configuration the
 autotuner (fdas_tune) measures fastest for its longest member, and its jobs
 are packed into chunks whose planes fit one reusable plane buffer.  A pass
-over the batch runs, per chunk, one persistent fdas_correlate_batch launch and
-the thresholded peak finder on every job's plane, so the full set of planes
-(tens of GB in BF16 for hundreds of trials) is never held at once.  A pass
-issues kernels only, so it can be recorded once as a HIP graph (capture) and
-replayed.
+over the batch runs, per chunk, fdas_correlate_batch_peaks: one persistent
+correlation launch that also flags the peak finder's tiles while it stores
+the planes, then one count, scan and write over all of the chunk's planes
+(fused=False instead runs fdas_correlate_batch and fdas_peaks on every job's
+plane).  The full set of planes (tens of GB in BF16 for hundreds of trials)
+is never held at once.  A pass issues kernels only, so it can be recorded
+once as a HIP graph (capture) and replayed.
 """
 from __future__ import annotations
 
+import ctypes
 import math
 
 from . import fdas as F
@@ -54,7 +57,9 @@ class BatchSearch:
         for i, v in enumerate(self.lengths):
             classes.setdefault(max(int(math.ceil(math.log2(v))), 0), []).append(i)
         self.tuned = {}
-        self.chunks = []          # (plan, job indices, plane offsets in the buffer)
+        self.chunks = []          # (plan, job indices, plane offsets in the buffer, first slot)
+        self.slot = [0] * len(self.lengths)   # row of job i in the peak lists (chunk order)
+        self._next_slot = 0
         for cls in sorted(classes):
             jobs = classes[cls]
             cmax = max(self.lengths[i] for i in jobs)
@@ -85,6 +90,13 @@ class BatchSearch:
         self.peaks_raw = torch.empty((len(self.lengths), self.peak_capacity, 24), dtype=torch.uint8,
                                      device=self.device)
         self.n_found = torch.zeros(len(self.lengths), dtype=torch.int64, device=self.device)
+        # scratch of the batched peak finder, shared by the chunks (they run in order on one stream)
+        need = 0
+        for pl, _, _, _ in self.chunks:
+            nb = ctypes.c_size_t(0)
+            F._check(F.lib().fdas_batch_peaks_workspace(pl._h, ctypes.byref(nb)), "fdas_batch_peaks_workspace")
+            need = max(need, nb.value)
+        self.peak_scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
 
     def _chunk(self, jobs, cmax, knobs, common):
         pl = F.Plan(max_bins=cmax, max_jobs=len(jobs), device=self.device, **knobs, **common)
@@ -100,29 +112,42 @@ class BatchSearch:
         for i in jobs:
             offs.append(po)
             po += self.n_z * self.lengths[i]
-        return pl, list(jobs), offs
+        slot0 = self._next_slot
+        for k, i in enumerate(jobs):
+            self.slot[i] = slot0 + k
+        self._next_slot += len(jobs)
+        return pl, list(jobs), offs, slot0
 
-    def run(self, spectra, threshold, stream=None, find_peaks=True):
+    def run(self, spectra, threshold, stream=None, find_peaks=True, fused=True):
         """One pass: planes chunk by chunk into the buffer, peaks of every
         job's plane into the per-job peak lists (asynchronous on stream).
-        find_peaks=False runs the correlations only (for timing)."""
-        import ctypes
+        find_peaks=False runs the correlations only (for timing); fused=False
+        finds the peaks with a separate fdas_peaks call per job."""
         import torch
         if spectra.dtype != torch.complex64 or not spectra.is_contiguous() or spectra.numel() < self.total_bins:
             raise ValueError("spectra must be a contiguous complex64 tensor holding every packed spectrum")
         s = F._stream_ptr(stream)
         L = F.lib()
         esz = self.buffer.element_size()
-        for pl, jobs, offs in self.chunks:
-            F._check(L.fdas_correlate_batch(pl._h, ctypes.c_void_p(spectra.data_ptr()),
-                                            ctypes.c_void_p(self.buffer.data_ptr()), s), "fdas_correlate_batch")
-            for i, po in zip(jobs, offs) if find_peaks else ():
+        sp = ctypes.c_void_p(spectra.data_ptr())
+        buf = ctypes.c_void_p(self.buffer.data_ptr())
+        for pl, jobs, offs, slot0 in self.chunks:
+            if find_peaks and fused:
+                F._check(L.fdas_correlate_batch_peaks(
+                    pl._h, sp, buf, float(threshold), ctypes.c_void_p(self.peaks_raw[slot0].data_ptr()),
+                    self.peak_capacity, ctypes.c_void_p(self.n_found[slot0:slot0 + 1].data_ptr()),
+                    ctypes.c_void_p(self.peak_scratch.data_ptr()), self.peak_scratch.numel(), s),
+                    "fdas_correlate_batch_peaks")
+                continue
+            F._check(L.fdas_correlate_batch(pl._h, sp, buf, s), "fdas_correlate_batch")
+            for k, (i, po) in enumerate(zip(jobs, offs) if find_peaks else ()):
                 F._check(L.fdas_peaks(pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz), self.lengths[i],
-                                      float(threshold), ctypes.c_void_p(self.peaks_raw[i].data_ptr()),
-                                      self.peak_capacity, ctypes.c_void_p(self.n_found[i:i + 1].data_ptr()), s),
+                                      float(threshold), ctypes.c_void_p(self.peaks_raw[slot0 + k].data_ptr()),
+                                      self.peak_capacity, ctypes.c_void_p(self.n_found[slot0 + k:].data_ptr()),
+                                      s),
                          "fdas_peaks")
 
-    def capture(self, spectra, threshold, find_peaks=True):
+    def capture(self, spectra, threshold, find_peaks=True, fused=True):
         """Record one pass (run) into a HIP graph and return it
         (torch.cuda.CUDAGraph).  Every launch of a pass has fixed arguments
         (each chunk has its own plan and job table, set at construction), and
@@ -133,20 +158,20 @@ class BatchSearch:
         side = torch.cuda.Stream(device=self.device)
         side.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(side):
-            self.run(spectra, threshold, find_peaks=find_peaks)      # warm-up on the capture stream
+            self.run(spectra, threshold, find_peaks=find_peaks, fused=fused)   # warm-up on the capture stream
         torch.cuda.current_stream(self.device).wait_stream(side)
         torch.cuda.synchronize(self.device)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.run(spectra, threshold, find_peaks=find_peaks)
+            self.run(spectra, threshold, find_peaks=find_peaks, fused=fused)
         return g
 
     def peaks(self, i):
         """Peak list of job i after run() (host copy): dict of z_idx, r, power, n_found."""
         import numpy as np
-        found = int(self.n_found[i].item())
+        found = int(self.n_found[self.slot[i]].item())
         k = min(found, self.peak_capacity)
-        raw = self.peaks_raw[i, :k].cpu().numpy()
+        raw = self.peaks_raw[self.slot[i], :k].cpu().numpy()
         rec = raw.view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
                                  ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
         return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(), "power": rec["power"].copy(),

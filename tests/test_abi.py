@@ -120,6 +120,24 @@ def test_layout_and_workspace_checks_on_host():
         assert L.fdas_harmonic_sum(h, fake, 100, 4, None, None) == F.E_INVALID
         assert L.fdas_harmonic_sum(h, ctypes.c_void_p(0x10001), 100, 4, fake, None) == F.E_INVALID
         assert L.fdas_harmonic_sum(None, fake, 100, 4, fake, None) == F.E_INVALID
+        # fused plane + peaks: argument and state checks only (no launch)
+        assert L.fdas_correlate_peaks(h, fake, 100, fake, 1.0, fake, 5, nf, None) == F.E_STATE   # no templates
+        assert L.fdas_correlate_peaks(h, fake, 100, fake, 1.0, None, 5, nf, None) == F.E_INVALID
+        assert L.fdas_correlate_peaks(h, fake, 100, fake, 1.0, fake, -1, nf, None) == F.E_INVALID
+        assert L.fdas_correlate_peaks(h, fake, 100, fake, 1.0, fake, 5, ctypes.c_void_p(0x20004), None) \
+            == F.E_INVALID
+        assert L.fdas_correlate_peaks(h, fake, 0, fake, 1.0, fake, 5, nf, None) == F.E_INVALID
+        assert L.fdas_correlate_peaks(h, fake, 4097, fake, 1.0, fake, 5, nf, None) == F.E_INVALID
+        assert L.fdas_correlate_peaks(h, ctypes.c_void_p(0x10008), 100, fake, 1.0, fake, 5, nf, None) \
+            == F.E_INVALID
+        assert L.fdas_correlate_peaks(None, fake, 100, fake, 1.0, fake, 5, nf, None) == F.E_INVALID
+        sb = ctypes.c_size_t(0)
+        assert L.fdas_batch_peaks_workspace(h, ctypes.byref(sb)) == F.E_STATE               # no batch
+        assert L.fdas_batch_peaks_workspace(h, None) == F.E_INVALID
+        assert L.fdas_correlate_batch_peaks(h, fake, fake, 1.0, fake, 5, nf, fake, 1 << 20, None) == F.E_STATE
+        assert L.fdas_correlate_batch_peaks(h, fake, fake, 1.0, None, 5, nf, fake, 1 << 20, None) == F.E_INVALID
+        assert L.fdas_correlate_batch_peaks(h, fake, fake, 1.0, fake, 5, None, fake, 1 << 20, None) \
+            == F.E_INVALID
     finally:
         L.fdas_destroy(h)
     L.fdas_destroy(None)
