@@ -299,12 +299,35 @@ def peaks_timing(pl, x, plane, thr, steps, ms_plane):
     return res
 
 
-def harmonic_timing(pl, plane, steps):
+def harmonic_timing(pl, plane, steps, thr):
     """fdas_harmonic_sum on the headline BF16 plane for H = 2, 4, 8, 16:
     time per call, summed cells per second and HBM fraction of the
-    algorithmic bytes (the plane read once plus the summed plane written)."""
+    algorithmic bytes (the plane read once plus the summed plane written);
+    then the sum with thresholded peaks, as fdas_harmonic_sum followed by
+    fdas_peaks and as one fdas_harmonic_sum_peaks call."""
+    import ctypes
     import torch
+    from paper_2206_12205_amd import fdas as F
+    L = F.lib()
     n_z, n = plane.shape
+    cap = 1 << 16
+    pk = torch.empty((cap, 24), dtype=torch.uint8, device=plane.device)
+    nf = torch.zeros(1, dtype=torch.int64, device=plane.device)
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+    pp, kp, fp = ctypes.c_void_p(plane.data_ptr()), ctypes.c_void_p(pk.data_ptr()), ctypes.c_void_p(nf.data_ptr())
+
+    def timed(fn, reps):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
     elem = plane.element_size()
     res = {}
     for H in (2, 4, 8, 16):
@@ -325,7 +348,19 @@ def harmonic_timing(pl, plane, steps):
         res[f"H{H}"] = {"ms": ms, "summed_cells_per_s": n_z * nh / (ms * 1e-3),
                         "algorithmic_GBs": alg / (ms * 1e-3) / 1e9,
                         "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        note(f"harmonic sum H={H}: {ms:.3f} ms")
+        op = ctypes.c_void_p(out.data_ptr())
+
+        def separate():
+            F._check(L.fdas_harmonic_sum(pl._h, pp, n, H, op, sp), "fdas_harmonic_sum")
+            F._check(L.fdas_peaks(pl._h, op, nh, float(thr), kp, cap, fp, sp), "fdas_peaks")
+
+        def fused():
+            F._check(L.fdas_harmonic_sum_peaks(pl._h, pp, n, H, op, float(thr), kp, cap, fp, sp),
+                     "fdas_harmonic_sum_peaks")
+        res[f"H{H}"]["with_peaks"] = {"threshold": thr, "separate_ms": timed(separate, reps),
+                                      "fused_ms": timed(fused, reps), "n_found": int(nf.item())}
+        note(f"harmonic sum H={H}: {ms:.3f} ms; with peaks: separate "
+             f"{res[f'H{H}']['with_peaks']['separate_ms']:.3f} ms, fused {res[f'H{H}']['with_peaks']['fused_ms']:.3f} ms")
         del out
     return res
 
@@ -610,7 +645,7 @@ def main():
 
     fused_pk = peaks_timing(pl_b, x, plane_b, cfg["threshold"], args.steps, ms_b)
     if not args.no_harmonic:
-        harm = harmonic_timing(pl_b, plane_b, args.steps)
+        harm = harmonic_timing(pl_b, plane_b, args.steps, cfg["threshold"])
     st_b = launch_stats(pl_b, x, plane_b)
     copy_gbs = copy_bandwidth(dev)
     fill_gbs = fill_bandwidth(dev)

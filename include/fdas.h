@@ -365,6 +365,19 @@ int fdas_band_max(fdas_plan_t plan, const void *plane, int64_t n_bins, const int
 int fdas_harmonic_sum(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_harm, void *out,
                       void *stream);
 
+/* Harmonic summing with thresholding in one call: the summed plane
+ * fdas_harmonic_sum writes to out, and exactly the list and count fdas_peaks
+ * then gives for it (an n_z x N_H plane, N_H = (n_bins - 1) / n_harm + 1;
+ * peaks, capacity and n_found as for fdas_peaks: peaks 16-byte and n_found
+ * 8-byte aligned, job = 0).  The summing kernel flags the peak finder's tiles
+ * (one row x 1024 bins) holding a stored sum above the threshold while it
+ * writes them, so the finder does not stream the summed plane back.  Same
+ * argument rules as fdas_harmonic_sum; FDAS_E_WORKSPACE without a workspace
+ * (the peak finder's counters live there).  Asynchronous on stream. */
+int fdas_harmonic_sum_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_harm, void *out,
+                            float threshold, fdas_peak *peaks, int64_t capacity, int64_t *n_found,
+                            void *stream);
+
 /* Candidate refinement: matched-filter power at continuous (r, z) and its
  * gradient (no plan needed).  The plane samples the power on integer r and a
  * z grid, and quantisation in both axes moves peaks into adjacent bins

@@ -302,6 +302,32 @@ int fdas_harmonic_sum(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t 
     return hip_status(fdas::launch_harmonic_sum(*p, plane, n_bins, n_harm, out, static_cast<hipStream_t>(stream)));
 }
 
+int fdas_harmonic_sum_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_harm, void *out,
+                            float threshold, fdas_peak *peaks, int64_t capacity, int64_t *n_found, void *stream) {
+    if (!p || !plane || !out || !n_found || capacity < 0 || (capacity > 0 && !peaks)) return FDAS_E_INVALID;
+    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
+    if ((reinterpret_cast<uintptr_t>(plane) % pe) != 0 || (reinterpret_cast<uintptr_t>(out) % pe) != 0 ||
+        (peaks && !aligned16(peaks)) || (reinterpret_cast<uintptr_t>(n_found) & 7u))
+        return FDAS_E_INVALID;
+    if (n_bins < 1 || n_bins > p->cfg.max_bins || n_harm < 1 || n_harm > fdas::kMaxHarmonics)
+        return FDAS_E_INVALID;
+    if (p->cfg.n_z > 65535) return FDAS_E_UNSUPPORTED;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nh = (n_bins - 1) / n_harm + 1;
+    const int64_t n_cb = (nh + fdas::kPeakTileCols - 1) / fdas::kPeakTileCols;
+    if (nh > fdas::kMarkMaxBins || (int64_t)p->cfg.n_z * n_cb >= 0x7fffffffLL) {   // sum, then the streaming finder
+        hipError_t e = fdas::launch_harmonic_sum(*p, plane, n_bins, n_harm, out, st);
+        if (e == hipSuccess) e = fdas::launch_peaks(*p, out, nh, threshold, peaks, capacity, n_found, st);
+        return hip_status(e);
+    }
+    fdas::PeakMarks m;
+    hipError_t e = fdas::peak_marks(*p, nh, threshold, &m, st);
+    if (e == hipSuccess) e = fdas::launch_harmonic_sum_marked(*p, plane, n_bins, n_harm, out, m, st);
+    if (e == hipSuccess) e = fdas::launch_peaks(*p, out, nh, threshold, peaks, capacity, n_found, st, true);
+    return hip_status(e);
+}
+
 int fdas_set_batch(fdas_plan_t p, const fdas_job *jobs, int32_t n_jobs, int64_t spectra_bins, int64_t plane_cells,
                    void *stream) {
     if (!p || !jobs || n_jobs < 1) return FDAS_E_INVALID;

@@ -19,8 +19,11 @@
 // kernel reads about (H + 1) / 2 planes' worth of cache lines, held in part
 // by the L2 and the last-level cache.  Sums in FP32 (FP64 for an FP64
 // plane); the output has the plane's dtype (bfloat16 rounded to nearest
-// even), so fdas_peaks thresholds it directly.
+// even), so fdas_peaks thresholds it directly.  The marking form (kMark)
+// also flags the peak finder's tiles of the summed plane while storing it,
+// so harmonic summing with thresholding needs no second read of the sums.
 #include "internal.hpp"
+#include "marks.hpp"
 #include "plane_io.hpp"
 
 namespace fdas {
@@ -50,12 +53,15 @@ struct hs_io<float> {
     using acc = float;
     static __device__ __forceinline__ float get(const float *p, int64_t i) { return p[i]; }
     static __device__ __forceinline__ void put(float *p, float v) { plane_store<float>::put(p, v); }
+    // a bound b with: stored value > thr implies v > b (exact here)
+    static __device__ __forceinline__ float mark_bound(float thr) { return thr; }
 };
 template <>
 struct hs_io<double> {
     using acc = double;
     static __device__ __forceinline__ double get(const double *p, int64_t i) { return p[i]; }
     static __device__ __forceinline__ void put(double *p, double v) { plane_store<double>::put(p, v); }
+    static __device__ __forceinline__ double mark_bound(float thr) { return (double)thr; }
 };
 template <>
 struct hs_io<__bf16> {
@@ -64,12 +70,19 @@ struct hs_io<__bf16> {
         return __uint_as_float((uint32_t)reinterpret_cast<const unsigned short *>(p)[i] << 16);   // exact
     }
     static __device__ __forceinline__ void put(__bf16 *p, float v) { plane_store<__bf16>::put(p, v); }
+    // Rounding to nearest bfloat16 moves a normal value by at most 2^-8 of
+    // itself, so a stored value above thr > 0 comes from v > thr (1 - 2^-8)
+    // (the product's own rounding is far inside that margin); tiny, zero,
+    // negative or NaN thresholds pass every value (flags may be a superset).
+    static __device__ __forceinline__ float mark_bound(float thr) {
+        return thr > 1e-30f ? thr * 0.99609375f : -INFINITY;
+    }
 };
 
-template <class PT>
+template <class PT, bool kMark>
 __global__ void __launch_bounds__(kHsThreads)
 k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, double z_step, int n_harm, int64_t nh,
-               PT *__restrict__ out) {
+               PT *__restrict__ out, PeakMarks m) {
     using A = typename hs_io<PT>::acc;
     __shared__ int rows[kMaxHarmonics];
     const int j = blockIdx.y;
@@ -93,30 +106,51 @@ k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, d
 #pragma unroll
     for (int i = 0; i < kHsPerThread; ++i)
         if (r0 + i < nh) hs_io<PT>::put(o + r0 + i, acc[i]);
+    if constexpr (kMark) {
+        // one compare of the largest kept sum (NaN sums are never above)
+        A mx = acc[0];
+#pragma unroll
+        for (int i = 1; i < kHsPerThread; ++i)
+            if (r0 + i < nh) mx = mx > acc[i] ? mx : acc[i];
+        if (mx > hs_io<PT>::mark_bound(m.thr))
+            mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)r0, (int)min(r0 + kHsPerThread - 1, nh - 1));
+    }
 }
 
-template <class PT>
-hipError_t run(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out, hipStream_t st) {
+template <class PT, bool kMark>
+hipError_t run(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out, const PeakMarks &m,
+               hipStream_t st) {
     const int64_t nh = (n - 1) / n_harm + 1;
     const int64_t per_block = (int64_t)kHsThreads * kHsPerThread;
     const int64_t bx = (nh + per_block - 1) / per_block;
     if (bx > 0x7fffffffLL || p.cfg.n_z > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_harmonic_sum<PT>, dim3((unsigned)bx, (unsigned)p.cfg.n_z), dim3(kHsThreads), 0, st,
+    hipLaunchKernelGGL((k_harmonic_sum<PT, kMark>), dim3((unsigned)bx, (unsigned)p.cfg.n_z), dim3(kHsThreads), 0, st,
                        static_cast<const PT *>(plane), n, p.cfg.n_z, p.cfg.z_min, p.cfg.z_step, n_harm, nh,
-                       static_cast<PT *>(out));
+                       static_cast<PT *>(out), m);
     return hipGetLastError();
+}
+
+template <bool kMark>
+hipError_t dispatch(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out, const PeakMarks &m,
+                    hipStream_t st) {
+    switch (p.cfg.plane_dtype) {
+        case FDAS_FP32: return run<float, kMark>(p, plane, n, n_harm, out, m, st);
+        case FDAS_BF16: return run<__bf16, kMark>(p, plane, n, n_harm, out, m, st);
+        case FDAS_FP64: return run<double, kMark>(p, plane, n, n_harm, out, m, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_harmonic_sum(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,
                                hipStream_t st) {
-    switch (p.cfg.plane_dtype) {
-        case FDAS_FP32: return run<float>(p, plane, n, n_harm, out, st);
-        case FDAS_BF16: return run<__bf16>(p, plane, n, n_harm, out, st);
-        case FDAS_FP64: return run<double>(p, plane, n, n_harm, out, st);
-        default: return hipErrorInvalidValue;
-    }
+    return dispatch<false>(p, plane, n, n_harm, out, PeakMarks{}, st);
+}
+
+hipError_t launch_harmonic_sum_marked(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,
+                                      const PeakMarks &marks, hipStream_t st) {
+    return dispatch<true>(p, plane, n, n_harm, out, marks, st);
 }
 
 }  // namespace fdas

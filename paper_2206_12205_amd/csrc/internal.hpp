@@ -137,5 +137,9 @@ hipError_t launch_band_max(const fdas_plan_s &p, const void *plane, int64_t n, c
 constexpr int kMaxHarmonics = 32;
 hipError_t launch_harmonic_sum(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,
                                hipStream_t st);
+// The same, also marking the peak tiles of the summed plane (marks from
+// peak_marks for its (n - 1) / n_harm + 1 bins).
+hipError_t launch_harmonic_sum_marked(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,
+                                      const PeakMarks &marks, hipStream_t st);
 
 }  // namespace fdas

@@ -92,6 +92,7 @@ def lib() -> ctypes.CDLL:
         L.fdas_batch_peaks_workspace.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         L.fdas_correlate_batch_peaks.argtypes = [P, P, P, ctypes.c_float, P, I64, P, P, ctypes.c_size_t, P]
         L.fdas_harmonic_sum.argtypes = [P, P, I64, I32, P, P]
+        L.fdas_harmonic_sum_peaks.argtypes = [P, P, I64, I32, P, ctypes.c_float, P, I64, P, P]
         L.fdas_band_max.argtypes = [P, P, I64, P, I32, P, P]
         L.fdas_prepare_workspace.argtypes = [I64, ctypes.POINTER(ctypes.c_size_t)]
         L.fdas_prepare.argtypes = [P, I64, P, P, ctypes.c_size_t, P]
@@ -140,13 +141,15 @@ def make_config(max_bins, z_min, z_step, n_z, n_taps, seg_len=0, compute="fp32",
 
 def peak_records(raw, found, capacity):
     """Peak records (a (capacity, 24) uint8 tensor of fdas_peak entries) ->
-    dict of numpy arrays z_idx, r, power, job and the true count n_found."""
+    dict of numpy arrays z_idx, r, power, job, the true count n_found and
+    truncated (more peaks than capacity: the list holds the first ones; the
+    C calls cannot tell without a device synchronisation, the wrapper can)."""
     import numpy as np
     k = min(int(found), int(capacity))
     rec = raw[:k].cpu().numpy().view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
                                               ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
     return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(), "power": rec["power"].copy(),
-            "job": rec["job"].copy(), "n_found": int(found)}
+            "job": rec["job"].copy(), "n_found": int(found), "truncated": int(found) > int(capacity)}
 
 
 class Plan:
@@ -379,6 +382,28 @@ class Plan:
         _check(lib().fdas_harmonic_sum(self._h, ctypes.c_void_p(plane.data_ptr()), n, int(n_harm),
                                        ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "fdas_harmonic_sum")
         return out
+
+    def harmonic_sum_peaks(self, plane, n_harm, threshold, capacity=1 << 16, out=None, stream=None):
+        """Harmonic sum and the thresholded peaks of the summed plane in one
+        call (fdas_harmonic_sum_peaks) -> (summed plane, peaks dict as from peaks())."""
+        import torch
+        if plane.dim() != 2 or plane.shape[0] != self.n_z or plane.dtype != self.torch_plane_dtype() \
+                or not plane.is_contiguous():
+            raise ValueError("plane must be a contiguous (n_z, n) tensor of the plan's plane dtype")
+        n = plane.shape[1]
+        nh = (n - 1) // int(n_harm) + 1 if n > 0 else 0
+        if out is None:
+            out = torch.empty((self.n_z, nh), dtype=plane.dtype, device=self.device)
+        if out.dtype != plane.dtype or tuple(out.shape) != (self.n_z, nh) or not out.is_contiguous():
+            raise ValueError("out has the wrong dtype, shape or layout")
+        pk = torch.empty((max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
+        nf = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().fdas_harmonic_sum_peaks(self._h, ctypes.c_void_p(plane.data_ptr()), n, int(n_harm),
+                                             ctypes.c_void_p(out.data_ptr()), float(threshold),
+                                             ctypes.c_void_p(pk.data_ptr()), int(capacity),
+                                             ctypes.c_void_p(nf.data_ptr()), _stream_ptr(stream)),
+               "fdas_harmonic_sum_peaks")
+        return out, peak_records(pk, int(nf.item()), capacity)
 
     def bank(self):
         """Template bank as a complex tensor view (FP32/FP64), raw bfloat16

@@ -120,6 +120,16 @@ def test_layout_and_workspace_checks_on_host():
         assert L.fdas_harmonic_sum(h, fake, 100, 4, None, None) == F.E_INVALID
         assert L.fdas_harmonic_sum(h, ctypes.c_void_p(0x10001), 100, 4, fake, None) == F.E_INVALID
         assert L.fdas_harmonic_sum(None, fake, 100, 4, fake, None) == F.E_INVALID
+        # harmonic sum with peaks: argument checks only
+        assert L.fdas_harmonic_sum_peaks(h, fake, 100, 0, fake, 1.0, fake, 5, nf, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum_peaks(h, fake, 100, 33, fake, 1.0, fake, 5, nf, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum_peaks(h, fake, 4097, 4, fake, 1.0, fake, 5, nf, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum_peaks(h, fake, 100, 4, fake, 1.0, None, 5, nf, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum_peaks(h, fake, 100, 4, fake, 1.0, fake, -1, nf, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum_peaks(h, fake, 100, 4, fake, 1.0, ctypes.c_void_p(0x10008), 5, nf, None) \
+            == F.E_INVALID
+        assert L.fdas_harmonic_sum_peaks(h, fake, 100, 4, None, 1.0, fake, 5, nf, None) == F.E_INVALID
+        assert L.fdas_harmonic_sum_peaks(None, fake, 100, 4, fake, 1.0, fake, 5, nf, None) == F.E_INVALID
         # fused plane + peaks: argument and state checks only (no launch)
         assert L.fdas_correlate_peaks(h, fake, 100, fake, 1.0, fake, 5, nf, None) == F.E_STATE   # no templates
         assert L.fdas_correlate_peaks(h, fake, 100, fake, 1.0, None, 5, nf, None) == F.E_INVALID

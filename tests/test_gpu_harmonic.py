@@ -112,6 +112,35 @@ def test_peaks_of_the_summed_plane(dev):
         assert np.array_equal(got["z_idx"], j) and np.array_equal(got["r"], r)
 
 
+@pytest.mark.parametrize("pd", ["fp32", "bf16", "fp64"])
+@pytest.mark.parametrize("n_harm", [1, 2, 8, 32])
+def test_harmonic_sum_peaks_fused(dev, pd, n_harm):
+    """fdas_harmonic_sum_peaks: the summed plane bitwise equal to
+    fdas_harmonic_sum's, and exactly the oracle's peak list of that summed
+    plane (thresholds above the noise, low, negative — every sum above — and
+    NaN; a small capacity keeps the first entries and the true count)."""
+    import torch
+    say(f"[harmonic] fused sum+peaks {pd} H={n_harm}")
+    sp = synth.config1(0)
+    compute = "fp64" if pd == "fp64" else "fp32"
+    pl = plan(dev, max_bins=sp.spec.size, z_min=C1["z_min"], z_step=C1["z_step"], n_z=C1["n_z"],
+              n_taps=C1["n_taps"], seg_len=C1["seg_len"], compute=compute, plane_dtype=pd)
+    P = pl.correlate(torch.from_numpy(sp.spec).to(dev))
+    S = pl.harmonic_sum(P, n_harm)
+    Sh = host(S)
+    ints = {2: torch.int16, 4: torch.int32, 8: torch.int64}[S.element_size()]
+    for thr, cap in ((2.0 * n_harm + 6.0, 4096), (3.0, 17), (-1.0, 1 << 20), (float("nan"), 8)):
+        out = torch.full_like(S, float("nan"))
+        S2, got = pl.harmonic_sum_peaks(P, n_harm, thr, capacity=cap, out=out)
+        assert torch.equal(S2.view(ints), S.view(ints)), f"thr={thr}: summed plane differs"
+        j, r, pw = OK_PEAKS.peaks(Sh, thr)
+        k = min(len(j), cap)
+        assert got["n_found"] == len(j), f"thr={thr}: {got['n_found']} vs {len(j)}"
+        assert got["truncated"] == (len(j) > cap)
+        assert np.array_equal(got["z_idx"], j[:k]) and np.array_equal(got["r"], r[:k]), f"thr={thr}"
+        assert np.array_equal(got["power"].astype(np.float64), pw[:k].astype(np.float32).astype(np.float64))
+
+
 def test_harmonic_series_of_chirps_on_the_gpu(dev):
     """The sum at the fundamental's cell of a noise-free harmonic series of
     chirps is the sum of their matched powers (the oracle pin's physics),
@@ -152,3 +181,11 @@ def test_single_dm_bf16_plane_sampled_rows(dev):
     want = HS.harmonic_sum(Pf, c["z_min"], c["z_step"], 8, out_rows=rows)
     got = host(S[rows])
     check(got, want, "bf16", 8, "single-DM rows")
+    # the fused call at full size: the same summed plane and the list
+    # fdas_peaks gives for it
+    for thr in (c["threshold"], 20.0):
+        a = pl.peaks(S, thr, capacity=1 << 20)
+        S2, b = pl.harmonic_sum_peaks(P, 8, thr, capacity=1 << 20)
+        assert torch.equal(S2.view(torch.int16), S.view(torch.int16))
+        assert a["n_found"] == b["n_found"]
+        assert np.array_equal(a["r"], b["r"]) and np.array_equal(a["z_idx"], b["z_idx"])
