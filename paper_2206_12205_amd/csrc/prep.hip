@@ -9,12 +9,15 @@
 //
 // Transform.  The N_t real samples read as N = N_t / 2 complex values
 // z[m] = x[2m] + i x[2m+1] (the series reinterpreted, no copy); a complex FFT
-// of length N in Stockham autosort passes over global memory (radix 4, one
-// radix-2 pass when log2 N is odd; thread j of a pass with sub-transform
-// length Ns reads R values j + r N / R, twiddles them by
+// of length N in Stockham autosort passes over global memory (radix 16 while
+// it fits, then radix 4, then one radix-2 pass if needed; thread j of a pass
+// with sub-transform length Ns reads R values j + r N / R, twiddles them by
 // exp(-2 pi i (j mod Ns) r / (Ns R)), takes an R-point DFT and writes them to
 // (j div Ns) Ns R + (j mod Ns) + r Ns, so the output is in natural order
-// after the last pass); twiddles from double-precision sincospi.  The real
+// after the last pass).  The 16-point DFT runs in registers as 4 x 4 with
+// the internal factors exp(-2 pi i m / 16) as constants; the pass twiddles
+// come from one double-precision sincospi per thread and its powers formed
+// in double precision.  The real
 // spectrum follows from E[k] = (Z[k] + conj Z[N-k]) / 2 (even samples),
 // O[k] = -i (Z[k] - conj Z[N-k]) / 2 (odd samples), X[k] = E[k] + e(-k / 2N) O[k].
 //
@@ -36,6 +39,78 @@ constexpr int kPrepThreads = 256;
 
 __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// 4-point DFT in place: A_k = sum_n a_n exp(-2 pi i n k / 4)
+__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
+    const float2 s02 = make_float2(a0.x + a2.x, a0.y + a2.y), d02 = make_float2(a0.x - a2.x, a0.y - a2.y);
+    const float2 s13 = make_float2(a1.x + a3.x, a1.y + a3.y), d13 = make_float2(a1.x - a3.x, a1.y - a3.y);
+    a0 = make_float2(s02.x + s13.x, s02.y + s13.y);
+    a2 = make_float2(s02.x - s13.x, s02.y - s13.y);
+    // -i d13 = (d13.y, -d13.x)
+    a1 = make_float2(d02.x + d13.y, d02.y - d13.x);
+    a3 = make_float2(d02.x - d13.y, d02.y + d13.x);
+}
+
+// 16-point DFT in registers, natural order in and out: n = 4 n1 + n2,
+// k = k1 + 4 k2; inner 4-point DFTs over n1, factors exp(-2 pi i n2 k1 / 16),
+// outer 4-point DFTs over n2.
+__device__ __forceinline__ void dft16(float2 (&v)[16]) {
+    constexpr float c1 = 0.92387953251128674f;   // cos(pi / 8)
+    constexpr float s1 = 0.38268343236508978f;   // sin(pi / 8)
+    constexpr float h = 0.70710678118654752f;    // cos(pi / 4)
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);   // v[4 k1 + n2]
+    // exp(-2 pi i m / 16) for m = n2 k1 in {1, 2, 3, 4, 6, 9}
+    const float2 w1 = make_float2(c1, -s1), w2 = make_float2(h, -h), w3 = make_float2(s1, -c1);
+    const float2 w4 = make_float2(0.0f, -1.0f), w6 = make_float2(-h, -h), w9 = make_float2(-c1, s1);
+    v[5] = cmulf(v[5], w1);   // k1 = 1, n2 = 1
+    v[6] = cmulf(v[6], w2);   // k1 = 1, n2 = 2
+    v[7] = cmulf(v[7], w3);   // k1 = 1, n2 = 3
+    v[9] = cmulf(v[9], w2);   // k1 = 2, n2 = 1
+    v[10] = cmulf(v[10], w4);
+    v[11] = cmulf(v[11], w6);
+    v[13] = cmulf(v[13], w3);   // k1 = 3, n2 = 1
+    v[14] = cmulf(v[14], w6);
+    v[15] = cmulf(v[15], w9);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);   // v[4 k1 + k2]
+    // natural order: X[k1 + 4 k2] = v[4 k1 + k2] (a 4 x 4 transpose)
+    float2 t[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = t[i];
+}
+
+__global__ void __launch_bounds__(kPrepThreads) k_stockham16(const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                              int64_t N, int64_t Ns) {
+    const int64_t j = blockIdx.x * (int64_t)kPrepThreads + threadIdx.x;
+    const int64_t Q = N / 16;
+    if (j >= Q) return;
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = in[j + r * Q];
+    const int64_t jm = j & (Ns - 1);
+    if (Ns > 1) {
+        // w = exp(-2 pi i jm / (16 Ns)); v[r] *= w^r, powers in double precision
+        double s, c;
+        sincospi(-2.0 * (double)jm / (double)(Ns * 16), &s, &c);
+        double pr = c, pi = s;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) {
+            v[r] = cmulf(v[r], make_float2((float)pr, (float)pi));
+            const double nr = pr * c - pi * s, ni = pr * s + pi * c;
+            pr = nr;
+            pi = ni;
+        }
+    }
+    dft16(v);
+    const int64_t base = (j / Ns) * Ns * 16 + jm;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[base + r * Ns] = v[r];
 }
 
 template <int R>
@@ -187,10 +262,16 @@ hipError_t launch_prepare(const float *series, int64_t n_t, void *out, void *ws,
     auto *hist = reinterpret_cast<uint32_t *>(bufB + N);
     auto *state = reinterpret_cast<SelState *>(hist + 2048);
     auto *X = static_cast<float2 *>(out);
-    // complex FFT of length N: radix-4 passes, then radix 2 if log2 N is odd
+    // complex FFT of length N: radix-16 passes, then radix 4, then radix 2
     const float2 *src = reinterpret_cast<const float2 *>(series);
     float2 *dst = bufA;
     int64_t Ns = 1;
+    while (Ns * 16 <= N) {
+        hipLaunchKernelGGL(k_stockham16, dim3(blocks_for(N / 16)), dim3(kPrepThreads), 0, st, src, dst, N, Ns);
+        Ns *= 16;
+        src = dst;
+        dst = (dst == bufA) ? bufB : bufA;
+    }
     while (Ns * 4 <= N) {
         hipLaunchKernelGGL(k_stockham<4>, dim3(blocks_for(N / 4)), dim3(kPrepThreads), 0, st, src, dst, N, Ns);
         Ns *= 4;
