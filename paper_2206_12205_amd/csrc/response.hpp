@@ -162,10 +162,12 @@ __device__ constexpr double kGLw[16] = {
 // over the observation (w the change of the drift; w = 0 is A(q, z)).  No
 // closed form: composite 16-point Gauss-Legendre quadrature with panels of
 // at most half a turn of phase (|phase'| <= pi (2|q| + 2|z| + |w|) on [0, 1]).
-__device__ inline cd response_jerk(double q, double z, double w) {
+// Panels first, first + stride, ... of that quadrature (a part of the sum,
+// so that a wave can split the panels over its lanes).
+__device__ inline cd response_jerk_panels(double q, double z, double w, int first, int stride) {
     const int npan = (int)ceil(2.0 * fabs(q) + 2.0 * fabs(z) + fabs(w)) + 2;
     cd s = {0.0, 0.0};
-    for (int pn = 0; pn < npan; ++pn) {
+    for (int pn = first; pn < npan; pn += stride) {
         for (int i = 0; i < 16; ++i) {
             const double u = (pn + kGLx[i]) / npan;
             const double wt = kGLw[i] / npan;
@@ -174,6 +176,8 @@ __device__ inline cd response_jerk(double q, double z, double w) {
     }
     return s;
 }
+
+__device__ inline cd response_jerk(double q, double z, double w) { return response_jerk_panels(q, z, w, 0, 1); }
 
 // A(q, z) for any real q, z.
 __device__ inline cd response(double q, double z) {

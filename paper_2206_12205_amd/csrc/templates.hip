@@ -34,13 +34,22 @@ __global__ void k_taps(cd *taps, int32_t n_z, int32_t M, double z_min, double z_
 
 // Taps of a jerk search plane: g_j[m] = conj(A(m - z_j/2 - w/6, z_j, w)),
 // m - z_j/2 - w/6 being the offset from the mean frequency r0 + z/2 + w/6.
-__global__ void k_taps_jerk(cd *taps, int32_t n_z, int32_t M, double z_min, double z_step, double w) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n_z * M) return;
+__global__ void __launch_bounds__(256) k_taps_jerk(cd *taps, int32_t n_z, int32_t M, double z_min, double z_step,
+                                                   double w) {
+    // one wave per tap: lanes take the quadrature panels in turn, then a
+    // butterfly sum over the wave (a fixed order, so the bank is reproducible)
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= (int64_t)n_z * M) return;   // uniform over the wave
     const int j = (int)(i / M);
     const int m = (int)(i % M) - M / 2;
     const double z = z_min + z_step * j;
-    taps[i] = conj(response_jerk((double)m - 0.5 * z - w / 6.0, z, w));
+    cd s = response_jerk_panels((double)m - 0.5 * z - w / 6.0, z, w, lane, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+        s.re += __shfl_xor(s.re, off);
+        s.im += __shfl_xor(s.im, off);
+    }
+    if (lane == 0) taps[i] = conj(s);
 }
 
 // One workgroup per template: l2 norm by a fixed-order tree reduction.
@@ -223,8 +232,8 @@ hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st, double w)
         hipLaunchKernelGGL(k_taps, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, taps, p.cfg.n_z, p.M,
                            p.cfg.z_min, p.cfg.z_step);
     else
-        hipLaunchKernelGGL(k_taps_jerk, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, taps, p.cfg.n_z, p.M,
-                           p.cfg.z_min, p.cfg.z_step, w);
+        hipLaunchKernelGGL(k_taps_jerk, dim3((unsigned)((nt + 3) / 4)), dim3(256), 0, st, taps, p.cfg.n_z, p.M,
+                           p.cfg.z_min, p.cfg.z_step, w);   // four taps (waves) per workgroup
     hipLaunchKernelGGL(k_normalise, dim3(p.cfg.n_z), dim3(256), 0, st, taps, p.M);
     const dim3 grid((unsigned)((p.L + 255) / 256), (unsigned)p.cfg.n_z);
     const size_t lds = (size_t)p.M * sizeof(cd);
