@@ -8,15 +8,19 @@
 // the largest value, NaN cells skipped, ties to the first cell in (z_idx, r)
 // order.
 //
-// Two passes over each window, both on a grid of (workgroups, windows): each
-// workgroup takes (row, 4096-column chunk) items of its window in turn.
-//   max   the largest value as an order-preserving unsigned key (a NaN-free
-//         total order of the plane type), one atomicMax per workgroup;
+// A grid of (workgroups, windows): each workgroup takes (row, 4096-column
+// chunk) items of its window in turn.  The value is ranked by an
+// order-preserving unsigned key (a NaN-free total order of the plane type).
+// FP32 and BF16 planes of fewer than 2^32 cells take one pass: the 32-bit
+// value key above the complement of the cell's row-major position in its
+// window, so one 64-bit maximum (one atomicMax per workgroup) finds the
+// largest value and its first cell together.  FP64 planes take two passes:
+//   max   the largest value key, one atomicMax per workgroup;
 //   first the smallest row-major position holding that value, one atomicMin
 //         per workgroup.
-// Both results are order-independent, so the output is deterministic.  The
-// two 64-bit accumulators of window b live in out[b] itself (the r field
-// and the z_idx/job pair) until a final kernel writes the peak record.
+// All results are order-independent, so the output is deterministic.  The
+// 64-bit accumulators of window b live in out[b] itself (the r field and
+// the z_idx/job pair) until a final kernel writes the peak record.
 #include "internal.hpp"
 
 namespace fdas {
@@ -137,6 +141,62 @@ k_band_pass(const PT *plane, int64_t n, int n_z, const int64_t *windows, fdas_pe
     }
 }
 
+// One pass for 32-bit value keys: (key << 32) | (2^32 - 1 - window position).
+template <class PT>
+__global__ void __launch_bounds__(kBandThreads)
+k_band_pass1(const PT *plane, int64_t n, int n_z, const int64_t *windows, fdas_peak *out) {
+    using V = typename band_io<PT>::V;
+    static_assert(sizeof(V) == 4, "32-bit value keys");
+    __shared__ uint64_t red[kBandThreads];
+    const int b = blockIdx.y;
+    const Win w = band_window(windows, b, n_z, n);
+    uint64_t *acc = reinterpret_cast<uint64_t *>(&out[b]);
+    const int64_t width = w.r_hi - w.r_lo;
+    uint64_t best = 0;
+    for (int64_t it = blockIdx.x; it < w.n_items; it += gridDim.x) {
+        const int64_t zr = it / w.chunks;   // row inside the window
+        const int64_t c0 = w.r_lo + (it % w.chunks) * kBandChunk;
+        const int64_t c1 = min(c0 + kBandChunk, w.r_hi);
+        const PT *row = plane + (w.z_lo + zr) * n;
+        const uint64_t pos0 = (uint64_t)(zr * width - w.r_lo);
+        for (int64_t c = c0 + threadIdx.x; c < c1; c += kBandThreads) {
+            const V v = band_io<PT>::get(row, c);
+            if (v != v) continue;                                  // NaN
+            const uint64_t k = (band_key(v) << 32) | (0xffffffffull - (pos0 + (uint64_t)c));
+            best = max(best, k);
+        }
+    }
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = kBandThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] != 0) atomicMax(reinterpret_cast<unsigned long long *>(&acc[0]), red[0]);
+}
+
+__global__ void k_band_finish1(fdas_peak *out, int n_windows, const int64_t *windows, int n_z, int64_t n) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_windows) return;
+    const uint64_t k = reinterpret_cast<const uint64_t *>(&out[b])[0];
+    const Win w = band_window(windows, b, n_z, n);
+    fdas_peak pk;
+    pk.job = 0;
+    pk.reserved = 0.0f;
+    if (k == 0) {
+        pk.r = -1;
+        pk.z_idx = -1;
+        pk.power = __int_as_float(0x7fc00000);   // NaN
+    } else {
+        const int64_t width = w.r_hi - w.r_lo;
+        const int64_t pos = (int64_t)(0xffffffffull - (k & 0xffffffffull));
+        pk.r = w.r_lo + pos % width;
+        pk.z_idx = (int32_t)(w.z_lo + pos / width);
+        pk.power = (float)band_value(k >> 32, false);
+    }
+    out[b] = pk;
+}
+
 __global__ void k_band_finish(fdas_peak *out, int n_windows, int64_t n, bool dbl) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_windows) return;
@@ -163,6 +223,14 @@ hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, const int64_t *
     const unsigned gb = (unsigned)((n_windows + 255) / 256);
     const dim3 grid(kBandGrid, (unsigned)n_windows);
     hipLaunchKernelGGL(k_band_clear, dim3(gb), dim3(256), 0, st, out, n_windows);
+    if constexpr (sizeof(typename band_io<PT>::V) == 4) {
+        if ((int64_t)p.cfg.n_z * n < ((int64_t)1 << 32)) {   // every clipped window position fits 32 bits
+            hipLaunchKernelGGL((k_band_pass1<PT>), grid, dim3(kBandThreads), 0, st, plane, n, p.cfg.n_z, windows,
+                               out);
+            hipLaunchKernelGGL(k_band_finish1, dim3(gb), dim3(256), 0, st, out, n_windows, windows, p.cfg.n_z, n);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_band_pass<PT, false>), grid, dim3(kBandThreads), 0, st, plane, n, p.cfg.n_z, windows, out);
     hipLaunchKernelGGL((k_band_pass<PT, true>), grid, dim3(kBandThreads), 0, st, plane, n, p.cfg.n_z, windows, out);
     hipLaunchKernelGGL(k_band_finish, dim3(gb), dim3(256), 0, st, out, n_windows, n, sizeof(PT) == 8);
