@@ -88,24 +88,46 @@ __device__ __forceinline__ int64_t bank_pos(int j, int k, int L, int order) {
     return (int64_t)j * L + (((wave * 4 + q) * 64 + lane) * 4 + p);
 }
 
+// Roots exp(-2 pi i e / L) from two LDS tables, e = 64 a + b: the high
+// table exp(-2 pi i 64 a / L) (L / 64 entries) times the low one
+// exp(-2 pi i b / L) (64 entries), each entry one FP64 sincospi, so a term
+// costs one complex FP64 product instead of a sincospi.  L is a power of two
+// (>= 1024), so e = m k mod L is a mask and steps by k from one tap to the
+// next.
+constexpr int kRootLo = 64;
+
+static size_t spectrum_lds_bytes(int32_t M, int32_t L) { return (size_t)(M + kRootLo + L / kRootLo) * sizeof(cd); }
+
 template <class B>
 __global__ void __launch_bounds__(256) k_spectrum(const cd *taps, B *bank, int32_t M, int32_t L, int order) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cd *g = reinterpret_cast<cd *>(smem_raw);
+    cd *wlo = g + M;
+    cd *whi = wlo + kRootLo;
     const int j = blockIdx.y;
     for (int i = threadIdx.x; i < M; i += 256) g[i] = taps[(int64_t)j * M + i];
+    for (int i = threadIdx.x; i < kRootLo; i += 256) {
+        double sn, cs;
+        sincospi(-2.0 * (double)i / (double)L, &sn, &cs);
+        wlo[i] = cd{cs, sn};
+    }
+    for (int i = threadIdx.x; i < L / kRootLo; i += 256) {
+        double sn, cs;
+        sincospi(-2.0 * (double)(kRootLo * i) / (double)L, &sn, &cs);
+        whi[i] = cd{cs, sn};
+    }
     __syncthreads();
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= L) return;
+    const uint32_t mask = (uint32_t)L - 1u;
+    uint32_t e = (uint32_t)(((int64_t)(-(M / 2)) * (int64_t)k) & (int64_t)mask);   // m = -M/2
     double re = 0.0, im = 0.0;
     for (int i = 0; i < M; ++i) {
-        const int64_t m = i - M / 2;
-        int64_t e = (m * (int64_t)k) % L;       // exp(-2 pi i e / L), exact integer reduction
-        if (e < 0) e += L;
-        double sn, cs;
-        sincospi(-2.0 * (double)e / (double)L, &sn, &cs);
+        const cd a = whi[e / kRootLo], b = wlo[e % kRootLo];
+        const double cs = a.re * b.re - a.im * b.im, sn = a.re * b.im + a.im * b.re;
         re += g[i].re * cs - g[i].im * sn;
         im += g[i].re * sn + g[i].im * cs;
+        e = (e + (uint32_t)k) & mask;
     }
     const double invL = 1.0 / (double)L;
     bank[bank_pos(j, k, L, order)] = bank_cast<B>(cd{re * invL, im * invL});
@@ -236,7 +258,7 @@ hipError_t launch_make_templates(const fdas_plan_s &p, hipStream_t st, double w)
                            p.cfg.z_min, p.cfg.z_step, w);   // four taps (waves) per workgroup
     hipLaunchKernelGGL(k_normalise, dim3(p.cfg.n_z), dim3(256), 0, st, taps, p.M);
     const dim3 grid((unsigned)((p.L + 255) / 256), (unsigned)p.cfg.n_z);
-    const size_t lds = (size_t)p.M * sizeof(cd);
+    const size_t lds = spectrum_lds_bytes(p.M, p.L);
     void *bank = ws + p.off_bank;
     hipError_t e = hipSuccess;
     switch (p.cfg.compute) {
