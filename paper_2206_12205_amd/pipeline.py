@@ -176,3 +176,25 @@ class BatchSearch:
                                  ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
         return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(), "power": rec["power"].copy(),
                 "n_found": found}
+
+
+def search_series(plan, series, threshold, harmonics=(1, 2, 4, 8, 16), capacity=1 << 16, stream=None):
+    """One dedispersed time series through the whole search on the GPU.
+
+    series     contiguous float32 device tensor, a power-of-two length n_t
+    plan       a fdas.Plan whose max_bins covers n_t / 2
+    threshold  a float, or a dict H -> float (noise powers of a sum of H
+               normalised powers have mean H)
+    Steps (each one library call): the normalised spectrum (fdas_prepare),
+    the plane with its thresholded peaks (fdas_correlate_peaks) and, for each
+    H > 1, the harmonic sum with its thresholded peaks
+    (fdas_harmonic_sum_peaks).  Returns (spectrum, plane, {H: peaks dict}).
+    """
+    spec = F.prepare(series, stream=stream)
+    thr = (lambda h: float(threshold[h])) if isinstance(threshold, dict) else (lambda h: float(threshold))
+    plane, pk1 = plan.correlate_peaks(spec, thr(1), capacity=capacity, stream=stream)
+    found = {1: pk1} if 1 in harmonics else {}
+    for h in harmonics:
+        if h > 1:
+            _, found[h] = plan.harmonic_sum_peaks(plane, h, thr(h), capacity=capacity, stream=stream)
+    return spec, plane, found
