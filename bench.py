@@ -392,8 +392,69 @@ def prep_timing(args, cfg, dev):
     note(f"spectrum preparation (2^{n_t.bit_length() - 1} samples): {ms:.3f} ms")
     return {"workload": f"{n_t} FP32 samples -> {n_t // 2} normalised bins", "ms": ms,
             "algorithmic_GBs": alg / (ms * 1e-3) / 1e9,
-            "fft_passes": ((n_t // 2).bit_length() - 1) // 2 + ((n_t // 2).bit_length() - 1) % 2,
+            "fft_passes": ((n_t // 2).bit_length() - 1) // 4 + int(((n_t // 2).bit_length() - 1) % 4 >= 2)
+                          + ((n_t // 2).bit_length() - 1) % 2,
             "note": "the workspace comes from torch's caching allocator per call (inside the timed loop)"}
+
+
+def series_search_timing(args, cfg, dev, pl):
+    """The whole search of one single-DM time series (2^23 FP32 samples of
+    the workload's first trial) as one timed unit: fdas_prepare, then
+    fdas_correlate_peaks, then fdas_harmonic_sum_peaks for H = 2, 4, 8, 16
+    (threshold: the workload's for the plane, +10 per doubling of H); every
+    buffer allocated beforehand, HIP events around the six calls."""
+    import ctypes
+    import numpy as np
+    import torch
+    import synth
+    from paper_2206_12205_amd import fdas as F
+    L = F.lib()
+    x, _ = synth.config2_series(0)
+    xs = torch.from_numpy(x.astype(np.float32)).to(dev)
+    n_t = xs.numel()
+    n = n_t // 2
+    nb = ctypes.c_size_t(0)
+    F._check(L.fdas_prepare_workspace(n_t, ctypes.byref(nb)), "fdas_prepare_workspace")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    spec = torch.empty(n, dtype=torch.complex64, device=dev)
+    plane = pl.empty_plane(n)
+    hs = (2, 4, 8, 16)
+    sums = {h: torch.empty((pl.n_z, (n - 1) // h + 1), dtype=plane.dtype, device=dev) for h in hs}
+    cap = 1 << 16
+    pk = torch.empty((len(hs) + 1, cap, 24), dtype=torch.uint8, device=dev)
+    nf = torch.zeros(len(hs) + 1, dtype=torch.int64, device=dev)
+    thr = {1: cfg["threshold"], 2: cfg["threshold"] + 10, 4: cfg["threshold"] + 20, 8: cfg["threshold"] + 30,
+           16: cfg["threshold"] + 40}
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+    V = ctypes.c_void_p
+
+    def one():
+        F._check(L.fdas_prepare(V(xs.data_ptr()), n_t, V(spec.data_ptr()), V(ws.data_ptr()), nb.value, sp),
+                 "fdas_prepare")
+        F._check(L.fdas_correlate_peaks(pl._h, V(spec.data_ptr()), n, V(plane.data_ptr()), float(thr[1]),
+                                        V(pk[0].data_ptr()), cap, V(nf[0:1].data_ptr()), sp), "fdas_correlate_peaks")
+        for i, h in enumerate(hs, 1):
+            F._check(L.fdas_harmonic_sum_peaks(pl._h, V(plane.data_ptr()), n, h, V(sums[h].data_ptr()),
+                                               float(thr[h]), V(pk[i].data_ptr()), cap, V(nf[i:i + 1].data_ptr()),
+                                               sp), "fdas_harmonic_sum_peaks")
+    for _ in range(5):
+        one()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(10, min(args.steps, 50))
+    e0.record(st)
+    for _ in range(reps):
+        one()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    found = nf.cpu().tolist()
+    note(f"whole series search (prepare, plane + peaks, H = 2..16 sums + peaks): {ms:.3f} ms")
+    return {"workload": f"{n_t} FP32 samples -> normalised spectrum -> {pl.n_z} x {n} BF16 plane with peaks -> "
+                        f"harmonic sums H = 2, 4, 8, 16 with peaks", "ms": ms,
+            "thresholds": {str(k): v for k, v in thr.items()},
+            "n_found": {"H1": found[0], **{f"H{h}": found[i] for i, h in enumerate(hs, 1)}}}
 
 
 def jerk_volume(args, cfg, dev, x, plane):
@@ -757,6 +818,7 @@ def main():
         del pl_d
 
     out["plane_and_peaks"] = {"workload": "the single-DM BF16 plane and its thresholded peaks", **fused_pk}
+    out["series_search"] = series_search_timing(args, cfg, dev, pl_b)
 
     if not args.no_harmonic:
         out["harmonic_sum"] = {"workload": "the single-DM BF16 plane, BF16 sums out", **harm}
