@@ -12,8 +12,8 @@
 // order written (no fused multiply-add), so the rows are exactly those of
 // that definition.
 //
-// One workgroup per (template row, block of 1024 fundamentals), 4 consecutive
-// fundamentals per thread; the workgroup's harmonic rows are computed once
+// One workgroup per (template row, block of 1024 fundamentals), 4 per thread
+// 256 apart; the workgroup's harmonic rows are computed once
 // into LDS.  Harmonic h of consecutive fundamentals is h bins apart, so the
 // reads of harmonic h touch every cache line of an h-times wider span: the
 // kernel reads about (H + 1) / 2 planes' worth of cache lines, held in part
@@ -88,7 +88,11 @@ k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, d
     const int j = blockIdx.y;
     if ((int)threadIdx.x < n_harm) rows[threadIdx.x] = harmonic_row(z_min, z_step, n_z, j, threadIdx.x + 1);
     __syncthreads();
-    const int64_t r0 = ((int64_t)blockIdx.x * kHsThreads + threadIdx.x) * kHsPerThread;
+    // the workgroup's fundamentals [rb, rb + 1024): thread t takes
+    // rb + t + 256 i, so each load instruction of a wave reads one compact run
+    // of cache lines and every line is requested once
+    const int64_t rb = (int64_t)blockIdx.x * (kHsThreads * kHsPerThread);
+    const int64_t r0 = rb + threadIdx.x;
     if (r0 >= nh) return;
     A acc[kHsPerThread];
 #pragma unroll
@@ -99,21 +103,26 @@ k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, d
         if (jh < 0) continue;
         const PT *row = plane + (int64_t)jh * n;
 #pragma unroll
-        for (int i = 0; i < kHsPerThread; ++i)
-            if (r0 + i < nh) acc[i] += hs_io<PT>::get(row, (int64_t)h * (r0 + i));
+        for (int i = 0; i < kHsPerThread; ++i) {
+            const int64_t r = r0 + i * kHsThreads;
+            if (r < nh) acc[i] += hs_io<PT>::get(row, (int64_t)h * r);
+        }
     }
     PT *o = out + (int64_t)j * nh;
 #pragma unroll
-    for (int i = 0; i < kHsPerThread; ++i)
-        if (r0 + i < nh) hs_io<PT>::put(o + r0 + i, acc[i]);
+    for (int i = 0; i < kHsPerThread; ++i) {
+        const int64_t r = r0 + i * kHsThreads;
+        if (r < nh) hs_io<PT>::put(o + r, acc[i]);
+    }
     if constexpr (kMark) {
-        // one compare of the largest kept sum (NaN sums are never above)
+        // one compare of the largest kept sum (NaN sums are never above); the
+        // workgroup's 1024 fundamentals are exactly one peak tile
+        static_assert(kHsThreads * kHsPerThread == kPeakTileCols, "one tile per workgroup");
         A mx = acc[0];
 #pragma unroll
         for (int i = 1; i < kHsPerThread; ++i)
-            if (r0 + i < nh) mx = mx > acc[i] ? mx : acc[i];
-        if (mx > hs_io<PT>::mark_bound(m.thr))
-            mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)r0, (int)min(r0 + kHsPerThread - 1, nh - 1));
+            if (r0 + i * kHsThreads < nh) mx = mx > acc[i] ? mx : acc[i];
+        if (mx > hs_io<PT>::mark_bound(m.thr)) mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)rb, (int)rb);
     }
 }
 
