@@ -12,7 +12,7 @@
 // order written (no fused multiply-add), so the rows are exactly those of
 // that definition.
 //
-// One workgroup per (template row, block of 1024 fundamentals), 4 per thread
+// One workgroup per (template row, block of 2048 fundamentals), 8 per thread
 // 256 apart; the workgroup's harmonic rows are computed once
 // into LDS.  Harmonic h of consecutive fundamentals is h bins apart, so the
 // reads of harmonic h touch every cache line of an h-times wider span: the
@@ -31,7 +31,7 @@ namespace fdas {
 namespace {
 
 constexpr int kHsThreads = 256;
-constexpr int kHsPerThread = 4;
+constexpr int kHsPerThread = 8;
 
 __device__ int harmonic_row(double z_min, double z_step, int n_z, int j, int h) {
 #pragma clang fp contract(off)
@@ -88,7 +88,7 @@ k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, d
     const int j = blockIdx.y;
     if ((int)threadIdx.x < n_harm) rows[threadIdx.x] = harmonic_row(z_min, z_step, n_z, j, threadIdx.x + 1);
     __syncthreads();
-    // the workgroup's fundamentals [rb, rb + 1024): thread t takes
+    // the workgroup's fundamentals [rb, rb + 2048): thread t takes
     // rb + t + 256 i, so each load instruction of a wave reads one compact run
     // of cache lines and every line is requested once
     const int64_t rb = (int64_t)blockIdx.x * (kHsThreads * kHsPerThread);
@@ -115,14 +115,20 @@ k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, d
         if (r < nh) hs_io<PT>::put(o + r, acc[i]);
     }
     if constexpr (kMark) {
-        // one compare of the largest kept sum (NaN sums are never above); the
-        // workgroup's 1024 fundamentals are exactly one peak tile
-        static_assert(kHsThreads * kHsPerThread == kPeakTileCols, "one tile per workgroup");
-        A mx = acc[0];
+        // per peak tile (1024 fundamentals) one compare of the largest kept
+        // sum (NaN sums are never above)
+        constexpr int kPerTile = kPeakTileCols / kHsThreads;
+        static_assert(kHsPerThread % kPerTile == 0, "whole tiles per workgroup");
 #pragma unroll
-        for (int i = 1; i < kHsPerThread; ++i)
-            if (r0 + i * kHsThreads < nh) mx = mx > acc[i] ? mx : acc[i];
-        if (mx > hs_io<PT>::mark_bound(m.thr)) mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)rb, (int)rb);
+        for (int t = 0; t < kHsPerThread / kPerTile; ++t) {
+            A mx = acc[t * kPerTile];
+#pragma unroll
+            for (int i = t * kPerTile + 1; i < (t + 1) * kPerTile; ++i)
+                if (r0 + i * kHsThreads < nh) mx = mx > acc[i] ? mx : acc[i];
+            const int64_t rt = rb + (int64_t)t * kPeakTileCols;
+            if (r0 + t * kPerTile * kHsThreads < nh && mx > hs_io<PT>::mark_bound(m.thr))
+                mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)rt, (int)rt);
+        }
     }
 }
 
