@@ -191,8 +191,10 @@ def batched_search(args, cfg, dev):
     note("batched: trials ready; planning and tuning")
     total = int(sum(lengths))
     t0 = time.perf_counter()
+    harm = {2: c3["threshold"] + 10, 4: c3["threshold"] + 20, 8: c3["threshold"] + 30, 16: c3["threshold"] + 40}
     bs = BatchSearch(lengths, c3["z_min"], c3["z_step"], c3["n_z"], c3["n_taps"], compute="bf16",
-                     plane_dtype="bf16", buffer_bytes=16 << 30, tune=True, device=dev)
+                     plane_dtype="bf16", buffer_bytes=16 << 30, tune=True, device=dev, harmonics=harm)
+    bs.harmonics = {}                      # plane and peaks only, until the harmonic timing below
     setup_s = time.perf_counter() - t0
     note(f"batched: {len(trials)} trials generated, {len(bs.chunks)} chunks planned and tuned ({setup_s:.1f} s)")
     res = {}
@@ -228,6 +230,24 @@ def batched_search(args, cfg, dev):
                                         "launches_per_pass": len(bs.chunks) * 7}
     note(f"batched correlate_and_peaks as one HIP graph: {ms:.1f} ms per pass")
     del g
+    # the full search of every trial: plane with peaks, then the sums over
+    # H = 2, 4, 8, 16 harmonics of every plane with their peaks
+    bs.harmonics = harm
+    bs.run(spectra, c3["threshold"])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        bs.run(spectra, c3["threshold"])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res["correlate_peaks_and_harmonic_sums"] = {
+        "ms_per_pass": ms, "harmonics": {str(h): t for h, t in harm.items()},
+        "launches_per_pass": len(bs.chunks) * 7 + len(lengths) * 4 * len(harm)}
+    note(f"batched plane + peaks + harmonic sums H = 2..16 with peaks: {ms:.1f} ms per pass")
+    bs.harmonics = {}
     # an injected pulsar counts as found when a peak sits within 2 bins of
     # the mean frequency of one of its harmonics
     found, noise_peaks, injected = 0, 0, 0

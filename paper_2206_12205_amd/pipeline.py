@@ -9,7 +9,8 @@ over the batch runs, per chunk, fdas_correlate_batch_peaks: one persistent
 correlation launch that also flags the peak finder's tiles while it stores
 the planes, then one count, scan and write over all of the chunk's planes
 (fused=False instead runs fdas_correlate_batch and fdas_peaks on every job's
-plane).  The full set of planes (tens of GB in BF16 for hundreds of trials)
+plane); with harmonics, every job's plane is then summed over its first H
+harmonics and thresholded (fdas_harmonic_sum_peaks, one call per job and H).  The full set of planes (tens of GB in BF16 for hundreds of trials)
 is never held at once.  A pass issues kernels only, so it can be recorded
 once as a HIP graph (capture) and replayed.
 """
@@ -29,10 +30,14 @@ class BatchSearch:
     buffer_bytes size of the reused plane buffer
     tune         measure the kernel configuration per length class (else the
                  library's defaults)
+    harmonics    {H: threshold} for H > 1: every job's plane is also summed
+                 over its first H harmonics (fdas_harmonic_sum_peaks, the
+                 sums through one reused buffer) and the sums thresholded
     """
 
     def __init__(self, lengths, z_min, z_step, n_z, n_taps, compute="bf16", plane_dtype="bf16",
-                 buffer_bytes=8 << 30, tune=True, tune_reps=3, device="cuda:0", peak_capacity=1 << 12):
+                 buffer_bytes=8 << 30, tune=True, tune_reps=3, device="cuda:0", peak_capacity=1 << 12,
+                 harmonics=None):
         import torch
         self.lengths = [int(v) for v in lengths]
         if not self.lengths or min(self.lengths) < 1:
@@ -97,6 +102,20 @@ class BatchSearch:
             F._check(F.lib().fdas_batch_peaks_workspace(pl._h, ctypes.byref(nb)), "fdas_batch_peaks_workspace")
             need = max(need, nb.value)
         self.peak_scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
+        # harmonic sums: one buffer for the largest job's smallest-H sum, one
+        # peak list per (H, job)
+        self.harmonics = {int(h): float(t) for h, t in (harmonics or {}).items()}
+        if any(h < 2 for h in self.harmonics):
+            raise ValueError("harmonics are sums over H >= 2 harmonics")
+        self.hpeaks_raw, self.hn_found = {}, {}
+        if self.harmonics:
+            h_min = min(self.harmonics)
+            self.sum_buffer = torch.empty(self.n_z * ((max_job - 1) // h_min + 1), dtype=self.buffer.dtype,
+                                          device=self.device)
+            for h in self.harmonics:
+                self.hpeaks_raw[h] = torch.empty((len(self.lengths), self.peak_capacity, 24), dtype=torch.uint8,
+                                                 device=self.device)
+                self.hn_found[h] = torch.zeros(len(self.lengths), dtype=torch.int64, device=self.device)
 
     def _chunk(self, jobs, cmax, knobs, common):
         pl = F.Plan(max_bins=cmax, max_jobs=len(jobs), device=self.device, **knobs, **common)
@@ -138,14 +157,23 @@ class BatchSearch:
                     self.peak_capacity, ctypes.c_void_p(self.n_found[slot0:slot0 + 1].data_ptr()),
                     ctypes.c_void_p(self.peak_scratch.data_ptr()), self.peak_scratch.numel(), s),
                     "fdas_correlate_batch_peaks")
+            else:
+                F._check(L.fdas_correlate_batch(pl._h, sp, buf, s), "fdas_correlate_batch")
+                for k, (i, po) in enumerate(zip(jobs, offs) if find_peaks else ()):
+                    F._check(L.fdas_peaks(pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz),
+                                          self.lengths[i], float(threshold),
+                                          ctypes.c_void_p(self.peaks_raw[slot0 + k].data_ptr()), self.peak_capacity,
+                                          ctypes.c_void_p(self.n_found[slot0 + k:].data_ptr()), s),
+                             "fdas_peaks")
+            if not find_peaks:
                 continue
-            F._check(L.fdas_correlate_batch(pl._h, sp, buf, s), "fdas_correlate_batch")
-            for k, (i, po) in enumerate(zip(jobs, offs) if find_peaks else ()):
-                F._check(L.fdas_peaks(pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz), self.lengths[i],
-                                      float(threshold), ctypes.c_void_p(self.peaks_raw[slot0 + k].data_ptr()),
-                                      self.peak_capacity, ctypes.c_void_p(self.n_found[slot0 + k:].data_ptr()),
-                                      s),
-                         "fdas_peaks")
+            for k, (i, po) in enumerate(zip(jobs, offs)):   # harmonic sums of every job's plane
+                for h, thr_h in self.harmonics.items():
+                    F._check(L.fdas_harmonic_sum_peaks(
+                        pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz), self.lengths[i], h,
+                        ctypes.c_void_p(self.sum_buffer.data_ptr()), float(thr_h),
+                        ctypes.c_void_p(self.hpeaks_raw[h][slot0 + k].data_ptr()), self.peak_capacity,
+                        ctypes.c_void_p(self.hn_found[h][slot0 + k:].data_ptr()), s), "fdas_harmonic_sum_peaks")
 
     def capture(self, spectra, threshold, find_peaks=True, fused=True):
         """Record one pass (run) into a HIP graph and return it
@@ -166,12 +194,14 @@ class BatchSearch:
             self.run(spectra, threshold, find_peaks=find_peaks, fused=fused)
         return g
 
-    def peaks(self, i):
-        """Peak list of job i after run() (host copy): dict of z_idx, r, power, n_found."""
+    def peaks(self, i, H=1):
+        """Peak list of job i after run() (host copy): dict of z_idx, r, power,
+        n_found; H > 1: the peaks of its sum over H harmonics."""
         import numpy as np
-        found = int(self.n_found[self.slot[i]].item())
+        raw_all, nf = (self.peaks_raw, self.n_found) if H == 1 else (self.hpeaks_raw[H], self.hn_found[H])
+        found = int(nf[self.slot[i]].item())
         k = min(found, self.peak_capacity)
-        raw = self.peaks_raw[self.slot[i], :k].cpu().numpy()
+        raw = raw_all[self.slot[i], :k].cpu().numpy()
         rec = raw.view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
                                  ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
         return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(), "power": rec["power"].copy(),

@@ -156,3 +156,36 @@ def test_batch_search_graph_replays_match_eager(dev):
                 assert np.array_equal(gi[k], wi[k]), f"replay {rep} job {i} {k}"
         _ = float(bs.buffer.float().sum().item())     # more eager work on the same stream
     del g
+
+
+def test_batch_search_harmonic_sums_match_single_plans(dev):
+    """Harmonic sums in the batched search: each job's list for H = 2 and 4
+    equals fdas_harmonic_sum_peaks on the plane of a single plan with the
+    same knobs (the sums pass through one reused buffer)."""
+    import torch
+    from paper_2206_12205_amd.fdas import Plan
+    from paper_2206_12205_amd.pipeline import BatchSearch
+    lengths = [20000, 70001, 3001, 150000, 1, 40000]
+    n_z, M = 9, 128
+    say(f"[pipeline] harmonic sums, lengths {lengths}")
+    parts = batch_spectra(lengths, seed=21)
+    x = torch.from_numpy(np.concatenate(parts)).to(dev)
+    harm = {2: 24.0, 4: 30.0}
+    bs = BatchSearch(lengths, -8.0, 2.0, n_z, M, compute="bf16", plane_dtype="bf16",
+                     buffer_bytes=n_z * 160000 * 2 * 2, device=dev, peak_capacity=256, harmonics=harm)
+    bs.run(x, 20.0)
+    torch.cuda.synchronize()
+    for i, n in enumerate(lengths):
+        cls = max(int(math.ceil(math.log2(n))), 0)
+        t = bs.tuned[cls]
+        cmax = max(v for v in lengths if max(int(math.ceil(math.log2(v))), 0) == cls)
+        pl = Plan(cmax, -8.0, 2.0, n_z, M, t["seg_len"], compute="bf16", plane_dtype="bf16", algo=t["algo"],
+                  z_chunk=t["z_chunk"], device=dev)
+        P = pl.correlate(torch.from_numpy(parts[i]).to(dev))
+        for h, thr in harm.items():
+            _, ref = pl.harmonic_sum_peaks(P, h, thr, capacity=256)
+            got = bs.peaks(i, h)
+            assert got["n_found"] == ref["n_found"], f"job {i} H={h}"
+            for k in ("z_idx", "r", "power"):
+                assert np.array_equal(got[k], ref[k]), f"job {i} H={h} {k}"
+    assert any(bs.peaks(i, 2)["n_found"] > 0 for i in range(len(lengths)))
