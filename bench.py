@@ -245,7 +245,7 @@ def batched_search(args, cfg, dev):
     ms = e0.elapsed_time(e1) / steps
     res["correlate_peaks_and_harmonic_sums"] = {
         "ms_per_pass": ms, "harmonics": {str(h): t for h, t in harm.items()},
-        "launches_per_pass": len(bs.chunks) * 7 + len(lengths) * 4 * len(harm)}
+        "launches_per_pass": len(bs.chunks) * 7 + len(lengths) * (1 + 5 * len(harm))}
     note(f"batched plane + peaks + harmonic sums H = 2..16 with peaks: {ms:.1f} ms per pass")
     bs.harmonics = {}
     # an injected pulsar counts as found when a peak sits within 2 bins of
@@ -384,6 +384,14 @@ def harmonic_timing(pl, plane, steps, thr):
         note(f"harmonic sum H={H}: {ms:.3f} ms; with peaks: separate "
              f"{res[f'H{H}']['with_peaks']['separate_ms']:.3f} ms, fused {res[f'H{H}']['with_peaks']['fused_ms']:.3f} ms")
         del out
+    # the four sums in one pass (fdas_harmonic_sums) against four calls
+    hs = (2, 4, 8, 16)
+    outs = pl.harmonic_sums(plane, hs)
+    ms1 = timed(lambda: pl.harmonic_sums(plane, hs, outs), max(10, min(steps, 100)))
+    res["H2_4_8_16_one_pass"] = {"ms": ms1, "separate_calls_ms": sum(res[f"H{h}"]["ms"] for h in hs)}
+    note(f"harmonic sums H = 2, 4, 8, 16 in one pass: {ms1:.3f} ms "
+         f"(four calls: {res['H2_4_8_16_one_pass']['separate_calls_ms']:.3f} ms)")
+    del outs
     return res
 
 
@@ -420,9 +428,10 @@ def prep_timing(args, cfg, dev):
 def series_search_timing(args, cfg, dev, pl):
     """The whole search of one single-DM time series (2^23 FP32 samples of
     the workload's first trial) as one timed unit: fdas_prepare, then
-    fdas_correlate_peaks, then fdas_harmonic_sum_peaks for H = 2, 4, 8, 16
-    (threshold: the workload's for the plane, +10 per doubling of H); every
-    buffer allocated beforehand, HIP events around the six calls."""
+    fdas_correlate_peaks, then the sums over H = 2, 4, 8, 16 harmonics in one
+    pass (fdas_harmonic_sums) and fdas_peaks on each (threshold: the
+    workload's for the plane, +10 per doubling of H); every buffer allocated
+    beforehand, HIP events around the calls."""
     import ctypes
     import numpy as np
     import torch
@@ -449,15 +458,18 @@ def series_search_timing(args, cfg, dev, pl):
     sp = ctypes.c_void_p(st.cuda_stream)
     V = ctypes.c_void_p
 
+    harr = (ctypes.c_int32 * len(hs))(*hs)
+    parr = (ctypes.c_void_p * len(hs))(*[sums[h].data_ptr() for h in hs])
+
     def one():
         F._check(L.fdas_prepare(V(xs.data_ptr()), n_t, V(spec.data_ptr()), V(ws.data_ptr()), nb.value, sp),
                  "fdas_prepare")
         F._check(L.fdas_correlate_peaks(pl._h, V(spec.data_ptr()), n, V(plane.data_ptr()), float(thr[1]),
                                         V(pk[0].data_ptr()), cap, V(nf[0:1].data_ptr()), sp), "fdas_correlate_peaks")
+        F._check(L.fdas_harmonic_sums(pl._h, V(plane.data_ptr()), n, len(hs), harr, parr, sp), "fdas_harmonic_sums")
         for i, h in enumerate(hs, 1):
-            F._check(L.fdas_harmonic_sum_peaks(pl._h, V(plane.data_ptr()), n, h, V(sums[h].data_ptr()),
-                                               float(thr[h]), V(pk[i].data_ptr()), cap, V(nf[i:i + 1].data_ptr()),
-                                               sp), "fdas_harmonic_sum_peaks")
+            F._check(L.fdas_peaks(pl._h, V(sums[h].data_ptr()), (n - 1) // h + 1, float(thr[h]), V(pk[i].data_ptr()),
+                                  cap, V(nf[i:i + 1].data_ptr()), sp), "fdas_peaks")
     for _ in range(5):
         one()
     torch.cuda.synchronize()

@@ -365,6 +365,17 @@ int fdas_band_max(fdas_plan_t plan, const void *plane, int64_t n_bins, const int
 int fdas_harmonic_sum(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_harm, void *out,
                       void *stream);
 
+/* Several harmonic sums in one pass over the plane: for an increasing list
+ * n_harm[0] < n_harm[1] < ... (n_levels in [1, 8], each in [1, 32]) the
+ * sums fdas_harmonic_sum gives for each, sum l written to outs[l] (device,
+ * n_z x ((n_bins - 1) / n_harm[l] + 1) of the plane dtype, element
+ * alignment; outs is a host array).  The harmonics are accumulated once in
+ * the order h = 1, 2, ..., so each sum is bitwise fdas_harmonic_sum's and
+ * the lower harmonics are read once for all sums.  Asynchronous on stream;
+ * FDAS_E_INVALID for bad lists or pointers. */
+int fdas_harmonic_sums(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_levels,
+                       const int32_t *n_harm, void *const *outs, void *stream);
+
 /* Harmonic summing with thresholding in one call: the summed plane
  * fdas_harmonic_sum writes to out, and exactly the list and count fdas_peaks
  * then gives for it (an n_z x N_H plane, N_H = (n_bins - 1) / n_harm + 1;

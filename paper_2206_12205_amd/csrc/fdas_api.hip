@@ -302,6 +302,22 @@ int fdas_harmonic_sum(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t 
     return hip_status(fdas::launch_harmonic_sum(*p, plane, n_bins, n_harm, out, static_cast<hipStream_t>(stream)));
 }
 
+int fdas_harmonic_sums(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_levels, const int32_t *n_harm,
+                       void *const *outs, void *stream) {
+    if (!p || !plane || !n_harm || !outs || n_levels < 1 || n_levels > 8) return FDAS_E_INVALID;
+    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
+    if ((reinterpret_cast<uintptr_t>(plane) % pe) != 0) return FDAS_E_INVALID;
+    if (n_bins < 1 || n_bins > p->cfg.max_bins) return FDAS_E_INVALID;
+    for (int32_t l = 0; l < n_levels; ++l) {
+        if (n_harm[l] < 1 || n_harm[l] > fdas::kMaxHarmonics || (l > 0 && n_harm[l] <= n_harm[l - 1]))
+            return FDAS_E_INVALID;
+        if (!outs[l] || (reinterpret_cast<uintptr_t>(outs[l]) % pe) != 0) return FDAS_E_INVALID;
+    }
+    if (p->cfg.n_z > 65535) return FDAS_E_UNSUPPORTED;
+    return hip_status(
+        fdas::launch_harmonic_sums(*p, plane, n_bins, n_levels, n_harm, outs, static_cast<hipStream_t>(stream)));
+}
+
 int fdas_harmonic_sum_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_harm, void *out,
                             float threshold, fdas_peak *peaks, int64_t capacity, int64_t *n_found, void *stream) {
     if (!p || !plane || !out || !n_found || capacity < 0 || (capacity > 0 && !peaks)) return FDAS_E_INVALID;

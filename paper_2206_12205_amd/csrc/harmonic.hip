@@ -132,6 +132,79 @@ k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, d
     }
 }
 
+// Several sums in one pass: S_H for every H of an increasing list, the
+// harmonics accumulated once in the order h = 1, 2, ... and each S_H written
+// when h reaches H (the same sequence of additions as the single-H kernel,
+// so every sum is bitwise the one k_harmonic_sum gives).  A fundamental r
+// takes harmonic h only while a requested sum still needs it (r below N_H of
+// some H >= h).
+constexpr int kMaxSumLevels = 8;
+
+template <class PT>
+struct SumLevels {
+    int32_t H[kMaxSumLevels];
+    int64_t nh[kMaxSumLevels];
+    PT *out[kMaxSumLevels];
+};
+
+template <class PT>
+__global__ void __launch_bounds__(kHsThreads)
+k_harmonic_sums(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, double z_step, int n_levels,
+                SumLevels<PT> lv) {
+    using A = typename hs_io<PT>::acc;
+    __shared__ int rows[kMaxHarmonics];
+    const int j = blockIdx.y;
+    const int h_max = lv.H[n_levels - 1];
+    if ((int)threadIdx.x < h_max) rows[threadIdx.x] = harmonic_row(z_min, z_step, n_z, j, threadIdx.x + 1);
+    __syncthreads();
+    const int64_t rb = (int64_t)blockIdx.x * (kHsThreads * kHsPerThread);
+    const int64_t r0 = rb + threadIdx.x;
+    if (r0 >= lv.nh[0]) return;                 // the largest N_H (smallest H)
+    A acc[kHsPerThread];
+#pragma unroll
+    for (int i = 0; i < kHsPerThread; ++i) acc[i] = 0;
+    int lvl = 0;
+    for (int h = 1; h <= h_max; ++h) {
+        const int64_t lim = lv.nh[lvl];         // fundamentals that still need harmonic h
+        if (r0 >= lim) break;                   // every later sum has an even smaller N_H
+        const int jh = rows[h - 1];
+        if (jh >= 0) {
+            const PT *row = plane + (int64_t)jh * n;
+#pragma unroll
+            for (int i = 0; i < kHsPerThread; ++i) {
+                const int64_t r = r0 + i * kHsThreads;
+                if (r < lim) acc[i] += hs_io<PT>::get(row, (int64_t)h * r);
+            }
+        }
+        if (h == lv.H[lvl]) {
+            PT *o = lv.out[lvl] + (int64_t)j * lim;
+#pragma unroll
+            for (int i = 0; i < kHsPerThread; ++i) {
+                const int64_t r = r0 + i * kHsThreads;
+                if (r < lim) hs_io<PT>::put(o + r, acc[i]);
+            }
+            if (++lvl == n_levels) break;
+        }
+    }
+}
+
+template <class PT>
+hipError_t run_sums(const fdas_plan_s &p, const void *plane, int64_t n, int n_levels, const int32_t *H,
+                    void *const *outs, hipStream_t st) {
+    SumLevels<PT> lv{};
+    for (int l = 0; l < n_levels; ++l) {
+        lv.H[l] = H[l];
+        lv.nh[l] = (n - 1) / H[l] + 1;
+        lv.out[l] = static_cast<PT *>(outs[l]);
+    }
+    const int64_t per_block = (int64_t)kHsThreads * kHsPerThread;
+    const int64_t bx = (lv.nh[0] + per_block - 1) / per_block;
+    if (bx > 0x7fffffffLL || p.cfg.n_z > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_harmonic_sums<PT>), dim3((unsigned)bx, (unsigned)p.cfg.n_z), dim3(kHsThreads), 0, st,
+                       static_cast<const PT *>(plane), n, p.cfg.n_z, p.cfg.z_min, p.cfg.z_step, n_levels, lv);
+    return hipGetLastError();
+}
+
 template <class PT, bool kMark>
 hipError_t run(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out, const PeakMarks &m,
                hipStream_t st) {
@@ -161,6 +234,16 @@ hipError_t dispatch(const fdas_plan_s &p, const void *plane, int64_t n, int n_ha
 hipError_t launch_harmonic_sum(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,
                                hipStream_t st) {
     return dispatch<false>(p, plane, n, n_harm, out, PeakMarks{}, st);
+}
+
+hipError_t launch_harmonic_sums(const fdas_plan_s &p, const void *plane, int64_t n, int n_levels, const int32_t *H,
+                                void *const *outs, hipStream_t st) {
+    switch (p.cfg.plane_dtype) {
+        case FDAS_FP32: return run_sums<float>(p, plane, n, n_levels, H, outs, st);
+        case FDAS_BF16: return run_sums<__bf16>(p, plane, n, n_levels, H, outs, st);
+        case FDAS_FP64: return run_sums<double>(p, plane, n, n_levels, H, outs, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_harmonic_sum_marked(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,

@@ -137,6 +137,10 @@ hipError_t launch_band_max(const fdas_plan_s &p, const void *plane, int64_t n, c
 constexpr int kMaxHarmonics = 32;
 hipError_t launch_harmonic_sum(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,
                                hipStream_t st);
+// Sums for an increasing list of n_levels (<= 8) harmonic counts in one
+// pass, sum l to outs[l].
+hipError_t launch_harmonic_sums(const fdas_plan_s &p, const void *plane, int64_t n, int n_levels, const int32_t *H,
+                                void *const *outs, hipStream_t st);
 // The same, also marking the peak tiles of the summed plane (marks from
 // peak_marks for its (n - 1) / n_harm + 1 bins).
 hipError_t launch_harmonic_sum_marked(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,

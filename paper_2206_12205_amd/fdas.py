@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
         L.fdas_correlate_batch_peaks.argtypes = [P, P, P, ctypes.c_float, P, I64, P, P, ctypes.c_size_t, P]
         L.fdas_harmonic_sum.argtypes = [P, P, I64, I32, P, P]
         L.fdas_harmonic_sum_peaks.argtypes = [P, P, I64, I32, P, ctypes.c_float, P, I64, P, P]
+        L.fdas_harmonic_sums.argtypes = [P, P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(P), P]
         L.fdas_band_max.argtypes = [P, P, I64, P, I32, P, P]
         L.fdas_prepare_workspace.argtypes = [I64, ctypes.POINTER(ctypes.c_size_t)]
         L.fdas_prepare.argtypes = [P, I64, P, P, ctypes.c_size_t, P]
@@ -382,6 +383,26 @@ class Plan:
         _check(lib().fdas_harmonic_sum(self._h, ctypes.c_void_p(plane.data_ptr()), n, int(n_harm),
                                        ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "fdas_harmonic_sum")
         return out
+
+    def harmonic_sums(self, plane, n_harms, outs=None, stream=None):
+        """Sums for an increasing list of harmonic counts in one pass
+        (fdas_harmonic_sums) -> list of (n_z, (n - 1) // H + 1) tensors."""
+        import torch
+        if plane.dim() != 2 or plane.shape[0] != self.n_z or plane.dtype != self.torch_plane_dtype() \
+                or not plane.is_contiguous():
+            raise ValueError("plane must be a contiguous (n_z, n) tensor of the plan's plane dtype")
+        n = plane.shape[1]
+        hs = [int(h) for h in n_harms]
+        if outs is None:
+            outs = [torch.empty((self.n_z, (n - 1) // h + 1), dtype=plane.dtype, device=self.device) for h in hs]
+        for h, o in zip(hs, outs):
+            if o.dtype != plane.dtype or tuple(o.shape) != (self.n_z, (n - 1) // h + 1) or not o.is_contiguous():
+                raise ValueError("an output has the wrong dtype, shape or layout")
+        harr = (ctypes.c_int32 * len(hs))(*hs)
+        parr = (ctypes.c_void_p * len(hs))(*[o.data_ptr() for o in outs])
+        _check(lib().fdas_harmonic_sums(self._h, ctypes.c_void_p(plane.data_ptr()), n, len(hs), harr, parr,
+                                        _stream_ptr(stream)), "fdas_harmonic_sums")
+        return outs
 
     def harmonic_sum_peaks(self, plane, n_harm, threshold, capacity=1 << 16, out=None, stream=None):
         """Harmonic sum and the thresholded peaks of the summed plane in one

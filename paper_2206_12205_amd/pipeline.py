@@ -10,7 +10,8 @@ correlation launch that also flags the peak finder's tiles while it stores
 the planes, then one count, scan and write over all of the chunk's planes
 (fused=False instead runs fdas_correlate_batch and fdas_peaks on every job's
 plane); with harmonics, every job's plane is then summed over its first H
-harmonics and thresholded (fdas_harmonic_sum_peaks, one call per job and H).  The full set of planes (tens of GB in BF16 for hundreds of trials)
+harmonics for every requested H in one pass (fdas_harmonic_sums) and each
+sum thresholded (fdas_peaks).  The full set of planes (tens of GB in BF16 for hundreds of trials)
 is never held at once.  A pass issues kernels only, so it can be recorded
 once as a HIP graph (capture) and replayed.
 """
@@ -31,8 +32,9 @@ class BatchSearch:
     tune         measure the kernel configuration per length class (else the
                  library's defaults)
     harmonics    {H: threshold} for H > 1: every job's plane is also summed
-                 over its first H harmonics (fdas_harmonic_sum_peaks, the
-                 sums through one reused buffer) and the sums thresholded
+                 over its first H harmonics (all H in one fdas_harmonic_sums
+                 pass, the sums through one reused buffer) and each sum
+                 thresholded
     """
 
     def __init__(self, lengths, z_min, z_step, n_z, n_taps, compute="bf16", plane_dtype="bf16",
@@ -109,9 +111,13 @@ class BatchSearch:
             raise ValueError("harmonics are sums over H >= 2 harmonics")
         self.hpeaks_raw, self.hn_found = {}, {}
         if self.harmonics:
-            h_min = min(self.harmonics)
-            self.sum_buffer = torch.empty(self.n_z * ((max_job - 1) // h_min + 1), dtype=self.buffer.dtype,
-                                          device=self.device)
+            # one region per H, all sums of a job written by one pass
+            self.sum_offs, tot = {}, 0
+            for h in sorted(self.harmonics):
+                self.sum_offs[h] = tot
+                tot += self.n_z * ((max_job - 1) // h + 1)
+                tot = (tot + 127) // 128 * 128         # keep every region 256-byte aligned
+            self.sum_buffer = torch.empty(tot, dtype=self.buffer.dtype, device=self.device)
             for h in self.harmonics:
                 self.hpeaks_raw[h] = torch.empty((len(self.lengths), self.peak_capacity, 24), dtype=torch.uint8,
                                                  device=self.device)
@@ -167,13 +173,21 @@ class BatchSearch:
                              "fdas_peaks")
             if not find_peaks:
                 continue
-            for k, (i, po) in enumerate(zip(jobs, offs)):   # harmonic sums of every job's plane
-                for h, thr_h in self.harmonics.items():
-                    F._check(L.fdas_harmonic_sum_peaks(
-                        pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz), self.lengths[i], h,
-                        ctypes.c_void_p(self.sum_buffer.data_ptr()), float(thr_h),
-                        ctypes.c_void_p(self.hpeaks_raw[h][slot0 + k].data_ptr()), self.peak_capacity,
-                        ctypes.c_void_p(self.hn_found[h][slot0 + k:].data_ptr()), s), "fdas_harmonic_sum_peaks")
+            if not self.harmonics:
+                continue
+            hs = sorted(self.harmonics)
+            harr = (ctypes.c_int32 * len(hs))(*hs)
+            sptr = [self.sum_buffer.data_ptr() + self.sum_offs[h] * esz for h in hs]
+            parr = (ctypes.c_void_p * len(hs))(*sptr)
+            for k, (i, po) in enumerate(zip(jobs, offs)):   # harmonic sums of every job's plane, one pass
+                F._check(L.fdas_harmonic_sums(pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz),
+                                              self.lengths[i], len(hs), harr, parr, s), "fdas_harmonic_sums")
+                for h, p_h in zip(hs, sptr):
+                    F._check(L.fdas_peaks(pl._h, ctypes.c_void_p(p_h), (self.lengths[i] - 1) // h + 1,
+                                          float(self.harmonics[h]),
+                                          ctypes.c_void_p(self.hpeaks_raw[h][slot0 + k].data_ptr()),
+                                          self.peak_capacity, ctypes.c_void_p(self.hn_found[h][slot0 + k:].data_ptr()),
+                                          s), "fdas_peaks")
 
     def capture(self, spectra, threshold, find_peaks=True, fused=True):
         """Record one pass (run) into a HIP graph and return it
@@ -215,16 +229,17 @@ def search_series(plan, series, threshold, harmonics=(1, 2, 4, 8, 16), capacity=
     plan       a fdas.Plan whose max_bins covers n_t / 2
     threshold  a float, or a dict H -> float (noise powers of a sum of H
                normalised powers have mean H)
-    Steps (each one library call): the normalised spectrum (fdas_prepare),
-    the plane with its thresholded peaks (fdas_correlate_peaks) and, for each
-    H > 1, the harmonic sum with its thresholded peaks
-    (fdas_harmonic_sum_peaks).  Returns (spectrum, plane, {H: peaks dict}).
+    Steps: the normalised spectrum (fdas_prepare), the plane with its
+    thresholded peaks (fdas_correlate_peaks), every sum over H > 1 harmonics
+    in one pass (fdas_harmonic_sums) and the thresholded peaks of each sum
+    (fdas_peaks).  Returns (spectrum, plane, {H: peaks dict}).
     """
     spec = F.prepare(series, stream=stream)
     thr = (lambda h: float(threshold[h])) if isinstance(threshold, dict) else (lambda h: float(threshold))
     plane, pk1 = plan.correlate_peaks(spec, thr(1), capacity=capacity, stream=stream)
     found = {1: pk1} if 1 in harmonics else {}
-    for h in harmonics:
-        if h > 1:
-            _, found[h] = plan.harmonic_sum_peaks(plane, h, thr(h), capacity=capacity, stream=stream)
+    hs = sorted(h for h in set(harmonics) if h > 1)
+    if hs:
+        for h, S in zip(hs, plan.harmonic_sums(plane, hs, stream=stream)):
+            found[h] = plan.peaks(S, thr(h), capacity=capacity, stream=stream)
     return spec, plane, found

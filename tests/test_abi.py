@@ -120,6 +120,19 @@ def test_layout_and_workspace_checks_on_host():
         assert L.fdas_harmonic_sum(h, fake, 100, 4, None, None) == F.E_INVALID
         assert L.fdas_harmonic_sum(h, ctypes.c_void_p(0x10001), 100, 4, fake, None) == F.E_INVALID
         assert L.fdas_harmonic_sum(None, fake, 100, 4, fake, None) == F.E_INVALID
+        # several harmonic sums: argument checks only
+        H3 = (ctypes.c_int32 * 3)(2, 4, 8)
+        Hbad = (ctypes.c_int32 * 3)(2, 2, 8)
+        Hbig = (ctypes.c_int32 * 1)(33)
+        O3 = (ctypes.c_void_p * 3)(0x10000, 0x20000, 0x30000)
+        O3bad = (ctypes.c_void_p * 3)(0x10000, None, 0x30000)
+        assert L.fdas_harmonic_sums(h, fake, 100, 3, Hbad, O3, None) == F.E_INVALID     # not increasing
+        assert L.fdas_harmonic_sums(h, fake, 100, 1, Hbig, O3, None) == F.E_INVALID     # H > 32
+        assert L.fdas_harmonic_sums(h, fake, 100, 3, H3, O3bad, None) == F.E_INVALID    # missing output
+        assert L.fdas_harmonic_sums(h, fake, 100, 0, H3, O3, None) == F.E_INVALID
+        assert L.fdas_harmonic_sums(h, fake, 100, 9, H3, O3, None) == F.E_INVALID
+        assert L.fdas_harmonic_sums(h, fake, 4097, 3, H3, O3, None) == F.E_INVALID
+        assert L.fdas_harmonic_sums(h, None, 100, 3, H3, O3, None) == F.E_INVALID
         # harmonic sum with peaks: argument checks only
         assert L.fdas_harmonic_sum_peaks(h, fake, 100, 0, fake, 1.0, fake, 5, nf, None) == F.E_INVALID
         assert L.fdas_harmonic_sum_peaks(h, fake, 100, 33, fake, 1.0, fake, 5, nf, None) == F.E_INVALID

@@ -141,6 +141,26 @@ def test_harmonic_sum_peaks_fused(dev, pd, n_harm):
         assert np.array_equal(got["power"].astype(np.float64), pw[:k].astype(np.float32).astype(np.float64))
 
 
+@pytest.mark.parametrize("pd", ["fp32", "bf16", "fp64"])
+@pytest.mark.parametrize("hs", [(2, 4, 8, 16), (1, 3, 32), (5,), (2, 3, 4, 5, 6, 7, 8, 9)])
+def test_harmonic_sums_one_pass_equal_single_sums(dev, pd, hs):
+    """fdas_harmonic_sums: every sum of the list bitwise equal to
+    fdas_harmonic_sum's for the same H (the same additions in the same order),
+    which the tests above hold against the oracle."""
+    import torch
+    say(f"[harmonic] one-pass sums {pd} {hs}")
+    sp = synth.config1(0)
+    compute = "fp64" if pd == "fp64" else "fp32"
+    pl = plan(dev, max_bins=sp.spec.size, z_min=C1["z_min"], z_step=C1["z_step"], n_z=C1["n_z"],
+              n_taps=C1["n_taps"], seg_len=C1["seg_len"], compute=compute, plane_dtype=pd)
+    P = pl.correlate(torch.from_numpy(sp.spec).to(dev))
+    got = pl.harmonic_sums(P, hs)
+    ints = {2: torch.int16, 4: torch.int32, 8: torch.int64}[P.element_size()]
+    for h, g in zip(hs, got):
+        want = pl.harmonic_sum(P, h)
+        assert torch.equal(g.view(ints), want.view(ints)), f"H={h}"
+
+
 def test_harmonic_series_of_chirps_on_the_gpu(dev):
     """The sum at the fundamental's cell of a noise-free harmonic series of
     chirps is the sum of their matched powers (the oracle pin's physics),
@@ -189,3 +209,7 @@ def test_single_dm_bf16_plane_sampled_rows(dev):
         assert torch.equal(S2.view(torch.int16), S.view(torch.int16))
         assert a["n_found"] == b["n_found"]
         assert np.array_equal(a["r"], b["r"]) and np.array_equal(a["z_idx"], b["z_idx"])
+    # several sums in one pass at full size: each bitwise the single-H sum
+    sums = pl.harmonic_sums(P, (2, 4, 8, 16))
+    for h, g in zip((2, 4, 8, 16), sums):
+        assert torch.equal(g.view(torch.int16), pl.harmonic_sum(P, h).view(torch.int16)), f"H={h}"
