@@ -245,7 +245,7 @@ def batched_search(args, cfg, dev):
     ms = e0.elapsed_time(e1) / steps
     res["correlate_peaks_and_harmonic_sums"] = {
         "ms_per_pass": ms, "harmonics": {str(h): t for h, t in harm.items()},
-        "launches_per_pass": len(bs.chunks) * 7 + len(lengths) * (1 + 5 * len(harm))}
+        "launches_per_pass": len(bs.chunks) * 7 + len(lengths) * (2 + 3 * len(harm))}
     note(f"batched plane + peaks + harmonic sums H = 2..16 with peaks: {ms:.1f} ms per pass")
     bs.harmonics = {}
     # an injected pulsar counts as found when a peak sits within 2 bins of
@@ -429,9 +429,9 @@ def series_search_timing(args, cfg, dev, pl):
     """The whole search of one single-DM time series (2^23 FP32 samples of
     the workload's first trial) as one timed unit: fdas_prepare, then
     fdas_correlate_peaks, then the sums over H = 2, 4, 8, 16 harmonics in one
-    pass (fdas_harmonic_sums) and fdas_peaks on each (threshold: the
-    workload's for the plane, +10 per doubling of H); every buffer allocated
-    beforehand, HIP events around the calls."""
+    pass with the thresholded peaks of each (fdas_harmonic_sums_peaks;
+    threshold: the workload's for the plane, +10 per doubling of H); every
+    buffer allocated beforehand, HIP events around the three calls."""
     import ctypes
     import numpy as np
     import torch
@@ -460,16 +460,18 @@ def series_search_timing(args, cfg, dev, pl):
 
     harr = (ctypes.c_int32 * len(hs))(*hs)
     parr = (ctypes.c_void_p * len(hs))(*[sums[h].data_ptr() for h in hs])
+    tarr = (ctypes.c_float * len(hs))(*[float(thr[h]) for h in hs])
+    karr = (ctypes.c_void_p * len(hs))(*[pk[i].data_ptr() for i in range(1, len(hs) + 1)])
+    scr = torch.empty(max(pl.harmonic_sums_peaks_bytes(n, hs), 1), dtype=torch.uint8, device=dev)
 
     def one():
         F._check(L.fdas_prepare(V(xs.data_ptr()), n_t, V(spec.data_ptr()), V(ws.data_ptr()), nb.value, sp),
                  "fdas_prepare")
         F._check(L.fdas_correlate_peaks(pl._h, V(spec.data_ptr()), n, V(plane.data_ptr()), float(thr[1]),
                                         V(pk[0].data_ptr()), cap, V(nf[0:1].data_ptr()), sp), "fdas_correlate_peaks")
-        F._check(L.fdas_harmonic_sums(pl._h, V(plane.data_ptr()), n, len(hs), harr, parr, sp), "fdas_harmonic_sums")
-        for i, h in enumerate(hs, 1):
-            F._check(L.fdas_peaks(pl._h, V(sums[h].data_ptr()), (n - 1) // h + 1, float(thr[h]), V(pk[i].data_ptr()),
-                                  cap, V(nf[i:i + 1].data_ptr()), sp), "fdas_peaks")
+        F._check(L.fdas_harmonic_sums_peaks(pl._h, V(plane.data_ptr()), n, len(hs), harr, parr, tarr, karr, cap,
+                                            V(nf[1:].data_ptr()), V(scr.data_ptr()), scr.numel(), sp),
+                 "fdas_harmonic_sums_peaks")
     for _ in range(5):
         one()
     torch.cuda.synchronize()

@@ -376,6 +376,25 @@ int fdas_harmonic_sum(fdas_plan_t plan, const void *plane, int64_t n_bins, int32
 int fdas_harmonic_sums(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_levels,
                        const int32_t *n_harm, void *const *outs, void *stream);
 
+/* The same sums with the thresholded peaks of each: sum l's list (the one
+ * fdas_peaks gives for outs[l] with thresholds[l]) goes to peaks[l] (host
+ * array of device pointers, capacity entries each, 16-byte aligned), its
+ * true count to n_found[l] (device, n_levels int64, 8-byte aligned).  The
+ * summing kernel flags the peak tiles of every sum while it stores them, so
+ * no sum is streamed back.
+ *   scratch  caller device memory (16-byte aligned) of at least the bytes
+ *            fdas_harmonic_sums_peaks_workspace gives for the same n_bins
+ *            and list: the flags of every sum and the peak counters
+ * FDAS_E_UNSUPPORTED for sums of 2^31 bins or tiles and more,
+ * FDAS_E_WORKSPACE for a missing or short scratch.  Asynchronous on stream,
+ * kernels only. */
+int fdas_harmonic_sums_peaks_workspace(fdas_plan_t plan, int64_t n_bins, int32_t n_levels,
+                                       const int32_t *n_harm, size_t *scratch_bytes);
+int fdas_harmonic_sums_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_levels,
+                             const int32_t *n_harm, void *const *outs, const float *thresholds,
+                             fdas_peak *const *peaks, int64_t capacity, int64_t *n_found, void *scratch,
+                             size_t scratch_bytes, void *stream);
+
 /* Harmonic summing with thresholding in one call: the summed plane
  * fdas_harmonic_sum writes to out, and exactly the list and count fdas_peaks
  * then gives for it (an n_z x N_H plane, N_H = (n_bins - 1) / n_harm + 1;

@@ -26,6 +26,7 @@ namespace {
 int hip_status(hipError_t e) { return fdas::hip_status_of(e); }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+static bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -314,8 +315,88 @@ int fdas_harmonic_sums(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t
         if (!outs[l] || (reinterpret_cast<uintptr_t>(outs[l]) % pe) != 0) return FDAS_E_INVALID;
     }
     if (p->cfg.n_z > 65535) return FDAS_E_UNSUPPORTED;
-    return hip_status(
-        fdas::launch_harmonic_sums(*p, plane, n_bins, n_levels, n_harm, outs, static_cast<hipStream_t>(stream)));
+    return hip_status(fdas::launch_harmonic_sums(*p, plane, n_bins, n_levels, n_harm, outs, nullptr,
+                                                 static_cast<hipStream_t>(stream)));
+}
+
+// Scratch of fdas_harmonic_sums_peaks: the peak finder's counters for the
+// largest sum (shared by the sums, which are finished one after the other),
+// then the tile and chunk flags of every sum back to back.
+struct SumsPeakLayout {
+    size_t work_bytes = 0, flags_off[8] = {}, total = 0;
+    int64_t nh[8] = {}, n_cb[8] = {}, tiles[8] = {}, chunks[8] = {};
+    bool fits = true;
+};
+
+static SumsPeakLayout sums_peak_layout(const fdas_plan_s &p, int64_t n_bins, int32_t n_levels, const int32_t *H) {
+    SumsPeakLayout L;
+    for (int32_t l = 0; l < n_levels; ++l) {
+        L.nh[l] = (n_bins - 1) / H[l] + 1;
+        L.n_cb[l] = (L.nh[l] + fdas::kPeakTileCols - 1) / fdas::kPeakTileCols;
+        L.tiles[l] = L.n_cb[l] * p.cfg.n_z;
+        L.chunks[l] = (L.tiles[l] + fdas::kPeakTilesPerChunk - 1) / fdas::kPeakTilesPerChunk;
+        if (L.nh[l] > fdas::kMarkMaxBins || L.tiles[l] >= 0x7fffffffLL) L.fits = false;
+    }
+    L.work_bytes = align_up(fdas::peak_work_bytes(L.tiles[0]), 256);
+    size_t off = L.work_bytes;
+    for (int32_t l = 0; l < n_levels; ++l) {
+        L.flags_off[l] = off;
+        off += (size_t)(L.tiles[l] + L.chunks[l]);
+    }
+    L.total = align_up(off, 256);
+    return L;
+}
+
+static int check_sums_list(const fdas_plan_s &p, int64_t n_bins, int32_t n_levels, const int32_t *n_harm) {
+    if (!n_harm || n_levels < 1 || n_levels > 8) return FDAS_E_INVALID;
+    if (n_bins < 1 || n_bins > p.cfg.max_bins) return FDAS_E_INVALID;
+    for (int32_t l = 0; l < n_levels; ++l)
+        if (n_harm[l] < 1 || n_harm[l] > fdas::kMaxHarmonics || (l > 0 && n_harm[l] <= n_harm[l - 1]))
+            return FDAS_E_INVALID;
+    if (p.cfg.n_z > 65535) return FDAS_E_UNSUPPORTED;
+    return FDAS_OK;
+}
+
+int fdas_harmonic_sums_peaks_workspace(fdas_plan_t p, int64_t n_bins, int32_t n_levels, const int32_t *n_harm,
+                                       size_t *scratch_bytes) {
+    if (!p || !scratch_bytes) return FDAS_E_INVALID;
+    const int s = check_sums_list(*p, n_bins, n_levels, n_harm);
+    if (s != FDAS_OK) return s;
+    const SumsPeakLayout L = sums_peak_layout(*p, n_bins, n_levels, n_harm);
+    if (!L.fits) return FDAS_E_UNSUPPORTED;
+    *scratch_bytes = L.total;
+    return FDAS_OK;
+}
+
+int fdas_harmonic_sums_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_levels,
+                             const int32_t *n_harm, void *const *outs, const float *thresholds,
+                             fdas_peak *const *peaks, int64_t capacity, int64_t *n_found, void *scratch,
+                             size_t scratch_bytes, void *stream) {
+    if (!p || !plane || !outs || !thresholds || !peaks || !n_found || capacity < 0) return FDAS_E_INVALID;
+    const int s = check_sums_list(*p, n_bins, n_levels, n_harm);
+    if (s != FDAS_OK) return s;
+    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
+    if ((reinterpret_cast<uintptr_t>(plane) % pe) != 0 || !aligned8(n_found)) return FDAS_E_INVALID;
+    for (int32_t l = 0; l < n_levels; ++l) {
+        if (!outs[l] || (reinterpret_cast<uintptr_t>(outs[l]) % pe) != 0) return FDAS_E_INVALID;
+        if ((capacity > 0 && !peaks[l]) || (peaks[l] && !aligned16(peaks[l]))) return FDAS_E_INVALID;
+    }
+    const SumsPeakLayout L = sums_peak_layout(*p, n_bins, n_levels, n_harm);
+    if (!L.fits) return FDAS_E_UNSUPPORTED;
+    if (!scratch || !aligned16(scratch) || scratch_bytes < L.total) return FDAS_E_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto *base = static_cast<unsigned char *>(scratch);
+    fdas::PeakMarks marks[8];
+    for (int32_t l = 0; l < n_levels; ++l) {
+        uint8_t *f = base + L.flags_off[l];
+        marks[l] = fdas::make_peak_marks(f, f + L.tiles[l], L.n_cb[l], thresholds[l]);
+    }
+    hipError_t e = fdas::peak_flags_clear(base + L.flags_off[0], (int64_t)(L.total - L.flags_off[0]), st);
+    if (e == hipSuccess) e = fdas::launch_harmonic_sums(*p, plane, n_bins, n_levels, n_harm, outs, marks, st);
+    for (int32_t l = 0; l < n_levels && e == hipSuccess; ++l)
+        e = fdas::peaks_finish_plane(*p, outs[l], L.nh[l], thresholds[l], marks[l].flags, marks[l].cflags, base,
+                                     peaks[l], capacity, n_found + l, st);
+    return hip_status(e);
 }
 
 int fdas_harmonic_sum_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_harm, void *out,
@@ -398,7 +479,6 @@ int fdas_correlate_batch(fdas_plan_t p, const void *spectra, void *planes, void 
     return FDAS_OK;
 }
 
-static bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 // The marking correlation indexes columns and tiles in 32 bits.
 static bool mark_fits(const fdas_plan_s &p, int64_t n_bins) {

@@ -145,9 +145,30 @@ struct SumLevels {
     int32_t H[kMaxSumLevels];
     int64_t nh[kMaxSumLevels];
     PT *out[kMaxSumLevels];
+    PeakMarks marks[kMaxSumLevels];   // marking form: the peak tiles of each sum
 };
 
-template <class PT>
+// kMark: each thread flags, per peak tile of a sum it writes, the tile when
+// its largest sum there passes the threshold lowered by the rounding bound
+// (flags may be a superset).
+template <class PT, bool kMark>
+__device__ __forceinline__ void mark_sums(const typename hs_io<PT>::acc (&acc)[kHsPerThread], int64_t r0,
+                                          int64_t rb, int64_t lim, int j, const PeakMarks &m) {
+    using A = typename hs_io<PT>::acc;
+    constexpr int kPerTile = kPeakTileCols / kHsThreads;
+#pragma unroll
+    for (int t = 0; t < kHsPerThread / kPerTile; ++t) {
+        if (r0 + t * kPerTile * kHsThreads >= lim) break;
+        A mx = acc[t * kPerTile];
+#pragma unroll
+        for (int i = t * kPerTile + 1; i < (t + 1) * kPerTile; ++i)
+            if (r0 + i * kHsThreads < lim) mx = mx > acc[i] ? mx : acc[i];
+        const int64_t rt = rb + (int64_t)t * kPeakTileCols;
+        if (mx > hs_io<PT>::mark_bound(m.thr)) mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)rt, (int)rt);
+    }
+}
+
+template <class PT, bool kMark>
 __global__ void __launch_bounds__(kHsThreads)
 k_harmonic_sums(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, double z_step, int n_levels,
                 SumLevels<PT> lv) {
@@ -183,24 +204,26 @@ k_harmonic_sums(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, 
                 const int64_t r = r0 + i * kHsThreads;
                 if (r < lim) hs_io<PT>::put(o + r, acc[i]);
             }
+            if constexpr (kMark) mark_sums<PT, kMark>(acc, r0, rb, lim, j, lv.marks[lvl]);
             if (++lvl == n_levels) break;
         }
     }
 }
 
-template <class PT>
+template <class PT, bool kMark>
 hipError_t run_sums(const fdas_plan_s &p, const void *plane, int64_t n, int n_levels, const int32_t *H,
-                    void *const *outs, hipStream_t st) {
+                    void *const *outs, const PeakMarks *marks, hipStream_t st) {
     SumLevels<PT> lv{};
     for (int l = 0; l < n_levels; ++l) {
         lv.H[l] = H[l];
         lv.nh[l] = (n - 1) / H[l] + 1;
         lv.out[l] = static_cast<PT *>(outs[l]);
+        if (marks) lv.marks[l] = marks[l];
     }
     const int64_t per_block = (int64_t)kHsThreads * kHsPerThread;
     const int64_t bx = (lv.nh[0] + per_block - 1) / per_block;
     if (bx > 0x7fffffffLL || p.cfg.n_z > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_harmonic_sums<PT>), dim3((unsigned)bx, (unsigned)p.cfg.n_z), dim3(kHsThreads), 0, st,
+    hipLaunchKernelGGL((k_harmonic_sums<PT, kMark>), dim3((unsigned)bx, (unsigned)p.cfg.n_z), dim3(kHsThreads), 0, st,
                        static_cast<const PT *>(plane), n, p.cfg.n_z, p.cfg.z_min, p.cfg.z_step, n_levels, lv);
     return hipGetLastError();
 }
@@ -237,11 +260,19 @@ hipError_t launch_harmonic_sum(const fdas_plan_s &p, const void *plane, int64_t 
 }
 
 hipError_t launch_harmonic_sums(const fdas_plan_s &p, const void *plane, int64_t n, int n_levels, const int32_t *H,
-                                void *const *outs, hipStream_t st) {
+                                void *const *outs, const PeakMarks *marks, hipStream_t st) {
+    if (marks) {
+        switch (p.cfg.plane_dtype) {
+            case FDAS_FP32: return run_sums<float, true>(p, plane, n, n_levels, H, outs, marks, st);
+            case FDAS_BF16: return run_sums<__bf16, true>(p, plane, n, n_levels, H, outs, marks, st);
+            case FDAS_FP64: return run_sums<double, true>(p, plane, n, n_levels, H, outs, marks, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (p.cfg.plane_dtype) {
-        case FDAS_FP32: return run_sums<float>(p, plane, n, n_levels, H, outs, st);
-        case FDAS_BF16: return run_sums<__bf16>(p, plane, n, n_levels, H, outs, st);
-        case FDAS_FP64: return run_sums<double>(p, plane, n, n_levels, H, outs, st);
+        case FDAS_FP32: return run_sums<float, false>(p, plane, n, n_levels, H, outs, nullptr, st);
+        case FDAS_BF16: return run_sums<__bf16, false>(p, plane, n, n_levels, H, outs, nullptr, st);
+        case FDAS_FP64: return run_sums<double, false>(p, plane, n, n_levels, H, outs, nullptr, st);
         default: return hipErrorInvalidValue;
     }
 }

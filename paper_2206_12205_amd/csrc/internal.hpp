@@ -120,6 +120,14 @@ hipError_t peak_marks(const fdas_plan_s &p, int64_t n, float thr, PeakMarks *mar
 // planes), then batch_peaks_finish: job i's peaks at out + i * capacity
 // (job = i), its count at n_found[i].
 size_t batch_peak_scratch_bytes(const fdas_plan_s &p);
+// Count, scan and write of one n-bin plane whose tile flags (flags, cflags)
+// a marking kernel set; counters in caller memory of peak_work_bytes(tiles).
+size_t peak_work_bytes(int64_t n_tiles);
+hipError_t peaks_finish_plane(const fdas_plan_s &p, const void *plane, int64_t n, float thr, const uint8_t *flags,
+                              const uint8_t *cflags, void *work, fdas_peak *out, int64_t capacity, int64_t *n_found,
+                              hipStream_t s);
+// Zeroes n bytes of tile and chunk flags (a kernel: graph-capturable).
+hipError_t peak_flags_clear(uint8_t *flags, int64_t n, hipStream_t s);
 hipError_t batch_peak_marks(const fdas_plan_s &p, void *scratch, float thr, PeakMarks *marks, hipStream_t s);
 hipError_t batch_peak_mark_pass(const fdas_plan_s &p, const void *planes, const PeakMarks &marks, hipStream_t s);
 hipError_t batch_peaks_finish(const fdas_plan_s &p, const void *planes, void *scratch, float thr, fdas_peak *out,
@@ -138,9 +146,10 @@ constexpr int kMaxHarmonics = 32;
 hipError_t launch_harmonic_sum(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,
                                hipStream_t st);
 // Sums for an increasing list of n_levels (<= 8) harmonic counts in one
-// pass, sum l to outs[l].
+// pass, sum l to outs[l]; marks (n_levels entries) or null: the peak tiles
+// of each sum flagged while it is stored.
 hipError_t launch_harmonic_sums(const fdas_plan_s &p, const void *plane, int64_t n, int n_levels, const int32_t *H,
-                                void *const *outs, hipStream_t st);
+                                void *const *outs, const PeakMarks *marks, hipStream_t st);
 // The same, also marking the peak tiles of the summed plane (marks from
 // peak_marks for its (n - 1) / n_harm + 1 bins).
 hipError_t launch_harmonic_sum_marked(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,

@@ -575,6 +575,58 @@ hipError_t launch_peaks(const fdas_plan_s &p, const void *plane, int64_t n, floa
     }
 }
 
+// Count, scan and write of one plane whose flags were set by a marking
+// kernel, with the counters in caller memory (work: peak_work_bytes).
+size_t peak_work_bytes(int64_t n_tiles) {
+    const int64_t n_chunks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
+    return up256((kPeakGrid + 1) * sizeof(int64_t)) + up256(kPeakGrid * sizeof(int32_t)) +
+           up256((size_t)n_tiles * sizeof(int32_t)) + up256((size_t)n_chunks * sizeof(int32_t));
+}
+
+template <class PT>
+hipError_t finish_plane(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, const uint8_t *flags,
+                        const uint8_t *cflags, void *work, fdas_peak *out, int64_t cap, int64_t *n_found,
+                        hipStream_t st) {
+    const int64_t n_cb = (n + kPeakTileCols - 1) / kPeakTileCols;
+    const int64_t n_tiles = n_cb * p.cfg.n_z;
+    const int64_t n_chunks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
+    unsigned char *b = static_cast<unsigned char *>(work);
+    size_t off = 0;
+    auto *wg_offsets = reinterpret_cast<int64_t *>(b + off);
+    off += up256((kPeakGrid + 1) * sizeof(int64_t));
+    auto *wg_totals = reinterpret_cast<int32_t *>(b + off);
+    off += up256(kPeakGrid * sizeof(int32_t));
+    auto *counts = reinterpret_cast<int32_t *>(b + off);
+    off += up256((size_t)n_tiles * sizeof(int32_t));
+    auto *block_counts = reinterpret_cast<int32_t *>(b + off);
+    ChunkSource<PT> src{plane, n, n_cb, n_tiles, nullptr, 0};
+    launch_finish<PT>(src, p.cfg.n_z, n_chunks, thr, flags, cflags, counts, block_counts, wg_totals, wg_offsets,
+                      nullptr, nullptr, n_found, out, cap, st);
+    return hipGetLastError();
+}
+
+hipError_t peaks_finish_plane(const fdas_plan_s &p, const void *plane, int64_t n, float thr, const uint8_t *flags,
+                              const uint8_t *cflags, void *work, fdas_peak *out, int64_t capacity, int64_t *n_found,
+                              hipStream_t st) {
+    switch (p.cfg.plane_dtype) {
+        case FDAS_FP32:
+            return finish_plane<float>(p, static_cast<const float *>(plane), n, thr, flags, cflags, work, out,
+                                       capacity, n_found, st);
+        case FDAS_BF16:
+            return finish_plane<unsigned short>(p, static_cast<const unsigned short *>(plane), n, thr, flags, cflags,
+                                                work, out, capacity, n_found, st);
+        case FDAS_FP64:
+            return finish_plane<double>(p, static_cast<const double *>(plane), n, thr, flags, cflags, work, out,
+                                        capacity, n_found, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t peak_flags_clear(uint8_t *flags, int64_t n, hipStream_t st) {
+    launch_clear(flags, n, st);
+    return hipGetLastError();
+}
+
 hipError_t peak_marks(const fdas_plan_s &p, int64_t n, float thr, PeakMarks *marks, hipStream_t st) {
     PeakScratch sc;
     if (!plane_scratch(p, n, &sc)) return hipErrorInvalidValue;

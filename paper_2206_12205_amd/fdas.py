@@ -94,6 +94,11 @@ def lib() -> ctypes.CDLL:
         L.fdas_harmonic_sum.argtypes = [P, P, I64, I32, P, P]
         L.fdas_harmonic_sum_peaks.argtypes = [P, P, I64, I32, P, ctypes.c_float, P, I64, P, P]
         L.fdas_harmonic_sums.argtypes = [P, P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(P), P]
+        L.fdas_harmonic_sums_peaks_workspace.argtypes = [P, I64, I32, ctypes.POINTER(I32),
+                                                         ctypes.POINTER(ctypes.c_size_t)]
+        L.fdas_harmonic_sums_peaks.argtypes = [P, P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(P),
+                                               ctypes.POINTER(ctypes.c_float), ctypes.POINTER(P), I64, P, P,
+                                               ctypes.c_size_t, P]
         L.fdas_band_max.argtypes = [P, P, I64, P, I32, P, P]
         L.fdas_prepare_workspace.argtypes = [I64, ctypes.POINTER(ctypes.c_size_t)]
         L.fdas_prepare.argtypes = [P, I64, P, P, ctypes.c_size_t, P]
@@ -403,6 +408,49 @@ class Plan:
         _check(lib().fdas_harmonic_sums(self._h, ctypes.c_void_p(plane.data_ptr()), n, len(hs), harr, parr,
                                         _stream_ptr(stream)), "fdas_harmonic_sums")
         return outs
+
+    def harmonic_sums_peaks_async(self, plane, n, n_harms, thresholds, outs, peaks, n_found, scratch,
+                                  stream=None):
+        """Enqueue fdas_harmonic_sums_peaks on raw device pointers: plane (an
+        n-bin plane), outs and peaks lists of device pointers, n_found a
+        device pointer to len(n_harms) int64, scratch a uint8 tensor of
+        harmonic_sums_peaks_bytes.  No host synchronisation."""
+        hs = [int(h) for h in n_harms]
+        harr = (ctypes.c_int32 * len(hs))(*hs)
+        oarr = (ctypes.c_void_p * len(hs))(*outs)
+        tarr = (ctypes.c_float * len(hs))(*[float(t) for t in thresholds])
+        parr = (ctypes.c_void_p * len(hs))(*[p for p, _ in peaks])
+        cap = peaks[0][1]
+        _check(lib().fdas_harmonic_sums_peaks(self._h, ctypes.c_void_p(plane), int(n), len(hs), harr, oarr, tarr,
+                                              parr, int(cap), ctypes.c_void_p(n_found),
+                                              ctypes.c_void_p(scratch.data_ptr()), scratch.numel(),
+                                              _stream_ptr(stream)), "fdas_harmonic_sums_peaks")
+
+    def harmonic_sums_peaks_bytes(self, n, n_harms):
+        hs = [int(h) for h in n_harms]
+        nb = ctypes.c_size_t(0)
+        _check(lib().fdas_harmonic_sums_peaks_workspace(self._h, int(n), len(hs), (ctypes.c_int32 * len(hs))(*hs),
+                                                        ctypes.byref(nb)), "fdas_harmonic_sums_peaks_workspace")
+        return nb.value
+
+    def harmonic_sums_peaks(self, plane, n_harms, thresholds, capacity=1 << 16, stream=None):
+        """Several harmonic sums in one pass with the thresholded peaks of
+        each (fdas_harmonic_sums_peaks) -> (list of sums, list of peaks dicts)."""
+        import torch
+        if plane.dim() != 2 or plane.shape[0] != self.n_z or plane.dtype != self.torch_plane_dtype() \
+                or not plane.is_contiguous():
+            raise ValueError("plane must be a contiguous (n_z, n) tensor of the plan's plane dtype")
+        n = plane.shape[1]
+        hs = [int(h) for h in n_harms]
+        outs = [torch.empty((self.n_z, (n - 1) // h + 1), dtype=plane.dtype, device=self.device) for h in hs]
+        pk = torch.empty((len(hs), max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
+        nf = torch.zeros(len(hs), dtype=torch.int64, device=self.device)
+        scr = torch.empty(max(self.harmonic_sums_peaks_bytes(n, hs), 1), dtype=torch.uint8, device=self.device)
+        self.harmonic_sums_peaks_async(plane.data_ptr(), n, hs, thresholds, [o.data_ptr() for o in outs],
+                                       [(pk[l].data_ptr(), int(capacity)) for l in range(len(hs))], nf.data_ptr(),
+                                       scr, stream)
+        found = nf.cpu().tolist()
+        return outs, [peak_records(pk[l], found[l], capacity) for l in range(len(hs))]
 
     def harmonic_sum_peaks(self, plane, n_harm, threshold, capacity=1 << 16, out=None, stream=None):
         """Harmonic sum and the thresholded peaks of the summed plane in one

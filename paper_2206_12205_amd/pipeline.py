@@ -121,7 +121,17 @@ class BatchSearch:
             for h in self.harmonics:
                 self.hpeaks_raw[h] = torch.empty((len(self.lengths), self.peak_capacity, 24), dtype=torch.uint8,
                                                  device=self.device)
-                self.hn_found[h] = torch.zeros(len(self.lengths), dtype=torch.int64, device=self.device)
+            # counts of one job's sums side by side (the call writes them together)
+            self.hn_found_all = torch.zeros((len(self.lengths), len(self.harmonics)), dtype=torch.int64,
+                                            device=self.device).t()
+            for l, h in enumerate(sorted(self.harmonics)):
+                self.hn_found[h] = self.hn_found_all[l]
+            # scratch of the fused sums-with-peaks call, for the longest job of any chunk
+            hs = sorted(self.harmonics)
+            need = 0
+            for pl, jobs, _, _ in self.chunks:
+                need = max(need, pl.harmonic_sums_peaks_bytes(max(self.lengths[i] for i in jobs), hs))
+            self.sums_scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
 
     def _chunk(self, jobs, cmax, knobs, common):
         pl = F.Plan(max_bins=cmax, max_jobs=len(jobs), device=self.device, **knobs, **common)
@@ -179,15 +189,14 @@ class BatchSearch:
             harr = (ctypes.c_int32 * len(hs))(*hs)
             sptr = [self.sum_buffer.data_ptr() + self.sum_offs[h] * esz for h in hs]
             parr = (ctypes.c_void_p * len(hs))(*sptr)
+            tarr = (ctypes.c_float * len(hs))(*[self.harmonics[h] for h in hs])
             for k, (i, po) in enumerate(zip(jobs, offs)):   # harmonic sums of every job's plane, one pass
-                F._check(L.fdas_harmonic_sums(pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz),
-                                              self.lengths[i], len(hs), harr, parr, s), "fdas_harmonic_sums")
-                for h, p_h in zip(hs, sptr):
-                    F._check(L.fdas_peaks(pl._h, ctypes.c_void_p(p_h), (self.lengths[i] - 1) // h + 1,
-                                          float(self.harmonics[h]),
-                                          ctypes.c_void_p(self.hpeaks_raw[h][slot0 + k].data_ptr()),
-                                          self.peak_capacity, ctypes.c_void_p(self.hn_found[h][slot0 + k:].data_ptr()),
-                                          s), "fdas_peaks")
+                pkarr = (ctypes.c_void_p * len(hs))(*[self.hpeaks_raw[h][slot0 + k].data_ptr() for h in hs])
+                F._check(L.fdas_harmonic_sums_peaks(
+                    pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz), self.lengths[i], len(hs), harr, parr,
+                    tarr, pkarr, self.peak_capacity, ctypes.c_void_p(self.hn_found_all[:, slot0 + k].data_ptr()),
+                    ctypes.c_void_p(self.sums_scratch.data_ptr()), self.sums_scratch.numel(), s),
+                    "fdas_harmonic_sums_peaks")
 
     def capture(self, spectra, threshold, find_peaks=True, fused=True):
         """Record one pass (run) into a HIP graph and return it
@@ -230,9 +239,9 @@ def search_series(plan, series, threshold, harmonics=(1, 2, 4, 8, 16), capacity=
     threshold  a float, or a dict H -> float (noise powers of a sum of H
                normalised powers have mean H)
     Steps: the normalised spectrum (fdas_prepare), the plane with its
-    thresholded peaks (fdas_correlate_peaks), every sum over H > 1 harmonics
-    in one pass (fdas_harmonic_sums) and the thresholded peaks of each sum
-    (fdas_peaks).  Returns (spectrum, plane, {H: peaks dict}).
+    thresholded peaks (fdas_correlate_peaks), and every sum over H > 1
+    harmonics in one pass with the thresholded peaks of each
+    (fdas_harmonic_sums_peaks).  Returns (spectrum, plane, {H: peaks dict}).
     """
     spec = F.prepare(series, stream=stream)
     thr = (lambda h: float(threshold[h])) if isinstance(threshold, dict) else (lambda h: float(threshold))
@@ -240,6 +249,6 @@ def search_series(plan, series, threshold, harmonics=(1, 2, 4, 8, 16), capacity=
     found = {1: pk1} if 1 in harmonics else {}
     hs = sorted(h for h in set(harmonics) if h > 1)
     if hs:
-        for h, S in zip(hs, plan.harmonic_sums(plane, hs, stream=stream)):
-            found[h] = plan.peaks(S, thr(h), capacity=capacity, stream=stream)
+        _, lists = plan.harmonic_sums_peaks(plane, hs, [thr(h) for h in hs], capacity=capacity, stream=stream)
+        found.update(zip(hs, lists))
     return spec, plane, found

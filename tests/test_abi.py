@@ -133,6 +133,13 @@ def test_layout_and_workspace_checks_on_host():
         assert L.fdas_harmonic_sums(h, fake, 100, 9, H3, O3, None) == F.E_INVALID
         assert L.fdas_harmonic_sums(h, fake, 4097, 3, H3, O3, None) == F.E_INVALID
         assert L.fdas_harmonic_sums(h, None, 100, 3, H3, O3, None) == F.E_INVALID
+        sb = ctypes.c_size_t(0)
+        assert L.fdas_harmonic_sums_peaks_workspace(h, 100, 3, H3, ctypes.byref(sb)) == F.OK and sb.value > 0
+        assert L.fdas_harmonic_sums_peaks_workspace(h, 100, 3, Hbad, ctypes.byref(sb)) == F.E_INVALID
+        T3 = (ctypes.c_float * 3)(1.0, 2.0, 3.0)
+        assert L.fdas_harmonic_sums_peaks(h, fake, 100, 3, H3, O3, T3, O3, 5, nf, fake, 1, None) == F.E_WORKSPACE
+        assert L.fdas_harmonic_sums_peaks(h, fake, 100, 3, H3, O3, None, O3, 5, nf, fake, 1 << 20, None) \
+            == F.E_INVALID
         # harmonic sum with peaks: argument checks only
         assert L.fdas_harmonic_sum_peaks(h, fake, 100, 0, fake, 1.0, fake, 5, nf, None) == F.E_INVALID
         assert L.fdas_harmonic_sum_peaks(h, fake, 100, 33, fake, 1.0, fake, 5, nf, None) == F.E_INVALID

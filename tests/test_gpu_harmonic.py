@@ -161,6 +161,30 @@ def test_harmonic_sums_one_pass_equal_single_sums(dev, pd, hs):
         assert torch.equal(g.view(ints), want.view(ints)), f"H={h}"
 
 
+@pytest.mark.parametrize("pd", ["fp32", "bf16", "fp64"])
+@pytest.mark.parametrize("hs", [(2, 4, 8, 16), (1, 3, 32), (5,)])
+def test_harmonic_sums_peaks_one_pass(dev, pd, hs):
+    """fdas_harmonic_sums_peaks: the sums bitwise those of fdas_harmonic_sum,
+    and each sum's list exactly the oracle's peaks of that sum (thresholds
+    above the noise, low, negative and NaN across the levels)."""
+    import torch
+    say(f"[harmonic] one-pass sums with peaks {pd} {hs}")
+    sp = synth.config1(0)
+    compute = "fp64" if pd == "fp64" else "fp32"
+    pl = plan(dev, max_bins=sp.spec.size, z_min=C1["z_min"], z_step=C1["z_step"], n_z=C1["n_z"],
+              n_taps=C1["n_taps"], seg_len=C1["seg_len"], compute=compute, plane_dtype=pd)
+    P = pl.correlate(torch.from_numpy(sp.spec).to(dev))
+    ints = {2: torch.int16, 4: torch.int32, 8: torch.int64}[P.element_size()]
+    for thrs in ([2.0 * h + 6.0 for h in hs], [3.0] * len(hs), [-1.0] + [float("nan")] * (len(hs) - 1)):
+        sums, lists = pl.harmonic_sums_peaks(P, hs, thrs, capacity=1 << 20)
+        for h, thr, S, got in zip(hs, thrs, sums, lists):
+            want = pl.harmonic_sum(P, h)
+            assert torch.equal(S.view(ints), want.view(ints)), f"H={h}"
+            j, r, pw = OK_PEAKS.peaks(host(want), thr)
+            assert got["n_found"] == len(j), f"H={h} thr={thr}: {got['n_found']} vs {len(j)}"
+            assert np.array_equal(got["z_idx"], j) and np.array_equal(got["r"], r), f"H={h} thr={thr}"
+
+
 def test_harmonic_series_of_chirps_on_the_gpu(dev):
     """The sum at the fundamental's cell of a noise-free harmonic series of
     chirps is the sum of their matched powers (the oracle pin's physics),
@@ -213,3 +237,8 @@ def test_single_dm_bf16_plane_sampled_rows(dev):
     sums = pl.harmonic_sums(P, (2, 4, 8, 16))
     for h, g in zip((2, 4, 8, 16), sums):
         assert torch.equal(g.view(torch.int16), pl.harmonic_sum(P, h).view(torch.int16)), f"H={h}"
+    sums, lists = pl.harmonic_sums_peaks(P, (2, 4, 8, 16), [c["threshold"] + 10.0 * k for k in (1, 2, 3, 4)],
+                                         capacity=1 << 20)
+    for h, S, got, thr in zip((2, 4, 8, 16), sums, lists, [c["threshold"] + 10.0 * k for k in (1, 2, 3, 4)]):
+        ref = pl.peaks(pl.harmonic_sum(P, h), thr, capacity=1 << 20)
+        assert got["n_found"] == ref["n_found"] and np.array_equal(got["r"], ref["r"]), f"H={h}"
