@@ -175,3 +175,63 @@ def test_band_max_against_brute_force_with_ties_nan_and_clipping():
             assert (z[k], r[k]) == (-1, -1) and np.isnan(p[k])
         else:
             assert (z[k], r[k], p[k]) == best
+
+
+# --- margins: pinned by hand-built planes and by what a margin means --------
+
+def test_margins_hand_built():
+    """Gaps worked out by hand: threshold gap, gap to each of the 8
+    neighbours, edge and corner cells, and the max(P, 1) floor."""
+    P = np.array([[1.0, 2.0, 3.0, 0.0],
+                  [4.0, 10.0, 7.5, 0.0],
+                  [0.0, 9.0, 2.0, 0.25]])
+    # centre cell 10 (thr 6): threshold gap 4; nearest neighbour 9 (below
+    # it, a following neighbour) -> gap 1 -> 1 / 10
+    # corner (0, 0) = 1 (thr 0.5): neighbours 2, 4, 10 -> gaps 1, 3, 9;
+    # threshold gap 0.5 is the smallest; floor max(1, 1) = 1
+    # edge (0, 2) = 3 (thr 0): neighbours 2, 0, 10, 7.5, 0 -> smallest |3 - 2| = 1
+    # corner (2, 3) = 0.25 (thr 0.2): threshold gap 0.05, neighbours 7.5, 0,
+    # 2 -> 0.25; floor max(0.25, 1) = 1 -> 0.05 (not 0.05 / 0.25)
+    got = peaks.margins(P, [1, 0, 0, 2], [1, 0, 2, 3], 6.0)
+    assert got[0] == pytest.approx(0.1, abs=1e-15)
+    assert peaks.margins(P, [0], [0], 0.5)[0] == pytest.approx(0.5, abs=1e-15)
+    assert peaks.margins(P, [0], [2], 0.0)[0] == pytest.approx(1.0 / 3.0, abs=1e-15)
+    assert peaks.margins(P, [2], [3], 0.2)[0] == pytest.approx(0.05, abs=1e-15)
+    # each of the 8 neighbours in turn is the closest one
+    for dj in (-1, 0, 1):
+        for dr in (-1, 0, 1):
+            if dj == 0 and dr == 0:
+                continue
+            Q = np.full((3, 3), 1.0)
+            Q[1, 1] = 8.0
+            Q[1 + dj, 1 + dr] = 7.75
+            assert peaks.margins(Q, [1], [1], 2.0)[0] == pytest.approx(0.25 / 8.0, abs=1e-15), (dj, dr)
+    # threshold gap smaller than every neighbour gap
+    Q = np.full((3, 3), 1.0)
+    Q[1, 1] = 8.0
+    assert peaks.margins(Q, [1], [1], 7.9)[0] == pytest.approx(0.1 / 8.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_margins_is_the_decrease_that_removes_a_peak(seed):
+    """For every peak the margin m is the smallest relative decrease that
+    un-peaks it: lowering the cell by 0.999 m max(P, 1) keeps it a peak,
+    lowering it by 1.001 m max(P, 1) removes it (it falls to the threshold or
+    to a neighbour).  Checked through the peak finder, edges and corners
+    included."""
+    g = np.random.default_rng(100 + seed)
+    P = np.round(g.exponential(2.0, size=(5, 9)), 2) + g.uniform(0, 1e-3, size=(5, 9))
+    if seed % 2:
+        P *= 0.3                      # many cells below 1: the max(P, 1) floor matters
+    thr = float(np.quantile(P, 0.4))
+    j, r, _ = peaks.peaks(P, thr)
+    assert len(j) > 0
+    m = peaks.margins(P, j, r, thr)
+    assert np.all(m > 0)
+    for jj, rr, mm in zip(j, r, m):
+        step = mm * max(P[jj, rr], 1.0)
+        for f, stays in ((0.999, True), (1.001, False)):
+            Q = P.copy()
+            Q[jj, rr] -= f * step
+            qj, qr, _ = peaks.peaks(Q, thr)
+            assert ((jj, rr) in set(zip(qj.tolist(), qr.tolist()))) == stays, (jj, rr, f)
