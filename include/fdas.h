@@ -155,7 +155,12 @@ typedef struct {
     size_t tables_bytes;
 } fdas_layout;
 
-/* Create a plan (host only, no device work).  Validates the configuration:
+/* Create a plan (host only, no device work).  The plan fixes what the
+ * search correlates with: the bank of acceleration templates the astronomer
+ * chooses (z grid and taps, Section "Detailed explanation": the templates
+ * are chosen per search and made once, Section "Template conversion"), the
+ * overlap-save segment length and the precision form (Section "Updating the
+ * pipeline to bfloat16").  Validates the configuration:
  * FDAS_E_INVALID for n_z < 1, odd or < 2 M, L not a power of two or not in
  * [1024, 16384], M >= L, max_bins < 1, z_step <= 0 with n_z > 1, a plane
  * dtype the compute dtype cannot produce; FDAS_E_UNSUPPORTED for FP8 and for
@@ -220,7 +225,10 @@ int fdas_prepare(const float *series, int64_t n_t, void *spectrum, void *workspa
  * the plane of this w. */
 int fdas_make_templates_jerk(fdas_plan_t plan, double w, void *stream);
 
-/* The f-fdot plane of one spectrum.
+/* The f-fdot plane of one spectrum (Section "Detailed explanation": the
+ * normalised spectrum correlated with every template by overlap-save --
+ * segment transform, product with each template's transform, inverse
+ * transform, |.|^2, the contaminated edges of each segment discarded).
  *   spectrum  device, n_bins complex64 values (interleaved re, im floats)
  *   n_bins    N, 1 <= N <= max_bins
  *   plane     device, n_z x N row-major cells of the plan's plane dtype
@@ -284,13 +292,25 @@ int fdas_tune(const fdas_config *cfg, const void *spectrum, int64_t n_bins, void
  * follows it (edge cells compare only neighbours that exist; NaN is never a
  * peak).  Peaks are written to out (device, capacity entries) in (z_idx, r)
  * order with job = 0; the true count goes to *n_found (device int64).  When
- * the count exceeds capacity the first capacity peaks are written and the
- * caller sees it by comparing *n_found with capacity (the call itself cannot
- * know without a device synchronisation and returns FDAS_OK).  The plane
+ * the count exceeds capacity the first capacity peaks are written; the call
+ * itself cannot know without a device synchronisation and returns FDAS_OK,
+ * and fdas_peaks_check then returns FDAS_E_CAPACITY.  The plane
  * pointer needs only the alignment of its element type (a job's plane inside
  * a batch buffer may start anywhere); out 16-byte, n_found 8-byte aligned. */
 int fdas_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, float threshold,
                fdas_peak *out, int64_t capacity, int64_t *n_found, void *stream);
+
+/* Overflow check of peak lists (synchronous; the one call here that waits
+ * for the device).  The peak calls cannot see an overflow without a device
+ * synchronisation, so they return FDAS_OK and leave the first capacity
+ * entries and the true count; this call waits for the work enqueued on
+ * stream, copies the n_lists true counts from n_found (device, 8-byte
+ * aligned int64) to counts (host, n_lists int64) and returns FDAS_E_CAPACITY
+ * when a count exceeds capacity (the lists then hold their first capacity
+ * peaks), FDAS_OK otherwise, FDAS_E_INVALID for null pointers, n_lists < 1
+ * or capacity < 0.  The Python binding makes this check after every peak
+ * call and raises on FDAS_E_CAPACITY unless truncation is asked for. */
+int fdas_peaks_check(const int64_t *n_found, int32_t n_lists, int64_t capacity, int64_t *counts, void *stream);
 
 /* Plane and peaks of one spectrum in one call: the plane fdas_correlate
  * writes and exactly the list and count fdas_peaks then gives for it (same

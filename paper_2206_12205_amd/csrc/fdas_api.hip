@@ -67,6 +67,17 @@ const char *fdas_strerror(int s) {
 
 int fdas_last_hip_error(void) { return g_last_hip; }
 
+int fdas_peaks_check(const int64_t *n_found, int32_t n_lists, int64_t capacity, int64_t *counts, void *stream) {
+    if (!n_found || !counts || n_lists < 1 || capacity < 0 || !aligned8(n_found)) return FDAS_E_INVALID;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(counts, n_found, sizeof(int64_t) * (size_t)n_lists, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e);
+    for (int32_t i = 0; i < n_lists; ++i)
+        if (counts[i] > capacity) return FDAS_E_CAPACITY;
+    return FDAS_OK;
+}
+
 int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes) {
     if (!cfg || !out || !workspace_bytes) return FDAS_E_INVALID;
     *out = nullptr;

@@ -115,19 +115,20 @@ k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, d
         if (r < nh) hs_io<PT>::put(o + r, acc[i]);
     }
     if constexpr (kMark) {
-        // per peak tile (1024 fundamentals) one compare of the largest kept
-        // sum (NaN sums are never above)
+        // per peak tile (1024 fundamentals) the OR of one compare per kept
+        // sum: a NaN sum is never above and cannot hide another sum of the
+        // tile (a running maximum would turn NaN at the first NaN)
         constexpr int kPerTile = kPeakTileCols / kHsThreads;
         static_assert(kHsPerThread % kPerTile == 0, "whole tiles per workgroup");
+        const A bound = hs_io<PT>::mark_bound(m.thr);
 #pragma unroll
         for (int t = 0; t < kHsPerThread / kPerTile; ++t) {
-            A mx = acc[t * kPerTile];
+            bool above = false;
 #pragma unroll
-            for (int i = t * kPerTile + 1; i < (t + 1) * kPerTile; ++i)
-                if (r0 + i * kHsThreads < nh) mx = mx > acc[i] ? mx : acc[i];
+            for (int i = t * kPerTile; i < (t + 1) * kPerTile; ++i)
+                above |= (r0 + i * kHsThreads < nh) & (acc[i] > bound);
             const int64_t rt = rb + (int64_t)t * kPeakTileCols;
-            if (r0 + t * kPerTile * kHsThreads < nh && mx > hs_io<PT>::mark_bound(m.thr))
-                mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)rt, (int)rt);
+            if (above) mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)rt, (int)rt);
         }
     }
 }
@@ -149,22 +150,23 @@ struct SumLevels {
 };
 
 // kMark: each thread flags, per peak tile of a sum it writes, the tile when
-// its largest sum there passes the threshold lowered by the rounding bound
+// one of its sums there passes the threshold lowered by the rounding bound
 // (flags may be a superset).
 template <class PT, bool kMark>
 __device__ __forceinline__ void mark_sums(const typename hs_io<PT>::acc (&acc)[kHsPerThread], int64_t r0,
                                           int64_t rb, int64_t lim, int j, const PeakMarks &m) {
     using A = typename hs_io<PT>::acc;
     constexpr int kPerTile = kPeakTileCols / kHsThreads;
+    const A bound = hs_io<PT>::mark_bound(m.thr);
 #pragma unroll
     for (int t = 0; t < kHsPerThread / kPerTile; ++t) {
         if (r0 + t * kPerTile * kHsThreads >= lim) break;
-        A mx = acc[t * kPerTile];
+        bool above = false;   // OR of per-sum compares: a NaN sum hides no other
 #pragma unroll
-        for (int i = t * kPerTile + 1; i < (t + 1) * kPerTile; ++i)
-            if (r0 + i * kHsThreads < lim) mx = mx > acc[i] ? mx : acc[i];
+        for (int i = t * kPerTile; i < (t + 1) * kPerTile; ++i)
+            above |= (r0 + i * kHsThreads < lim) & (acc[i] > bound);
         const int64_t rt = rb + (int64_t)t * kPeakTileCols;
-        if (mx > hs_io<PT>::mark_bound(m.thr)) mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)rt, (int)rt);
+        if (above) mark_run(m, (uint32_t)j * (uint32_t)m.n_cb, 0, (int)rt, (int)rt);
     }
 }
 

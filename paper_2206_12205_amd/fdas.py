@@ -61,6 +61,16 @@ class FdasError(RuntimeError):
         self.status = status
 
 
+class PeakCapacityError(FdasError):
+    """FDAS_E_CAPACITY: a peak list overflowed.  `result` holds what the call
+    would have returned (every list with its first `capacity` peaks and its
+    true n_found, flagged truncated)."""
+
+    def __init__(self, what: str, result):
+        super().__init__(E_CAPACITY, what)
+        self.result = result
+
+
 _lib = None
 
 
@@ -106,6 +116,7 @@ def lib() -> ctypes.CDLL:
         L.fdas_make_templates_jerk.argtypes = [P, D, P]
         L.fdas_refine.argtypes = [P, I64, I32, P, P, P, P, P, I32, I32, D, D, P]
         L.fdas_refine_backward.argtypes = [P, I64, I32, P, P, P, P, P, I32, P]
+        L.fdas_peaks_check.argtypes = [P, I32, I64, ctypes.POINTER(I64), P]
         L.fdas_strerror.argtypes = [ctypes.c_int]
         L.fdas_strerror.restype = ctypes.c_char_p
         L.fdas_last_hip_error.restype = ctypes.c_int
@@ -143,6 +154,23 @@ def make_config(max_bins, z_min, z_step, n_z, n_taps, seg_len=0, compute="fp32",
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
     return FdasConfig(int(max_bins), float(z_min), float(z_step), int(n_z), int(n_taps),
                       int(seg_len), c, pd, int(z_chunk), a, int(max_jobs))
+
+
+def peak_counts(n_found, n_lists, capacity, stream=None):
+    """True counts of n_lists peak lists (fdas_peaks_check: waits for the
+    stream, copies the device counts) -> (list of counts, overflowed)."""
+    counts = (ctypes.c_int64 * int(n_lists))()
+    st = lib().fdas_peaks_check(ctypes.c_void_p(n_found.data_ptr()), int(n_lists), int(capacity), counts,
+                                _stream_ptr(stream))
+    if st not in (OK, E_CAPACITY):
+        raise FdasError(st, "fdas_peaks_check")
+    return [int(v) for v in counts], st == E_CAPACITY
+
+
+def _capacity_result(what, overflowed, truncate, result):
+    if overflowed and not truncate:
+        raise PeakCapacityError(what, result)
+    return result
 
 
 def peak_records(raw, found, capacity):
@@ -274,8 +302,10 @@ class Plan:
         po = self.batch_offsets[i][1]
         return planes[po:po + self.n_z * nb].view(self.n_z, nb)
 
-    def peaks(self, plane, threshold, capacity=1 << 16, stream=None):
-        """Peaks of a plane -> dict of numpy arrays z_idx, r, power and n_found."""
+    def peaks(self, plane, threshold, capacity=1 << 16, stream=None, truncate=False):
+        """Peaks of a plane -> dict of numpy arrays z_idx, r, power and n_found.
+        More peaks than capacity raises PeakCapacityError (the first ones and
+        the true count in its result) unless truncate is set."""
         import torch
         n = plane.shape[1]
         out = torch.empty((max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
@@ -284,11 +314,13 @@ class Plan:
                                 float(threshold), ctypes.c_void_p(out.data_ptr()),
                                 int(capacity), ctypes.c_void_p(nf.data_ptr()),
                                 _stream_ptr(stream)), "fdas_peaks")
-        return peak_records(out, int(nf.item()), capacity)
+        (found,), over = peak_counts(nf, 1, capacity, stream)
+        return _capacity_result("fdas_peaks", over, truncate, peak_records(out, found, capacity))
 
-    def correlate_peaks(self, spectrum, threshold, capacity=1 << 16, plane=None, stream=None):
+    def correlate_peaks(self, spectrum, threshold, capacity=1 << 16, plane=None, stream=None, truncate=False):
         """Plane and thresholded peaks of a spectrum in one call
-        (fdas_correlate_peaks) -> (plane, peaks dict as from peaks())."""
+        (fdas_correlate_peaks) -> (plane, peaks dict as from peaks());
+        overflow as for peaks()."""
         import torch
         if spectrum.dtype != torch.complex64 or not spectrum.is_contiguous():
             raise ValueError("spectrum must be a contiguous complex64 tensor")
@@ -305,7 +337,9 @@ class Plan:
                                           ctypes.c_void_p(out.data_ptr()), int(capacity),
                                           ctypes.c_void_p(nf.data_ptr()), _stream_ptr(stream)),
                "fdas_correlate_peaks")
-        return plane, peak_records(out, int(nf.item()), capacity)
+        (found,), over = peak_counts(nf, 1, capacity, stream)
+        return _capacity_result("fdas_correlate_peaks", over, truncate,
+                                (plane, peak_records(out, found, capacity)))
 
     def batch_peaks_scratch(self):
         """Device scratch for fdas_correlate_batch_peaks on the stored batch
@@ -342,9 +376,11 @@ class Plan:
                                                 ctypes.c_void_p(scr.data_ptr()), scr.numel(),
                                                 _stream_ptr(stream)), "fdas_correlate_batch_peaks")
 
-    def correlate_batch_peaks(self, spectra, threshold, capacity=1 << 12, planes=None, stream=None):
+    def correlate_batch_peaks(self, spectra, threshold, capacity=1 << 12, planes=None, stream=None,
+                              truncate=False):
         """Planes of the stored batch and every job's peaks
-        (fdas_correlate_batch_peaks) -> (planes, list of peaks dicts)."""
+        (fdas_correlate_batch_peaks) -> (planes, list of peaks dicts);
+        overflow of any job's list as for peaks()."""
         import torch
         if planes is None:
             planes = torch.empty(self.batch_cells, dtype=self.torch_plane_dtype(), device=self.device)
@@ -352,8 +388,9 @@ class Plan:
         out = torch.empty((n_jobs, max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
         nf = torch.zeros(n_jobs, dtype=torch.int64, device=self.device)
         self.correlate_batch_peaks_async(spectra, planes, threshold, out, nf, stream)
-        found = nf.cpu().tolist()
-        return planes, [peak_records(out[i], found[i], capacity) for i in range(n_jobs)]
+        found, over = peak_counts(nf, n_jobs, capacity, stream)
+        return _capacity_result("fdas_correlate_batch_peaks", over, truncate,
+                                (planes, [peak_records(out[i], found[i], capacity) for i in range(n_jobs)]))
 
     def band_max(self, plane, windows, stream=None):
         """Highest cell of each window (z_lo, z_hi, r_lo, r_hi) of a plane
@@ -433,9 +470,10 @@ class Plan:
                                                         ctypes.byref(nb)), "fdas_harmonic_sums_peaks_workspace")
         return nb.value
 
-    def harmonic_sums_peaks(self, plane, n_harms, thresholds, capacity=1 << 16, stream=None):
+    def harmonic_sums_peaks(self, plane, n_harms, thresholds, capacity=1 << 16, stream=None, truncate=False):
         """Several harmonic sums in one pass with the thresholded peaks of
-        each (fdas_harmonic_sums_peaks) -> (list of sums, list of peaks dicts)."""
+        each (fdas_harmonic_sums_peaks) -> (list of sums, list of peaks
+        dicts); overflow of any list as for peaks()."""
         import torch
         if plane.dim() != 2 or plane.shape[0] != self.n_z or plane.dtype != self.torch_plane_dtype() \
                 or not plane.is_contiguous():
@@ -449,12 +487,15 @@ class Plan:
         self.harmonic_sums_peaks_async(plane.data_ptr(), n, hs, thresholds, [o.data_ptr() for o in outs],
                                        [(pk[l].data_ptr(), int(capacity)) for l in range(len(hs))], nf.data_ptr(),
                                        scr, stream)
-        found = nf.cpu().tolist()
-        return outs, [peak_records(pk[l], found[l], capacity) for l in range(len(hs))]
+        found, over = peak_counts(nf, len(hs), capacity, stream)
+        return _capacity_result("fdas_harmonic_sums_peaks", over, truncate,
+                                (outs, [peak_records(pk[l], found[l], capacity) for l in range(len(hs))]))
 
-    def harmonic_sum_peaks(self, plane, n_harm, threshold, capacity=1 << 16, out=None, stream=None):
+    def harmonic_sum_peaks(self, plane, n_harm, threshold, capacity=1 << 16, out=None, stream=None,
+                           truncate=False):
         """Harmonic sum and the thresholded peaks of the summed plane in one
-        call (fdas_harmonic_sum_peaks) -> (summed plane, peaks dict as from peaks())."""
+        call (fdas_harmonic_sum_peaks) -> (summed plane, peaks dict as from
+        peaks()); overflow as for peaks()."""
         import torch
         if plane.dim() != 2 or plane.shape[0] != self.n_z or plane.dtype != self.torch_plane_dtype() \
                 or not plane.is_contiguous():
@@ -472,7 +513,8 @@ class Plan:
                                              ctypes.c_void_p(pk.data_ptr()), int(capacity),
                                              ctypes.c_void_p(nf.data_ptr()), _stream_ptr(stream)),
                "fdas_harmonic_sum_peaks")
-        return out, peak_records(pk, int(nf.item()), capacity)
+        (found,), over = peak_counts(nf, 1, capacity, stream)
+        return _capacity_result("fdas_harmonic_sum_peaks", over, truncate, (out, peak_records(pk, found, capacity)))
 
     def bank(self):
         """Template bank as a complex tensor view (FP32/FP64), raw bfloat16

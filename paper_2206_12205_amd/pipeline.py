@@ -217,9 +217,11 @@ class BatchSearch:
             self.run(spectra, threshold, find_peaks=find_peaks, fused=fused)
         return g
 
-    def peaks(self, i, H=1):
+    def peaks(self, i, H=1, truncate=False):
         """Peak list of job i after run() (host copy): dict of z_idx, r, power,
-        n_found; H > 1: the peaks of its sum over H harmonics."""
+        n_found; H > 1: the peaks of its sum over H harmonics.  A list that
+        overflowed peak_capacity raises fdas.PeakCapacityError (its first
+        entries and true count in the error's result) unless truncate is set."""
         import numpy as np
         raw_all, nf = (self.peaks_raw, self.n_found) if H == 1 else (self.hpeaks_raw[H], self.hn_found[H])
         found = int(nf[self.slot[i]].item())
@@ -227,8 +229,11 @@ class BatchSearch:
         raw = raw_all[self.slot[i], :k].cpu().numpy()
         rec = raw.view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
                                  ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
-        return {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(), "power": rec["power"].copy(),
-                "n_found": found}
+        res = {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(), "power": rec["power"].copy(),
+               "n_found": found, "truncated": found > self.peak_capacity}
+        if res["truncated"] and not truncate:
+            raise F.PeakCapacityError(f"job {i} peaks (H = {H})", res)
+        return res
 
 
 def search_series(plan, series, threshold, harmonics=(1, 2, 4, 8, 16), capacity=1 << 16, stream=None):

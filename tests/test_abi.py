@@ -191,6 +191,20 @@ def test_prepare_argument_checks():
     assert L.fdas_prepare(fake, 1024, fake, None, 1 << 20, None) == F.E_WORKSPACE
 
 
+def test_peaks_check_argument_checks_on_host():
+    """fdas_peaks_check (the synchronous overflow check): bad arguments are
+    refused before any device call."""
+    import ctypes
+    L = F.lib()
+    counts = (ctypes.c_int64 * 4)()
+    fake = ctypes.c_void_p(0x10000)
+    assert L.fdas_peaks_check(None, 1, 5, counts, None) == F.E_INVALID
+    assert L.fdas_peaks_check(fake, 1, 5, None, None) == F.E_INVALID
+    assert L.fdas_peaks_check(fake, 0, 5, counts, None) == F.E_INVALID
+    assert L.fdas_peaks_check(fake, 1, -1, counts, None) == F.E_INVALID
+    assert L.fdas_peaks_check(ctypes.c_void_p(0x10004), 1, 5, counts, None) == F.E_INVALID
+
+
 def test_null_arguments():
     L = F.lib()
     assert L.fdas_plan(None, None, None) == F.E_INVALID

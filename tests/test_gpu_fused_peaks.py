@@ -89,7 +89,7 @@ def test_fused_single_matches_oracle(dev, kw, n):
     host = widen(ref)
     for thr, cap in ((12.0, 1 << 16), (3.0, 1 << 18), (3.0, 7), (-1.0, 1 << 22), (float("nan"), 16)):
         plane = torch.full_like(ref, float("nan"))
-        plane, got = pl.correlate_peaks(x, thr, capacity=cap, plane=plane)
+        plane, got = pl.correlate_peaks(x, thr, capacity=cap, plane=plane, truncate=True)
         assert torch.equal(plane.view(torch.int16 if plane.element_size() == 2 else torch.int32),
                            ref.view(torch.int16 if ref.element_size() == 2 else torch.int32)), "plane differs"
         assert_same_peaks(got, host, thr, cap, job=0, what=f"thr={thr} cap={cap}")
@@ -114,7 +114,7 @@ def test_fused_batch_matches_oracle(dev, kw):
     ref = pl.correlate_batch(spectra)
     for thr, cap in ((12.0, 1 << 14), (3.0, 33), (-1.0, 1 << 22), (float("nan"), 4)):
         planes = torch.full_like(ref, float("nan"))
-        planes, got = pl.correlate_batch_peaks(spectra, thr, capacity=cap, planes=planes)
+        planes, got = pl.correlate_batch_peaks(spectra, thr, capacity=cap, planes=planes, truncate=True)
         assert torch.equal(planes.view(torch.int16 if planes.element_size() == 2 else torch.int32),
                            ref.view(torch.int16 if ref.element_size() == 2 else torch.int32)), "planes differ"
         for i in range(len(LENGTHS)):

@@ -131,7 +131,7 @@ def test_harmonic_sum_peaks_fused(dev, pd, n_harm):
     ints = {2: torch.int16, 4: torch.int32, 8: torch.int64}[S.element_size()]
     for thr, cap in ((2.0 * n_harm + 6.0, 4096), (3.0, 17), (-1.0, 1 << 20), (float("nan"), 8)):
         out = torch.full_like(S, float("nan"))
-        S2, got = pl.harmonic_sum_peaks(P, n_harm, thr, capacity=cap, out=out)
+        S2, got = pl.harmonic_sum_peaks(P, n_harm, thr, capacity=cap, out=out, truncate=True)
         assert torch.equal(S2.view(ints), S.view(ints)), f"thr={thr}: summed plane differs"
         j, r, pw = OK_PEAKS.peaks(Sh, thr)
         k = min(len(j), cap)
@@ -242,3 +242,42 @@ def test_single_dm_bf16_plane_sampled_rows(dev):
     for h, S, got, thr in zip((2, 4, 8, 16), sums, lists, [c["threshold"] + 10.0 * k for k in (1, 2, 3, 4)]):
         ref = pl.peaks(pl.harmonic_sum(P, h), thr, capacity=1 << 20)
         assert got["n_found"] == ref["n_found"] and np.array_equal(got["r"], ref["r"]), f"H={h}"
+
+
+@pytest.mark.parametrize("pd", ["fp32", "bf16", "fp64"])
+def test_harmonic_marks_survive_nan_sums(dev, pd):
+    """NaN cells in the plane: a thread whose sums in one peak tile are
+    (above the threshold, NaN, below, below) must still flag the tile, so
+    both fused calls list exactly the oracle's peaks of the summed plane.
+    Each thread holds the fundamentals r0 + 256 i, four per 1024-bin tile."""
+    import torch
+    say(f"[harmonic] NaN sums beside peaks {pd}")
+    n_z, n = 5, 16384
+    compute = "fp64" if pd == "fp64" else "fp32"
+    pl = plan(dev, max_bins=n, z_min=-4.0, z_step=2.0, n_z=n_z, n_taps=64, seg_len=1024, compute=compute,
+              plane_dtype=pd)
+    g = np.random.default_rng(5)
+    base = g.uniform(0.0, 1.0, size=(n_z, n))
+    tdt = {"fp32": torch.float32, "bf16": torch.bfloat16, "fp64": torch.float64}[pd]
+    for H in (1, 3):
+        nh = (n - 1) // H + 1
+        Pn = base.copy()
+        cells = [(1, 100), (3, 1024 + 37), (2, 4096 + 700)]    # fundamentals in three tiles
+        for j, r in cells:
+            # row j of the sum is row j of the plane for z = 0 rows only; put
+            # the bright term on every row the harmonics of (j, r) read
+            for h in range(1, H + 1):
+                Pn[:, h * r] = 0.0
+            Pn[j, r] = 60.0
+            Pn[:, r + 256] = np.nan              # the same thread's next sum in that tile
+        P = torch.from_numpy(Pn).to(tdt).to(dev).contiguous()
+        S = pl.harmonic_sum(P, H)
+        Sh = host(S)
+        thr = 50.0
+        j, r, _ = OK_PEAKS.peaks(Sh, thr)
+        assert len(j) >= len(cells)
+        _, got = pl.harmonic_sum_peaks(P, H, thr, capacity=1 << 12)
+        assert np.array_equal(got["z_idx"], j) and np.array_equal(got["r"], r), f"H={H} single"
+        _, lists = pl.harmonic_sums_peaks(P, [H], [thr], capacity=1 << 12)
+        assert np.array_equal(lists[0]["z_idx"], j) and np.array_equal(lists[0]["r"], r), f"H={H} one-pass"
+        assert nh == S.shape[1]

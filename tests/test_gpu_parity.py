@@ -183,11 +183,30 @@ def test_peaks_exact_on_same_plane(dev, cfg1_oracle, plane_dtype):
         assert got["n_found"] == len(j)
         assert np.array_equal(got["z_idx"], j) and np.array_equal(got["r"], r)
         assert np.array_equal(got["power"].astype(np.float64), pw)
-    # capacity overflow: the first `capacity` peaks in order, true count reported
-    got = gpu_peaks_on(pl, plane, 6.0, cap=5)
+    # capacity overflow: FDAS_E_CAPACITY, the first `capacity` peaks in
+    # order and the true count (the wrapper raises after the count's D2H;
+    # fdas_peaks_check gives the same status to a C caller)
+    import ctypes
+    import torch
+    from paper_2206_12205_amd import fdas as F
     j, r, _ = OK_PEAKS.peaks(host, 6.0)
-    assert got["n_found"] == len(j) > 5
+    with pytest.raises(F.PeakCapacityError) as ei:
+        gpu_peaks_on(pl, plane, 6.0, cap=5)
+    assert ei.value.status == F.E_CAPACITY
+    got = ei.value.result
+    assert got["n_found"] == len(j) > 5 and got["truncated"]
     assert np.array_equal(got["r"], r[:5]) and np.array_equal(got["z_idx"], j[:5])
+    got = pl.peaks(plane, 6.0, capacity=5, truncate=True)
+    assert got["n_found"] == len(j) and np.array_equal(got["r"], r[:5])
+    out = torch.empty((5, 24), dtype=torch.uint8, device=plane.device)
+    nf = torch.zeros(1, dtype=torch.int64, device=plane.device)
+    L = F.lib()
+    assert L.fdas_peaks(pl._h, ctypes.c_void_p(plane.data_ptr()), plane.shape[1], 6.0,
+                        ctypes.c_void_p(out.data_ptr()), 5, ctypes.c_void_p(nf.data_ptr()), None) == F.OK
+    counts = (ctypes.c_int64 * 1)()
+    assert L.fdas_peaks_check(ctypes.c_void_p(nf.data_ptr()), 1, 5, counts, None) == F.E_CAPACITY
+    assert counts[0] == len(j)
+    assert L.fdas_peaks_check(ctypes.c_void_p(nf.data_ptr()), 1, len(j), counts, None) == F.OK
 
 
 def test_peaks_fp32_match_oracle_plane(dev, cfg1_oracle):
