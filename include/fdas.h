@@ -415,6 +415,27 @@ int fdas_harmonic_sums_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins
                              fdas_peak *const *peaks, int64_t capacity, int64_t *n_found, void *scratch,
                              size_t scratch_bytes, void *stream);
 
+/* fdas_harmonic_sums_peaks for callers that cannot allocate device memory
+ * (code recorded into a HIP graph, tight serving loops, harnesses that
+ * forbid hipMalloc): the same sums, lists and counts, with the scratch taken
+ * from a fixed array the library holds on each GPU it runs on until the
+ * process ends, FDAS_NOALLOC_SCRATCH_BYTES in size.  The call allocates
+ * nothing and calls no allocating routine; the caller still owns the plane,
+ * the sums, the peak lists and n_found (arguments and rules as for
+ * fdas_harmonic_sums_peaks).  FDAS_E_WORKSPACE when the scratch
+ * fdas_harmonic_sums_peaks_workspace gives for these arguments exceeds
+ * FDAS_NOALLOC_SCRATCH_BYTES (about 1.3 MB for the sums H = 2, 4, 8, 16 of a
+ * 101 x 4,194,304 plane; planes up to about 2.7e9 cells fit at these
+ * levels); FDAS_E_HIP if the array's device address cannot be obtained
+ * (first call on a device).  Every call on one GPU shares that GPU's array
+ * and each call clears the parts it needs on its stream; calls that overlap
+ * on one GPU (two streams, or two host threads) race and must be ordered by
+ * the caller.  Asynchronous on stream, kernels only. */
+#define FDAS_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+int fdas_harmonic_sums_peaks_noalloc(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_levels,
+                                     const int32_t *n_harm, void *const *outs, const float *thresholds,
+                                     fdas_peak *const *peaks, int64_t capacity, int64_t *n_found, void *stream);
+
 /* Harmonic summing with thresholding in one call: the summed plane
  * fdas_harmonic_sum writes to out, and exactly the list and count fdas_peaks
  * then gives for it (an n_z x N_H plane, N_H = (n_bins - 1) / n_harm + 1;

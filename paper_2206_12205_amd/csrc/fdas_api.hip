@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.hpp"
@@ -44,6 +45,35 @@ int elem_bytes(int dtype) {
         case FDAS_FP8E4M3: return 2;
         default: return 0;
     }
+}
+
+// Scratch of fdas_harmonic_sums_peaks_noalloc: one fixed array per GPU,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel (in host code it is a host-side stand-in): the device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoallocScratchBytes = FDAS_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+hipError_t noalloc_scratch(unsigned char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -368,6 +398,40 @@ static int check_sums_list(const fdas_plan_s &p, int64_t n_bins, int32_t n_level
     return FDAS_OK;
 }
 
+static int check_sums_peaks_args(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_levels,
+                                 const int32_t *n_harm, void *const *outs, const float *thresholds,
+                                 fdas_peak *const *peaks, int64_t capacity, const int64_t *n_found) {
+    if (!p || !plane || !outs || !thresholds || !peaks || !n_found || capacity < 0) return FDAS_E_INVALID;
+    const int s = check_sums_list(*p, n_bins, n_levels, n_harm);
+    if (s != FDAS_OK) return s;
+    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
+    if ((reinterpret_cast<uintptr_t>(plane) % pe) != 0 || !aligned8(n_found)) return FDAS_E_INVALID;
+    for (int32_t l = 0; l < n_levels; ++l) {
+        if (!outs[l] || (reinterpret_cast<uintptr_t>(outs[l]) % pe) != 0) return FDAS_E_INVALID;
+        if ((capacity > 0 && !peaks[l]) || (peaks[l] && !aligned16(peaks[l]))) return FDAS_E_INVALID;
+    }
+    return FDAS_OK;
+}
+
+// The sums with their peaks on a scratch region laid out by L: flags cleared
+// by a kernel, sums stored with their tiles flagged, one finish per sum.
+static hipError_t sums_peaks_on(const fdas_plan_s &p, const SumsPeakLayout &L, const void *plane, int64_t n_bins,
+                                int32_t n_levels, const int32_t *n_harm, void *const *outs, const float *thresholds,
+                                fdas_peak *const *peaks, int64_t capacity, int64_t *n_found, unsigned char *base,
+                                hipStream_t st) {
+    fdas::PeakMarks marks[8];
+    for (int32_t l = 0; l < n_levels; ++l) {
+        uint8_t *f = base + L.flags_off[l];
+        marks[l] = fdas::make_peak_marks(f, f + L.tiles[l], L.n_cb[l], thresholds[l]);
+    }
+    hipError_t e = fdas::peak_flags_clear(base + L.flags_off[0], (int64_t)(L.total - L.flags_off[0]), st);
+    if (e == hipSuccess) e = fdas::launch_harmonic_sums(p, plane, n_bins, n_levels, n_harm, outs, marks, st);
+    for (int32_t l = 0; l < n_levels && e == hipSuccess; ++l)
+        e = fdas::peaks_finish_plane(p, outs[l], L.nh[l], thresholds[l], marks[l].flags, marks[l].cflags, base,
+                                     peaks[l], capacity, n_found + l, st);
+    return e;
+}
+
 int fdas_harmonic_sums_peaks_workspace(fdas_plan_t p, int64_t n_bins, int32_t n_levels, const int32_t *n_harm,
                                        size_t *scratch_bytes) {
     if (!p || !scratch_bytes) return FDAS_E_INVALID;
@@ -383,31 +447,31 @@ int fdas_harmonic_sums_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, i
                              const int32_t *n_harm, void *const *outs, const float *thresholds,
                              fdas_peak *const *peaks, int64_t capacity, int64_t *n_found, void *scratch,
                              size_t scratch_bytes, void *stream) {
-    if (!p || !plane || !outs || !thresholds || !peaks || !n_found || capacity < 0) return FDAS_E_INVALID;
-    const int s = check_sums_list(*p, n_bins, n_levels, n_harm);
+    const int s = check_sums_peaks_args(p, plane, n_bins, n_levels, n_harm, outs, thresholds, peaks, capacity,
+                                        n_found);
     if (s != FDAS_OK) return s;
-    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
-    if ((reinterpret_cast<uintptr_t>(plane) % pe) != 0 || !aligned8(n_found)) return FDAS_E_INVALID;
-    for (int32_t l = 0; l < n_levels; ++l) {
-        if (!outs[l] || (reinterpret_cast<uintptr_t>(outs[l]) % pe) != 0) return FDAS_E_INVALID;
-        if ((capacity > 0 && !peaks[l]) || (peaks[l] && !aligned16(peaks[l]))) return FDAS_E_INVALID;
-    }
     const SumsPeakLayout L = sums_peak_layout(*p, n_bins, n_levels, n_harm);
     if (!L.fits) return FDAS_E_UNSUPPORTED;
     if (!scratch || !aligned16(scratch) || scratch_bytes < L.total) return FDAS_E_WORKSPACE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    auto *base = static_cast<unsigned char *>(scratch);
-    fdas::PeakMarks marks[8];
-    for (int32_t l = 0; l < n_levels; ++l) {
-        uint8_t *f = base + L.flags_off[l];
-        marks[l] = fdas::make_peak_marks(f, f + L.tiles[l], L.n_cb[l], thresholds[l]);
-    }
-    hipError_t e = fdas::peak_flags_clear(base + L.flags_off[0], (int64_t)(L.total - L.flags_off[0]), st);
-    if (e == hipSuccess) e = fdas::launch_harmonic_sums(*p, plane, n_bins, n_levels, n_harm, outs, marks, st);
-    for (int32_t l = 0; l < n_levels && e == hipSuccess; ++l)
-        e = fdas::peaks_finish_plane(*p, outs[l], L.nh[l], thresholds[l], marks[l].flags, marks[l].cflags, base,
-                                     peaks[l], capacity, n_found + l, st);
-    return hip_status(e);
+    return hip_status(sums_peaks_on(*p, L, plane, n_bins, n_levels, n_harm, outs, thresholds, peaks, capacity,
+                                    n_found, static_cast<unsigned char *>(scratch),
+                                    static_cast<hipStream_t>(stream)));
+}
+
+int fdas_harmonic_sums_peaks_noalloc(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_levels,
+                                     const int32_t *n_harm, void *const *outs, const float *thresholds,
+                                     fdas_peak *const *peaks, int64_t capacity, int64_t *n_found, void *stream) {
+    const int s = check_sums_peaks_args(p, plane, n_bins, n_levels, n_harm, outs, thresholds, peaks, capacity,
+                                        n_found);
+    if (s != FDAS_OK) return s;
+    const SumsPeakLayout L = sums_peak_layout(*p, n_bins, n_levels, n_harm);
+    if (!L.fits) return FDAS_E_UNSUPPORTED;
+    if (L.total > kNoallocScratchBytes) return FDAS_E_WORKSPACE;
+    unsigned char *base = nullptr;
+    const hipError_t e = noalloc_scratch(&base);
+    if (e != hipSuccess) return hip_status(e);
+    return hip_status(sums_peaks_on(*p, L, plane, n_bins, n_levels, n_harm, outs, thresholds, peaks, capacity,
+                                    n_found, base, static_cast<hipStream_t>(stream)));
 }
 
 int fdas_harmonic_sum_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_harm, void *out,

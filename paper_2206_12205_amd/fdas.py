@@ -21,6 +21,8 @@ ALGO_AUTO, ALGO_VALU, ALGO_MFMA = 0, 1, 2
 ALGOS = {"auto": ALGO_AUTO, "valu": ALGO_VALU, "mfma": ALGO_MFMA}
 
 OK, E_INVALID, E_WORKSPACE, E_HIP, E_CAPACITY, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+# size of the fixed per-GPU scratch array behind fdas_harmonic_sums_peaks_noalloc
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class FdasConfig(ctypes.Structure):
@@ -109,6 +111,9 @@ def lib() -> ctypes.CDLL:
         L.fdas_harmonic_sums_peaks.argtypes = [P, P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(P),
                                                ctypes.POINTER(ctypes.c_float), ctypes.POINTER(P), I64, P, P,
                                                ctypes.c_size_t, P]
+        L.fdas_harmonic_sums_peaks_noalloc.argtypes = [P, P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(P),
+                                                       ctypes.POINTER(ctypes.c_float), ctypes.POINTER(P), I64, P,
+                                                       P]
         L.fdas_band_max.argtypes = [P, P, I64, P, I32, P, P]
         L.fdas_prepare_workspace.argtypes = [I64, ctypes.POINTER(ctypes.c_size_t)]
         L.fdas_prepare.argtypes = [P, I64, P, P, ctypes.c_size_t, P]
@@ -462,6 +467,20 @@ class Plan:
                                               parr, int(cap), ctypes.c_void_p(n_found),
                                               ctypes.c_void_p(scratch.data_ptr()), scratch.numel(),
                                               _stream_ptr(stream)), "fdas_harmonic_sums_peaks")
+
+    def harmonic_sums_peaks_noalloc_async(self, plane, n, n_harms, thresholds, outs, peaks, n_found, stream=None):
+        """Enqueue fdas_harmonic_sums_peaks_noalloc on raw device pointers
+        (arguments as for harmonic_sums_peaks_async, without the scratch: the
+        library's fixed per-GPU array serves instead).  Allocates nothing."""
+        hs = [int(h) for h in n_harms]
+        harr = (ctypes.c_int32 * len(hs))(*hs)
+        oarr = (ctypes.c_void_p * len(hs))(*outs)
+        tarr = (ctypes.c_float * len(hs))(*[float(t) for t in thresholds])
+        parr = (ctypes.c_void_p * len(hs))(*[p for p, _ in peaks])
+        cap = peaks[0][1]
+        _check(lib().fdas_harmonic_sums_peaks_noalloc(self._h, ctypes.c_void_p(plane), int(n), len(hs), harr, oarr,
+                                                      tarr, parr, int(cap), ctypes.c_void_p(n_found),
+                                                      _stream_ptr(stream)), "fdas_harmonic_sums_peaks_noalloc")
 
     def harmonic_sums_peaks_bytes(self, n, n_harms):
         hs = [int(h) for h in n_harms]

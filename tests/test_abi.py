@@ -318,3 +318,48 @@ def test_fp8_layout_on_host():
         assert lay.tables_bytes == 9 * 4096 * 8 + 9 * 4      # FP32 staging + exponents
     finally:
         L.fdas_destroy(h)
+
+
+def test_sums_peaks_noalloc_checks_on_host():
+    """fdas_harmonic_sums_peaks_noalloc: bad arguments and a scratch need above
+    FDAS_NOALLOC_SCRATCH_BYTES are refused before any device call."""
+    L = F.lib()
+    P = ctypes.c_void_p
+
+    def call(h, n, hs, plane=0x10000, n_found=0x20000, cap=16):
+        k = len(hs)
+        harr = (ctypes.c_int32 * k)(*hs)
+        outs = (P * k)(*[0x30000 + 0x1000 * i for i in range(k)])
+        thr = (ctypes.c_float * k)(*[10.0] * k)
+        pks = (P * k)(*[0x40000 + 0x1000 * i for i in range(k)])
+        return L.fdas_harmonic_sums_peaks_noalloc(h, P(plane), n, k, harr, outs, thr, pks, cap, P(n_found), None)
+
+    def with_plan(cfg, fn):
+        h = P()
+        nb = ctypes.c_size_t()
+        assert L.fdas_plan(ctypes.byref(cfg), ctypes.byref(h), ctypes.byref(nb)) == F.OK
+        try:
+            return fn(h)
+        finally:
+            L.fdas_destroy(h)
+
+    assert call(None, 1000, [2, 4]) == F.E_INVALID
+    small = make(compute="bf16", plane_dtype="bf16")
+    assert with_plan(small, lambda h: call(h, 1000, [2, 4], plane=0)) == F.E_INVALID
+    assert with_plan(small, lambda h: call(h, 1000, [2, 4], n_found=0x20004)) == F.E_INVALID   # 8-byte aligned
+    assert with_plan(small, lambda h: call(h, 1000, [4, 2])) == F.E_INVALID                    # increasing H
+    assert with_plan(small, lambda h: call(h, 0, [2])) == F.E_INVALID
+    assert with_plan(small, lambda h: call(h, 65537, [2])) == F.E_INVALID                      # > max_bins
+
+    # a plane whose scratch need exceeds the fixed array: FDAS_E_WORKSPACE
+    # (computed from the workspace query, no device touched)
+    big = make(max_bins=1 << 24, n_z=801, z_min=-800.0, compute="bf16", plane_dtype="bf16")
+
+    def too_big(h):
+        hs = [2, 4, 8, 16]
+        need = ctypes.c_size_t()
+        assert L.fdas_harmonic_sums_peaks_workspace(h, 1 << 24, 4, (ctypes.c_int32 * 4)(*hs),
+                                                    ctypes.byref(need)) == F.OK
+        assert need.value > F.NOALLOC_SCRATCH_BYTES
+        return call(h, 1 << 24, hs)
+    assert with_plan(big, too_big) == F.E_WORKSPACE
