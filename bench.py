@@ -35,8 +35,32 @@ def note(msg):
     print(f"[bench {time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
+PREROLL_MS = 40.0
+
+
+def preroll(fn, min_ms=PREROLL_MS):
+    """Run fn (one launch) back to back until at least min_ms of device time
+    has passed, whatever the warm-up count: the GPU clock needs a few tens of
+    milliseconds of steady load to settle, so the timed window then starts at
+    the steady clock.  Outside every timed region."""
+    import torch
+    st = torch.cuda.current_stream()
+    spent = 0.0
+    while spent < min_ms:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(16):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        spent += e0.elapsed_time(e1)
+    return spent
+
+
 def time_correlate(pl, x, plane, steps, warmup):
     import torch
+    preroll(lambda: pl.correlate(x, plane))
     for _ in range(warmup):
         pl.correlate(x, plane)
     torch.cuda.synchronize()
@@ -60,6 +84,7 @@ def launch_stats(pl, x, plane, n=256):
     import statistics
     import torch
     st = torch.cuda.current_stream()
+    preroll(lambda: pl.correlate(x, plane))
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
     for a, b in ev:
         a.record(st)
@@ -300,6 +325,7 @@ def peaks_timing(pl, x, plane, thr, steps, ms_plane):
 
     res = {}
     for name, fn in (("correlate_then_peaks", separate), ("correlate_peaks_fused", fused)):
+        preroll(fn)
         for _ in range(max(steps // 4, 5)):
             fn()
         torch.cuda.synchronize()
@@ -340,6 +366,7 @@ def harmonic_timing(pl, plane, steps, thr):
     pp, kp, fp = ctypes.c_void_p(plane.data_ptr()), ctypes.c_void_p(pk.data_ptr()), ctypes.c_void_p(nf.data_ptr())
 
     def timed(fn, reps):
+        preroll(fn)
         for _ in range(10):
             fn()
         torch.cuda.synchronize()
@@ -354,6 +381,7 @@ def harmonic_timing(pl, plane, steps, thr):
     res = {}
     for H in (2, 4, 8, 16):
         out = pl.harmonic_sum(plane, H)
+        preroll(lambda: pl.harmonic_sum(plane, H, out))
         for _ in range(10):
             pl.harmonic_sum(plane, H, out)
         torch.cuda.synchronize()
@@ -489,6 +517,75 @@ def series_search_timing(args, cfg, dev, pl):
                         f"harmonic sums H = 2, 4, 8, 16 with peaks", "ms": ms,
             "thresholds": {str(k): v for k, v in thr.items()},
             "n_found": {"H1": found[0], **{f"H{h}": found[i] for i, h in enumerate(hs, 1)}}}
+
+
+def refinement_timing(cfg, dev, x, steps):
+    """Candidate refinement of the single-DM spectrum: the 4,096 highest
+    local maxima of its FP32 plane, each moved by a seeded offset
+    (U[-0.5, 0.5] in r, U[-1, 1] in z), 20 ascent steps of the 32-tap
+    interpolated power with its analytic gradient (fdas_refine), and the
+    backward kernel alone (fdas_refine_backward on the same points).  Device
+    buffers are allocated once; the start points are restored outside the
+    timed launches."""
+    import ctypes
+    import numpy as np
+    import torch
+    import synth
+    from paper_2206_12205_amd import fdas as F
+    from paper_2206_12205_amd.fdas import Plan
+    L = F.lib()
+    n = x.numel()
+    pl = Plan(max_bins=n, z_min=cfg["z_min"], z_step=cfg["z_step"], n_z=cfg["n_z"], n_taps=cfg["n_taps"],
+              seg_len=0, compute="fp32", plane_dtype="fp32", device=dev)
+    pk = pl.peaks(pl.correlate(x), 8.0, capacity=1 << 20)
+    n_cand, n_steps, taps = 4096, 20, 32
+    top = np.argsort(-pk["power"], kind="stable")[:n_cand]
+    dr, dz = synth.refine_offsets(n_cand)
+    r0 = torch.from_numpy(pk["r"][top].astype(np.float64) + dr).to(dev)
+    z0 = torch.from_numpy(cfg["z_min"] + cfg["z_step"] * pk["z_idx"][top].astype(np.float64) + dz).to(dev)
+    del pl
+    r, z = r0.clone(), z0.clone()
+    P, gr, gz = (torch.empty_like(r0) for _ in range(3))
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+    V = lambda t: ctypes.c_void_p(t.data_ptr())
+
+    def ascend():
+        F._check(L.fdas_refine(V(x), n, n_cand, V(r), V(z), V(P), V(gr), V(gz), taps, n_steps, 1.0, 1.0, sp),
+                 "fdas_refine")
+
+    def backward():
+        F._check(L.fdas_refine_backward(V(x), n, n_cand, V(r0), V(z0), V(P), V(gr), V(gz), taps, sp),
+                 "fdas_refine_backward")
+
+    def timed(fn, reset):
+        total = 0.0
+        for i in range(steps + 3):
+            if reset:
+                r.copy_(r0)
+                z.copy_(z0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            e1.synchronize()
+            if i >= 3:
+                total += e0.elapsed_time(e1)
+        return total / steps
+    ms_a = timed(ascend, True)
+    P_end = P.clone()
+    F._check(L.fdas_refine(V(x), n, n_cand, V(r0), V(z0), V(P), V(gr), V(gz), taps, 0, 1.0, 1.0, sp),
+             "fdas_refine")
+    gain = float((P_end / P).median().item())
+    ms_b = timed(backward, False)
+    res = {"workload": f"{n_cand} single-DM candidates (highest FP32 plane maxima, seeded offsets), "
+                       f"{n_steps} ascent steps, {taps} taps, FP64 positions",
+           "ms_20_steps": ms_a, "candidates_per_s": n_cand / (ms_a * 1e-3),
+           "candidate_steps_per_s": n_cand * n_steps / (ms_a * 1e-3),
+           "backward_ms": ms_b, "median_power_gain": gain}
+    note(f"refinement: {n_cand} candidates x {n_steps} steps in {ms_a:.3f} ms "
+         f"({res['candidates_per_s']:.3g} candidates/s); backward alone {ms_b:.4f} ms")
+    return res
 
 
 def jerk_volume(args, cfg, dev, x, plane):
@@ -651,14 +748,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=200,
-                    help="untimed launches before each timed window; the GPU clock needs ~100 "
-                         "back-to-back launches (~30 ms) to reach its steady state")
+                    help="untimed launches before each timed window (after a pre-roll of at least "
+                         f"{PREROLL_MS:.0f} ms of device time that brings the GPU clock to its steady state)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched many-spectra search (256 dedispersion trials)")
     ap.add_argument("--no-harmonic", action="store_true", help="skip the harmonic-sum timing")
     ap.add_argument("--no-jerk", action="store_true", help="skip the jerk-volume timing")
+    ap.add_argument("--no-refine", action="store_true", help="skip the candidate-refinement timing")
     ap.add_argument("--no-canopy", action="store_true", help="skip the noise-canopy experiment")
     ap.add_argument("--no-prep", action="store_true", help="skip the spectrum-preparation timing")
     ap.add_argument("--no-wide", action="store_true",
@@ -856,6 +954,9 @@ def main():
 
     if not args.no_harmonic:
         out["harmonic_sum"] = {"workload": "the single-DM BF16 plane, BF16 sums out", **harm}
+
+    if not args.no_refine:
+        out["refinement"] = refinement_timing(cfg, dev, x, max(10, min(args.steps, 50)))
 
     if not args.no_jerk:
         out["jerk"] = jerk_volume(args, cfg, dev, x, plane_b)
