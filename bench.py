@@ -424,33 +424,47 @@ def harmonic_timing(pl, plane, steps, thr):
 
 
 def prep_timing(args, cfg, dev):
-    """fdas_prepare on a single-DM-length series (2^23 FP32 samples, seeded
-    noise on the device): real FFT, DC, median normalisation.  Algorithmic
+    """fdas_prepare on seeded noise series on the device (FP32 samples): the
+    single-DM length 2^23 and a 3 * 2^k length of the batched workload.  The
+    workspace is allocated once, outside the timed launches.  Algorithmic
     bytes: the series read once and the spectrum written once."""
+    import ctypes
     import torch
-    from paper_2206_12205_amd.fdas import prepare
-    n_t = cfg["n_t"]
-    g = torch.Generator(device=dev).manual_seed(12205)
-    xs = torch.randn(n_t, dtype=torch.float32, device=dev, generator=g)
-    out = prepare(xs)
-    for _ in range(10):
-        prepare(xs, out)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    from paper_2206_12205_amd import fdas as F
+    L = F.lib()
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
     reps = max(10, min(args.steps, 100))
-    e0.record()
-    for _ in range(reps):
-        prepare(xs, out)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    alg = n_t * 4 + (n_t // 2) * 8
-    note(f"spectrum preparation (2^{n_t.bit_length() - 1} samples): {ms:.3f} ms")
-    return {"workload": f"{n_t} FP32 samples -> {n_t // 2} normalised bins", "ms": ms,
-            "algorithmic_GBs": alg / (ms * 1e-3) / 1e9,
-            "fft_passes": ((n_t // 2).bit_length() - 1) // 4 + int(((n_t // 2).bit_length() - 1) % 4 >= 2)
-                          + ((n_t // 2).bit_length() - 1) % 2,
-            "note": "the workspace comes from torch's caching allocator per call (inside the timed loop)"}
+    res = {}
+    for n_t in (cfg["n_t"], 3 << 21):
+        g = torch.Generator(device=dev).manual_seed(12205)
+        xs = torch.randn(n_t, dtype=torch.float32, device=dev, generator=g)
+        out = torch.empty(n_t // 2, dtype=torch.complex64, device=dev)
+        nb = ctypes.c_size_t(0)
+        F._check(L.fdas_prepare_workspace(n_t, ctypes.byref(nb)), "fdas_prepare_workspace")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        args_c = (ctypes.c_void_p(xs.data_ptr()), n_t, ctypes.c_void_p(out.data_ptr()),
+                  ctypes.c_void_p(ws.data_ptr()), nb.value, sp)
+
+        def one():
+            F._check(L.fdas_prepare(*args_c), "fdas_prepare")
+        preroll(one)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            one()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        alg = n_t * 4 + (n_t // 2) * 8
+        res[str(n_t)] = {"workload": f"{n_t} FP32 samples -> {n_t // 2} normalised bins", "ms": ms,
+                         "algorithmic_GBs": alg / (ms * 1e-3) / 1e9,
+                         "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        note(f"spectrum preparation ({n_t} samples): {ms:.4f} ms, "
+             f"{res[str(n_t)]['algorithmic_GBs']:.0f} GB/s algorithmic")
+        del xs, out, ws
+    return res
 
 
 def series_search_timing(args, cfg, dev, pl):

@@ -193,12 +193,15 @@ int fdas_make_templates(fdas_plan_t plan, void *stream);
  * and bfloat16"):
  *   X[k] = sum_t x[t] exp(-2 pi i k t / N_t),  k in [0, N_t / 2)  (Nyquist dropped),
  *   X[0] = 0,   X[k] /= sqrt(median_{k >= 1} |X[k]|^2 / ln 2)
- * so that white-noise powers become Exp(1).  The FFT runs as radix-4/2
- * Stockham passes over global memory on N_t / 2 complex points, twiddles
- * from double precision; the median is an exact selection.
+ * so that white-noise powers become Exp(1).  The complex FFT of the N_t / 2
+ * points z[m] = x[2m] + i x[2m+1] runs as a four-step transform of two passes
+ * whose sub-transforms stay in LDS (N_t / 2 = N1 N2 with N1 <= 4096 and
+ * N2 <= 2048), the real split fused into the second; other power-of-two
+ * lengths take Stockham passes over global memory.  The median is an exact
+ * selection.
  *   series     device, n_t floats (8-byte aligned)
- *   n_t        a power of two in [4, 2^28] (FDAS_E_UNSUPPORTED otherwise;
- *              FDAS_E_INVALID below 4)
+ *   n_t        a power of two in [4, 2^28], or 3 * 2^a in [384, 3 * 2^22]
+ *              (FDAS_E_UNSUPPORTED otherwise; FDAS_E_INVALID below 4)
  *   spectrum   device, n_t / 2 complex64 (16-byte aligned): the result
  *   workspace  device, at least fdas_prepare_workspace's bytes (16-byte
  *              aligned), FDAS_E_WORKSPACE otherwise

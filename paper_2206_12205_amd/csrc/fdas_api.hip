@@ -301,7 +301,7 @@ int fdas_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, float threshold
         fdas::launch_peaks(*p, plane, n_bins, threshold, out, capacity, n_found, static_cast<hipStream_t>(stream)));
 }
 
-static bool prep_length_ok(int64_t n_t) { return n_t >= 4 && n_t <= ((int64_t)1 << 28) && (n_t & (n_t - 1)) == 0; }
+static bool prep_length_ok(int64_t n_t) { return fdas::prep_length_supported(n_t); }
 
 int fdas_prepare_workspace(int64_t n_t, size_t *workspace_bytes) {
     if (!workspace_bytes) return FDAS_E_INVALID;

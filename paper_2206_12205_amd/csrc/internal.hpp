@@ -135,6 +135,9 @@ hipError_t batch_peaks_finish(const fdas_plan_s &p, const void *planes, void *sc
 
 // Spectrum preparation (prep.hip).
 size_t prep_workspace_bytes(int64_t n_t);
+// Series lengths fdas_prepare handles: 2^a (4 <= n_t <= 2^28) and 3 * 2^a (the
+// four-step form: 3 * 2^7 <= n_t <= 3 * 2^22).
+bool prep_length_supported(int64_t n_t);
 hipError_t launch_prepare(const float *series, int64_t n_t, void *out, void *ws, hipStream_t st);
 
 // Band maxima (bands.hip).

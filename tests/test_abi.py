@@ -179,7 +179,12 @@ def test_prepare_argument_checks():
     nb = ctypes.c_size_t(0)
     assert L.fdas_prepare_workspace(1 << 20, ctypes.byref(nb)) == F.OK
     assert nb.value >= (1 << 19) * 16
-    assert L.fdas_prepare_workspace(3 << 10, ctypes.byref(nb)) == F.E_UNSUPPORTED
+    # 3 * 2^a lengths: the four-step form, 3 * 2^7 .. 3 * 2^22 samples
+    for n_t in (3 << 7, 3 << 10, 3 << 22):
+        assert L.fdas_prepare_workspace(n_t, ctypes.byref(nb)) == F.OK, n_t
+        assert nb.value >= (n_t // 2) * 16
+    for n_t in (3 << 6, 3 << 23, 5 << 10, 6, 1000):
+        assert L.fdas_prepare_workspace(n_t, ctypes.byref(nb)) == F.E_UNSUPPORTED, n_t
     assert L.fdas_prepare_workspace(2, ctypes.byref(nb)) == F.E_INVALID
     assert L.fdas_prepare_workspace(1024, None) == F.E_INVALID
     fake = ctypes.c_void_p(0x10000)

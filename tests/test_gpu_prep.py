@@ -31,7 +31,11 @@ def gpu_prepare(x, dev):
     return prepare(torch.from_numpy(np.asarray(x, dtype=np.float32)).to(dev)).cpu().numpy()
 
 
-@pytest.mark.parametrize("n_t", [4, 8, 2048, 4096, 1 << 17, 1 << 20])
+# the global-pass lengths (4 .. 32 samples, 2^25), the four-step form's
+# smallest (64 = 8 x 4 complex, 384 = 24 x 8 with the radix-3 pass) and
+# largest (2^24, 3 * 2^22) lengths, and 3 * 2^k lengths between
+@pytest.mark.parametrize("n_t", [4, 8, 32, 64, 384, 1536, 2048, 4096, 6144, 1 << 17, 3 << 17, 1 << 20,
+                                 3 << 20, 3 << 22, 1 << 24, 1 << 25])
 def test_prepare_matches_oracle(dev, n_t):
     say(f"[prep] n_t={n_t}")
     rng = np.random.default_rng(n_t)
@@ -44,6 +48,19 @@ def test_prepare_matches_oracle(dev, n_t):
     if n_t >= 2048:
         p = np.sort(np.abs(got[1:].astype(np.complex128)) ** 2)
         assert abs(p[(p.size - 1) // 2] / math.log(2.0) - 1.0) < 2e-6
+
+
+@pytest.mark.parametrize("n_t", [1 << 16, 3 << 16])
+def test_prepare_degenerate_median(dev, n_t):
+    """A unit impulse at t = 0: every bin k >= 1 has power exactly 1, so the
+    median's histogram bin gathers every key of the spectrum and the exact
+    selection runs over all of them; the result is sqrt(ln 2) in every bin."""
+    x = np.zeros(n_t, dtype=np.float32)
+    x[0] = 1.0
+    got = gpu_prepare(x, dev)
+    want = OPR.prepare(x.astype(np.float64))
+    assert got[0] == 0 and np.allclose(want[1:], math.sqrt(math.log(2.0)))
+    assert np.max(np.abs(got[1:] - want[1:])) <= 1e-6
 
 
 def test_prepare_single_dm_series_then_plane(dev):
