@@ -268,9 +268,14 @@ def batched_search(args, cfg, dev):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    # per chunk: 7 launches of the correlation with its peaks, 5 of the
+    # batched harmonic sums with their peaks (layout, sums and marks, count,
+    # scan, write)
     res["correlate_peaks_and_harmonic_sums"] = {
         "ms_per_pass": ms, "harmonics": {str(h): t for h, t in harm.items()},
-        "launches_per_pass": len(bs.chunks) * 7 + len(lengths) * (2 + 3 * len(harm))}
+        "harmonic_sums_ms_per_pass": ms - res["correlate_and_peaks"]["ms_per_pass"],
+        "launches_per_pass": len(bs.chunks) * (7 + 5),
+        "harmonic_peaks_found": sum(int(v) for v in bs.hn_found_all.cpu().tolist())}
     note(f"batched plane + peaks + harmonic sums H = 2..16 with peaks: {ms:.1f} ms per pass")
     bs.harmonics = {}
     # an injected pulsar counts as found when a peak sits within 2 bins of

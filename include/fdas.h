@@ -452,6 +452,35 @@ int fdas_harmonic_sum_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins,
                             float threshold, fdas_peak *peaks, int64_t capacity, int64_t *n_found,
                             void *stream);
 
+/* Harmonic sums with their thresholded peaks for every job of the batch set
+ * by fdas_set_batch, in one launch sequence (Section "Detailed explanation":
+ * the harmonics of a signal at (r, z) sit at (h r, h z)): for each level l
+ * and job i, the peaks fdas_harmonic_sums_peaks lists for job i's plane
+ * (at planes + its plane offset, as fdas_correlate_batch writes it) with
+ * n_harm[l] and thresholds[l].  The sums themselves are never stored: one
+ * summing launch over all jobs flags the tiles (one row x 1024 fundamentals)
+ * where a sum, rounded to the plane's type as a store would round it, may
+ * exceed its level's threshold, and the finder recomputes the sums of the
+ * flagged tiles and their neighbours from the planes, so every listed cell
+ * and power is bitwise the stored sum's.
+ *   n_harm, thresholds  host arrays of n_levels (1..8) entries, n_harm
+ *              increasing, each in 1..32
+ *   peaks      device, n_levels x n_jobs x capacity records (16-byte
+ *              aligned): list (l, i) at peaks + (l n_jobs + i) capacity, job = i
+ *   n_found    device, n_levels x n_jobs int64 (8-byte aligned): true counts
+ *   scratch    caller device memory (16-byte aligned) of at least the bytes
+ *              fdas_batch_harmonic_sums_peaks_workspace gives for the same
+ *              batch and levels (flags, counts, list layout, harmonic rows)
+ * FDAS_E_STATE without a batch, FDAS_E_UNSUPPORTED for more than 65535
+ * templates or 2^31 tiles or summing workgroups, FDAS_E_WORKSPACE for a
+ * missing or short scratch.  Asynchronous on stream, kernels only
+ * (graph-capturable): four launches per call. */
+int fdas_batch_harmonic_sums_peaks_workspace(fdas_plan_t plan, int32_t n_levels, const int32_t *n_harm,
+                                             size_t *scratch_bytes);
+int fdas_batch_harmonic_sums_peaks(fdas_plan_t plan, const void *planes, int32_t n_levels, const int32_t *n_harm,
+                                   const float *thresholds, fdas_peak *peaks, int64_t capacity, int64_t *n_found,
+                                   void *scratch, size_t scratch_bytes, void *stream);
+
 /* Candidate refinement: matched-filter power at continuous (r, z) and its
  * gradient (no plan needed).  The plane samples the power on integer r and a
  * z grid, and quantisation in both axes moves peaks into adjacent bins

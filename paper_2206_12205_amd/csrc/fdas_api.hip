@@ -615,6 +615,46 @@ int fdas_correlate_batch_peaks(fdas_plan_t p, const void *spectra, void *planes,
     return hip_status(e);
 }
 
+static int check_batch_sums(fdas_plan_t p, int32_t n_levels, const int32_t *n_harm) {
+    if (!p || !n_harm || n_levels < 1 || n_levels > 8) return FDAS_E_INVALID;
+    for (int32_t l = 0; l < n_levels; ++l)
+        if (n_harm[l] < 1 || n_harm[l] > fdas::kMaxHarmonics || (l > 0 && n_harm[l] <= n_harm[l - 1]))
+            return FDAS_E_INVALID;
+    if (p->batch_jobs < 1) return FDAS_E_STATE;
+    if (p->cfg.n_z > 65535 || p->batch_jobs > 32767) return FDAS_E_UNSUPPORTED;
+    const fdas::BatchSumsLayout L = fdas::batch_sums_layout(*p, n_levels, n_harm);
+    if (L.blocks > 0x7fffffffLL || L.tiles >= 0x7fffffffLL) return FDAS_E_UNSUPPORTED;
+    return FDAS_OK;
+}
+
+int fdas_batch_harmonic_sums_peaks_workspace(fdas_plan_t p, int32_t n_levels, const int32_t *n_harm,
+                                             size_t *scratch_bytes) {
+    if (!scratch_bytes) return FDAS_E_INVALID;
+    const int s = check_batch_sums(p, n_levels, n_harm);
+    if (s != FDAS_OK) return s;
+    *scratch_bytes = fdas::batch_sums_layout(*p, n_levels, n_harm).bytes;
+    return FDAS_OK;
+}
+
+int fdas_batch_harmonic_sums_peaks(fdas_plan_t p, const void *planes, int32_t n_levels, const int32_t *n_harm,
+                                   const float *thresholds, fdas_peak *peaks, int64_t capacity, int64_t *n_found,
+                                   void *scratch, size_t scratch_bytes, void *stream) {
+    const int s = check_batch_sums(p, n_levels, n_harm);
+    if (s != FDAS_OK) return s;
+    if (!planes || !thresholds || !n_found || capacity < 0 || (capacity > 0 && !peaks)) return FDAS_E_INVALID;
+    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
+    if ((reinterpret_cast<uintptr_t>(planes) % pe) != 0 || (peaks && !aligned16(peaks)) || !aligned8(n_found))
+        return FDAS_E_INVALID;
+    const fdas::BatchSumsLayout L = fdas::batch_sums_layout(*p, n_levels, n_harm);
+    if (capacity > 0 && L.lists > INT64_MAX / capacity) return FDAS_E_INVALID;
+    if (!p->ws) return FDAS_E_WORKSPACE;
+    if (!scratch || !aligned16(scratch) || scratch_bytes < L.bytes) return FDAS_E_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = fdas::launch_batch_sums_mark(*p, L, planes, n_levels, n_harm, thresholds, scratch, st);
+    if (e == hipSuccess) e = fdas::batch_sums_finish(*p, L, planes, scratch, peaks, capacity, n_found, st);
+    return hip_status(e);
+}
+
 int fdas_refine(const void *spectrum, int64_t n_bins, int32_t n_cand, double *r, double *z, double *power,
                 double *dp_dr, double *dp_dz, int32_t taps, int32_t n_steps, double eta_r_scale, double eta_z_scale,
                 void *stream) {

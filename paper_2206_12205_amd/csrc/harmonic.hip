@@ -22,7 +22,11 @@
 // even), so fdas_peaks thresholds it directly.  The marking form (kMark)
 // also flags the peak finder's tiles of the summed plane while storing it,
 // so harmonic summing with thresholding needs no second read of the sums.
+#include "harmonic_rows.hpp"
 #include "internal.hpp"
+
+#include <algorithm>
+#include <climits>
 #include "marks.hpp"
 #include "plane_io.hpp"
 
@@ -31,19 +35,10 @@ namespace fdas {
 namespace {
 
 constexpr int kHsThreads = 256;
+// word 3 of a raw buffer resource on gfx9-family parts (32-bit data format,
+// no swizzle; out-of-range offsets read zero)
+constexpr int kBufferWord3 = 0x00020000;
 constexpr int kHsPerThread = 8;
-
-__device__ int harmonic_row(double z_min, double z_step, int n_z, int j, int h) {
-#pragma clang fp contract(off)
-    if (n_z == 1) return ((double)h * z_min == z_min) ? 0 : -1;
-    const double t = z_min + (double)j * z_step;
-    const double u = (double)h * t;
-    const double v = u - z_min;
-    const double x = v / z_step;
-    const double f = floor(x + 0.5);
-    if (!(f >= 0.0 && f < (double)n_z)) return -1;   // outside the grid (or NaN)
-    return (int)f;
-}
 
 // plane element -> accumulation type
 template <class PT>
@@ -52,6 +47,9 @@ template <>
 struct hs_io<float> {
     using acc = float;
     static __device__ __forceinline__ float get(const float *p, int64_t i) { return p[i]; }
+    static __device__ __forceinline__ float getb(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
     static __device__ __forceinline__ void put(float *p, float v) { plane_store<float>::put(p, v); }
     // a bound b with: stored value > thr implies v > b (exact here)
     static __device__ __forceinline__ float mark_bound(float thr) { return thr; }
@@ -60,6 +58,9 @@ template <>
 struct hs_io<double> {
     using acc = double;
     static __device__ __forceinline__ double get(const double *p, int64_t i) { return p[i]; }
+    static __device__ __forceinline__ double getb(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
     static __device__ __forceinline__ void put(double *p, double v) { plane_store<double>::put(p, v); }
     static __device__ __forceinline__ double mark_bound(float thr) { return (double)thr; }
 };
@@ -68,6 +69,9 @@ struct hs_io<__bf16> {
     using acc = float;
     static __device__ __forceinline__ float get(const __bf16 *p, int64_t i) {
         return __uint_as_float((uint32_t)reinterpret_cast<const unsigned short *>(p)[i] << 16);   // exact
+    }
+    static __device__ __forceinline__ float getb(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);
     }
     static __device__ __forceinline__ void put(__bf16 *p, float v) { plane_store<__bf16>::put(p, v); }
     // Rounding to nearest bfloat16 moves a normal value by at most 2^-8 of
@@ -78,6 +82,50 @@ struct hs_io<__bf16> {
         return thr > 1e-30f ? thr * 0.99609375f : -INFINITY;
     }
 };
+
+// Add harmonics h_lo .. h_hi, in that order, of this thread's fundamentals
+// r0 + 256 i below lim to acc; rows[h - 1] is harmonic h's row (the same for
+// the whole workgroup, -1: left out).  No load sits behind a branch (a
+// fundamental or harmonic that is left out loads the row's first cell and
+// keeps its sum), so the kHsPerThread loads of a harmonic are in flight
+// together.  (More harmonics in flight per thread measured slower: the
+// kernel is bound by the traffic into L2, not by latency.)  A load is a
+// buffer load, the row as a buffer resource (scalar registers) plus one
+// 32-bit byte offset, so a row must hold less than 4 GB; longer rows use
+// 64-bit addresses.
+template <class PT>
+__device__ __forceinline__ void add_harmonics(typename hs_io<PT>::acc (&acc)[kHsPerThread], const PT *plane,
+                                              int64_t n, const int *rows, int h_lo, int h_hi, int64_t r0,
+                                              int64_t lim) {
+    using A = typename hs_io<PT>::acc;
+    const bool wide = n >= (int64_t)(0xffffffffu / sizeof(PT));
+    const uint32_t ru = (uint32_t)r0;
+    const int32_t row_bytes = (int32_t)(uint32_t)(n * (int64_t)sizeof(PT));
+    for (int h = h_lo; h <= h_hi; ++h) {
+        const int jh = __builtin_amdgcn_readfirstlane(rows[h - 1]);
+        const PT *base = plane + (int64_t)max(jh, 0) * n;
+        A v[kHsPerThread];
+        if (!wide) {
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<PT *>(base), (short)0, row_bytes, kBufferWord3);
+#pragma unroll
+            for (int i = 0; i < kHsPerThread; ++i) {
+                const bool ok = jh >= 0 && r0 + i * kHsThreads < lim;
+                const uint32_t off = (uint32_t)h * (ru + (uint32_t)(i * kHsThreads)) * (uint32_t)sizeof(PT);
+                v[i] = hs_io<PT>::getb(rs, ok ? off : 0u);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kHsPerThread; ++i) {
+                const int64_t r = r0 + i * kHsThreads;
+                v[i] = hs_io<PT>::get(base, jh >= 0 && r < lim ? (int64_t)h * r : 0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kHsPerThread; ++i)
+            acc[i] = jh >= 0 && r0 + i * kHsThreads < lim ? acc[i] + v[i] : acc[i];
+    }
+}
 
 template <class PT, bool kMark>
 __global__ void __launch_bounds__(kHsThreads)
@@ -93,21 +141,12 @@ k_harmonic_sum(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, d
     // of cache lines and every line is requested once
     const int64_t rb = (int64_t)blockIdx.x * (kHsThreads * kHsPerThread);
     const int64_t r0 = rb + threadIdx.x;
-    if (r0 >= nh) return;
+    if (rb >= nh) return;      // uniform: every load below is unconditional
     A acc[kHsPerThread];
 #pragma unroll
     for (int i = 0; i < kHsPerThread; ++i) acc[i] = 0;
     // h r <= H (N_H - 1) <= N - 1 for every kept fundamental r < N_H
-    for (int h = 1; h <= n_harm; ++h) {
-        const int jh = rows[h - 1];
-        if (jh < 0) continue;
-        const PT *row = plane + (int64_t)jh * n;
-#pragma unroll
-        for (int i = 0; i < kHsPerThread; ++i) {
-            const int64_t r = r0 + i * kHsThreads;
-            if (r < nh) acc[i] += hs_io<PT>::get(row, (int64_t)h * r);
-        }
-    }
+    add_harmonics<PT>(acc, plane, n, rows, 1, n_harm, r0, nh);
     PT *o = out + (int64_t)j * nh;
 #pragma unroll
     for (int i = 0; i < kHsPerThread; ++i) {
@@ -160,7 +199,7 @@ __device__ __forceinline__ void mark_sums(const typename hs_io<PT>::acc (&acc)[k
     const A bound = hs_io<PT>::mark_bound(m.thr);
 #pragma unroll
     for (int t = 0; t < kHsPerThread / kPerTile; ++t) {
-        if (r0 + t * kPerTile * kHsThreads >= lim) break;
+        if (rb + (int64_t)t * kPeakTileCols >= lim) break;   // uniform
         bool above = false;   // OR of per-sum compares: a NaN sum hides no other
 #pragma unroll
         for (int i = t * kPerTile; i < (t + 1) * kPerTile; ++i)
@@ -182,33 +221,203 @@ k_harmonic_sums(const PT *__restrict__ plane, int64_t n, int n_z, double z_min, 
     __syncthreads();
     const int64_t rb = (int64_t)blockIdx.x * (kHsThreads * kHsPerThread);
     const int64_t r0 = rb + threadIdx.x;
-    if (r0 >= lv.nh[0]) return;                 // the largest N_H (smallest H)
+    if (rb >= lv.nh[0]) return;                 // the largest N_H (smallest H); uniform
     A acc[kHsPerThread];
 #pragma unroll
     for (int i = 0; i < kHsPerThread; ++i) acc[i] = 0;
-    int lvl = 0;
-    for (int h = 1; h <= h_max; ++h) {
-        const int64_t lim = lv.nh[lvl];         // fundamentals that still need harmonic h
-        if (r0 >= lim) break;                   // every later sum has an even smaller N_H
-        const int jh = rows[h - 1];
-        if (jh >= 0) {
-            const PT *row = plane + (int64_t)jh * n;
+    // level l adds harmonics H_{l-1} + 1 .. H_l to the fundamentals below
+    // its N_H (every later sum has an even smaller N_H); the exits are taken
+    // by the whole workgroup, threads past N_H are masked
+    int h_lo = 1;
+    for (int lvl = 0; lvl < n_levels; ++lvl) {
+        const int64_t lim = lv.nh[lvl];
+        if (rb >= lim) break;
+        add_harmonics<PT>(acc, plane, n, rows, h_lo, lv.H[lvl], r0, lim);
+        h_lo = lv.H[lvl] + 1;
+        PT *o = lv.out[lvl] + (int64_t)j * lim;
 #pragma unroll
-            for (int i = 0; i < kHsPerThread; ++i) {
-                const int64_t r = r0 + i * kHsThreads;
-                if (r < lim) acc[i] += hs_io<PT>::get(row, (int64_t)h * r);
+        for (int i = 0; i < kHsPerThread; ++i) {
+            const int64_t r = r0 + i * kHsThreads;
+            if (r < lim) hs_io<PT>::put(o + r, acc[i]);
+        }
+        if constexpr (kMark) mark_sums<PT, kMark>(acc, r0, rb, lim, j, lv.marks[lvl]);
+    }
+}
+
+// Batch form: the sums of every job of a batch, marking only (the sums are
+// never stored).  Workgroup u takes the unit units[u] = (job << 16 | row j,
+// block b): fundamentals [2048 b, 2048 b + 2048) of template row j (the
+// order of the units is set by k_batch_sums_prep for cache reuse).  At each
+// level H_l the sums of this thread are tested against list l * n_jobs +
+// job's threshold and its tiles flagged (flags are a superset of the tiles
+// holding a stored sum above the threshold, as in the marking form).  rows:
+// the [n_z][hmax] harmonic rows, read by scalar loads.
+template <class PT>
+__global__ void __launch_bounds__(kHsThreads)
+k_batch_sums_mark(const PT *__restrict__ planes, const fdas_batch_job *__restrict__ jobs,
+                  const SumJob *__restrict__ lists, const int2 *__restrict__ units, int n_jobs, int n_levels,
+                  const int32_t *__restrict__ rows, int hmax, uint8_t *flags, uint8_t *cflags) {
+    using A = typename hs_io<PT>::acc;
+    constexpr int64_t kPerUnit = (int64_t)kHsThreads * kHsPerThread;
+    const int2 unit = units[blockIdx.x];
+    const int job = unit.x >> 16;
+    const int j = unit.x & 0xffff;
+    const int64_t rb = (int64_t)unit.y * kPerUnit;
+    const int64_t r0 = rb + threadIdx.x;
+    const int64_t n = jobs[job].n_bins;
+    const PT *plane = planes + jobs[job].plane_off;
+    const int32_t *rz = rows + (int64_t)j * hmax;
+    A acc[kHsPerThread];
+#pragma unroll
+    for (int i = 0; i < kHsPerThread; ++i) acc[i] = 0;
+    // exits are taken by the whole workgroup; threads past N_H are masked
+    int h_lo = 1;
+    for (int lvl = 0; lvl < n_levels; ++lvl) {
+        const SumJob &sj = lists[lvl * n_jobs + job];
+        const int64_t lim = sj.nh;
+        if (rb >= lim) break;
+        add_harmonics<PT>(acc, plane, n, rz, h_lo, sj.H, r0, lim);
+        h_lo = sj.H + 1;
+        PeakMarks m;
+        m.flags = flags + sj.tile_base;
+        m.cflags = cflags + sj.chunk_base;
+        m.n_cb = (int32_t)((sj.nh + kPeakTileCols - 1) / kPeakTileCols);
+        m.tb = -1;
+        m.thr = sj.thr;
+        mark_sums<PT, true>(acc, r0, rb, lim, j, m);
+    }
+}
+
+// Order of the summing workgroups (the unit table).  On a grid whose z_min
+// is a multiple of z_step, template j has z_j = m_j z_step and its harmonic
+// h lies in the row of m = h m_j, at column h r.  So the templates
+// m_j = a m (a = 1, 2, ...), taking fundamentals near a x, all read row q m
+// near column q x (q = a h), whatever the split of q into a and h.  Units
+// (template j, block b of 2048 fundamentals) of a job are ordered by
+// R = floor(b / s_j), s_j = max(|m_j|, 1), then by j, then by b: the units
+// of one R read each band of a row between them, so the band comes from
+// memory about once instead of once for every harmonic that reads it.  The
+// order changes no result; on other grids it is merely an order.  Units of
+// job i come after those of the jobs before it.  One wave per (job, R):
+// P(R) = sum_j min(s_j R, nb) units come before R, and template j has
+// clamp(nb - s_j R, 0, s_j) units in R.
+__device__ __forceinline__ int unit_scale(double z_min, double z_step, int j) {
+    const int m = (int)rint((z_min + (double)j * z_step) / z_step);
+    return m < 0 ? (m == INT_MIN ? INT_MAX : -m) : (m == 0 ? 1 : m);
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ void build_units(const fdas_batch_job *__restrict__ jobs, int n_jobs, int H0, int n_z, double z_min,
+                            double z_step, int2 *units) {
+    constexpr int64_t kPerUnit = (int64_t)kHsThreads * kHsPerThread;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int64_t tb = 0, ub = 0;          // first task (R of job i) and first unit of job i
+    for (int i = 0; i < n_jobs; ++i) {
+        const int64_t nh = (jobs[i].n_bins - 1) / H0 + 1;
+        const int64_t nb = (nh + kPerUnit - 1) / kPerUnit;
+        for (int64_t R = ((wave - tb) % n_waves + n_waves) % n_waves; R < nb; R += n_waves) {
+            int64_t P = 0;
+            for (int j = lane; j < n_z; j += 64) P += min((int64_t)unit_scale(z_min, z_step, j) * R, nb);
+            P = wave_sum64(P);
+            int64_t carry = 0;
+            for (int j0 = 0; j0 < n_z; j0 += 64) {
+                const int j = j0 + lane;
+                int64_t c = 0, first = 0;
+                if (j < n_z) {
+                    const int64_t sj = unit_scale(z_min, z_step, j);
+                    first = sj * R;
+                    c = max((int64_t)0, min(nb - first, sj));
+                }
+                int64_t incl = c;           // inclusive scan over the wave
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int64_t v = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += v;
+                }
+                const int64_t pos = ub + P + carry + incl - c;
+                for (int64_t k = 0; k < c; ++k) units[pos + k] = make_int2((i << 16) | j, (int)(first + k));
+                carry += __shfl(incl, 63, 64);
             }
         }
-        if (h == lv.H[lvl]) {
-            PT *o = lv.out[lvl] + (int64_t)j * lim;
-#pragma unroll
-            for (int i = 0; i < kHsPerThread; ++i) {
-                const int64_t r = r0 + i * kHsThreads;
-                if (r < lim) hs_io<PT>::put(o + r, acc[i]);
-            }
-            if constexpr (kMark) mark_sums<PT, kMark>(acc, r0, rb, lim, j, lv.marks[lvl]);
-            if (++lvl == n_levels) break;
+        tb += nb;
+        ub += (int64_t)n_z * nb;
+    }
+}
+
+// Set-up of a batch sums call (one launch): every workgroup clears its share
+// of the flags and per-list totals; workgroup 0 lays out the lists (level
+// by level, job by job: columns, first tile, first chunk, and for the first
+// level the first summing workgroup) by prefix sums; workgroup 1 computes
+// the harmonic rows.
+struct SumLevelsArg {
+    int32_t H[kMaxSumLevels];
+    float thr[kMaxSumLevels];
+};
+
+__global__ void __launch_bounds__(1024)
+k_batch_sums_prep(const fdas_batch_job *__restrict__ jobs, int n_jobs, int n_levels, SumLevelsArg lv, int n_z,
+                  double z_min, double z_step, SumJob *lists, int32_t *rows, int hmax, int2 *units,
+                  uint8_t *clear, int64_t clear_bytes) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < clear_bytes;
+         i += (int64_t)gridDim.x * blockDim.x)
+        clear[i] = 0;
+    build_units(jobs, n_jobs, lv.H[0], n_z, z_min, z_step, units);
+    if (blockIdx.x == 1) {
+        for (int i = threadIdx.x; i < n_z * hmax; i += blockDim.x)
+            rows[i] = harmonic_row(z_min, z_step, n_z, i / hmax, i % hmax + 1);
+    }
+    if (blockIdx.x != 0) return;
+    __shared__ int64_t part[3][1024];
+    __shared__ int64_t carry[3];
+    if (threadIdx.x < 3) carry[threadIdx.x] = 0;
+    const int S = n_levels * n_jobs;
+    const int64_t per_block = (int64_t)kHsThreads * kHsPerThread;
+    for (int s0 = 0; s0 < S; s0 += 1024) {
+        const int s = s0 + (int)threadIdx.x;
+        int64_t nh = 0, tiles = 0, chunks = 0, blocks = 0;
+        if (s < S) {
+            const int l = s / n_jobs, i = s - l * n_jobs;
+            nh = (jobs[i].n_bins - 1) / lv.H[l] + 1;
+            tiles = (int64_t)n_z * ((nh + kPeakTileCols - 1) / kPeakTileCols);
+            chunks = (tiles + kPeakTilesPerChunk - 1) / kPeakTilesPerChunk;
+            if (l == 0) blocks = (int64_t)n_z * ((nh + per_block - 1) / per_block);
         }
+        part[0][threadIdx.x] = tiles;
+        part[1][threadIdx.x] = chunks;
+        part[2][threadIdx.x] = blocks;
+        __syncthreads();
+        for (int w = 1; w < 1024; w <<= 1) {
+            int64_t v[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) v[q] = threadIdx.x >= (unsigned)w ? part[q][threadIdx.x - w] : 0;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 3; ++q) part[q][threadIdx.x] += v[q];
+            __syncthreads();
+        }
+        if (s < S) {
+            const int l = s / n_jobs, i = s - l * n_jobs;
+            SumJob sj;
+            sj.nh = nh;
+            sj.tile_base = carry[0] + part[0][threadIdx.x] - tiles;
+            sj.chunk_base = carry[1] + part[1][threadIdx.x] - chunks;
+            sj.block_base = carry[2] + part[2][threadIdx.x] - blocks;
+            sj.H = lv.H[l];
+            sj.job = i;
+            sj.thr = lv.thr[l];
+            sj.level = l;
+            lists[s] = sj;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) carry[threadIdx.x] += part[threadIdx.x][1023];
+        __syncthreads();
     }
 }
 
@@ -282,6 +491,87 @@ hipError_t launch_harmonic_sums(const fdas_plan_s &p, const void *plane, int64_t
 hipError_t launch_harmonic_sum_marked(const fdas_plan_s &p, const void *plane, int64_t n, int n_harm, void *out,
                                       const PeakMarks &marks, hipStream_t st) {
     return dispatch<true>(p, plane, n, n_harm, out, marks, st);
+}
+
+BatchSumsLayout batch_sums_layout(const fdas_plan_s &p, int n_levels, const int32_t *H) {
+    BatchSumsLayout L;
+    const int64_t J = p.batch_jobs, S = (int64_t)n_levels * J;
+    const int64_t per_block = (int64_t)kHsThreads * kHsPerThread;
+    for (int l = 0; l < n_levels; ++l)
+        for (const fdas_batch_job &j : p.batch_host) {
+            const int64_t nh = (j.n_bins - 1) / H[l] + 1;
+            const int64_t tiles = (int64_t)p.cfg.n_z * ((nh + kPeakTileCols - 1) / kPeakTileCols);
+            L.tiles += tiles;
+            L.chunks += (tiles + kPeakTilesPerChunk - 1) / kPeakTilesPerChunk;
+            if (l == 0) L.blocks += (int64_t)p.cfg.n_z * ((nh + per_block - 1) / per_block);
+        }
+    L.lists = S;
+    L.hmax = H[n_levels - 1];
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = 0;
+    L.off_counts = off;
+    off = up(off + (size_t)L.tiles * 4);
+    L.off_block_counts = off;
+    off = up(off + (size_t)L.chunks * 4);
+    L.off_wg_totals = off;
+    off = up(off + (size_t)kBatchPeakGrid * 4);
+    L.off_wg_offsets = off;
+    off = up(off + (size_t)(kBatchPeakGrid + 1) * 8);
+    L.off_prefix = off;
+    off = up(off + (size_t)S * 8);
+    L.off_totals = off;                        // per-list totals, then tile flags, then chunk flags
+    L.clear_bytes = (size_t)S * 8 + (size_t)L.tiles + (size_t)L.chunks;
+    off = up(off + L.clear_bytes);
+    L.off_lists = off;
+    off = up(off + (size_t)S * sizeof(SumJob));
+    L.off_rows = off;
+    off = up(off + (size_t)p.cfg.n_z * L.hmax * 4);
+    L.off_units = off;
+    off = up(off + (size_t)L.blocks * 8);
+    L.bytes = off;
+    return L;
+}
+
+namespace {
+template <class PT>
+hipError_t run_batch_sums(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, int n_levels,
+                          const int32_t *H, const float *thr, unsigned char *scratch, hipStream_t st) {
+    const auto *jobs = reinterpret_cast<const fdas_batch_job *>(static_cast<const unsigned char *>(p.ws) +
+                                                               p.off_batch + p.batch_hdr);
+    SumLevelsArg lv{};
+    for (int l = 0; l < n_levels; ++l) {
+        lv.H[l] = H[l];
+        lv.thr[l] = thr[l];
+    }
+    auto *lists = reinterpret_cast<SumJob *>(scratch + L.off_lists);
+    auto *rows = reinterpret_cast<int32_t *>(scratch + L.off_rows);
+    uint8_t *clear = scratch + L.off_totals;
+    uint8_t *flags = clear + (size_t)L.lists * 8;
+    uint8_t *cflags = flags + L.tiles;
+    // enough workgroups for the clearing and for the unit table (one wave per (job, R))
+    const int64_t tasks = L.blocks / std::max(p.cfg.n_z, 1);
+    const unsigned cg = (unsigned)std::max<int64_t>(
+        2, std::min<int64_t>(1024, std::max<int64_t>((L.clear_bytes + 4095) / 4096, (tasks + 15) / 16)));
+    auto *units = reinterpret_cast<int2 *>(scratch + L.off_units);
+    hipLaunchKernelGGL(k_batch_sums_prep, dim3(cg), dim3(1024), 0, st, jobs, p.batch_jobs, n_levels, lv, p.cfg.n_z,
+                       p.cfg.z_min, p.cfg.z_step, lists, rows, L.hmax, units, clear, (int64_t)L.clear_bytes);
+    if (L.blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_batch_sums_mark<PT>), dim3((unsigned)L.blocks), dim3(kHsThreads), 0, st,
+                       static_cast<const PT *>(planes), jobs, lists, units, p.batch_jobs, n_levels, rows, L.hmax,
+                       flags, cflags);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_batch_sums_mark(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, int n_levels,
+                                  const int32_t *H, const float *thr, void *scratch, hipStream_t st) {
+    auto *b = static_cast<unsigned char *>(scratch);
+    switch (p.cfg.plane_dtype) {
+        case FDAS_FP32: return run_batch_sums<float>(p, L, planes, n_levels, H, thr, b, st);
+        case FDAS_BF16: return run_batch_sums<__bf16>(p, L, planes, n_levels, H, thr, b, st);
+        case FDAS_FP64: return run_batch_sums<double>(p, L, planes, n_levels, H, thr, b, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace fdas

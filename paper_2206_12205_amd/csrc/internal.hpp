@@ -151,6 +151,21 @@ hipError_t launch_harmonic_sum(const fdas_plan_s &p, const void *plane, int64_t 
 // Sums for an increasing list of n_levels (<= 8) harmonic counts in one
 // pass, sum l to outs[l]; marks (n_levels entries) or null: the peak tiles
 // of each sum flagged while it is stored.
+// Harmonic sums of every job of a stored batch with their thresholded
+// peaks, the sums never stored (harmonic.hip marks, peaks.hip finishes).
+// Caller scratch layout (byte offsets, 256-aligned regions).
+constexpr int kBatchPeakGrid = 2048;   // workgroups of the batched count and write kernels
+struct BatchSumsLayout {
+    int64_t tiles = 0, chunks = 0, blocks = 0, lists = 0;
+    int hmax = 0;
+    size_t off_counts = 0, off_block_counts = 0, off_wg_totals = 0, off_wg_offsets = 0, off_prefix = 0;
+    size_t off_totals = 0, off_lists = 0, off_rows = 0, off_units = 0, clear_bytes = 0, bytes = 0;
+};
+BatchSumsLayout batch_sums_layout(const fdas_plan_s &p, int n_levels, const int32_t *H);
+hipError_t launch_batch_sums_mark(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, int n_levels,
+                                  const int32_t *H, const float *thr, void *scratch, hipStream_t s);
+hipError_t batch_sums_finish(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, void *scratch,
+                             fdas_peak *out, int64_t capacity, int64_t *n_found, hipStream_t s);
 hipError_t launch_harmonic_sums(const fdas_plan_s &p, const void *plane, int64_t n, int n_levels, const int32_t *H,
                                 void *const *outs, const PeakMarks *marks, hipStream_t st);
 // The same, also marking the peak tiles of the summed plane (marks from

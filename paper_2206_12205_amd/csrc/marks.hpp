@@ -63,6 +63,21 @@ __device__ __forceinline__ void mark_run(const PeakMarks &m, uint32_t row_tile0,
     }
 }
 
+// The harmonic-sum lists of a batch (fdas_batch_harmonic_sums_peaks): list
+// l * n_jobs + i holds the peaks of job i's sum over H_l harmonics, a virtual
+// plane of n_z x nh cells that is never stored (its flagged tiles are
+// recomputed from the job's plane).  Tiles and chunks of all lists share one
+// index space, lists in order.
+struct SumJob {
+    int64_t nh;          // columns of the sum (fundamentals r < N_H)
+    int64_t tile_base;   // first tile among all lists' tiles
+    int64_t chunk_base;  // first chunk
+    int64_t block_base;  // lists of the first level: first workgroup of the summing kernel
+    int32_t H, job;
+    float thr;
+    int32_t level;
+};
+
 // Largest row length a marking correlation accepts (32-bit columns with a
 // segment of headroom).
 constexpr int64_t kMarkMaxBins = ((int64_t)1 << 31) - 65536;

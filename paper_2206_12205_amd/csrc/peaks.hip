@@ -39,7 +39,7 @@ constexpr int kPeakThreads = 256;
 constexpr int kCellsPerThread = kPeakTileCols / kPeakThreads;   // 4
 
 // Workgroups of the count and write kernels (each owns a range of chunks).
-constexpr int kPeakGrid = 2048;
+constexpr int kPeakGrid = kBatchPeakGrid;
 
 // counts (int32) and flags (uint8) per tile, totals (int32) and flags per
 // chunk of 16 tiles, totals and offsets per workgroup, with padding
@@ -65,20 +65,34 @@ __device__ __forceinline__ double plane_val<unsigned short>(const unsigned short
 template <class PT>
 using peak_val_t = typename std::conditional<sizeof(PT) == 8, double, float>::type;
 
+// Cells of a stored plane (n columns per row).  stage() fills buf with
+// rows z-1..z+1, columns c0-1 .. c0+kPeakTileCols (-inf outside the n_c
+// columns and n_z rows).
 template <class PT>
-__device__ __forceinline__ int tile_flags(const PT *plane, int64_t n, int n_z, int z, int64_t c0, float thr_f,
-                                          peak_val_t<PT> (*buf)[kPeakTileCols + 2], bool *flag) {
+struct PlaneCells {
     using V = peak_val_t<PT>;
-    const V thr = (V)thr_f;
-    for (int i = threadIdx.x; i < 3 * (kPeakTileCols + 2); i += kPeakThreads) {
-        const int row = i / (kPeakTileCols + 2);
-        const int col = i % (kPeakTileCols + 2);
-        const int zz = z + row - 1;
-        const int64_t cc = c0 + col - 1;
-        V v = -INFINITY;
-        if (zz >= 0 && zz < n_z && cc >= 0 && cc < n) v = (V)plane_val<PT>(plane, (int64_t)zz * n + cc);
-        buf[row][col] = v;
+    const PT *plane;
+    int64_t n;
+    __device__ __forceinline__ void stage(V (*buf)[kPeakTileCols + 2], int64_t n_c, int n_z, int z,
+                                          int64_t c0) const {
+        for (int i = threadIdx.x; i < 3 * (kPeakTileCols + 2); i += kPeakThreads) {
+            const int row = i / (kPeakTileCols + 2);
+            const int col = i % (kPeakTileCols + 2);
+            const int zz = z + row - 1;
+            const int64_t cc = c0 + col - 1;
+            V v = -INFINITY;
+            if (zz >= 0 && zz < n_z && cc >= 0 && cc < n_c) v = (V)plane_val<PT>(plane, (int64_t)zz * n + cc);
+            buf[row][col] = v;
+        }
     }
+};
+
+template <class Cells>
+__device__ __forceinline__ int tile_flags(const Cells &cells, int64_t n, int n_z, int z, int64_t c0, float thr_f,
+                                          typename Cells::V (*buf)[kPeakTileCols + 2], bool *flag) {
+    using V = typename Cells::V;
+    const V thr = (V)thr_f;
+    cells.stage(buf, n, n_z, z, c0);
     __syncthreads();
     int cnt = 0;
 #pragma unroll
@@ -182,10 +196,10 @@ __global__ void __launch_bounds__(256) k_peak_mark(const PT *plane, int64_t n, i
 // Peaks of the flagged tiles of chunk ch of one plane (n_tiles tiles of
 // n_cb per row): counts[tile] for each flagged tile; returns the chunk's
 // total on thread 0.  Called by the whole workgroup; contains barriers.
-template <class PT>
-__device__ __forceinline__ int count_chunk(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles,
+template <class Cells>
+__device__ __forceinline__ int count_chunk(const Cells &cells, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles,
                                            int64_t ch, float thr, const uint8_t *flags, int32_t *counts,
-                                           peak_val_t<PT> (*buf)[kPeakTileCols + 2], int *sum) {
+                                           typename Cells::V (*buf)[kPeakTileCols + 2], int *sum) {
     int total = 0;   // thread 0: peaks of this chunk's tiles
     for (int i = 0; i < kTilesPerBlock; ++i) {
         const int64_t tile = ch * kTilesPerBlock + i;
@@ -195,7 +209,7 @@ __device__ __forceinline__ int count_chunk(const PT *plane, int64_t n, int n_z, 
         const int64_t c0 = (tile % n_cb) * kPeakTileCols;
         if (threadIdx.x == 0) *sum = 0;      // visible after the barrier inside tile_flags
         bool flag[kCellsPerThread];
-        const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
+        const int cnt = tile_flags(cells, n, n_z, z, c0, thr, buf, flag);
         if (cnt) atomicAdd(sum, cnt);
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -250,36 +264,145 @@ __device__ __forceinline__ int job_of_chunk(const fdas_batch_job *jobs, int n_jo
 
 // Where the chunks of a plane live: one plane, or a batch (chunk ch belongs
 // to job job_of_chunk(ch), whose tiles start at its tile_base).
+// A chunk's place: its cells, its plane's width and tiles, the chunk index
+// inside that plane, the plane's first tile, the threshold, the list it
+// writes to (slot) and the job its records name.
+template <class Cells>
+struct ChunkLocal {
+    Cells cells;
+    int64_t n, n_cb, n_tiles, ch, tile_base;
+    float thr;
+    int slot, job;
+};
+
 template <class PT>
 struct ChunkSource {
+    using Cells = PlaneCells<PT>;
+    using V = peak_val_t<PT>;
     const PT *plane;                  // single plane / the batch's planes buffer
     int64_t n, n_cb, n_tiles;         // single plane
     const fdas_batch_job *jobs;       // batch (null for a single plane)
     int n_jobs;
+    float thr;
 
-    struct Local {
-        const PT *plane;
-        int64_t n, n_cb, n_tiles, ch, tile_base;
-        int job;
-    };
-    __device__ __forceinline__ Local at(int64_t ch, int n_z) const {
-        if (!jobs) return Local{plane, n, n_cb, n_tiles, ch, 0, 0};
+    __device__ __forceinline__ ChunkLocal<Cells> at(int64_t ch, int n_z) const {
+        if (!jobs) return ChunkLocal<Cells>{Cells{plane, n}, n, n_cb, n_tiles, ch, 0, thr, 0, 0};
         const int jb = job_of_chunk(jobs, n_jobs, ch);
         const int64_t nb = jobs[jb].n_bins;
         const int64_t cb = (nb + kPeakTileCols - 1) / kPeakTileCols;
-        return Local{plane + jobs[jb].plane_off, nb, cb, cb * n_z, ch - jobs[jb].chunk_base, jobs[jb].tile_base,
-                     jb};
+        return ChunkLocal<Cells>{Cells{plane + jobs[jb].plane_off, nb}, nb, cb, cb * n_z, ch - jobs[jb].chunk_base,
+                                 jobs[jb].tile_base, thr, jb, jb};
+    }
+};
+
+// Cells of a harmonic sum that is never stored: S_H[z, r] = sum_{h <= H}
+// P[z_h, h r] over the job's plane, added in the order h = 1, 2, ... in the
+// summing kernel's precision and rounded to the plane's type as its store
+// would be, so every cell is bitwise the value the sum would hold.  rows:
+// [n_z][hmax] harmonic rows (-1: off the grid).  stage() takes the
+// harmonics in the outer loop and the thread's cells in the inner one, the
+// loads of kSumBatch harmonics issued before their additions, so a tile
+// costs about H / kSumBatch memory round trips, not one per harmonic and cell.
+constexpr int kSumBatch = 4;
+
+template <class PT>
+struct SumCells {
+    using V = peak_val_t<PT>;
+    const PT *plane;
+    int64_t n;                        // the job's bins (plane row length)
+    const int32_t *rows;
+    int hmax, H;
+    __device__ __forceinline__ void stage(V (*buf)[kPeakTileCols + 2], int64_t n_c, int n_z, int z,
+                                          int64_t c0) const {
+        constexpr int W = kPeakTileCols + 2;
+        constexpr int Q = (3 * W + kPeakThreads - 1) / kPeakThreads;   // cells per thread
+        V acc[Q];
+        bool in[Q];                   // cell inside the sum (row on the grid, column below n_c)
+        int trow[Q];                  // its template row 0..2 (z-1, z, z+1)
+        int64_t col[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = threadIdx.x + q * kPeakThreads;
+            trow[q] = i / W;
+            col[q] = c0 + (i - trow[q] * W) - 1;
+            const int zz = z + trow[q] - 1;
+            in[q] = i < 3 * W && zz >= 0 && zz < n_z && col[q] >= 0 && col[q] < n_c;
+            acc[q] = V(0);
+        }
+        for (int h = 1; h <= H; h += kSumBatch) {
+            V v[kSumBatch][Q];
+            int jr[kSumBatch][3];
+#pragma unroll
+            for (int u = 0; u < kSumBatch; ++u)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int zz = z + k - 1;
+                    jr[u][k] = (h + u <= H && zz >= 0 && zz < n_z) ? rows[zz * hmax + h + u - 1] : -1;
+                }
+#pragma unroll
+            for (int u = 0; u < kSumBatch; ++u)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int jh = trow[q] == 0 ? jr[u][0] : trow[q] == 1 ? jr[u][1] : jr[u][2];
+                    v[u][q] = (in[q] && jh >= 0) ? (V)plane_val<PT>(plane, (int64_t)jh * n + (int64_t)(h + u) * col[q])
+                                                 : V(0);
+                }
+#pragma unroll
+            for (int u = 0; u < kSumBatch; ++u)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int jh = trow[q] == 0 ? jr[u][0] : trow[q] == 1 ? jr[u][1] : jr[u][2];
+                    if (in[q] && jh >= 0) acc[q] += v[u][q];
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = threadIdx.x + q * kPeakThreads;
+            if (i >= 3 * W) continue;
+            V val = -INFINITY;
+            if (in[q]) {
+                if constexpr (sizeof(PT) == 2) val = (float)(__bf16)acc[q];   // the bfloat16 store, widened
+                else val = acc[q];
+            }
+            buf[trow[q]][i - trow[q] * W] = val;
+        }
+    }
+};
+
+template <class PT>
+struct SumSource {
+    using Cells = SumCells<PT>;
+    using V = peak_val_t<PT>;
+    const PT *planes;
+    const fdas_batch_job *jobs;
+    const SumJob *lists;
+    int n_lists;
+    const int32_t *rows;
+    int hmax;
+
+    __device__ __forceinline__ ChunkLocal<Cells> at(int64_t ch, int n_z) const {
+        int lo = 0, hi = n_lists - 1;   // the last list whose first chunk is <= ch
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (lists[mid].chunk_base <= ch) lo = mid;
+            else hi = mid - 1;
+        }
+        const SumJob &sj = lists[lo];
+        const fdas_batch_job &jb = jobs[sj.job];
+        const int64_t cb = (sj.nh + kPeakTileCols - 1) / kPeakTileCols;
+        return ChunkLocal<Cells>{Cells{planes + jb.plane_off, jb.n_bins, rows, hmax, sj.H}, sj.nh, cb, cb * n_z,
+                                 ch - sj.chunk_base, sj.tile_base, sj.thr, lo, sj.job};
     }
 };
 
 // Count: per flagged chunk its total (block_counts), per workgroup the sum
 // (wg_totals), per job the sum (job_totals, batch only: one atomic per
 // chunk with peaks, zeroed with the flags).
-template <class PT>
+template <class Src>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_count(ChunkSource<PT> src, int n_z, int64_t n_chunks, float thr, const uint8_t *flags, const uint8_t *cflags,
-             int32_t *counts, int32_t *block_counts, int32_t *wg_totals, unsigned long long *job_totals) {
-    __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
+k_peak_count(Src src, int n_z, int64_t n_chunks, const uint8_t *flags, const uint8_t *cflags, int32_t *counts,
+             int32_t *block_counts, int32_t *wg_totals, unsigned long long *job_totals) {
+    __shared__ typename Src::V buf[3][kPeakTileCols + 2];
     __shared__ int sum, list[kPeakThreads], wave_cnt[kPeakThreads / 64];
     int64_t r0, r1;
     chunk_range(n_chunks, &r0, &r1);
@@ -289,12 +412,12 @@ k_peak_count(ChunkSource<PT> src, int n_z, int64_t n_chunks, float thr, const ui
         for (int k = 0; k < nf; ++k) {
             const int64_t ch = c0 + list[k];
             const auto loc = src.at(ch, n_z);
-            const int t = count_chunk<PT>(loc.plane, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, thr,
-                                          flags + loc.tile_base, counts + loc.tile_base, buf, &sum);
+            const int t = count_chunk(loc.cells, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, loc.thr,
+                                      flags + loc.tile_base, counts + loc.tile_base, buf, &sum);
             if (threadIdx.x == 0) {
                 block_counts[ch] = t;
                 total += t;
-                if (job_totals && t) atomicAdd(&job_totals[loc.job], (unsigned long long)t);
+                if (job_totals && t) atomicAdd(&job_totals[loc.slot], (unsigned long long)t);
             }
         }
         __syncthreads();                         // list is rewritten by the next group
@@ -334,14 +457,14 @@ __global__ void __launch_bounds__(1024) k_peak_scan(const T *vals, int64_t n, in
 
 // Recompute the flags of one tile that holds peaks and write them at the
 // tile's offset in column order, dropping those at or beyond the capacity.
-template <class PT>
-__device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t tile,
+template <class Cells>
+__device__ __forceinline__ void write_tile(const Cells &cells, int64_t n, int n_z, int64_t n_cb, int64_t tile,
                                            float thr, int64_t tile_off, fdas_peak *out, int64_t capacity, int job,
-                                           peak_val_t<PT> (*buf)[kPeakTileCols + 2], int *pre) {
+                                           typename Cells::V (*buf)[kPeakTileCols + 2], int *pre) {
     const int z = (int)(tile / n_cb);
     const int64_t c0 = (tile % n_cb) * kPeakTileCols;
     bool flag[kCellsPerThread];
-    const int cnt = tile_flags<PT>(plane, n, n_z, z, c0, thr, buf, flag);
+    const int cnt = tile_flags(cells, n, n_z, z, c0, thr, buf, flag);
     pre[threadIdx.x] = cnt;
     __syncthreads();
     for (int w = 1; w < kPeakThreads; w <<= 1) {
@@ -370,18 +493,18 @@ __device__ __forceinline__ void write_tile(const PT *plane, int64_t n, int n_z, 
 
 // The peaks of chunk ch of one plane, written from offset off on.  Called by
 // the whole workgroup; contains barriers.
-template <class PT>
-__device__ __forceinline__ void write_chunk(const PT *plane, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles,
+template <class Cells>
+__device__ __forceinline__ void write_chunk(const Cells &cells, int64_t n, int n_z, int64_t n_cb, int64_t n_tiles,
                                             int64_t ch, float thr, const uint8_t *flags, const int32_t *counts,
                                             int64_t off, fdas_peak *out, int64_t capacity, int job,
-                                            peak_val_t<PT> (*buf)[kPeakTileCols + 2], int *pre) {
+                                            typename Cells::V (*buf)[kPeakTileCols + 2], int *pre) {
     for (int i = 0; i < kTilesPerBlock; ++i) {
         const int64_t tile = ch * kTilesPerBlock + i;
         if (tile >= n_tiles) break;
         if (flags[tile] == 0) continue;      // uniform: counts[tile] was not written
         const int cnt = counts[tile];
         if (cnt == 0) continue;              // uniform: no peak in this tile
-        write_tile<PT>(plane, n, n_z, n_cb, tile, thr, off, out, capacity, job, buf, pre);
+        write_tile(cells, n, n_z, n_cb, tile, thr, off, out, capacity, job, buf, pre);
         off += cnt;
         __syncthreads();                     // buf and pre are reused by the next tile
     }
@@ -390,12 +513,12 @@ __device__ __forceinline__ void write_chunk(const PT *plane, int64_t n, int n_z,
 // Write: each workgroup walks its flagged chunks in order from its offset;
 // a batch job's list starts at out + job * capacity and its offsets at the
 // job's prefix (job_prefix).
-template <class PT>
+template <class Src>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_write(ChunkSource<PT> src, int n_z, int64_t n_chunks, float thr, const uint8_t *flags, const uint8_t *cflags,
+k_peak_write(Src src, int n_z, int64_t n_chunks, const uint8_t *flags, const uint8_t *cflags,
              const int32_t *counts, const int32_t *block_counts, const int64_t *wg_offsets,
              const int64_t *job_prefix, fdas_peak *out, int64_t capacity) {
-    __shared__ peak_val_t<PT> buf[3][kPeakTileCols + 2];
+    __shared__ typename Src::V buf[3][kPeakTileCols + 2];
     __shared__ int pre[kPeakThreads], list[kPeakThreads], wave_cnt[kPeakThreads / 64];
     int64_t r0, r1;
     chunk_range(n_chunks, &r0, &r1);
@@ -407,10 +530,9 @@ k_peak_write(ChunkSource<PT> src, int n_z, int64_t n_chunks, float thr, const ui
             const int cnt = block_counts[ch];
             if (cnt == 0) continue;              // uniform
             const auto loc = src.at(ch, n_z);
-            const int64_t off = job_prefix ? run - job_prefix[loc.job] : run;
-            write_chunk<PT>(loc.plane, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, thr, flags + loc.tile_base,
-                            counts + loc.tile_base, off, out + (int64_t)loc.job * capacity, capacity, loc.job, buf,
-                            pre);
+            const int64_t off = job_prefix ? run - job_prefix[loc.slot] : run;
+            write_chunk(loc.cells, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, loc.thr, flags + loc.tile_base,
+                        counts + loc.tile_base, off, out + (int64_t)loc.slot * capacity, capacity, loc.job, buf, pre);
             run += cnt;
         }
         __syncthreads();                         // list is rewritten by the next group
@@ -464,21 +586,58 @@ unsigned mark_grid(int64_t total, size_t elem) {
 }
 
 // Count, scan and write over n_chunks chunks (flags already set).
-template <class PT>
-void launch_finish(const ChunkSource<PT> &src, int n_z, int64_t n_chunks, float thr, const uint8_t *flags,
-                   const uint8_t *cflags, int32_t *counts, int32_t *block_counts, int32_t *wg_totals,
-                   int64_t *wg_offsets, unsigned long long *job_totals, int64_t *job_prefix, int64_t *n_found,
+// Both scans of a batch in one workgroup: workgroup offsets, then the
+// per-list prefixes and counts.
+__global__ void __launch_bounds__(1024) k_peak_scan_batch(const int32_t *wg_totals, int64_t n_wg, int64_t *wg_offsets,
+                                                          const unsigned long long *job_totals, int64_t n_lists,
+                                                          int64_t *job_prefix, int64_t *n_found) {
+    __shared__ int64_t part[1024];
+    for (int round = 0; round < 2; ++round) {
+        const int64_t n = round == 0 ? n_wg : n_lists;
+        const int64_t per = (n + 1023) / 1024;
+        const int64_t b = threadIdx.x * per;
+        const int64_t e = min(b + per, n);
+        int64_t s = 0;
+        for (int64_t i = b; i < e; ++i) s += round == 0 ? (int64_t)wg_totals[i] : (int64_t)job_totals[i];
+        part[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 1; w < 1024; w <<= 1) {
+            const int64_t v = threadIdx.x >= (unsigned)w ? part[threadIdx.x - w] : 0;
+            __syncthreads();
+            part[threadIdx.x] += v;
+            __syncthreads();
+        }
+        int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+        for (int64_t i = b; i < e; ++i) {
+            const int64_t v = round == 0 ? (int64_t)wg_totals[i] : (int64_t)job_totals[i];
+            if (round == 0) {
+                wg_offsets[i] = run;
+            } else {
+                job_prefix[i] = run;
+                n_found[i] = v;
+            }
+            run += v;
+        }
+        if (round == 0 && threadIdx.x == 1023) wg_offsets[n_wg] = part[1023];
+        __syncthreads();
+    }
+}
+
+template <class Src>
+void launch_finish(const Src &src, int n_z, int64_t n_chunks, const uint8_t *flags, const uint8_t *cflags,
+                   int32_t *counts, int32_t *block_counts, int32_t *wg_totals, int64_t *wg_offsets,
+                   unsigned long long *job_totals, int64_t n_lists, int64_t *job_prefix, int64_t *n_found,
                    fdas_peak *out, int64_t cap, hipStream_t st) {
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_chunks, kPeakGrid));
-    hipLaunchKernelGGL(k_peak_count<PT>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, thr, flags, cflags,
+    hipLaunchKernelGGL(k_peak_count<Src>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, flags, cflags,
                        counts, block_counts, wg_totals, job_totals);
-    // workgroup offsets; a single plane's total is its count
-    hipLaunchKernelGGL(k_peak_scan<int32_t>, dim3(1), dim3(1024), 0, st, wg_totals, (int64_t)grid, wg_offsets,
-                       job_totals ? wg_offsets + grid : n_found, (int64_t *)nullptr);
-    if (job_totals)   // per-job prefixes and counts
-        hipLaunchKernelGGL(k_peak_scan<unsigned long long>, dim3(1), dim3(1024), 0, st, job_totals,
-                           (int64_t)src.n_jobs, job_prefix, wg_offsets + grid, n_found);
-    hipLaunchKernelGGL(k_peak_write<PT>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, thr, flags, cflags,
+    if (job_totals)   // workgroup offsets, per-list prefixes and counts
+        hipLaunchKernelGGL(k_peak_scan_batch, dim3(1), dim3(1024), 0, st, wg_totals, (int64_t)grid, wg_offsets,
+                           job_totals, n_lists, job_prefix, n_found);
+    else              // workgroup offsets; a single plane's total is its count
+        hipLaunchKernelGGL(k_peak_scan<int32_t>, dim3(1), dim3(1024), 0, st, wg_totals, (int64_t)grid, wg_offsets,
+                           n_found, (int64_t *)nullptr);
+    hipLaunchKernelGGL(k_peak_write<Src>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, flags, cflags,
                        counts, block_counts, wg_offsets, job_prefix, out, cap);
 }
 
@@ -493,9 +652,9 @@ hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, fdas
         hipLaunchKernelGGL(k_peak_mark<PT>, dim3(mark_grid(total, sizeof(PT))), dim3(256), 0, st, plane, n, total,
                            make_peak_marks(sc.flags, sc.cflags, sc.n_cb, thr));
     }
-    ChunkSource<PT> src{plane, n, sc.n_cb, sc.n_tiles, nullptr, 0};
-    launch_finish<PT>(src, p.cfg.n_z, sc.n_chunks, thr, sc.flags, sc.cflags, sc.counts, sc.block_counts,
-                      sc.wg_totals, sc.wg_offsets, nullptr, nullptr, n_found, out, cap, st);
+    ChunkSource<PT> src{plane, n, sc.n_cb, sc.n_tiles, nullptr, 0, thr};
+    launch_finish(src, p.cfg.n_z, sc.n_chunks, sc.flags, sc.cflags, sc.counts, sc.block_counts, sc.wg_totals,
+                  sc.wg_offsets, nullptr, 0, nullptr, n_found, out, cap, st);
     return hipGetLastError();
 }
 
@@ -553,9 +712,9 @@ hipError_t run_batch_finish(const fdas_plan_s &p, const PT *planes, void *scratc
     const BatchScratch sc = batch_scratch(p, scratch);
     const auto *jobs = reinterpret_cast<const fdas_batch_job *>(static_cast<const unsigned char *>(p.ws) +
                                                                p.off_batch + p.batch_hdr);
-    ChunkSource<PT> src{planes, 0, 0, 0, jobs, p.batch_jobs};
-    launch_finish<PT>(src, p.cfg.n_z, p.batch_peak_chunks, thr, sc.flags, sc.cflags, sc.counts, sc.block_counts,
-                      sc.wg_totals, sc.wg_offsets, sc.job_totals, sc.job_prefix, n_found, out, cap, st);
+    ChunkSource<PT> src{planes, 0, 0, 0, jobs, p.batch_jobs, thr};
+    launch_finish(src, p.cfg.n_z, p.batch_peak_chunks, sc.flags, sc.cflags, sc.counts, sc.block_counts,
+                  sc.wg_totals, sc.wg_offsets, sc.job_totals, p.batch_jobs, sc.job_prefix, n_found, out, cap, st);
     return hipGetLastError();
 }
 
@@ -599,9 +758,9 @@ hipError_t finish_plane(const fdas_plan_s &p, const PT *plane, int64_t n, float 
     auto *counts = reinterpret_cast<int32_t *>(b + off);
     off += up256((size_t)n_tiles * sizeof(int32_t));
     auto *block_counts = reinterpret_cast<int32_t *>(b + off);
-    ChunkSource<PT> src{plane, n, n_cb, n_tiles, nullptr, 0};
-    launch_finish<PT>(src, p.cfg.n_z, n_chunks, thr, flags, cflags, counts, block_counts, wg_totals, wg_offsets,
-                      nullptr, nullptr, n_found, out, cap, st);
+    ChunkSource<PT> src{plane, n, n_cb, n_tiles, nullptr, 0, thr};
+    launch_finish(src, p.cfg.n_z, n_chunks, flags, cflags, counts, block_counts, wg_totals, wg_offsets, nullptr, 0,
+                  nullptr, n_found, out, cap, st);
     return hipGetLastError();
 }
 
@@ -669,6 +828,39 @@ hipError_t batch_peaks_finish(const fdas_plan_s &p, const void *planes, void *sc
         case FDAS_FP64:
             return run_batch_finish<double>(p, static_cast<const double *>(planes), scratch, thr, out, capacity,
                                             n_found, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class PT>
+hipError_t run_batch_sums_finish(const fdas_plan_s &p, const BatchSumsLayout &L, const PT *planes,
+                                 unsigned char *b, fdas_peak *out, int64_t cap, int64_t *n_found, hipStream_t st) {
+    const auto *jobs = reinterpret_cast<const fdas_batch_job *>(static_cast<const unsigned char *>(p.ws) +
+                                                               p.off_batch + p.batch_hdr);
+    auto *totals = reinterpret_cast<unsigned long long *>(b + L.off_totals);
+    uint8_t *flags = b + L.off_totals + (size_t)L.lists * 8;
+    SumSource<PT> src{planes, jobs, reinterpret_cast<const SumJob *>(b + L.off_lists), (int)L.lists,
+                      reinterpret_cast<const int32_t *>(b + L.off_rows), L.hmax};
+    launch_finish(src, p.cfg.n_z, L.chunks, flags, flags + L.tiles, reinterpret_cast<int32_t *>(b + L.off_counts),
+                  reinterpret_cast<int32_t *>(b + L.off_block_counts), reinterpret_cast<int32_t *>(b + L.off_wg_totals),
+                  reinterpret_cast<int64_t *>(b + L.off_wg_offsets), totals, L.lists,
+                  reinterpret_cast<int64_t *>(b + L.off_prefix), n_found, out, cap, st);
+    return hipGetLastError();
+}
+
+hipError_t batch_sums_finish(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, void *scratch,
+                             fdas_peak *out, int64_t capacity, int64_t *n_found, hipStream_t st) {
+    auto *b = static_cast<unsigned char *>(scratch);
+    switch (p.cfg.plane_dtype) {
+        case FDAS_FP32:
+            return run_batch_sums_finish<float>(p, L, static_cast<const float *>(planes), b, out, capacity, n_found,
+                                                st);
+        case FDAS_BF16:
+            return run_batch_sums_finish<unsigned short>(p, L, static_cast<const unsigned short *>(planes), b, out,
+                                                         capacity, n_found, st);
+        case FDAS_FP64:
+            return run_batch_sums_finish<double>(p, L, static_cast<const double *>(planes), b, out, capacity,
+                                                 n_found, st);
         default: return hipErrorInvalidValue;
     }
 }

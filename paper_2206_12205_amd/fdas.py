@@ -114,6 +114,10 @@ def lib() -> ctypes.CDLL:
         L.fdas_harmonic_sums_peaks_noalloc.argtypes = [P, P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(P),
                                                        ctypes.POINTER(ctypes.c_float), ctypes.POINTER(P), I64, P,
                                                        P]
+        L.fdas_batch_harmonic_sums_peaks_workspace.argtypes = [P, I32, ctypes.POINTER(I32),
+                                                               ctypes.POINTER(ctypes.c_size_t)]
+        L.fdas_batch_harmonic_sums_peaks.argtypes = [P, P, I32, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_float),
+                                                     P, I64, P, P, ctypes.c_size_t, P]
         L.fdas_band_max.argtypes = [P, P, I64, P, I32, P, P]
         L.fdas_prepare_workspace.argtypes = [I64, ctypes.POINTER(ctypes.c_size_t)]
         L.fdas_prepare.argtypes = [P, I64, P, P, ctypes.c_size_t, P]
@@ -481,6 +485,47 @@ class Plan:
         _check(lib().fdas_harmonic_sums_peaks_noalloc(self._h, ctypes.c_void_p(plane), int(n), len(hs), harr, oarr,
                                                       tarr, parr, int(cap), ctypes.c_void_p(n_found),
                                                       _stream_ptr(stream)), "fdas_harmonic_sums_peaks_noalloc")
+
+    def batch_sums_peaks_bytes(self, n_harms):
+        """Scratch bytes of fdas_batch_harmonic_sums_peaks for the stored batch."""
+        hs = [int(h) for h in n_harms]
+        nb = ctypes.c_size_t(0)
+        _check(lib().fdas_batch_harmonic_sums_peaks_workspace(self._h, len(hs), (ctypes.c_int32 * len(hs))(*hs),
+                                                              ctypes.byref(nb)),
+               "fdas_batch_harmonic_sums_peaks_workspace")
+        return nb.value
+
+    def batch_sums_peaks_async(self, planes_ptr, n_harms, thresholds, peaks_ptr, capacity, n_found_ptr, scratch,
+                               stream=None):
+        """Enqueue fdas_batch_harmonic_sums_peaks on raw device pointers:
+        peaks_ptr holds n_levels x n_jobs x capacity records, n_found_ptr
+        n_levels x n_jobs int64, scratch a uint8 tensor of
+        batch_sums_peaks_bytes.  No host synchronisation."""
+        hs = [int(h) for h in n_harms]
+        harr = (ctypes.c_int32 * len(hs))(*hs)
+        tarr = (ctypes.c_float * len(hs))(*[float(t) for t in thresholds])
+        _check(lib().fdas_batch_harmonic_sums_peaks(self._h, ctypes.c_void_p(planes_ptr), len(hs), harr, tarr,
+                                                    ctypes.c_void_p(peaks_ptr), int(capacity),
+                                                    ctypes.c_void_p(n_found_ptr), ctypes.c_void_p(scratch.data_ptr()),
+                                                    scratch.numel(), _stream_ptr(stream)),
+               "fdas_batch_harmonic_sums_peaks")
+
+    def batch_sums_peaks(self, planes, n_harms, thresholds, capacity=1 << 12, stream=None, truncate=False):
+        """Peaks of every job's harmonic sums of the stored batch
+        (fdas_batch_harmonic_sums_peaks) -> list over levels of lists over
+        jobs of peaks dicts; overflow of any list as for peaks()."""
+        import torch
+        hs = [int(h) for h in n_harms]
+        n_jobs = len(self.batch_offsets)
+        pk = torch.empty((len(hs), n_jobs, max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
+        nf = torch.zeros((len(hs), n_jobs), dtype=torch.int64, device=self.device)
+        scr = torch.empty(max(self.batch_sums_peaks_bytes(hs), 1), dtype=torch.uint8, device=self.device)
+        self.batch_sums_peaks_async(planes.data_ptr(), hs, thresholds, pk.data_ptr(), capacity, nf.data_ptr(), scr,
+                                    stream)
+        found, over = peak_counts(nf, len(hs) * n_jobs, capacity, stream)
+        res = [[peak_records(pk[l, i], found[l * n_jobs + i], capacity) for i in range(n_jobs)]
+               for l in range(len(hs))]
+        return _capacity_result("fdas_batch_harmonic_sums_peaks", over, truncate, res)
 
     def harmonic_sums_peaks_bytes(self, n, n_harms):
         hs = [int(h) for h in n_harms]

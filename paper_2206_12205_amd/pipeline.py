@@ -9,10 +9,10 @@ over the batch runs, per chunk, fdas_correlate_batch_peaks: one persistent
 correlation launch that also flags the peak finder's tiles while it stores
 the planes, then one count, scan and write over all of the chunk's planes
 (fused=False instead runs fdas_correlate_batch and fdas_peaks on every job's
-plane); with harmonics, every job's plane is then summed over its first H
-harmonics for every requested H in one pass (fdas_harmonic_sums) and each
-sum thresholded (fdas_peaks).  The full set of planes (tens of GB in BF16 for hundreds of trials)
-is never held at once.  A pass issues kernels only, so it can be recorded
+plane); with harmonics, one fdas_batch_harmonic_sums_peaks call per chunk
+then finds the thresholded peaks of every job's sums over its first H
+harmonics, for every requested H, without storing the sums.  The full set of
+planes (tens of GB in BF16 for hundreds of trials) is never held at once.  A pass issues kernels only, so it can be recorded
 once as a HIP graph (capture) and replayed.
 """
 from __future__ import annotations
@@ -31,10 +31,9 @@ class BatchSearch:
     buffer_bytes size of the reused plane buffer
     tune         measure the kernel configuration per length class (else the
                  library's defaults)
-    harmonics    {H: threshold} for H > 1: every job's plane is also summed
-                 over its first H harmonics (all H in one fdas_harmonic_sums
-                 pass, the sums through one reused buffer) and each sum
-                 thresholded
+    harmonics    {H: threshold} for H > 1: the peaks of every job's sum over
+                 its first H harmonics are found too (all H and all jobs of a
+                 chunk in one fdas_batch_harmonic_sums_peaks call)
     """
 
     def __init__(self, lengths, z_min, z_step, n_z, n_taps, compute="bf16", plane_dtype="bf16",
@@ -104,34 +103,26 @@ class BatchSearch:
             F._check(F.lib().fdas_batch_peaks_workspace(pl._h, ctypes.byref(nb)), "fdas_batch_peaks_workspace")
             need = max(need, nb.value)
         self.peak_scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
-        # harmonic sums: one buffer for the largest job's smallest-H sum, one
-        # peak list per (H, job)
+        # harmonic sums: per chunk one fdas_batch_harmonic_sums_peaks call (the
+        # sums of every job of the chunk, never stored); its lists (level l,
+        # job k of the chunk) at list_base[chunk] + l * jobs_in_chunk + k
         self.harmonics = {int(h): float(t) for h, t in (harmonics or {}).items()}
         if any(h < 2 for h in self.harmonics):
             raise ValueError("harmonics are sums over H >= 2 harmonics")
-        self.hpeaks_raw, self.hn_found = {}, {}
         if self.harmonics:
-            # one region per H, all sums of a job written by one pass
-            self.sum_offs, tot = {}, 0
-            for h in sorted(self.harmonics):
-                self.sum_offs[h] = tot
-                tot += self.n_z * ((max_job - 1) // h + 1)
-                tot = (tot + 127) // 128 * 128         # keep every region 256-byte aligned
-            self.sum_buffer = torch.empty(tot, dtype=self.buffer.dtype, device=self.device)
-            for h in self.harmonics:
-                self.hpeaks_raw[h] = torch.empty((len(self.lengths), self.peak_capacity, 24), dtype=torch.uint8,
-                                                 device=self.device)
-            # counts of one job's sums side by side (the call writes them together)
-            self.hn_found_all = torch.zeros((len(self.lengths), len(self.harmonics)), dtype=torch.int64,
-                                            device=self.device).t()
-            for l, h in enumerate(sorted(self.harmonics)):
-                self.hn_found[h] = self.hn_found_all[l]
-            # scratch of the fused sums-with-peaks call, for the longest job of any chunk
             hs = sorted(self.harmonics)
-            need = 0
+            self.list_base, tot, need = [], 0, 0
             for pl, jobs, _, _ in self.chunks:
-                need = max(need, pl.harmonic_sums_peaks_bytes(max(self.lengths[i] for i in jobs), hs))
+                self.list_base.append(tot)
+                tot += len(hs) * len(jobs)
+                need = max(need, pl.batch_sums_peaks_bytes(hs))
+            self.hpeaks_all = torch.empty((tot, self.peak_capacity, 24), dtype=torch.uint8, device=self.device)
+            self.hn_found_all = torch.zeros(tot, dtype=torch.int64, device=self.device)
             self.sums_scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
+            self.chunk_of = {}
+            for c, (_, jobs, _, _) in enumerate(self.chunks):
+                for k, i in enumerate(jobs):
+                    self.chunk_of[i] = (c, k)
 
     def _chunk(self, jobs, cmax, knobs, common):
         pl = F.Plan(max_bins=cmax, max_jobs=len(jobs), device=self.device, **knobs, **common)
@@ -166,7 +157,7 @@ class BatchSearch:
         esz = self.buffer.element_size()
         sp = ctypes.c_void_p(spectra.data_ptr())
         buf = ctypes.c_void_p(self.buffer.data_ptr())
-        for pl, jobs, offs, slot0 in self.chunks:
+        for c, (pl, jobs, offs, slot0) in enumerate(self.chunks):
             if find_peaks and fused:
                 F._check(L.fdas_correlate_batch_peaks(
                     pl._h, sp, buf, float(threshold), ctypes.c_void_p(self.peaks_raw[slot0].data_ptr()),
@@ -181,22 +172,13 @@ class BatchSearch:
                                           ctypes.c_void_p(self.peaks_raw[slot0 + k].data_ptr()), self.peak_capacity,
                                           ctypes.c_void_p(self.n_found[slot0 + k:].data_ptr()), s),
                              "fdas_peaks")
-            if not find_peaks:
-                continue
-            if not self.harmonics:
+            if not find_peaks or not self.harmonics:
                 continue
             hs = sorted(self.harmonics)
-            harr = (ctypes.c_int32 * len(hs))(*hs)
-            sptr = [self.sum_buffer.data_ptr() + self.sum_offs[h] * esz for h in hs]
-            parr = (ctypes.c_void_p * len(hs))(*sptr)
-            tarr = (ctypes.c_float * len(hs))(*[self.harmonics[h] for h in hs])
-            for k, (i, po) in enumerate(zip(jobs, offs)):   # harmonic sums of every job's plane, one pass
-                pkarr = (ctypes.c_void_p * len(hs))(*[self.hpeaks_raw[h][slot0 + k].data_ptr() for h in hs])
-                F._check(L.fdas_harmonic_sums_peaks(
-                    pl._h, ctypes.c_void_p(self.buffer.data_ptr() + po * esz), self.lengths[i], len(hs), harr, parr,
-                    tarr, pkarr, self.peak_capacity, ctypes.c_void_p(self.hn_found_all[:, slot0 + k].data_ptr()),
-                    ctypes.c_void_p(self.sums_scratch.data_ptr()), self.sums_scratch.numel(), s),
-                    "fdas_harmonic_sums_peaks")
+            lb = self.list_base[c]
+            pl.batch_sums_peaks_async(self.buffer.data_ptr(), hs, [self.harmonics[h] for h in hs],
+                                      self.hpeaks_all[lb].data_ptr(), self.peak_capacity,
+                                      self.hn_found_all[lb:].data_ptr(), self.sums_scratch, stream)
 
     def capture(self, spectra, threshold, find_peaks=True, fused=True):
         """Record one pass (run) into a HIP graph and return it
@@ -223,10 +205,16 @@ class BatchSearch:
         overflowed peak_capacity raises fdas.PeakCapacityError (its first
         entries and true count in the error's result) unless truncate is set."""
         import numpy as np
-        raw_all, nf = (self.peaks_raw, self.n_found) if H == 1 else (self.hpeaks_raw[H], self.hn_found[H])
-        found = int(nf[self.slot[i]].item())
+        if H == 1:
+            raw_all, nf, row = self.peaks_raw, self.n_found, self.slot[i]
+        else:
+            c, k = self.chunk_of[i]
+            lvl = sorted(self.harmonics).index(H)
+            raw_all, nf = self.hpeaks_all, self.hn_found_all
+            row = self.list_base[c] + lvl * len(self.chunks[c][1]) + k
+        found = int(nf[row].item())
         k = min(found, self.peak_capacity)
-        raw = raw_all[self.slot[i], :k].cpu().numpy()
+        raw = raw_all[row, :k].cpu().numpy()
         rec = raw.view(np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"),
                                  ("power", "<f4"), ("reserved", "<f4")])).reshape(-1)
         res = {"z_idx": rec["z_idx"].copy(), "r": rec["r"].copy(), "power": rec["power"].copy(),

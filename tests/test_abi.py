@@ -368,3 +368,33 @@ def test_sums_peaks_noalloc_checks_on_host():
         assert need.value > F.NOALLOC_SCRATCH_BYTES
         return call(h, 1 << 24, hs)
     assert with_plan(big, too_big) == F.E_WORKSPACE
+
+
+def test_batch_sums_checks_on_host():
+    """fdas_batch_harmonic_sums_peaks(_workspace): bad levels are refused and
+    a plan with no stored batch answers FDAS_E_STATE, before any device call."""
+    L = F.lib()
+    P = ctypes.c_void_p
+    h = P()
+    nb = ctypes.c_size_t()
+    assert L.fdas_plan(ctypes.byref(make(compute="bf16", plane_dtype="bf16")), ctypes.byref(h),
+                       ctypes.byref(nb)) == F.OK
+    try:
+        def ws(hs):
+            need = ctypes.c_size_t()
+            return L.fdas_batch_harmonic_sums_peaks_workspace(h, len(hs), (ctypes.c_int32 * len(hs))(*hs),
+                                                              ctypes.byref(need))
+
+        def run(hs):
+            k = len(hs)
+            return L.fdas_batch_harmonic_sums_peaks(h, P(0x10000), k, (ctypes.c_int32 * k)(*hs),
+                                                    (ctypes.c_float * k)(*[10.0] * k), P(0x40000), 16,
+                                                    P(0x20000), P(0x50000), 1 << 20, None)
+        assert ws([]) == F.E_INVALID
+        assert ws([4, 2]) == F.E_INVALID                  # increasing H
+        assert ws(list(range(2, 11))) == F.E_INVALID      # more than 8 levels
+        assert ws([2, 4]) == F.E_STATE                    # no batch stored
+        assert run([2, 4]) == F.E_STATE
+        assert L.fdas_batch_harmonic_sums_peaks_workspace(h, 2, (ctypes.c_int32 * 2)(2, 4), None) == F.E_INVALID
+    finally:
+        L.fdas_destroy(h)

@@ -1,0 +1,87 @@
+"""GPU checks of fdas_batch_harmonic_sums_peaks: the harmonic sums of every
+job of a batch with their thresholded peaks, the sums never stored.
+
+Bars (integer and index work on the same planes): every (level, job) list
+is bitwise the list fdas_harmonic_sums_peaks gives for that job's plane (the
+same cells in the same order, the same powers, the same true count), and the
+oracle's peak definition applied to the oracle's sum of the GPU plane
+(oracle/harmonic.py, rounded to the plane type as the stored sum is) gives the
+same cells.  Ragged jobs (1 .. 200,000 bins), BF16 / FP32 / FP64 planes,
+thresholds with few peaks, many peaks (small capacity: the first entries and
+the true count) and none.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import harmonic as HS
+from oracle import peaks as OK_PEAKS
+
+pytestmark = pytest.mark.gpu
+
+ZMIN, ZSTEP, NZ, M = -16.0, 2.0, 17, 128
+LENGTHS = [70001, 1, 3839, 12345, 200000, 517, 1025, 40000]
+REC = np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"), ("power", "<f4"), ("reserved", "<f4")])
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def noise_planes(dev, pl, seed, dtype):
+    """Exp(1) noise planes for the stored batch with a few bright cells."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    P = -torch.log1p(-torch.rand(pl.batch_cells, generator=g, dtype=torch.float64))
+    idx = torch.randint(0, pl.batch_cells, (60,), generator=g)
+    P[idx] = 20.0 + 40.0 * torch.rand(60, generator=g, dtype=torch.float64)
+    return P.to(dtype).to(dev).contiguous()
+
+
+@pytest.mark.parametrize("plane_dtype", ["bf16", "fp32", "fp64"])
+def test_batch_sums_match_per_job_calls(dev, plane_dtype):
+    import torch
+    from paper_2206_12205_amd.fdas import Plan
+    tdt = {"bf16": torch.bfloat16, "fp32": torch.float32, "fp64": torch.float64}[plane_dtype]
+    compute = "fp64" if plane_dtype == "fp64" else "fp32"
+    pl = Plan(max_bins=max(LENGTHS), z_min=ZMIN, z_step=ZSTEP, n_z=NZ, n_taps=M, compute=compute,
+              plane_dtype=plane_dtype, device=dev, max_jobs=len(LENGTHS))
+    pl.set_batch(LENGTHS)
+    planes = noise_planes(dev, pl, 7, tdt)
+    hs = [2, 4, 8, 16]
+    cases = (([12.0, 16.0, 24.0, 36.0], 1 << 14), ([6.0, 9.0, 14.0, 24.0], 40), ([1e9] * 4, 4))
+    for thr, cap in cases:
+        say(f"[batch sums] {plane_dtype} thresholds {thr} capacity {cap}")
+        got = pl.batch_sums_peaks(planes, hs, thr, capacity=cap, truncate=True)
+        for i, n in enumerate(LENGTHS):
+            P = pl.batch_plane(planes, i).contiguous()
+            _, want = pl.harmonic_sums_peaks(P, hs, thr, capacity=cap, truncate=True)
+            for l, h in enumerate(hs):
+                a, b = got[l][i], want[l]
+                what = f"job {i} (n={n}) H={h}"
+                assert a["n_found"] == b["n_found"], what
+                assert np.array_equal(a["z_idx"], b["z_idx"]) and np.array_equal(a["r"], b["r"]), what
+                assert np.array_equal(a["power"], b["power"]), what
+                assert np.all(a["job"] == i), what
+        # the oracle on the two longest jobs at the first thresholds
+        if cap == 1 << 14:
+            for i in (4, 0):
+                host = pl.batch_plane(planes, i).to(torch.float64).cpu().numpy()
+                for l, h in enumerate(hs):
+                    S = HS.harmonic_sum(host, ZMIN, ZSTEP, h)
+                    if plane_dtype == "bf16":
+                        S = torch.from_numpy(S.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+                    elif plane_dtype == "fp32":
+                        S = S.astype(np.float32).astype(np.float64)
+                    j, r, _ = OK_PEAKS.peaks(S, thr[l])
+                    a = got[l][i]
+                    # the GPU adds in single precision (BF16 / FP32 planes), the
+                    # oracle in double: compare the cells whose margins clear
+                    # that rounding (one bfloat16 step for BF16 sums)
+                    tol = {"bf16": 1e-2, "fp32": 1e-5, "fp64": 1e-9}[plane_dtype]
+                    amb = OK_PEAKS.margins(S, j, r, thr[l]) < tol
+                    oset = {x for x, m in zip(zip(j.tolist(), r.tolist()), amb) if not m}
+                    gset = set(zip(a["z_idx"].tolist(), a["r"].tolist()))
+                    assert oset <= gset, f"job {i} H={h}: {sorted(oset - gset)[:5]}"

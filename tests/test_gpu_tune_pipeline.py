@@ -161,7 +161,7 @@ def test_batch_search_graph_replays_match_eager(dev):
 def test_batch_search_harmonic_sums_match_single_plans(dev):
     """Harmonic sums in the batched search: each job's list for H = 2 and 4
     equals fdas_harmonic_sum_peaks on the plane of a single plan with the
-    same knobs (the sums pass through one reused buffer)."""
+    same knobs (one batched sums call per chunk, the sums never stored)."""
     import torch
     from paper_2206_12205_amd.fdas import Plan
     from paper_2206_12205_amd.pipeline import BatchSearch
