@@ -300,11 +300,12 @@ struct ChunkSource {
 // summing kernel's precision and rounded to the plane's type as its store
 // would be, so every cell is bitwise the value the sum would hold.  rows:
 // [n_z][hmax] harmonic rows (-1: off the grid).  stage() takes the
-// harmonics in the outer loop and the thread's cells in the inner one, the
-// loads of kSumBatch harmonics issued before their additions, so a tile
-// costs about H / kSumBatch memory round trips, not one per harmonic and cell.
-constexpr int kSumBatch = 4;
-
+// harmonics in the outer loop and the three template rows and the thread's
+// cells inside it; no load sits behind a branch (a cell left out reads the
+// row's first cell and keeps its sum), so the 15 loads of a harmonic are in
+// flight together and a tile costs about H memory round trips.  A load is
+// a buffer load (the row as a resource, a 32-bit byte offset) when a row
+// holds less than 4 GB.
 template <class PT>
 struct SumCells {
     using V = peak_val_t<PT>;
@@ -312,60 +313,74 @@ struct SumCells {
     int64_t n;                        // the job's bins (plane row length)
     const int32_t *rows;
     int hmax, H;
+
+    __device__ __forceinline__ static V load(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+        if constexpr (sizeof(PT) == 8)
+            return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        else if constexpr (sizeof(PT) == 4)
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        else
+            return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0) << 16);
+    }
+
     __device__ __forceinline__ void stage(V (*buf)[kPeakTileCols + 2], int64_t n_c, int n_z, int z,
                                           int64_t c0) const {
         constexpr int W = kPeakTileCols + 2;
-        constexpr int Q = (3 * W + kPeakThreads - 1) / kPeakThreads;   // cells per thread
-        V acc[Q];
-        bool in[Q];                   // cell inside the sum (row on the grid, column below n_c)
-        int trow[Q];                  // its template row 0..2 (z-1, z, z+1)
-        int64_t col[Q];
+        constexpr int Q = (W + kPeakThreads - 1) / kPeakThreads;        // cells per thread and row
+        const bool wide = n >= (int64_t)(0xffffffffu / sizeof(PT));
+        const int32_t row_bytes = (int32_t)(uint32_t)(n * (int64_t)sizeof(PT));
+        V acc[3][Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int i = threadIdx.x + q * kPeakThreads;
-            trow[q] = i / W;
-            col[q] = c0 + (i - trow[q] * W) - 1;
-            const int zz = z + trow[q] - 1;
-            in[q] = i < 3 * W && zz >= 0 && zz < n_z && col[q] >= 0 && col[q] < n_c;
-            acc[q] = V(0);
-        }
-        for (int h = 1; h <= H; h += kSumBatch) {
-            V v[kSumBatch][Q];
-            int jr[kSumBatch][3];
+        for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int u = 0; u < kSumBatch; ++u)
+            for (int q = 0; q < Q; ++q) acc[k][q] = V(0);
+        for (int h = 1; h <= H; ++h) {
+            int jr[3];
+            V v[3][Q];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int zz = z + k - 1;
-                    jr[u][k] = (h + u <= H && zz >= 0 && zz < n_z) ? rows[zz * hmax + h + u - 1] : -1;
-                }
-#pragma unroll
-            for (int u = 0; u < kSumBatch; ++u)
+            for (int k = 0; k < 3; ++k) {
+                const int zz = z + k - 1;
+                jr[k] = (zz >= 0 && zz < n_z) ? __builtin_amdgcn_readfirstlane(rows[zz * hmax + h - 1]) : -1;
+                const PT *base = plane + (int64_t)max(jr[k], 0) * n;
+                const __amdgpu_buffer_rsrc_t rs =
+                    __builtin_amdgcn_make_buffer_rsrc(const_cast<PT *>(base), (short)0, row_bytes, 0x00020000);
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    const int jh = trow[q] == 0 ? jr[u][0] : trow[q] == 1 ? jr[u][1] : jr[u][2];
-                    v[u][q] = (in[q] && jh >= 0) ? (V)plane_val<PT>(plane, (int64_t)jh * n + (int64_t)(h + u) * col[q])
-                                                 : V(0);
+                    const int x = threadIdx.x + q * kPeakThreads;
+                    const int64_t col = c0 - 1 + x;
+                    const bool ok = x < W && jr[k] >= 0 && col >= 0 && col < n_c;
+                    if (!wide) {
+                        v[k][q] = load(rs, ok ? (uint32_t)h * (uint32_t)col * (uint32_t)sizeof(PT) : 0u);
+                    } else {
+                        v[k][q] = (V)plane_val<PT>(base, ok ? (int64_t)h * col : 0);
+                    }
                 }
-#pragma unroll
-            for (int u = 0; u < kSumBatch; ++u)
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const int jh = trow[q] == 0 ? jr[u][0] : trow[q] == 1 ? jr[u][1] : jr[u][2];
-                    if (in[q] && jh >= 0) acc[q] += v[u][q];
-                }
-        }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int i = threadIdx.x + q * kPeakThreads;
-            if (i >= 3 * W) continue;
-            V val = -INFINITY;
-            if (in[q]) {
-                if constexpr (sizeof(PT) == 2) val = (float)(__bf16)acc[q];   // the bfloat16 store, widened
-                else val = acc[q];
             }
-            buf[trow[q]][i - trow[q] * W] = val;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int x = threadIdx.x + q * kPeakThreads;
+                    const int64_t col = c0 - 1 + x;
+                    const bool ok = x < W && jr[k] >= 0 && col >= 0 && col < n_c;
+                    acc[k][q] = ok ? acc[k][q] + v[k][q] : acc[k][q];
+                }
         }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int x = threadIdx.x + q * kPeakThreads;
+                if (x >= W) continue;
+                const int zz = z + k - 1;
+                const int64_t col = c0 - 1 + x;
+                V val = -INFINITY;
+                if (zz >= 0 && zz < n_z && col >= 0 && col < n_c) {
+                    if constexpr (sizeof(PT) == 2) val = (float)(__bf16)acc[k][q];   // the bfloat16 store, widened
+                    else val = acc[k][q];
+                }
+                buf[k][x] = val;
+            }
     }
 };
 
