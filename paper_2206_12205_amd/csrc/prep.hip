@@ -399,6 +399,17 @@ struct FsState {
     float scale;        // 1 / sqrt(median / ln 2)
 };
 
+// Workgroups are dispatched to the 8 XCDs in turn (block b to XCD b mod 8),
+// each XCD with its own L2.  Pass 1 reads C complex values (as little as 32
+// bytes) of every row and pass 2 writes 32-byte runs of the spectrum, so
+// neighbouring blocks share cache lines: the blocks of one XCD take
+// consecutive indices, so that those lines meet in one L2 and leave it once.
+__device__ __forceinline__ int xcd_local(int b, int nb) {
+    const int full = nb & ~7;
+    if (b >= full) return b;
+    return (b & 7) * (full >> 3) + (b >> 3);
+}
+
 // Pass 1: the columns n2 in [c0, c0 + C) of z (viewed N1 x N2), FFT over n1,
 // times e(-n2 k1 / N), to Y[k1][n2].  Workgroup 0 also clears the median
 // state and histogram (used only by the later passes).
@@ -406,7 +417,7 @@ __global__ void __launch_bounds__(kFsThreads) k_cols(const float2 *__restrict__ 
                                                       int N2, int C, uint32_t *hist, FsState *state) {
     extern __shared__ float2 sh[];
     const int stride = row_words(N1);             // odd: the C rows start in different banks
-    const int c0 = blockIdx.x * C;
+    const int c0 = xcd_local((int)blockIdx.x, (int)gridDim.x) * C;
     const int64_t N = (int64_t)N1 * N2;
     // every workgroup clears its share of the histogram copies
     for (int i = blockIdx.x * kFsThreads + threadIdx.x; i < kHistWords; i += gridDim.x * kFsThreads) hist[i] = 0;
@@ -626,7 +637,7 @@ __global__ void __launch_bounds__(kFsThreads) k_rows(const float2 *__restrict__ 
                                                       const FsState *state, float2 *__restrict__ X) {
     extern __shared__ float2 sh[];
     const int st = row_words(N2);
-    const int g = blockIdx.x;
+    const int g = xcd_local((int)blockIdx.x, (int)gridDim.x);
     uint32_t *lh = reinterpret_cast<uint32_t *>(sh + 8 * st);
     if constexpr (!kFinal) {
         for (int i = threadIdx.x; i < kHistBins; i += kFsThreads) lh[i] = 0;
