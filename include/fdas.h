@@ -427,8 +427,8 @@ int fdas_harmonic_sums_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins
  * the sums, the peak lists and n_found (arguments and rules as for
  * fdas_harmonic_sums_peaks).  FDAS_E_WORKSPACE when the scratch
  * fdas_harmonic_sums_peaks_workspace gives for these arguments exceeds
- * FDAS_NOALLOC_SCRATCH_BYTES (about 1.3 MB for the sums H = 2, 4, 8, 16 of a
- * 101 x 4,194,304 plane; planes up to about 2.7e9 cells fit at these
+ * FDAS_NOALLOC_SCRATCH_BYTES (about 1.7 MB for the sums H = 2, 4, 8, 16 of a
+ * 101 x 4,194,304 plane; planes up to about 2.6e9 cells fit at these
  * levels); FDAS_E_HIP if the array's device address cannot be obtained
  * (first call on a device).  Every call on one GPU shares that GPU's array
  * and each call clears the parts it needs on its stream; calls that overlap

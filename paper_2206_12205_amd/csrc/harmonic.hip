@@ -514,9 +514,9 @@ BatchSumsLayout batch_sums_layout(const fdas_plan_s &p, int n_levels, const int3
     L.off_block_counts = off;
     off = up(off + (size_t)L.chunks * 4);
     L.off_wg_totals = off;
-    off = up(off + (size_t)kBatchPeakGrid * 4);
+    off = up(off + (size_t)kPeakRanges * 4);
     L.off_wg_offsets = off;
-    off = up(off + (size_t)(kBatchPeakGrid + 1) * 8);
+    off = up(off + (size_t)(kPeakRanges + 1) * 8);
     L.off_prefix = off;
     off = up(off + (size_t)S * 8);
     L.off_totals = off;                        // per-list totals, then tile flags, then chunk flags

@@ -154,7 +154,12 @@ hipError_t launch_harmonic_sum(const fdas_plan_s &p, const void *plane, int64_t 
 // Harmonic sums of every job of a stored batch with their thresholded
 // peaks, the sums never stored (harmonic.hip marks, peaks.hip finishes).
 // Caller scratch layout (byte offsets, 256-aligned regions).
-constexpr int kBatchPeakGrid = 2048;   // workgroups of the batched count and write kernels
+constexpr int kBatchPeakGrid = 2048;   // workgroups of the count and write kernels
+// Chunk ranges of the count and write kernels: the chunks are cut into at
+// most this many ranges, workgroup b taking ranges b, b + kBatchPeakGrid, ...
+// (tiles that may hold peaks cluster where a bright signal is, so short
+// ranges spread them over many workgroups); one total and one offset each.
+constexpr int kPeakRanges = 32768;
 struct BatchSumsLayout {
     int64_t tiles = 0, chunks = 0, blocks = 0, lists = 0;
     int hmax = 0;

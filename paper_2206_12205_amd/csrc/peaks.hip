@@ -38,13 +38,14 @@ namespace fdas {
 constexpr int kPeakThreads = 256;
 constexpr int kCellsPerThread = kPeakTileCols / kPeakThreads;   // 4
 
-// Workgroups of the count and write kernels (each owns a range of chunks).
+// Workgroups of the count and write kernels (each takes every kPeakGrid-th
+// range of chunks).
 constexpr int kPeakGrid = kBatchPeakGrid;
 
 // counts (int32) and flags (uint8) per tile, totals (int32) and flags per
-// chunk of 16 tiles, totals and offsets per workgroup, with padding
+// chunk of 16 tiles, totals and offsets per chunk range, with padding
 size_t peak_scratch_bytes(int64_t n_tiles) {
-    return (size_t)n_tiles * 6 + (size_t)kPeakGrid * (sizeof(int32_t) + sizeof(int64_t)) + 4096;
+    return (size_t)n_tiles * 6 + (size_t)kPeakRanges * (sizeof(int32_t) + sizeof(int64_t)) + 4096;
 }
 
 template <class PT>
@@ -244,10 +245,11 @@ __device__ __forceinline__ int flagged_chunks(const uint8_t *cflags, int64_t c0,
     return total;
 }
 
-// Chunk range of workgroup b: [b per, min((b + 1) per, n_chunks)).
-__device__ __forceinline__ void chunk_range(int64_t n_chunks, int64_t *r0, int64_t *r1) {
-    const int64_t per = (n_chunks + gridDim.x - 1) / gridDim.x;
-    *r0 = (int64_t)blockIdx.x * per;
+// Chunk range v of n_ranges: [v per, min((v + 1) per, n_chunks)).
+__device__ __forceinline__ void chunk_range(int64_t n_chunks, int64_t n_ranges, int64_t v, int64_t *r0,
+                                            int64_t *r1) {
+    const int64_t per = (n_chunks + n_ranges - 1) / n_ranges;
+    *r0 = v * per;
     *r1 = min(*r0 + per, n_chunks);
 }
 
@@ -410,39 +412,41 @@ struct SumSource {
     }
 };
 
-// Count: per flagged chunk its total (block_counts), per workgroup the sum
-// (wg_totals), per job the sum (job_totals, batch only: one atomic per
+// Count: per flagged chunk its total (block_counts), per chunk range the sum
+// (range_totals), per job the sum (job_totals, batch only: one atomic per
 // chunk with peaks, zeroed with the flags).
 template <class Src>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_count(Src src, int n_z, int64_t n_chunks, const uint8_t *flags, const uint8_t *cflags, int32_t *counts,
-             int32_t *block_counts, int32_t *wg_totals, unsigned long long *job_totals) {
+k_peak_count(Src src, int n_z, int64_t n_chunks, int64_t n_ranges, const uint8_t *flags, const uint8_t *cflags,
+             int32_t *counts, int32_t *block_counts, int32_t *range_totals, unsigned long long *job_totals) {
     __shared__ typename Src::V buf[3][kPeakTileCols + 2];
     __shared__ int sum, list[kPeakThreads], wave_cnt[kPeakThreads / 64];
-    int64_t r0, r1;
-    chunk_range(n_chunks, &r0, &r1);
-    int total = 0;   // thread 0
-    for (int64_t c0 = r0; c0 < r1; c0 += kPeakThreads) {
-        const int nf = flagged_chunks(cflags, c0, r1, list, wave_cnt);
-        for (int k = 0; k < nf; ++k) {
-            const int64_t ch = c0 + list[k];
-            const auto loc = src.at(ch, n_z);
-            const int t = count_chunk(loc.cells, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, loc.thr,
-                                      flags + loc.tile_base, counts + loc.tile_base, buf, &sum);
-            if (threadIdx.x == 0) {
-                block_counts[ch] = t;
-                total += t;
-                if (job_totals && t) atomicAdd(&job_totals[loc.slot], (unsigned long long)t);
+    for (int64_t v = blockIdx.x; v < n_ranges; v += gridDim.x) {
+        int64_t r0, r1;
+        chunk_range(n_chunks, n_ranges, v, &r0, &r1);
+        int total = 0;   // thread 0
+        for (int64_t c0 = r0; c0 < r1; c0 += kPeakThreads) {
+            const int nf = flagged_chunks(cflags, c0, r1, list, wave_cnt);
+            for (int k = 0; k < nf; ++k) {
+                const int64_t ch = c0 + list[k];
+                const auto loc = src.at(ch, n_z);
+                const int t = count_chunk(loc.cells, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, loc.thr,
+                                          flags + loc.tile_base, counts + loc.tile_base, buf, &sum);
+                if (threadIdx.x == 0) {
+                    block_counts[ch] = t;
+                    total += t;
+                    if (job_totals && t) atomicAdd(&job_totals[loc.slot], (unsigned long long)t);
+                }
             }
+            __syncthreads();                     // list is rewritten by the next group
         }
-        __syncthreads();                         // list is rewritten by the next group
+        if (threadIdx.x == 0) range_totals[v] = total;
     }
-    if (threadIdx.x == 0) wg_totals[blockIdx.x] = total;
 }
 
-// Single workgroup: exclusive scan of n values -> offsets (int64), the total
-// -> *total; with copy != null the values are also copied there (per-job
-// counts of a batch).
+// Single workgroup: exclusive scan of n values -> offsets[0 .. n) (int64),
+// the total -> offsets[n] and *total; with copy != null the values are also
+// copied there (per-job counts of a batch).
 template <class T>
 __global__ void __launch_bounds__(1024) k_peak_scan(const T *vals, int64_t n, int64_t *offsets, int64_t *total,
                                                     int64_t *copy) {
@@ -467,7 +471,10 @@ __global__ void __launch_bounds__(1024) k_peak_scan(const T *vals, int64_t n, in
         run += (int64_t)vals[i];
         if (copy) copy[i] = (int64_t)vals[i];
     }
-    if (threadIdx.x == 1023) *total = part[1023];
+    if (threadIdx.x == 1023) {
+        offsets[n] = part[1023];
+        *total = part[1023];
+    }
 }
 
 // Recompute the flags of one tile that holds peaks and write them at the
@@ -525,32 +532,36 @@ __device__ __forceinline__ void write_chunk(const Cells &cells, int64_t n, int n
     }
 }
 
-// Write: each workgroup walks its flagged chunks in order from its offset;
-// a batch job's list starts at out + job * capacity and its offsets at the
-// job's prefix (job_prefix).
+// Write: each workgroup walks the flagged chunks of each of its ranges in
+// order from the range's offset; a batch job's list starts at out + job *
+// capacity and its offsets at the job's prefix (job_prefix).
 template <class Src>
 __global__ void __launch_bounds__(kPeakThreads)
-k_peak_write(Src src, int n_z, int64_t n_chunks, const uint8_t *flags, const uint8_t *cflags,
-             const int32_t *counts, const int32_t *block_counts, const int64_t *wg_offsets,
+k_peak_write(Src src, int n_z, int64_t n_chunks, int64_t n_ranges, const uint8_t *flags, const uint8_t *cflags,
+             const int32_t *counts, const int32_t *block_counts, const int64_t *range_offsets,
              const int64_t *job_prefix, fdas_peak *out, int64_t capacity) {
     __shared__ typename Src::V buf[3][kPeakTileCols + 2];
     __shared__ int pre[kPeakThreads], list[kPeakThreads], wave_cnt[kPeakThreads / 64];
-    int64_t r0, r1;
-    chunk_range(n_chunks, &r0, &r1);
-    int64_t run = wg_offsets[blockIdx.x];   // peaks of all chunks before this one
-    for (int64_t c0 = r0; c0 < r1; c0 += kPeakThreads) {
-        const int nf = flagged_chunks(cflags, c0, r1, list, wave_cnt);
-        for (int k = 0; k < nf; ++k) {
-            const int64_t ch = c0 + list[k];
-            const int cnt = block_counts[ch];
-            if (cnt == 0) continue;              // uniform
-            const auto loc = src.at(ch, n_z);
-            const int64_t off = job_prefix ? run - job_prefix[loc.slot] : run;
-            write_chunk(loc.cells, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, loc.thr, flags + loc.tile_base,
-                        counts + loc.tile_base, off, out + (int64_t)loc.slot * capacity, capacity, loc.job, buf, pre);
-            run += cnt;
+    for (int64_t v = blockIdx.x; v < n_ranges; v += gridDim.x) {
+        int64_t r0, r1;
+        chunk_range(n_chunks, n_ranges, v, &r0, &r1);
+        int64_t run = range_offsets[v];       // peaks of all chunks before this range
+        if (range_offsets[v + 1] == run) continue;   // uniform: no peak in this range
+        for (int64_t c0 = r0; c0 < r1; c0 += kPeakThreads) {
+            const int nf = flagged_chunks(cflags, c0, r1, list, wave_cnt);
+            for (int k = 0; k < nf; ++k) {
+                const int64_t ch = c0 + list[k];
+                const int cnt = block_counts[ch];
+                if (cnt == 0) continue;          // uniform
+                const auto loc = src.at(ch, n_z);
+                const int64_t off = job_prefix ? run - job_prefix[loc.slot] : run;
+                write_chunk(loc.cells, loc.n, n_z, loc.n_cb, loc.n_tiles, loc.ch, loc.thr, flags + loc.tile_base,
+                            counts + loc.tile_base, off, out + (int64_t)loc.slot * capacity, capacity, loc.job, buf,
+                            pre);
+                run += cnt;
+            }
+            __syncthreads();                     // list is rewritten by the next group
         }
-        __syncthreads();                         // list is rewritten by the next group
     }
 }
 
@@ -563,8 +574,8 @@ struct PeakScratch {
     int64_t n_cb, n_tiles, n_chunks;
     int32_t *counts;         // per tile
     int32_t *block_counts;   // per chunk
-    int32_t *wg_totals;      // per count workgroup
-    int64_t *wg_offsets;     // per count workgroup, then the total
+    int32_t *wg_totals;      // per chunk range
+    int64_t *wg_offsets;     // per chunk range, then the total
     uint8_t *flags;          // per tile
     uint8_t *cflags;         // per chunk (right after flags: one clear covers both)
 };
@@ -577,9 +588,9 @@ bool plane_scratch(const fdas_plan_s &p, int64_t n, PeakScratch *o) {
     unsigned char *b = static_cast<unsigned char *>(p.ws) + p.off_scr;
     size_t off = 0;
     o->wg_offsets = reinterpret_cast<int64_t *>(b + off);
-    off = up256(off + (kPeakGrid + 1) * sizeof(int64_t));
+    off = up256(off + (kPeakRanges + 1) * sizeof(int64_t));
     o->wg_totals = reinterpret_cast<int32_t *>(b + off);
-    off = up256(off + kPeakGrid * sizeof(int32_t));
+    off = up256(off + kPeakRanges * sizeof(int32_t));
     o->counts = reinterpret_cast<int32_t *>(b + off);
     off = up256(off + (size_t)o->n_tiles * sizeof(int32_t));
     o->block_counts = reinterpret_cast<int32_t *>(b + off);
@@ -643,17 +654,18 @@ void launch_finish(const Src &src, int n_z, int64_t n_chunks, const uint8_t *fla
                    int32_t *counts, int32_t *block_counts, int32_t *wg_totals, int64_t *wg_offsets,
                    unsigned long long *job_totals, int64_t n_lists, int64_t *job_prefix, int64_t *n_found,
                    fdas_peak *out, int64_t cap, hipStream_t st) {
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_chunks, kPeakGrid));
-    hipLaunchKernelGGL(k_peak_count<Src>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, flags, cflags,
-                       counts, block_counts, wg_totals, job_totals);
-    if (job_totals)   // workgroup offsets, per-list prefixes and counts
-        hipLaunchKernelGGL(k_peak_scan_batch, dim3(1), dim3(1024), 0, st, wg_totals, (int64_t)grid, wg_offsets,
+    const int64_t n_ranges = std::max<int64_t>(1, std::min<int64_t>(n_chunks, kPeakRanges));
+    const unsigned grid = (unsigned)std::min<int64_t>(n_ranges, kPeakGrid);
+    hipLaunchKernelGGL(k_peak_count<Src>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, n_ranges, flags,
+                       cflags, counts, block_counts, wg_totals, job_totals);
+    if (job_totals)   // range offsets, per-list prefixes and counts
+        hipLaunchKernelGGL(k_peak_scan_batch, dim3(1), dim3(1024), 0, st, wg_totals, n_ranges, wg_offsets,
                            job_totals, n_lists, job_prefix, n_found);
-    else              // workgroup offsets; a single plane's total is its count
-        hipLaunchKernelGGL(k_peak_scan<int32_t>, dim3(1), dim3(1024), 0, st, wg_totals, (int64_t)grid, wg_offsets,
+    else              // range offsets; a single plane's total is its count
+        hipLaunchKernelGGL(k_peak_scan<int32_t>, dim3(1), dim3(1024), 0, st, wg_totals, n_ranges, wg_offsets,
                            n_found, (int64_t *)nullptr);
-    hipLaunchKernelGGL(k_peak_write<Src>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, flags, cflags,
-                       counts, block_counts, wg_offsets, job_prefix, out, cap);
+    hipLaunchKernelGGL(k_peak_write<Src>, dim3(grid), dim3(kPeakThreads), 0, st, src, n_z, n_chunks, n_ranges, flags,
+                       cflags, counts, block_counts, wg_offsets, job_prefix, out, cap);
 }
 
 template <class PT>
@@ -677,8 +689,8 @@ hipError_t run(const fdas_plan_s &p, const PT *plane, int64_t n, float thr, fdas
 struct BatchScratch {
     int32_t *counts;                 // per tile of all jobs
     int32_t *block_counts;           // per chunk
-    int32_t *wg_totals;              // per count workgroup
-    int64_t *wg_offsets;             // per count workgroup, then the grand total
+    int32_t *wg_totals;              // per chunk range
+    int64_t *wg_offsets;             // per chunk range, then the grand total
     int64_t *job_prefix;             // per job
     unsigned long long *job_totals;  // per job (zeroed with the flags, right before them)
     uint8_t *flags;                  // per tile
@@ -696,9 +708,9 @@ BatchScratch batch_scratch(const fdas_plan_s &p, void *base) {
     o.block_counts = reinterpret_cast<int32_t *>(b + off);
     off = up256(off + C * sizeof(int32_t));
     o.wg_totals = reinterpret_cast<int32_t *>(b + off);
-    off = up256(off + kPeakGrid * sizeof(int32_t));
+    off = up256(off + kPeakRanges * sizeof(int32_t));
     o.wg_offsets = reinterpret_cast<int64_t *>(b + off);
-    off = up256(off + (kPeakGrid + 1) * sizeof(int64_t));
+    off = up256(off + (kPeakRanges + 1) * sizeof(int64_t));
     o.job_prefix = reinterpret_cast<int64_t *>(b + off);
     off = up256(off + J * sizeof(int64_t));
     o.job_totals = reinterpret_cast<unsigned long long *>(b + off);
@@ -753,7 +765,7 @@ hipError_t launch_peaks(const fdas_plan_s &p, const void *plane, int64_t n, floa
 // kernel, with the counters in caller memory (work: peak_work_bytes).
 size_t peak_work_bytes(int64_t n_tiles) {
     const int64_t n_chunks = (n_tiles + kTilesPerBlock - 1) / kTilesPerBlock;
-    return up256((kPeakGrid + 1) * sizeof(int64_t)) + up256(kPeakGrid * sizeof(int32_t)) +
+    return up256((kPeakRanges + 1) * sizeof(int64_t)) + up256(kPeakRanges * sizeof(int32_t)) +
            up256((size_t)n_tiles * sizeof(int32_t)) + up256((size_t)n_chunks * sizeof(int32_t));
 }
 
@@ -767,9 +779,9 @@ hipError_t finish_plane(const fdas_plan_s &p, const PT *plane, int64_t n, float 
     unsigned char *b = static_cast<unsigned char *>(work);
     size_t off = 0;
     auto *wg_offsets = reinterpret_cast<int64_t *>(b + off);
-    off += up256((kPeakGrid + 1) * sizeof(int64_t));
+    off += up256((kPeakRanges + 1) * sizeof(int64_t));
     auto *wg_totals = reinterpret_cast<int32_t *>(b + off);
-    off += up256(kPeakGrid * sizeof(int32_t));
+    off += up256(kPeakRanges * sizeof(int32_t));
     auto *counts = reinterpret_cast<int32_t *>(b + off);
     off += up256((size_t)n_tiles * sizeof(int32_t));
     auto *block_counts = reinterpret_cast<int32_t *>(b + off);
