@@ -85,3 +85,48 @@ def test_batch_sums_match_per_job_calls(dev, plane_dtype):
                     oset = {x for x, m in zip(zip(j.tolist(), r.tolist()), amb) if not m}
                     gset = set(zip(a["z_idx"].tolist(), a["r"].tolist()))
                     assert oset <= gset, f"job {i} H={h}: {sorted(oset - gset)[:5]}"
+
+
+def test_batch_sums_single_harmonic_is_the_plane(dev):
+    """H = 1 is the plane itself (one term, added to zero, rounded as stored):
+    its list for every job equals fdas_peaks of that job's plane, beside a
+    second level H = 3 checked against the per-job call."""
+    import torch
+    from paper_2206_12205_amd.fdas import Plan
+    pl = Plan(max_bins=max(LENGTHS), z_min=ZMIN, z_step=ZSTEP, n_z=NZ, n_taps=M, compute="bf16",
+              plane_dtype="bf16", device=dev, max_jobs=len(LENGTHS))
+    pl.set_batch(LENGTHS)
+    planes = noise_planes(dev, pl, 11, torch.bfloat16)
+    hs, thr = [1, 3], [7.0, 12.0]
+    got = pl.batch_sums_peaks(planes, hs, thr, capacity=1 << 14, truncate=True)
+    for i, n in enumerate(LENGTHS):
+        P = pl.batch_plane(planes, i).contiguous()
+        want1 = pl.peaks(P, thr[0], capacity=1 << 14, truncate=True)
+        _, want = pl.harmonic_sums_peaks(P, hs, thr, capacity=1 << 14, truncate=True)
+        for a, b, what in ((got[0][i], want1, "H=1 vs fdas_peaks"), (got[1][i], want[1], "H=3")):
+            assert a["n_found"] == b["n_found"], f"job {i} {what}"
+            for k in ("z_idx", "r", "power"):
+                assert np.array_equal(a[k], b[k]), f"job {i} {what} {k}"
+        assert got[0][i]["n_found"] > 0 or n < 100
+
+
+def test_batch_sums_on_an_unaligned_grid(dev):
+    """A z grid whose z_min is no multiple of z_step (the workgroup order's
+    template families do not exist there): the lists still equal the
+    per-job calls."""
+    import torch
+    from paper_2206_12205_amd.fdas import Plan
+    pl = Plan(max_bins=max(LENGTHS), z_min=-15.0, z_step=1.7, n_z=19, n_taps=M, compute="fp32",
+              plane_dtype="fp32", device=dev, max_jobs=len(LENGTHS))
+    pl.set_batch(LENGTHS)
+    planes = noise_planes(dev, pl, 13, torch.float32)
+    hs, thr = [2, 5, 9], [10.0, 18.0, 27.0]
+    got = pl.batch_sums_peaks(planes, hs, thr, capacity=1 << 14, truncate=True)
+    for i, n in enumerate(LENGTHS):
+        P = pl.batch_plane(planes, i).contiguous()
+        _, want = pl.harmonic_sums_peaks(P, hs, thr, capacity=1 << 14, truncate=True)
+        for l, h in enumerate(hs):
+            a, b = got[l][i], want[l]
+            assert a["n_found"] == b["n_found"], f"job {i} H={h}"
+            for k in ("z_idx", "r", "power"):
+                assert np.array_equal(a[k], b[k]), f"job {i} H={h} {k}"
