@@ -13,15 +13,19 @@
 // that definition.
 //
 // One workgroup per (template row, block of 2048 fundamentals), 8 per thread
-// 256 apart; the workgroup's harmonic rows are computed once
-// into LDS.  Harmonic h of consecutive fundamentals is h bins apart, so the
-// reads of harmonic h touch every cache line of an h-times wider span: the
-// kernel reads about (H + 1) / 2 planes' worth of cache lines, held in part
-// by the L2 and the last-level cache.  Sums in FP32 (FP64 for an FP64
-// plane); the output has the plane's dtype (bfloat16 rounded to nearest
-// even), so fdas_peaks thresholds it directly.  The marking form (kMark)
-// also flags the peak finder's tiles of the summed plane while storing it,
-// so harmonic summing with thresholding needs no second read of the sums.
+// 256 apart; the workgroup's harmonic rows are computed once into LDS.
+// Harmonic h of consecutive fundamentals is h bins apart, so the reads of
+// harmonic h touch every cache line of an h-times wider span; for a single H
+// the cells one row skips are read by other rows' harmonics while the L2
+// still holds the lines, and each plane byte comes into L2 about once (the
+// several-H pass, whose low harmonics reach further, about 2.5 times).  Sums
+// in FP32 (FP64 for an FP64 plane); the output has the plane's dtype
+// (bfloat16 rounded to nearest even), so fdas_peaks thresholds it directly.
+// The marking form (kMark) also flags the peak finder's tiles of the summed
+// plane while storing it, so harmonic summing with thresholding needs no
+// second read of the sums.  The batch form (k_batch_sums_mark) sums every
+// job of a batch and only flags the tiles; the sums are recomputed for the
+// flagged tiles by the peak finder and never stored.
 #include "harmonic_rows.hpp"
 #include "internal.hpp"
 
