@@ -384,7 +384,9 @@ int fdas_band_max(fdas_plan_t plan, const void *plane, int64_t n_bins, const int
  *            FP64 plane), bfloat16 output rounded to nearest even.  fdas_peaks
  *            on out with n_bins = N_H thresholds the summed plane.
  * Needs no workspace.  FDAS_E_INVALID for bad pointers or sizes,
- * FDAS_E_UNSUPPORTED for more than 65535 templates. */
+ * FDAS_E_UNSUPPORTED for more than 65535 templates or a plane row of 4 GB
+ * less 1 MB or more (n_bins x the plane value size; the same limit holds
+ * for every harmonic-sum call below). */
 int fdas_harmonic_sum(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_harm, void *out,
                       void *stream);
 

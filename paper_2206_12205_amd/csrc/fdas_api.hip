@@ -333,6 +333,13 @@ int fdas_band_max(fdas_plan_t p, const void *plane, int64_t n_bins, const int64_
         fdas::launch_band_max(*p, plane, n_bins, windows, n_windows, out, static_cast<hipStream_t>(stream)));
 }
 
+// The summing kernels address a plane row as one buffer resource with 32-bit
+// byte offsets (plus the step between a thread's fundamentals): a row of
+// n_bins values must stay below 4 GB less 1 MB.
+static bool sum_rows_fit(const fdas_plan_s &p, int64_t n_bins) {
+    return (uint64_t)n_bins * (uint64_t)(elem_bytes(p.cfg.plane_dtype) / 2) < 0xfff00000ull;
+}
+
 int fdas_harmonic_sum(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_harm, void *out, void *stream) {
     if (!p || !plane || !out) return FDAS_E_INVALID;
     const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
@@ -340,7 +347,7 @@ int fdas_harmonic_sum(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t 
         return FDAS_E_INVALID;
     if (n_bins < 1 || n_bins > p->cfg.max_bins || n_harm < 1 || n_harm > fdas::kMaxHarmonics)
         return FDAS_E_INVALID;
-    if (p->cfg.n_z > 65535) return FDAS_E_UNSUPPORTED;
+    if (p->cfg.n_z > 65535 || !sum_rows_fit(*p, n_bins)) return FDAS_E_UNSUPPORTED;
     return hip_status(fdas::launch_harmonic_sum(*p, plane, n_bins, n_harm, out, static_cast<hipStream_t>(stream)));
 }
 
@@ -355,7 +362,7 @@ int fdas_harmonic_sums(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t
             return FDAS_E_INVALID;
         if (!outs[l] || (reinterpret_cast<uintptr_t>(outs[l]) % pe) != 0) return FDAS_E_INVALID;
     }
-    if (p->cfg.n_z > 65535) return FDAS_E_UNSUPPORTED;
+    if (p->cfg.n_z > 65535 || !sum_rows_fit(*p, n_bins)) return FDAS_E_UNSUPPORTED;
     return hip_status(fdas::launch_harmonic_sums(*p, plane, n_bins, n_levels, n_harm, outs, nullptr,
                                                  static_cast<hipStream_t>(stream)));
 }
@@ -394,7 +401,7 @@ static int check_sums_list(const fdas_plan_s &p, int64_t n_bins, int32_t n_level
     for (int32_t l = 0; l < n_levels; ++l)
         if (n_harm[l] < 1 || n_harm[l] > fdas::kMaxHarmonics || (l > 0 && n_harm[l] <= n_harm[l - 1]))
             return FDAS_E_INVALID;
-    if (p.cfg.n_z > 65535) return FDAS_E_UNSUPPORTED;
+    if (p.cfg.n_z > 65535 || !sum_rows_fit(p, n_bins)) return FDAS_E_UNSUPPORTED;
     return FDAS_OK;
 }
 
@@ -483,7 +490,7 @@ int fdas_harmonic_sum_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, in
         return FDAS_E_INVALID;
     if (n_bins < 1 || n_bins > p->cfg.max_bins || n_harm < 1 || n_harm > fdas::kMaxHarmonics)
         return FDAS_E_INVALID;
-    if (p->cfg.n_z > 65535) return FDAS_E_UNSUPPORTED;
+    if (p->cfg.n_z > 65535 || !sum_rows_fit(*p, n_bins)) return FDAS_E_UNSUPPORTED;
     if (!p->ws) return FDAS_E_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nh = (n_bins - 1) / n_harm + 1;
@@ -621,7 +628,7 @@ static int check_batch_sums(fdas_plan_t p, int32_t n_levels, const int32_t *n_ha
         if (n_harm[l] < 1 || n_harm[l] > fdas::kMaxHarmonics || (l > 0 && n_harm[l] <= n_harm[l - 1]))
             return FDAS_E_INVALID;
     if (p->batch_jobs < 1) return FDAS_E_STATE;
-    if (p->cfg.n_z > 65535 || p->batch_jobs > 32767) return FDAS_E_UNSUPPORTED;
+    if (p->cfg.n_z > 65535 || p->batch_jobs > 32767 || !sum_rows_fit(*p, p->cfg.max_bins)) return FDAS_E_UNSUPPORTED;
     const fdas::BatchSumsLayout L = fdas::batch_sums_layout(*p, n_levels, n_harm);
     if (L.blocks > 0x7fffffffLL || L.tiles >= 0x7fffffffLL) return FDAS_E_UNSUPPORTED;
     return FDAS_OK;

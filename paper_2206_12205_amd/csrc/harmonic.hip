@@ -51,8 +51,8 @@ template <>
 struct hs_io<float> {
     using acc = float;
     static __device__ __forceinline__ float get(const float *p, int64_t i) { return p[i]; }
-    static __device__ __forceinline__ float getb(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    static __device__ __forceinline__ float getb(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
     }
     static __device__ __forceinline__ void put(float *p, float v) { plane_store<float>::put(p, v); }
     // a bound b with: stored value > thr implies v > b (exact here)
@@ -62,8 +62,8 @@ template <>
 struct hs_io<double> {
     using acc = double;
     static __device__ __forceinline__ double get(const double *p, int64_t i) { return p[i]; }
-    static __device__ __forceinline__ double getb(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    static __device__ __forceinline__ double getb(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
     }
     static __device__ __forceinline__ void put(double *p, double v) { plane_store<double>::put(p, v); }
     static __device__ __forceinline__ double mark_bound(float thr) { return (double)thr; }
@@ -74,8 +74,8 @@ struct hs_io<__bf16> {
     static __device__ __forceinline__ float get(const __bf16 *p, int64_t i) {
         return __uint_as_float((uint32_t)reinterpret_cast<const unsigned short *>(p)[i] << 16);   // exact
     }
-    static __device__ __forceinline__ float getb(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-        return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0) << 16);
+    static __device__ __forceinline__ float getb(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+        return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0) << 16);
     }
     static __device__ __forceinline__ void put(__bf16 *p, float v) { plane_store<__bf16>::put(p, v); }
     // Rounding to nearest bfloat16 moves a normal value by at most 2^-8 of
@@ -90,41 +90,30 @@ struct hs_io<__bf16> {
 // Add harmonics h_lo .. h_hi, in that order, of this thread's fundamentals
 // r0 + 256 i below lim to acc; rows[h - 1] is harmonic h's row (the same for
 // the whole workgroup, -1: left out).  No load sits behind a branch (a
-// fundamental or harmonic that is left out loads the row's first cell and
-// keeps its sum), so the kHsPerThread loads of a harmonic are in flight
-// together.  (More harmonics in flight per thread measured slower: the
-// kernel is bound by the traffic into L2, not by latency.)  A load is a
-// buffer load, the row as a buffer resource (scalar registers) plus one
-// 32-bit byte offset, so a row must hold less than 4 GB; longer rows use
-// 64-bit addresses.
+// fundamental or harmonic that is left out reads offset 0 of its row, or a
+// zero past the row's end, and keeps its sum), so the kHsPerThread loads of
+// a harmonic are in flight together.  A load is a buffer load: the row as a
+// buffer resource and the step 256 h i between the thread's fundamentals as
+// the scalar offset, so a harmonic costs one 32-bit address register per
+// lane (the register file bounds how many loads are in flight on a SIMD).
+// A row must hold less than 4 GB (the callers refuse larger rows).
 template <class PT>
 __device__ __forceinline__ void add_harmonics(typename hs_io<PT>::acc (&acc)[kHsPerThread], const PT *plane,
                                               int64_t n, const int *rows, int h_lo, int h_hi, int64_t r0,
                                               int64_t lim) {
     using A = typename hs_io<PT>::acc;
-    const bool wide = n >= (int64_t)(0xffffffffu / sizeof(PT));
     const uint32_t ru = (uint32_t)r0;
     const int32_t row_bytes = (int32_t)(uint32_t)(n * (int64_t)sizeof(PT));
     for (int h = h_lo; h <= h_hi; ++h) {
         const int jh = __builtin_amdgcn_readfirstlane(rows[h - 1]);
         const PT *base = plane + (int64_t)max(jh, 0) * n;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<PT *>(base), (short)0, row_bytes, kBufferWord3);
+        const uint32_t vo = jh >= 0 ? (uint32_t)h * ru * (uint32_t)sizeof(PT) : 0u;
+        const uint32_t step = (uint32_t)h * (uint32_t)(kHsThreads * sizeof(PT));   // uniform
         A v[kHsPerThread];
-        if (!wide) {
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<PT *>(base), (short)0, row_bytes, kBufferWord3);
 #pragma unroll
-            for (int i = 0; i < kHsPerThread; ++i) {
-                const bool ok = jh >= 0 && r0 + i * kHsThreads < lim;
-                const uint32_t off = (uint32_t)h * (ru + (uint32_t)(i * kHsThreads)) * (uint32_t)sizeof(PT);
-                v[i] = hs_io<PT>::getb(rs, ok ? off : 0u);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < kHsPerThread; ++i) {
-                const int64_t r = r0 + i * kHsThreads;
-                v[i] = hs_io<PT>::get(base, jh >= 0 && r < lim ? (int64_t)h * r : 0);
-            }
-        }
+        for (int i = 0; i < kHsPerThread; ++i) v[i] = hs_io<PT>::getb(rs, vo, step * (uint32_t)i);
 #pragma unroll
         for (int i = 0; i < kHsPerThread; ++i)
             acc[i] = jh >= 0 && r0 + i * kHsThreads < lim ? acc[i] + v[i] : acc[i];

@@ -398,3 +398,28 @@ def test_batch_sums_checks_on_host():
         assert L.fdas_batch_harmonic_sums_peaks_workspace(h, 2, (ctypes.c_int32 * 2)(2, 4), None) == F.E_INVALID
     finally:
         L.fdas_destroy(h)
+
+
+def test_harmonic_sums_refuse_rows_of_4_gb():
+    """The summing kernels address a row with 32-bit offsets: a plan whose
+    rows would reach 4 GB less 1 MB gets FDAS_E_UNSUPPORTED from every
+    harmonic-sum call (checked on the host, no device touched)."""
+    L = F.lib()
+    P = ctypes.c_void_p
+    big = 1 << 31          # bins: 4 GB of BF16 values per row
+    h = P()
+    nb = ctypes.c_size_t()
+    assert L.fdas_plan(ctypes.byref(make(max_bins=big, n_z=3, z_min=-2.0, compute="bf16", plane_dtype="bf16")),
+                       ctypes.byref(h), ctypes.byref(nb)) == F.OK
+    try:
+        hs = (ctypes.c_int32 * 2)(2, 4)
+        outs = (P * 2)(P(0x30000), P(0x40000))
+        assert L.fdas_harmonic_sum(h, P(0x10000), big, 2, P(0x20000), None) == F.E_UNSUPPORTED
+        assert L.fdas_harmonic_sums(h, P(0x10000), big, 2, hs, outs, None) == F.E_UNSUPPORTED
+        need = ctypes.c_size_t()
+        assert L.fdas_harmonic_sums_peaks_workspace(h, big, 2, hs, ctypes.byref(need)) == F.E_UNSUPPORTED
+        # a row just below the limit is accepted by the host checks
+        ok = (0xfff00000 // 2) - 1
+        assert L.fdas_harmonic_sums_peaks_workspace(h, ok, 2, hs, ctypes.byref(need)) == F.OK
+    finally:
+        L.fdas_destroy(h)
