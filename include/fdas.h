@@ -476,7 +476,7 @@ int fdas_harmonic_sum_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins,
  * FDAS_E_STATE without a batch, FDAS_E_UNSUPPORTED for more than 65535
  * templates or 2^31 tiles or summing workgroups, FDAS_E_WORKSPACE for a
  * missing or short scratch.  Asynchronous on stream, kernels only
- * (graph-capturable): four launches per call. */
+ * (graph-capturable): five launches per call. */
 int fdas_batch_harmonic_sums_peaks_workspace(fdas_plan_t plan, int32_t n_levels, const int32_t *n_harm,
                                              size_t *scratch_bytes);
 int fdas_batch_harmonic_sums_peaks(fdas_plan_t plan, const void *planes, int32_t n_levels, const int32_t *n_harm,

@@ -8,7 +8,8 @@ oracle's peak definition applied to the oracle's sum of the GPU plane
 (oracle/harmonic.py, rounded to the plane type as the stored sum is) gives the
 same cells.  Ragged jobs (1 .. 200,000 bins), BF16 / FP32 / FP64 planes,
 thresholds with few peaks, many peaks (small capacity: the first entries and
-the true count) and none.
+the true count) and none; lengths in whole 16-byte chunks beside ragged
+ones; z grids symmetric about z = 0, offset, one-sided and of 201 templates.
 """
 import sys
 
@@ -21,7 +22,9 @@ from oracle import peaks as OK_PEAKS
 pytestmark = pytest.mark.gpu
 
 ZMIN, ZSTEP, NZ, M = -16.0, 2.0, 17, 128
+# ragged lengths, and lengths in whole 16-byte chunks of every plane type
 LENGTHS = [70001, 1, 3839, 12345, 200000, 517, 1025, 40000]
+CHUNKED = [70000, 8, 3840, 12344, 200000, 520, 1024, 40000]
 REC = np.dtype([("r", "<i8"), ("z_idx", "<i4"), ("job", "<i4"), ("power", "<f4"), ("reserved", "<f4")])
 
 
@@ -40,27 +43,29 @@ def noise_planes(dev, pl, seed, dtype):
     return P.to(dtype).to(dev).contiguous()
 
 
+@pytest.mark.parametrize("form", ["ragged", "chunked"])
 @pytest.mark.parametrize("plane_dtype", ["bf16", "fp32", "fp64"])
-def test_batch_sums_match_per_job_calls(dev, plane_dtype):
+def test_batch_sums_match_per_job_calls(dev, plane_dtype, form):
     import torch
     from paper_2206_12205_amd.fdas import Plan
     tdt = {"bf16": torch.bfloat16, "fp32": torch.float32, "fp64": torch.float64}[plane_dtype]
     compute = "fp64" if plane_dtype == "fp64" else "fp32"
-    pl = Plan(max_bins=max(LENGTHS), z_min=ZMIN, z_step=ZSTEP, n_z=NZ, n_taps=M, compute=compute,
-              plane_dtype=plane_dtype, device=dev, max_jobs=len(LENGTHS))
-    pl.set_batch(LENGTHS)
+    lengths = LENGTHS if form == "ragged" else CHUNKED
+    pl = Plan(max_bins=max(lengths), z_min=ZMIN, z_step=ZSTEP, n_z=NZ, n_taps=M, compute=compute,
+              plane_dtype=plane_dtype, device=dev, max_jobs=len(lengths))
+    pl.set_batch(lengths)
     planes = noise_planes(dev, pl, 7, tdt)
     hs = [2, 4, 8, 16]
     cases = (([12.0, 16.0, 24.0, 36.0], 1 << 14), ([6.0, 9.0, 14.0, 24.0], 40), ([1e9] * 4, 4))
     for thr, cap in cases:
         say(f"[batch sums] {plane_dtype} thresholds {thr} capacity {cap}")
         got = pl.batch_sums_peaks(planes, hs, thr, capacity=cap, truncate=True)
-        for i, n in enumerate(LENGTHS):
+        for i, n in enumerate(lengths):
             P = pl.batch_plane(planes, i).contiguous()
             _, want = pl.harmonic_sums_peaks(P, hs, thr, capacity=cap, truncate=True)
             for l, h in enumerate(hs):
                 a, b = got[l][i], want[l]
-                what = f"job {i} (n={n}) H={h}"
+                what = f"{form} job {i} (n={n}) H={h}"
                 assert a["n_found"] == b["n_found"], what
                 assert np.array_equal(a["z_idx"], b["z_idx"]) and np.array_equal(a["r"], b["r"]), what
                 assert np.array_equal(a["power"], b["power"]), what
@@ -130,3 +135,42 @@ def test_batch_sums_on_an_unaligned_grid(dev):
             assert a["n_found"] == b["n_found"], f"job {i} H={h}"
             for k in ("z_idx", "r", "power"):
                 assert np.array_equal(a[k], b[k]), f"job {i} H={h} {k}"
+
+
+def _per_job_lists_equal(pl, planes, lengths, hs, thr, cap, what):
+    got = pl.batch_sums_peaks(planes, hs, thr, capacity=cap, truncate=True)
+    total = 0
+    for i, n in enumerate(lengths):
+        P = pl.batch_plane(planes, i).contiguous()
+        _, want = pl.harmonic_sums_peaks(P, hs, thr, capacity=cap, truncate=True)
+        for l, h in enumerate(hs):
+            a, b = got[l][i], want[l]
+            assert a["n_found"] == b["n_found"], f"{what} job {i} (n={n}) H={h}"
+            for k in ("z_idx", "r", "power"):
+                assert np.array_equal(a[k], b[k]), f"{what} job {i} (n={n}) H={h} {k}"
+            total += int(a["n_found"])
+    return total
+
+
+@pytest.mark.parametrize("z_min,z_step,n_z", [
+    (-100.0, 2.0, 101),   # the single-DM grid: 50 rows each side and z = 0
+    (-10.0, 1.0, 60),     # values -10 .. 49: sides of different sizes
+    (10.0, 1.0, 60),      # values 10 .. 69: positive rows only, none below 10
+    (-40.0, 1.0, 30),     # values -40 .. -11: negative rows only
+    (-200.0, 2.0, 201),   # 201 templates
+])
+def test_batch_sums_on_other_grids(dev, z_min, z_step, n_z):
+    """Grids beside the default one (template families reach the grid edge
+    at other harmonics, or exist on one side only): every (level, job) list
+    equals the per-job call's, at thresholds with many peaks."""
+    import torch
+    from paper_2206_12205_amd.fdas import Plan
+    lengths = [65536, 8, 4104, 24576, 131072, 1000] if n_z <= 101 else [16384, 4096, 1000]
+    pl = Plan(max_bins=max(lengths), z_min=z_min, z_step=z_step, n_z=n_z, n_taps=M, compute="bf16",
+              plane_dtype="bf16", device=dev, max_jobs=len(lengths))
+    pl.set_batch(lengths)
+    planes = noise_planes(dev, pl, 17, torch.bfloat16)
+    hs, thr = [2, 3, 8, 16, 32], [9.0, 12.0, 20.0, 32.0, 52.0]
+    say(f"[batch sums] grid {z_min} {z_step} {n_z}")
+    total = _per_job_lists_equal(pl, planes, lengths, hs, thr, 1 << 15, f"grid {z_min}/{z_step}/{n_z}")
+    assert total > 100
