@@ -444,36 +444,88 @@ k_peak_count(Src src, int n_z, int64_t n_chunks, int64_t n_ranges, const uint8_t
     }
 }
 
-// Single workgroup: exclusive scan of n values -> offsets[0 .. n) (int64),
-// the total -> offsets[n] and *total; with copy != null the values are also
-// copied there (per-job counts of a batch).
+// Exclusive scan of n values by one workgroup of 1024 threads: offsets[i] =
+// vals[0] + .. + vals[i - 1] (int64), copy[i] = vals[i] when copy is not
+// null; returns the total.  Thread t takes the run [t per, t per + per), per
+// = ceil(n / 1024) rounded up to a multiple of 4.  For 32-bit values and
+// runs of up to kScanRegs inside the array, the run is read as 16-byte loads
+// from one address, all in flight together, and written back from the
+// registers, so it costs one memory round trip instead of one per value;
+// other runs are summed and written by loops.  part: 1024 int64 of LDS.
+constexpr int kScanRegs = 32;
+
 template <class T>
-__global__ void __launch_bounds__(1024) k_peak_scan(const T *vals, int64_t n, int64_t *offsets, int64_t *total,
-                                                    int64_t *copy) {
-    __shared__ int64_t part[1024];
-    const int64_t per = (n + 1023) / 1024;
+__device__ int64_t block_exclusive_scan(const T *vals, int64_t n, int64_t *offsets, int64_t *copy, int64_t *part) {
+    const int64_t per = (((n + 1023) / 1024) + 3) & ~(int64_t)3;
     const int64_t b = threadIdx.x * per;
     const int64_t e = min(b + per, n);
+    constexpr bool kWide = sizeof(T) == 4;
+    const bool wide = kWide && per <= kScanRegs && b + per <= n &&
+                      (reinterpret_cast<uintptr_t>(vals) % 16) == 0;   // whole run, 16-byte aligned
+    uint32_t v[kScanRegs];
     int64_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += (int64_t)vals[i];
+    __syncthreads();   // part may still be read from a previous scan
+    if (wide) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(vals + b);
+#pragma unroll
+        for (int i = 0; i < kScanRegs / 4; ++i) {
+            if (4 * i < per) {
+                const uint4 u = q[i];
+                v[4 * i] = u.x;
+                v[4 * i + 1] = u.y;
+                v[4 * i + 2] = u.z;
+                v[4 * i + 3] = u.w;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kScanRegs; ++i)
+            if (i < per) s += (int64_t)(T)v[i];
+    } else {
+        for (int64_t i = b; i < e; ++i) s += (int64_t)vals[i];
+    }
     part[threadIdx.x] = s;
     __syncthreads();
     // inclusive Hillis-Steele scan over the 1024 partial sums
     for (int w = 1; w < 1024; w <<= 1) {
-        const int64_t v = threadIdx.x >= (unsigned)w ? part[threadIdx.x - w] : 0;
+        const int64_t x = threadIdx.x >= (unsigned)w ? part[threadIdx.x - w] : 0;
         __syncthreads();
-        part[threadIdx.x] += v;
+        part[threadIdx.x] += x;
         __syncthreads();
     }
     int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-    for (int64_t i = b; i < e; ++i) {
-        offsets[i] = run;
-        run += (int64_t)vals[i];
-        if (copy) copy[i] = (int64_t)vals[i];
+    if (wide) {
+        int64_t *o = offsets + b;
+#pragma unroll
+        for (int i = 0; i < kScanRegs; ++i) {
+            if (i < per) {
+                const int64_t x = (int64_t)(T)v[i];
+                o[i] = run;
+                if (copy) copy[b + i] = x;
+                run += x;
+            }
+        }
+    } else {
+        for (int64_t i = b; i < e; ++i) {
+            const int64_t x = (int64_t)vals[i];
+            offsets[i] = run;
+            if (copy) copy[i] = x;
+            run += x;
+        }
     }
+    return part[1023];
+}
+
+// Single workgroup: exclusive scan of n >= 1 values -> offsets[0 .. n)
+// (int64), the total -> offsets[n] and *total; with copy != null the values
+// are also copied there (per-job counts of a batch).
+template <class T>
+__global__ void __launch_bounds__(1024) k_peak_scan(const T *vals, int64_t n, int64_t *offsets, int64_t *total,
+                                                    int64_t *copy) {
+    __shared__ int64_t part[1024];
+    const int64_t t = block_exclusive_scan(vals, n, offsets, copy, part);
     if (threadIdx.x == 1023) {
-        offsets[n] = part[1023];
-        *total = part[1023];
+        offsets[n] = t;
+        *total = t;
     }
 }
 
@@ -618,35 +670,9 @@ __global__ void __launch_bounds__(1024) k_peak_scan_batch(const int32_t *wg_tota
                                                           const unsigned long long *job_totals, int64_t n_lists,
                                                           int64_t *job_prefix, int64_t *n_found) {
     __shared__ int64_t part[1024];
-    for (int round = 0; round < 2; ++round) {
-        const int64_t n = round == 0 ? n_wg : n_lists;
-        const int64_t per = (n + 1023) / 1024;
-        const int64_t b = threadIdx.x * per;
-        const int64_t e = min(b + per, n);
-        int64_t s = 0;
-        for (int64_t i = b; i < e; ++i) s += round == 0 ? (int64_t)wg_totals[i] : (int64_t)job_totals[i];
-        part[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 1; w < 1024; w <<= 1) {
-            const int64_t v = threadIdx.x >= (unsigned)w ? part[threadIdx.x - w] : 0;
-            __syncthreads();
-            part[threadIdx.x] += v;
-            __syncthreads();
-        }
-        int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
-        for (int64_t i = b; i < e; ++i) {
-            const int64_t v = round == 0 ? (int64_t)wg_totals[i] : (int64_t)job_totals[i];
-            if (round == 0) {
-                wg_offsets[i] = run;
-            } else {
-                job_prefix[i] = run;
-                n_found[i] = v;
-            }
-            run += v;
-        }
-        if (round == 0 && threadIdx.x == 1023) wg_offsets[n_wg] = part[1023];
-        __syncthreads();
-    }
+    const int64_t t = block_exclusive_scan(wg_totals, n_wg, wg_offsets, (int64_t *)nullptr, part);
+    if (threadIdx.x == 1023) wg_offsets[n_wg] = t;
+    block_exclusive_scan(job_totals, n_lists, job_prefix, n_found, part);
 }
 
 template <class Src>
