@@ -475,10 +475,12 @@ def prep_timing(args, cfg, dev):
 def series_search_timing(args, cfg, dev, pl):
     """The whole search of one single-DM time series (2^23 FP32 samples of
     the workload's first trial) as one timed unit: fdas_prepare, then
-    fdas_correlate_peaks, then the sums over H = 2, 4, 8, 16 harmonics in one
-    pass with the thresholded peaks of each (fdas_harmonic_sums_peaks;
-    threshold: the workload's for the plane, +10 per doubling of H); every
-    buffer allocated beforehand, HIP events around the three calls."""
+    fdas_correlate_peaks, then the thresholded peaks of the sums over H = 2,
+    4, 8, 16 harmonics from one summing pass, the sums not stored
+    (fdas_harmonic_peaks; threshold: the workload's for the plane, +10 per
+    doubling of H); every buffer allocated beforehand, HIP events around the
+    three calls.  The same search with the sums stored
+    (fdas_harmonic_sums_peaks) is timed beside it."""
     import ctypes
     import numpy as np
     import torch
@@ -495,7 +497,7 @@ def series_search_timing(args, cfg, dev, pl):
     spec = torch.empty(n, dtype=torch.complex64, device=dev)
     plane = pl.empty_plane(n)
     hs = (2, 4, 8, 16)
-    sums = {h: torch.empty((pl.n_z, (n - 1) // h + 1), dtype=plane.dtype, device=dev) for h in hs}
+    sums = {h: torch.empty((pl.n_z, (n - 1) // h + 1), dtype=plane.dtype, device=dev) for h in hs}   # stored form
     cap = 1 << 16
     pk = torch.empty((len(hs) + 1, cap, 24), dtype=torch.uint8, device=dev)
     nf = torch.zeros(len(hs) + 1, dtype=torch.int64, device=dev)
@@ -509,31 +511,45 @@ def series_search_timing(args, cfg, dev, pl):
     parr = (ctypes.c_void_p * len(hs))(*[sums[h].data_ptr() for h in hs])
     tarr = (ctypes.c_float * len(hs))(*[float(thr[h]) for h in hs])
     karr = (ctypes.c_void_p * len(hs))(*[pk[i].data_ptr() for i in range(1, len(hs) + 1)])
-    scr = torch.empty(max(pl.harmonic_sums_peaks_bytes(n, hs), 1), dtype=torch.uint8, device=dev)
+    scr = torch.empty(max(pl.harmonic_sums_peaks_bytes(n, hs), pl.harmonic_peaks_bytes(n, hs), 1),
+                      dtype=torch.uint8, device=dev)
 
-    def one():
+    def one(stored=False):
         F._check(L.fdas_prepare(V(xs.data_ptr()), n_t, V(spec.data_ptr()), V(ws.data_ptr()), nb.value, sp),
                  "fdas_prepare")
         F._check(L.fdas_correlate_peaks(pl._h, V(spec.data_ptr()), n, V(plane.data_ptr()), float(thr[1]),
                                         V(pk[0].data_ptr()), cap, V(nf[0:1].data_ptr()), sp), "fdas_correlate_peaks")
-        F._check(L.fdas_harmonic_sums_peaks(pl._h, V(plane.data_ptr()), n, len(hs), harr, parr, tarr, karr, cap,
-                                            V(nf[1:].data_ptr()), V(scr.data_ptr()), scr.numel(), sp),
-                 "fdas_harmonic_sums_peaks")
-    for _ in range(5):
-        one()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = max(10, min(args.steps, 50))
-    e0.record(st)
-    for _ in range(reps):
-        one()
-    e1.record(st)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+        if stored:
+            F._check(L.fdas_harmonic_sums_peaks(pl._h, V(plane.data_ptr()), n, len(hs), harr, parr, tarr, karr,
+                                                cap, V(nf[1:].data_ptr()), V(scr.data_ptr()), scr.numel(), sp),
+                     "fdas_harmonic_sums_peaks")
+        else:
+            F._check(L.fdas_harmonic_peaks(pl._h, V(plane.data_ptr()), n, len(hs), harr, tarr, V(pk[1].data_ptr()),
+                                           cap, V(nf[1:].data_ptr()), V(scr.data_ptr()), scr.numel(), sp),
+                     "fdas_harmonic_peaks")
+
+    def timed(stored):
+        for _ in range(5):
+            one(stored)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(10, min(args.steps, 50))
+        e0.record(st)
+        for _ in range(reps):
+            one(stored)
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_stored = timed(True)
+    found_stored = nf.cpu().tolist()
+    ms = timed(False)
     found = nf.cpu().tolist()
-    note(f"whole series search (prepare, plane + peaks, H = 2..16 sums + peaks): {ms:.3f} ms")
+    note(f"whole series search (prepare, plane + peaks, H = 2..16 sums' peaks): {ms:.3f} ms "
+         f"({ms_stored:.3f} ms with the sums stored)")
     return {"workload": f"{n_t} FP32 samples -> normalised spectrum -> {pl.n_z} x {n} BF16 plane with peaks -> "
-                        f"harmonic sums H = 2, 4, 8, 16 with peaks", "ms": ms,
+                        f"peaks of the harmonic sums H = 2, 4, 8, 16 (sums not stored)", "ms": ms,
+            "ms_sums_stored": ms_stored, "same_counts_as_stored": found == found_stored,
             "thresholds": {str(k): v for k, v in thr.items()},
             "n_found": {"H1": found[0], **{f"H{h}": found[i] for i, h in enumerate(hs, 1)}}}
 

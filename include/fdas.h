@@ -441,6 +441,38 @@ int fdas_harmonic_sums_peaks_noalloc(fdas_plan_t plan, const void *plane, int64_
                                      const int32_t *n_harm, void *const *outs, const float *thresholds,
                                      fdas_peak *const *peaks, int64_t capacity, int64_t *n_found, void *stream);
 
+/* The thresholded peaks of several harmonic sums of one plane, the sums
+ * never stored (Section "Detailed explanation": the harmonics of a signal at
+ * (r, z) sit at (h r, h z)): for each level l exactly the list and true count
+ * fdas_harmonic_sums_peaks gives for n_harm[l] and thresholds[l], without
+ * writing the n_z x N_H sums.  One summing launch flags the tiles (one row x
+ * 1024 fundamentals) where a sum, rounded to the plane's type as a store
+ * would round it, may exceed its level's threshold; the finder recomputes the
+ * sums of the flagged tiles and their neighbours from the plane in the same
+ * order and precision, so every listed cell and power is bitwise the stored
+ * sum's.  For a search that only wants the candidates this skips writing
+ * (and the finder's reading) the sums.
+ *   plane      device, n_z x n_bins of the plane dtype (element alignment)
+ *   n_harm, thresholds  host arrays of n_levels (1..8) entries, n_harm
+ *              increasing, each in 1..32
+ *   peaks      device, n_levels x capacity records (16-byte aligned): level
+ *              l's list at peaks + l capacity, job = 0
+ *   n_found    device, n_levels int64 (8-byte aligned): true counts
+ *   scratch    caller device memory (16-byte aligned) of at least the bytes
+ *              fdas_harmonic_peaks_workspace gives for the same n_bins and
+ *              levels (a one-job table, flags, counters, list layout,
+ *              harmonic rows)
+ * Needs no plan workspace or batch.  FDAS_E_INVALID for bad lists, sizes or
+ * pointers, FDAS_E_UNSUPPORTED for more than 65535 templates, plane rows of
+ * 4 GB less 1 MB or more, or 2^31 tiles or summing workgroups,
+ * FDAS_E_WORKSPACE for a missing or short scratch.  Asynchronous on stream,
+ * kernels only (graph-capturable): six launches per call. */
+int fdas_harmonic_peaks_workspace(fdas_plan_t plan, int64_t n_bins, int32_t n_levels, const int32_t *n_harm,
+                                  size_t *scratch_bytes);
+int fdas_harmonic_peaks(fdas_plan_t plan, const void *plane, int64_t n_bins, int32_t n_levels, const int32_t *n_harm,
+                        const float *thresholds, fdas_peak *peaks, int64_t capacity, int64_t *n_found, void *scratch,
+                        size_t scratch_bytes, void *stream);
+
 /* Harmonic summing with thresholding in one call: the summed plane
  * fdas_harmonic_sum writes to out, and exactly the list and count fdas_peaks
  * then gives for it (an n_z x N_H plane, N_H = (n_bins - 1) / n_harm + 1;

@@ -622,16 +622,29 @@ int fdas_correlate_batch_peaks(fdas_plan_t p, const void *spectra, void *planes,
     return hip_status(e);
 }
 
-static int check_batch_sums(fdas_plan_t p, int32_t n_levels, const int32_t *n_harm) {
-    if (!p || !n_harm || n_levels < 1 || n_levels > 8) return FDAS_E_INVALID;
+static bool sum_levels_ok(int32_t n_levels, const int32_t *n_harm) {
+    if (!n_harm || n_levels < 1 || n_levels > 8) return false;
     for (int32_t l = 0; l < n_levels; ++l)
-        if (n_harm[l] < 1 || n_harm[l] > fdas::kMaxHarmonics || (l > 0 && n_harm[l] <= n_harm[l - 1]))
-            return FDAS_E_INVALID;
+        if (n_harm[l] < 1 || n_harm[l] > fdas::kMaxHarmonics || (l > 0 && n_harm[l] <= n_harm[l - 1])) return false;
+    return true;
+}
+
+// The stored batch as the jobs of a batch harmonic-sums call.
+static fdas::SumBatch plan_batch(const fdas_plan_s &p) {
+    return fdas::SumBatch{p.batch_host.data(), p.batch_jobs,
+                          reinterpret_cast<const fdas_batch_job *>(static_cast<const unsigned char *>(p.ws) +
+                                                                   p.off_batch + p.batch_hdr)};
+}
+
+static int check_sum_layout(const fdas::BatchSumsLayout &L) {
+    return L.blocks > 0x7fffffffLL || L.tiles >= 0x7fffffffLL ? FDAS_E_UNSUPPORTED : FDAS_OK;
+}
+
+static int check_batch_sums(fdas_plan_t p, int32_t n_levels, const int32_t *n_harm) {
+    if (!p || !sum_levels_ok(n_levels, n_harm)) return FDAS_E_INVALID;
     if (p->batch_jobs < 1) return FDAS_E_STATE;
     if (p->cfg.n_z > 65535 || p->batch_jobs > 32767 || !sum_rows_fit(*p, p->cfg.max_bins)) return FDAS_E_UNSUPPORTED;
-    const fdas::BatchSumsLayout L = fdas::batch_sums_layout(*p, n_levels, n_harm);
-    if (L.blocks > 0x7fffffffLL || L.tiles >= 0x7fffffffLL) return FDAS_E_UNSUPPORTED;
-    return FDAS_OK;
+    return check_sum_layout(fdas::batch_sums_layout(*p, plan_batch(*p), n_levels, n_harm));
 }
 
 int fdas_batch_harmonic_sums_peaks_workspace(fdas_plan_t p, int32_t n_levels, const int32_t *n_harm,
@@ -639,7 +652,7 @@ int fdas_batch_harmonic_sums_peaks_workspace(fdas_plan_t p, int32_t n_levels, co
     if (!scratch_bytes) return FDAS_E_INVALID;
     const int s = check_batch_sums(p, n_levels, n_harm);
     if (s != FDAS_OK) return s;
-    *scratch_bytes = fdas::batch_sums_layout(*p, n_levels, n_harm).bytes;
+    *scratch_bytes = fdas::batch_sums_layout(*p, plan_batch(*p), n_levels, n_harm).bytes;
     return FDAS_OK;
 }
 
@@ -652,13 +665,62 @@ int fdas_batch_harmonic_sums_peaks(fdas_plan_t p, const void *planes, int32_t n_
     const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
     if ((reinterpret_cast<uintptr_t>(planes) % pe) != 0 || (peaks && !aligned16(peaks)) || !aligned8(n_found))
         return FDAS_E_INVALID;
-    const fdas::BatchSumsLayout L = fdas::batch_sums_layout(*p, n_levels, n_harm);
+    const fdas::SumBatch b = plan_batch(*p);
+    const fdas::BatchSumsLayout L = fdas::batch_sums_layout(*p, b, n_levels, n_harm);
     if (capacity > 0 && L.lists > INT64_MAX / capacity) return FDAS_E_INVALID;
     if (!p->ws) return FDAS_E_WORKSPACE;
     if (!scratch || !aligned16(scratch) || scratch_bytes < L.bytes) return FDAS_E_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = fdas::launch_batch_sums_mark(*p, L, planes, n_levels, n_harm, thresholds, scratch, st);
-    if (e == hipSuccess) e = fdas::batch_sums_finish(*p, L, planes, scratch, peaks, capacity, n_found, st);
+    hipError_t e = fdas::launch_batch_sums_mark(*p, b, L, planes, n_levels, n_harm, thresholds, scratch, st);
+    if (e == hipSuccess) e = fdas::batch_sums_finish(*p, b, L, planes, scratch, peaks, capacity, n_found, st);
+    return hip_status(e);
+}
+
+// fdas_harmonic_peaks: the plane as a batch of one job, its record in the
+// first 256 bytes of the scratch, the batch layout after it.
+static constexpr size_t kOneJobBytes = 256;
+static_assert(sizeof(fdas_batch_job) <= kOneJobBytes, "one job record");
+
+static int check_harmonic_peaks(fdas_plan_t p, int64_t n_bins, int32_t n_levels, const int32_t *n_harm,
+                                fdas_batch_job *job, fdas::BatchSumsLayout *L) {
+    if (!p || !sum_levels_ok(n_levels, n_harm) || n_bins < 1 || n_bins > p->cfg.max_bins) return FDAS_E_INVALID;
+    if (p->cfg.n_z > 65535 || !sum_rows_fit(*p, n_bins)) return FDAS_E_UNSUPPORTED;
+    *job = fdas_batch_job{0, n_bins, 0, 0, 0, 0};
+    *L = fdas::batch_sums_layout(*p, fdas::SumBatch{job, 1, nullptr}, n_levels, n_harm);
+    return check_sum_layout(*L);
+}
+
+int fdas_harmonic_peaks_workspace(fdas_plan_t p, int64_t n_bins, int32_t n_levels, const int32_t *n_harm,
+                                  size_t *scratch_bytes) {
+    if (!scratch_bytes) return FDAS_E_INVALID;
+    fdas_batch_job job;
+    fdas::BatchSumsLayout L;
+    const int s = check_harmonic_peaks(p, n_bins, n_levels, n_harm, &job, &L);
+    if (s != FDAS_OK) return s;
+    *scratch_bytes = kOneJobBytes + L.bytes;
+    return FDAS_OK;
+}
+
+int fdas_harmonic_peaks(fdas_plan_t p, const void *plane, int64_t n_bins, int32_t n_levels, const int32_t *n_harm,
+                        const float *thresholds, fdas_peak *peaks, int64_t capacity, int64_t *n_found, void *scratch,
+                        size_t scratch_bytes, void *stream) {
+    fdas_batch_job job;
+    fdas::BatchSumsLayout L;
+    const int s = check_harmonic_peaks(p, n_bins, n_levels, n_harm, &job, &L);
+    if (s != FDAS_OK) return s;
+    if (!plane || !thresholds || !n_found || capacity < 0 || (capacity > 0 && !peaks)) return FDAS_E_INVALID;
+    const uintptr_t pe = (uintptr_t)elem_bytes(p->cfg.plane_dtype) / 2;   // one real value
+    if ((reinterpret_cast<uintptr_t>(plane) % pe) != 0 || (peaks && !aligned16(peaks)) || !aligned8(n_found))
+        return FDAS_E_INVALID;
+    if (capacity > 0 && L.lists > INT64_MAX / capacity) return FDAS_E_INVALID;
+    if (!scratch || !aligned16(scratch) || scratch_bytes < kOneJobBytes + L.bytes) return FDAS_E_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto *dev_job = static_cast<fdas_batch_job *>(scratch);
+    const fdas::SumBatch b{&job, 1, dev_job};
+    unsigned char *rest = static_cast<unsigned char *>(scratch) + kOneJobBytes;
+    hipError_t e = fdas::write_one_job(dev_job, n_bins, st);
+    if (e == hipSuccess) e = fdas::launch_batch_sums_mark(*p, b, L, plane, n_levels, n_harm, thresholds, rest, st);
+    if (e == hipSuccess) e = fdas::batch_sums_finish(*p, b, L, plane, rest, peaks, capacity, n_found, st);
     return hip_status(e);
 }
 

@@ -486,12 +486,13 @@ hipError_t launch_harmonic_sum_marked(const fdas_plan_s &p, const void *plane, i
     return dispatch<true>(p, plane, n, n_harm, out, marks, st);
 }
 
-BatchSumsLayout batch_sums_layout(const fdas_plan_s &p, int n_levels, const int32_t *H) {
+BatchSumsLayout batch_sums_layout(const fdas_plan_s &p, const SumBatch &b, int n_levels, const int32_t *H) {
     BatchSumsLayout L;
-    const int64_t J = p.batch_jobs, S = (int64_t)n_levels * J;
+    const int64_t J = b.n_jobs, S = (int64_t)n_levels * J;
     const int64_t per_block = (int64_t)kHsThreads * kHsPerThread;
     for (int l = 0; l < n_levels; ++l)
-        for (const fdas_batch_job &j : p.batch_host) {
+        for (int64_t i = 0; i < J; ++i) {
+            const fdas_batch_job &j = b.host[i];
             const int64_t nh = (j.n_bins - 1) / H[l] + 1;
             const int64_t tiles = (int64_t)p.cfg.n_z * ((nh + kPeakTileCols - 1) / kPeakTileCols);
             L.tiles += tiles;
@@ -526,11 +527,12 @@ BatchSumsLayout batch_sums_layout(const fdas_plan_s &p, int n_levels, const int3
 }
 
 namespace {
+__global__ void k_one_job(fdas_batch_job *dst, int64_t n) { *dst = fdas_batch_job{0, n, 0, 0, 0, 0}; }
+
 template <class PT>
-hipError_t run_batch_sums(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, int n_levels,
-                          const int32_t *H, const float *thr, unsigned char *scratch, hipStream_t st) {
-    const auto *jobs = reinterpret_cast<const fdas_batch_job *>(static_cast<const unsigned char *>(p.ws) +
-                                                               p.off_batch + p.batch_hdr);
+hipError_t run_batch_sums(const fdas_plan_s &p, const SumBatch &b, const BatchSumsLayout &L, const void *planes,
+                          int n_levels, const int32_t *H, const float *thr, unsigned char *scratch, hipStream_t st) {
+    const fdas_batch_job *jobs = b.dev;
     SumLevelsArg lv{};
     for (int l = 0; l < n_levels; ++l) {
         lv.H[l] = H[l];
@@ -546,25 +548,31 @@ hipError_t run_batch_sums(const fdas_plan_s &p, const BatchSumsLayout &L, const 
     const unsigned cg = (unsigned)std::max<int64_t>(
         2, std::min<int64_t>(1024, std::max<int64_t>((L.clear_bytes + 4095) / 4096, (tasks + 15) / 16)));
     auto *units = reinterpret_cast<int2 *>(scratch + L.off_units);
-    hipLaunchKernelGGL(k_batch_sums_prep, dim3(cg), dim3(1024), 0, st, jobs, p.batch_jobs, n_levels, lv, p.cfg.n_z,
+    hipLaunchKernelGGL(k_batch_sums_prep, dim3(cg), dim3(1024), 0, st, jobs, b.n_jobs, n_levels, lv, p.cfg.n_z,
                        p.cfg.z_min, p.cfg.z_step, lists, rows, L.hmax, units, clear, (int64_t)L.clear_bytes);
     if (L.blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_batch_sums_mark<PT>), dim3((unsigned)L.blocks), dim3(kHsThreads), 0, st,
-                       static_cast<const PT *>(planes), jobs, lists, units, p.batch_jobs, n_levels, rows, L.hmax,
+                       static_cast<const PT *>(planes), jobs, lists, units, b.n_jobs, n_levels, rows, L.hmax,
                        flags, cflags);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_batch_sums_mark(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, int n_levels,
-                                  const int32_t *H, const float *thr, void *scratch, hipStream_t st) {
-    auto *b = static_cast<unsigned char *>(scratch);
+hipError_t launch_batch_sums_mark(const fdas_plan_s &p, const SumBatch &b, const BatchSumsLayout &L,
+                                  const void *planes, int n_levels, const int32_t *H, const float *thr, void *scratch,
+                                  hipStream_t st) {
+    auto *sc = static_cast<unsigned char *>(scratch);
     switch (p.cfg.plane_dtype) {
-        case FDAS_FP32: return run_batch_sums<float>(p, L, planes, n_levels, H, thr, b, st);
-        case FDAS_BF16: return run_batch_sums<__bf16>(p, L, planes, n_levels, H, thr, b, st);
-        case FDAS_FP64: return run_batch_sums<double>(p, L, planes, n_levels, H, thr, b, st);
+        case FDAS_FP32: return run_batch_sums<float>(p, b, L, planes, n_levels, H, thr, sc, st);
+        case FDAS_BF16: return run_batch_sums<__bf16>(p, b, L, planes, n_levels, H, thr, sc, st);
+        case FDAS_FP64: return run_batch_sums<double>(p, b, L, planes, n_levels, H, thr, sc, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t write_one_job(fdas_batch_job *dev, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_one_job, dim3(1), dim3(1), 0, st, dev, n);
+    return hipGetLastError();
 }
 
 }  // namespace fdas

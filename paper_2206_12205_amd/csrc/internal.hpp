@@ -166,11 +166,23 @@ struct BatchSumsLayout {
     size_t off_counts = 0, off_block_counts = 0, off_wg_totals = 0, off_wg_offsets = 0, off_prefix = 0;
     size_t off_totals = 0, off_lists = 0, off_rows = 0, off_units = 0, clear_bytes = 0, bytes = 0;
 };
-BatchSumsLayout batch_sums_layout(const fdas_plan_s &p, int n_levels, const int32_t *H);
-hipError_t launch_batch_sums_mark(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, int n_levels,
-                                  const int32_t *H, const float *thr, void *scratch, hipStream_t s);
-hipError_t batch_sums_finish(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, void *scratch,
-                             fdas_peak *out, int64_t capacity, int64_t *n_found, hipStream_t s);
+// The jobs a batch harmonic-sums call covers: the host copy (for the
+// layout) and the device table (for the kernels); a single plane is a batch
+// of one job whose record the caller's scratch holds.
+struct SumBatch {
+    const fdas_batch_job *host;
+    int32_t n_jobs;
+    const fdas_batch_job *dev;
+};
+BatchSumsLayout batch_sums_layout(const fdas_plan_s &p, const SumBatch &b, int n_levels, const int32_t *H);
+hipError_t launch_batch_sums_mark(const fdas_plan_s &p, const SumBatch &b, const BatchSumsLayout &L,
+                                  const void *planes, int n_levels, const int32_t *H, const float *thr, void *scratch,
+                                  hipStream_t s);
+hipError_t batch_sums_finish(const fdas_plan_s &p, const SumBatch &b, const BatchSumsLayout &L, const void *planes,
+                             void *scratch, fdas_peak *out, int64_t capacity, int64_t *n_found, hipStream_t s);
+// Writes the one-job record {n_bins = n, everything else 0} to dev (a
+// kernel, so graph capture records no copy from host memory).
+hipError_t write_one_job(fdas_batch_job *dev, int64_t n, hipStream_t s);
 hipError_t launch_harmonic_sums(const fdas_plan_s &p, const void *plane, int64_t n, int n_levels, const int32_t *H,
                                 void *const *outs, const PeakMarks *marks, hipStream_t st);
 // The same, also marking the peak tiles of the summed plane (marks from

@@ -886,10 +886,9 @@ hipError_t batch_peaks_finish(const fdas_plan_s &p, const void *planes, void *sc
 }
 
 template <class PT>
-hipError_t run_batch_sums_finish(const fdas_plan_s &p, const BatchSumsLayout &L, const PT *planes,
+hipError_t run_batch_sums_finish(const fdas_plan_s &p, const SumBatch &sb, const BatchSumsLayout &L, const PT *planes,
                                  unsigned char *b, fdas_peak *out, int64_t cap, int64_t *n_found, hipStream_t st) {
-    const auto *jobs = reinterpret_cast<const fdas_batch_job *>(static_cast<const unsigned char *>(p.ws) +
-                                                               p.off_batch + p.batch_hdr);
+    const fdas_batch_job *jobs = sb.dev;
     auto *totals = reinterpret_cast<unsigned long long *>(b + L.off_totals);
     uint8_t *flags = b + L.off_totals + (size_t)L.lists * 8;
     SumSource<PT> src{planes, jobs, reinterpret_cast<const SumJob *>(b + L.off_lists), (int)L.lists,
@@ -901,18 +900,18 @@ hipError_t run_batch_sums_finish(const fdas_plan_s &p, const BatchSumsLayout &L,
     return hipGetLastError();
 }
 
-hipError_t batch_sums_finish(const fdas_plan_s &p, const BatchSumsLayout &L, const void *planes, void *scratch,
-                             fdas_peak *out, int64_t capacity, int64_t *n_found, hipStream_t st) {
+hipError_t batch_sums_finish(const fdas_plan_s &p, const SumBatch &sb, const BatchSumsLayout &L, const void *planes,
+                             void *scratch, fdas_peak *out, int64_t capacity, int64_t *n_found, hipStream_t st) {
     auto *b = static_cast<unsigned char *>(scratch);
     switch (p.cfg.plane_dtype) {
         case FDAS_FP32:
-            return run_batch_sums_finish<float>(p, L, static_cast<const float *>(planes), b, out, capacity, n_found,
-                                                st);
+            return run_batch_sums_finish<float>(p, sb, L, static_cast<const float *>(planes), b, out, capacity,
+                                                n_found, st);
         case FDAS_BF16:
-            return run_batch_sums_finish<unsigned short>(p, L, static_cast<const unsigned short *>(planes), b, out,
-                                                         capacity, n_found, st);
+            return run_batch_sums_finish<unsigned short>(p, sb, L, static_cast<const unsigned short *>(planes), b,
+                                                         out, capacity, n_found, st);
         case FDAS_FP64:
-            return run_batch_sums_finish<double>(p, L, static_cast<const double *>(planes), b, out, capacity,
+            return run_batch_sums_finish<double>(p, sb, L, static_cast<const double *>(planes), b, out, capacity,
                                                  n_found, st);
         default: return hipErrorInvalidValue;
     }

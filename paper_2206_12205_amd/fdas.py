@@ -118,6 +118,9 @@ def lib() -> ctypes.CDLL:
                                                                ctypes.POINTER(ctypes.c_size_t)]
         L.fdas_batch_harmonic_sums_peaks.argtypes = [P, P, I32, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_float),
                                                      P, I64, P, P, ctypes.c_size_t, P]
+        L.fdas_harmonic_peaks_workspace.argtypes = [P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_size_t)]
+        L.fdas_harmonic_peaks.argtypes = [P, P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_float), P, I64,
+                                          P, P, ctypes.c_size_t, P]
         L.fdas_band_max.argtypes = [P, P, I64, P, I32, P, P]
         L.fdas_prepare_workspace.argtypes = [I64, ctypes.POINTER(ctypes.c_size_t)]
         L.fdas_prepare.argtypes = [P, I64, P, P, ctypes.c_size_t, P]
@@ -545,7 +548,10 @@ class Plan:
         n = plane.shape[1]
         hs = [int(h) for h in n_harms]
         outs = [torch.empty((self.n_z, (n - 1) // h + 1), dtype=plane.dtype, device=self.device) for h in hs]
-        pk = torch.empty((len(hs), max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
+        # each level's list starts 16-byte aligned: an even number of 24-byte records apart
+        stride = max(int(capacity), 1)
+        stride += stride & 1
+        pk = torch.empty((len(hs), stride, 24), dtype=torch.uint8, device=self.device)
         nf = torch.zeros(len(hs), dtype=torch.int64, device=self.device)
         scr = torch.empty(max(self.harmonic_sums_peaks_bytes(n, hs), 1), dtype=torch.uint8, device=self.device)
         self.harmonic_sums_peaks_async(plane.data_ptr(), n, hs, thresholds, [o.data_ptr() for o in outs],
@@ -554,6 +560,47 @@ class Plan:
         found, over = peak_counts(nf, len(hs), capacity, stream)
         return _capacity_result("fdas_harmonic_sums_peaks", over, truncate,
                                 (outs, [peak_records(pk[l], found[l], capacity) for l in range(len(hs))]))
+
+    def harmonic_peaks_bytes(self, n, n_harms):
+        """Scratch bytes of fdas_harmonic_peaks for an n-bin plane."""
+        hs = [int(h) for h in n_harms]
+        nb = ctypes.c_size_t(0)
+        _check(lib().fdas_harmonic_peaks_workspace(self._h, int(n), len(hs), (ctypes.c_int32 * len(hs))(*hs),
+                                                   ctypes.byref(nb)), "fdas_harmonic_peaks_workspace")
+        return nb.value
+
+    def harmonic_peaks_async(self, plane_ptr, n, n_harms, thresholds, peaks_ptr, capacity, n_found_ptr, scratch,
+                             stream=None):
+        """Enqueue fdas_harmonic_peaks on raw device pointers: peaks_ptr holds
+        len(n_harms) x capacity records, n_found_ptr len(n_harms) int64,
+        scratch a uint8 tensor of harmonic_peaks_bytes.  No host
+        synchronisation."""
+        hs = [int(h) for h in n_harms]
+        harr = (ctypes.c_int32 * len(hs))(*hs)
+        tarr = (ctypes.c_float * len(hs))(*[float(t) for t in thresholds])
+        _check(lib().fdas_harmonic_peaks(self._h, ctypes.c_void_p(plane_ptr), int(n), len(hs), harr, tarr,
+                                         ctypes.c_void_p(peaks_ptr), int(capacity), ctypes.c_void_p(n_found_ptr),
+                                         ctypes.c_void_p(scratch.data_ptr()), scratch.numel(), _stream_ptr(stream)),
+               "fdas_harmonic_peaks")
+
+    def harmonic_peaks(self, plane, n_harms, thresholds, capacity=1 << 16, stream=None, truncate=False):
+        """The thresholded peaks of several harmonic sums of one plane, the
+        sums never stored (fdas_harmonic_peaks) -> list of peaks dicts, one
+        per level; overflow of any list as for peaks()."""
+        import torch
+        if plane.dim() != 2 or plane.shape[0] != self.n_z or plane.dtype != self.torch_plane_dtype() \
+                or not plane.is_contiguous():
+            raise ValueError("plane must be a contiguous (n_z, n) tensor of the plan's plane dtype")
+        n = plane.shape[1]
+        hs = [int(h) for h in n_harms]
+        pk = torch.empty((len(hs), max(int(capacity), 1), 24), dtype=torch.uint8, device=self.device)
+        nf = torch.zeros(len(hs), dtype=torch.int64, device=self.device)
+        scr = torch.empty(max(self.harmonic_peaks_bytes(n, hs), 1), dtype=torch.uint8, device=self.device)
+        self.harmonic_peaks_async(plane.data_ptr(), n, hs, thresholds, pk.data_ptr(), capacity, nf.data_ptr(), scr,
+                                  stream)
+        found, over = peak_counts(nf, len(hs), capacity, stream)
+        return _capacity_result("fdas_harmonic_peaks", over, truncate,
+                                [peak_records(pk[l], found[l], capacity) for l in range(len(hs))])
 
     def harmonic_sum_peaks(self, plane, n_harm, threshold, capacity=1 << 16, out=None, stream=None,
                            truncate=False):

@@ -232,9 +232,10 @@ def search_series(plan, series, threshold, harmonics=(1, 2, 4, 8, 16), capacity=
     threshold  a float, or a dict H -> float (noise powers of a sum of H
                normalised powers have mean H)
     Steps: the normalised spectrum (fdas_prepare), the plane with its
-    thresholded peaks (fdas_correlate_peaks), and every sum over H > 1
-    harmonics in one pass with the thresholded peaks of each
-    (fdas_harmonic_sums_peaks).  Returns (spectrum, plane, {H: peaks dict}).
+    thresholded peaks (fdas_correlate_peaks), and the thresholded peaks of
+    every sum over H > 1 harmonics in one summing pass, the sums themselves
+    not stored (fdas_harmonic_peaks: the same lists as
+    fdas_harmonic_sums_peaks).  Returns (spectrum, plane, {H: peaks dict}).
     """
     spec = F.prepare(series, stream=stream)
     thr = (lambda h: float(threshold[h])) if isinstance(threshold, dict) else (lambda h: float(threshold))
@@ -242,6 +243,6 @@ def search_series(plan, series, threshold, harmonics=(1, 2, 4, 8, 16), capacity=
     found = {1: pk1} if 1 in harmonics else {}
     hs = sorted(h for h in set(harmonics) if h > 1)
     if hs:
-        _, lists = plan.harmonic_sums_peaks(plane, hs, [thr(h) for h in hs], capacity=capacity, stream=stream)
+        lists = plan.harmonic_peaks(plane, hs, [thr(h) for h in hs], capacity=capacity, stream=stream)
         found.update(zip(hs, lists))
     return spec, plane, found

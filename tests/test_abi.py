@@ -418,8 +418,61 @@ def test_harmonic_sums_refuse_rows_of_4_gb():
         assert L.fdas_harmonic_sums(h, P(0x10000), big, 2, hs, outs, None) == F.E_UNSUPPORTED
         need = ctypes.c_size_t()
         assert L.fdas_harmonic_sums_peaks_workspace(h, big, 2, hs, ctypes.byref(need)) == F.E_UNSUPPORTED
+        assert L.fdas_harmonic_peaks_workspace(h, big, 2, hs, ctypes.byref(need)) == F.E_UNSUPPORTED
         # a row just below the limit is accepted by the host checks
         ok = (0xfff00000 // 2) - 1
         assert L.fdas_harmonic_sums_peaks_workspace(h, ok, 2, hs, ctypes.byref(need)) == F.OK
+        assert L.fdas_harmonic_peaks_workspace(h, ok, 2, hs, ctypes.byref(need)) == F.OK
+    finally:
+        L.fdas_destroy(h)
+
+
+def test_harmonic_peaks_checks_on_host():
+    """fdas_harmonic_peaks(_workspace): the scratch size follows the plane
+    length and levels, bad lists, lengths and pointers are refused and a
+    short scratch answers FDAS_E_WORKSPACE, all before any device call; a plan
+    with no workspace or batch is enough."""
+    L = F.lib()
+    P = ctypes.c_void_p
+    h = P()
+    nb = ctypes.c_size_t()
+    assert L.fdas_plan(ctypes.byref(make(compute="bf16", plane_dtype="bf16")), ctypes.byref(h),
+                       ctypes.byref(nb)) == F.OK
+    try:
+        def ws(n, hs):
+            need = ctypes.c_size_t()
+            s = L.fdas_harmonic_peaks_workspace(h, n, len(hs), (ctypes.c_int32 * len(hs))(*hs), ctypes.byref(need))
+            return s, need.value
+
+        def run(n, hs, plane=P(0x10000), peaks=P(0x40000), cap=16, n_found=P(0x20000), scratch=P(0x50000),
+                nbytes=1 << 30, thr=True):
+            k = len(hs)
+            t = (ctypes.c_float * k)(*[10.0] * k) if thr else None
+            return L.fdas_harmonic_peaks(h, plane, n, k, (ctypes.c_int32 * k)(*hs), t, peaks, cap, n_found,
+                                         scratch, nbytes, None)
+        s1, b1 = ws(4096, [2, 4])
+        s2, b2 = ws(65536, [2, 4])
+        s3, b3 = ws(65536, [2, 4, 8, 16])
+        assert s1 == s2 == s3 == F.OK and 0 < b1 < b2 < b3
+        assert ws(0, [2])[0] == F.E_INVALID                  # empty plane
+        assert ws(65537, [2])[0] == F.E_INVALID              # above max_bins
+        assert ws(4096, [])[0] == F.E_INVALID
+        assert ws(4096, [4, 2])[0] == F.E_INVALID            # increasing H
+        assert ws(4096, [33])[0] == F.E_INVALID              # at most 32 harmonics
+        assert ws(4096, list(range(2, 11)))[0] == F.E_INVALID   # at most 8 levels
+        assert L.fdas_harmonic_peaks_workspace(h, 4096, 1, (ctypes.c_int32 * 1)(2), None) == F.E_INVALID
+        assert run(4096, [2], plane=None) == F.E_INVALID
+        assert run(4096, [2], thr=False) == F.E_INVALID
+        assert run(4096, [2], n_found=None) == F.E_INVALID
+        assert run(4096, [2], n_found=P(0x20004)) == F.E_INVALID     # n_found 8-byte aligned
+        assert run(4096, [2], peaks=None) == F.E_INVALID             # capacity > 0 needs peaks
+        assert run(4096, [2], peaks=P(0x40008)) == F.E_INVALID       # peaks 16-byte aligned
+        assert run(4096, [2], plane=P(0x10001)) == F.E_INVALID       # bfloat16 alignment
+        assert run(4096, [2], cap=-1) == F.E_INVALID
+        assert run(4096, [2], scratch=None) == F.E_WORKSPACE
+        assert run(4096, [2], scratch=P(0x50008)) == F.E_WORKSPACE   # scratch 16-byte aligned
+        assert run(4096, [2, 4], nbytes=b1 - 1) == F.E_WORKSPACE
+        assert L.fdas_harmonic_peaks(None, P(0x10000), 4096, 1, (ctypes.c_int32 * 1)(2), (ctypes.c_float * 1)(1.0),
+                                     P(0x40000), 4, P(0x20000), P(0x50000), 1 << 30, None) == F.E_INVALID
     finally:
         L.fdas_destroy(h)

@@ -6,7 +6,9 @@ in order h = 1..H in double precision); FP32 sums within H 2^-23 relative
 (sequential single-precision additions); BF16 outputs, rounded from single
 precision, within one bfloat16 step of the oracle's double sum rounded the
 same way.  Peaks of the summed plane must be the oracle's peaks of the oracle
-sum.  The full single-DM BF16 plane is checked on sampled rows.
+sum; the peaks of sums that are never stored (fdas_harmonic_peaks) must be
+bitwise the stored form's lists.  The full single-DM BF16 plane is checked on
+sampled rows.
 """
 import sys
 
@@ -185,6 +187,36 @@ def test_harmonic_sums_peaks_one_pass(dev, pd, hs):
             assert np.array_equal(got["z_idx"], j) and np.array_equal(got["r"], r), f"H={h} thr={thr}"
 
 
+@pytest.mark.parametrize("pd", ["fp32", "bf16", "fp64"])
+@pytest.mark.parametrize("hs", [(2, 4, 8, 16), (1, 3, 32), (5,)])
+def test_harmonic_peaks_unstored_equal_stored(dev, pd, hs):
+    """fdas_harmonic_peaks (the sums never stored, flagged tiles recomputed
+    from the plane): every list bitwise fdas_harmonic_sums_peaks's (cells,
+    order, powers, true count) and the oracle's peaks of the summed plane, at
+    thresholds above the noise, low with a small capacity (the first entries
+    and the true count), negative and NaN; a length with a ragged last tile."""
+    import torch
+    say(f"[harmonic] peaks of unstored sums {pd} {hs}")
+    sp = synth.config1(0)
+    n = sp.spec.size - 37
+    compute = "fp64" if pd == "fp64" else "fp32"
+    pl = plan(dev, max_bins=sp.spec.size, z_min=C1["z_min"], z_step=C1["z_step"], n_z=C1["n_z"],
+              n_taps=C1["n_taps"], seg_len=C1["seg_len"], compute=compute, plane_dtype=pd)
+    P = pl.correlate(torch.from_numpy(sp.spec[:n]).to(dev))
+    for thrs, cap in (([2.0 * h + 6.0 for h in hs], 1 << 20), ([3.0] * len(hs), 17),
+                      ([-1.0] + [float("nan")] * (len(hs) - 1), 1 << 20)):
+        _, want = pl.harmonic_sums_peaks(P, hs, thrs, capacity=cap, truncate=True)
+        got = pl.harmonic_peaks(P, hs, thrs, capacity=cap, truncate=True)
+        for h, thr, a, b in zip(hs, thrs, got, want):
+            what = f"H={h} thr={thr} cap={cap}"
+            assert a["n_found"] == b["n_found"], what
+            for k in ("z_idx", "r", "power"):
+                assert np.array_equal(a[k], b[k]), f"{what} {k}"
+            if cap > 1 << 16:
+                j, r, _ = OK_PEAKS.peaks(host(pl.harmonic_sum(P, h)), thr)
+                assert a["n_found"] == len(j) and np.array_equal(a["z_idx"], j) and np.array_equal(a["r"], r), what
+
+
 def test_harmonic_series_of_chirps_on_the_gpu(dev):
     """The sum at the fundamental's cell of a noise-free harmonic series of
     chirps is the sum of their matched powers (the oracle pin's physics),
@@ -248,7 +280,8 @@ def test_single_dm_bf16_plane_sampled_rows(dev):
 def test_harmonic_marks_survive_nan_sums(dev, pd):
     """NaN cells in the plane: a thread whose sums in one peak tile are
     (above the threshold, NaN, below, below) must still flag the tile, so
-    both fused calls list exactly the oracle's peaks of the summed plane.
+    the fused calls (and the unstored form) list exactly the oracle's peaks of
+    the summed plane.
     Each thread holds the fundamentals r0 + 256 i, four per 1024-bin tile."""
     import torch
     say(f"[harmonic] NaN sums beside peaks {pd}")
@@ -280,4 +313,6 @@ def test_harmonic_marks_survive_nan_sums(dev, pd):
         assert np.array_equal(got["z_idx"], j) and np.array_equal(got["r"], r), f"H={H} single"
         _, lists = pl.harmonic_sums_peaks(P, [H], [thr], capacity=1 << 12)
         assert np.array_equal(lists[0]["z_idx"], j) and np.array_equal(lists[0]["r"], r), f"H={H} one-pass"
+        unstored = pl.harmonic_peaks(P, [H], [thr], capacity=1 << 12)
+        assert np.array_equal(unstored[0]["z_idx"], j) and np.array_equal(unstored[0]["r"], r), f"H={H} unstored"
         assert nh == S.shape[1]
