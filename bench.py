@@ -794,6 +794,7 @@ def main():
     ap.add_argument("--no-refine", action="store_true", help="skip the candidate-refinement timing")
     ap.add_argument("--no-canopy", action="store_true", help="skip the noise-canopy experiment")
     ap.add_argument("--no-prep", action="store_true", help="skip the spectrum-preparation timing")
+    ap.add_argument("--no-series", action="store_true", help="skip the whole-series search timing")
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the wide workload (201 x 8.4M planes in FP32, BF16 and FP8 vs FP64)")
     ap.add_argument("--trials", type=int, default=256,
@@ -985,7 +986,8 @@ def main():
         del pl_d
 
     out["plane_and_peaks"] = {"workload": "the single-DM BF16 plane and its thresholded peaks", **fused_pk}
-    out["series_search"] = series_search_timing(args, cfg, dev, pl_b)
+    if not args.no_series:
+        out["series_search"] = series_search_timing(args, cfg, dev, pl_b)
 
     if not args.no_harmonic:
         out["harmonic_sum"] = {"workload": "the single-DM BF16 plane, BF16 sums out", **harm}
