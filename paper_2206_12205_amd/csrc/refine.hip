@@ -24,10 +24,12 @@
 // curvature of an isolated peak, r += s_r 3 / (2 pi^2 P) dP/dr and
 // z += s_z 90 / (pi^2 P) dP/dz.
 //
-// One wave per candidate, lane i holds tap i; the three sums are reduced by
-// an XOR butterfly (fixed order, the same on every lane), so every lane sees
-// the same (r, z) trajectory.  Everything is FP64: a bin index near 4e6 has
-// an FP32 spacing of half a bin.
+// One segment of 32 lanes per candidate when taps <= 32 (two candidates per
+// wave), else the whole wave; lane i of the segment holds tap i; the three
+// sums are reduced by an XOR butterfly inside the segment (fixed order, the
+// same on every lane), so every lane sees the same (r, z) trajectory.
+// Everything is FP64: a bin index near 4e6 has an FP32 spacing of half a
+// bin.
 #include "internal.hpp"
 #include "response.hpp"
 
@@ -65,9 +67,11 @@ __device__ void response_d(double q, double z, cd &A, cd &Aq, cd &Az) {
     Az = {-M_PI * m2.im, M_PI * m2.re};
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+// Sum over the lanes of a segment of `width` (32 or 64) lanes.
+__device__ __forceinline__ double seg_sum(double v, int width) {
+    if (width == 64) v += __shfl_xor(v, 32, 64);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
@@ -75,8 +79,8 @@ struct RefineOut {
     double P, dPr, dPz;
 };
 
-// Every lane returns the same values.
-__device__ RefineOut eval_point(const float2 *spec, int64_t n, double r, double z, int taps, int lane) {
+// Every lane of the segment (width lanes) returns the same values.
+__device__ RefineOut eval_point(const float2 *spec, int64_t n, double r, double z, int taps, int lane, int width) {
     cd F = {0, 0}, Fr = {0, 0}, Fz = {0, 0};
     if (lane < taps) {
         const int64_t k = (int64_t)floor(r) - taps / 2 + 1 + lane;
@@ -90,9 +94,9 @@ __device__ RefineOut eval_point(const float2 *spec, int64_t n, double r, double 
             Fz = x * conj(Az - 0.5 * Aq);
         }
     }
-    F = {wave_sum(F.re), wave_sum(F.im)};
-    Fr = {wave_sum(Fr.re), wave_sum(Fr.im)};
-    Fz = {wave_sum(Fz.re), wave_sum(Fz.im)};
+    F = {seg_sum(F.re, width), seg_sum(F.im, width)};
+    Fr = {seg_sum(Fr.re, width), seg_sum(Fr.im, width)};
+    Fz = {seg_sum(Fz.re, width), seg_sum(Fz.im, width)};
     RefineOut o;
     o.P = F.re * F.re + F.im * F.im;
     o.dPr = 2.0 * (F.re * Fr.re + F.im * Fr.im);
@@ -103,18 +107,19 @@ __device__ RefineOut eval_point(const float2 *spec, int64_t n, double r, double 
 __global__ void __launch_bounds__(64) k_refine(const float2 *spec, int64_t n, int32_t n_cand, double *r, double *z,
                                                double *power, double *dp_dr, double *dp_dz, int32_t taps,
                                                int32_t n_steps, double s_r, double s_z) {
-    const int cand = blockIdx.x;
-    if (cand >= n_cand) return;
-    const int lane = threadIdx.x;
+    const int width = taps <= 32 ? 32 : 64;   // lanes per candidate
+    const int cand = blockIdx.x * (64 / width) + (int)threadIdx.x / width;
+    if (cand >= n_cand) return;   // a whole segment: its shuffles stay inside it
+    const int lane = (int)threadIdx.x % width;
     double rr = r[cand], zz = z[cand];
     const double pi2 = M_PI * M_PI;
     for (int it = 0; it < n_steps; ++it) {
-        const RefineOut o = eval_point(spec, n, rr, zz, taps, lane);
+        const RefineOut o = eval_point(spec, n, rr, zz, taps, lane, width);
         const double Ps = fmax(o.P, 1e-30);
         rr += s_r * 3.0 / (2.0 * pi2 * Ps) * o.dPr;
         zz += s_z * 90.0 / (pi2 * Ps) * o.dPz;
     }
-    const RefineOut o = eval_point(spec, n, rr, zz, taps, lane);
+    const RefineOut o = eval_point(spec, n, rr, zz, taps, lane, width);
     if (lane == 0) {
         r[cand] = rr;
         z[cand] = zz;
@@ -128,10 +133,12 @@ __global__ void __launch_bounds__(64) k_refine(const float2 *spec, int64_t n, in
 __global__ void __launch_bounds__(64) k_refine_backward(const float2 *spec, int64_t n, int32_t n_cand, const double *r,
                                                         const double *z, const double *grad_p, double *grad_r,
                                                         double *grad_z, int32_t taps) {
-    const int cand = blockIdx.x;
+    const int width = taps <= 32 ? 32 : 64;
+    const int cand = blockIdx.x * (64 / width) + (int)threadIdx.x / width;
     if (cand >= n_cand) return;
-    const RefineOut o = eval_point(spec, n, r[cand], z[cand], taps, threadIdx.x);
-    if (threadIdx.x == 0) {
+    const int lane = (int)threadIdx.x % width;
+    const RefineOut o = eval_point(spec, n, r[cand], z[cand], taps, lane, width);
+    if (lane == 0) {
         const double g = grad_p[cand];
         grad_r[cand] = g * o.dPr;
         grad_z[cand] = g * o.dPz;
@@ -142,7 +149,9 @@ hipError_t launch_refine(const void *spec, int64_t n, int32_t n_cand, double *r,
                          double *dp_dr, double *dp_dz, int32_t taps, int32_t n_steps, double s_r, double s_z,
                          hipStream_t st) {
     if (n_cand == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_refine, dim3((unsigned)n_cand), dim3(64), 0, st, static_cast<const float2 *>(spec), n,
+    const int per = taps <= 32 ? 2 : 1;   // candidates per wave
+    hipLaunchKernelGGL(k_refine, dim3((unsigned)((n_cand + per - 1) / per)), dim3(64), 0, st,
+                       static_cast<const float2 *>(spec), n,
                        n_cand, r, z, power, dp_dr, dp_dz, taps, n_steps, s_r, s_z);
     return hipGetLastError();
 }
@@ -150,8 +159,9 @@ hipError_t launch_refine(const void *spec, int64_t n, int32_t n_cand, double *r,
 hipError_t launch_refine_backward(const void *spec, int64_t n, int32_t n_cand, const double *r, const double *z,
                                   const double *grad_p, double *grad_r, double *grad_z, int32_t taps, hipStream_t st) {
     if (n_cand == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_refine_backward, dim3((unsigned)n_cand), dim3(64), 0, st, static_cast<const float2 *>(spec),
-                       n, n_cand, r, z, grad_p, grad_r, grad_z, taps);
+    const int per = taps <= 32 ? 2 : 1;   // candidates per wave
+    hipLaunchKernelGGL(k_refine_backward, dim3((unsigned)((n_cand + per - 1) / per)), dim3(64), 0, st,
+                       static_cast<const float2 *>(spec), n, n_cand, r, z, grad_p, grad_r, grad_z, taps);
     return hipGetLastError();
 }
 

@@ -49,6 +49,28 @@ def test_refine_values_and_gradients_match_oracle(dev):
     assert np.max(np.abs(gz - gzo) / scale) < 1e-8
 
 
+@pytest.mark.parametrize("taps", [2, 16, 32, 34, 64])
+def test_refine_tap_counts_and_odd_batches(dev, taps):
+    """Two candidates share a wave up to 32 taps (a 32-lane segment each),
+    one takes the whole wave above: values and gradients match the oracle for
+    every tap count, with an odd number of candidates (the last wave holds
+    one) and candidates at both ends of the spectrum."""
+    import torch
+    from paper_2206_12205_amd.fdas import refine
+    say(f"[refine] {taps} taps, 31 candidates")
+    x = chirps_spectrum()
+    g = np.random.default_rng(taps)
+    r = np.concatenate([[1500.25, 0.3, x.size - 1.6], g.uniform(20, 8000, 28)])
+    z = np.concatenate([[8.0, 2.0, -3.0], g.uniform(-40, 40, 28)])
+    _, _, P, gr, gz = refine(torch.from_numpy(x).to(dev), torch.from_numpy(r), torch.from_numpy(z), taps=taps)
+    P, gr, gz = (t.cpu().numpy() for t in (P, gr, gz))
+    Po, gro, gzo = ORF.power_grad(x, r, z, taps)
+    scale = np.maximum(Po, 1.0)
+    assert np.max(np.abs(P - Po) / scale) < 1e-9
+    assert np.max(np.abs(gr - gro) / scale) < 1e-8
+    assert np.max(np.abs(gz - gzo) / scale) < 1e-8
+
+
 def test_refine_gradient_matches_finite_differences(dev):
     import torch
     from paper_2206_12205_amd.fdas import refine
