@@ -451,7 +451,7 @@ k_peak_count(Src src, int n_z, int64_t n_chunks, int64_t n_ranges, const uint8_t
 // runs of up to kScanRegs inside the array, the run is read as 16-byte loads
 // from one address, all in flight together, and written back from the
 // registers, so it costs one memory round trip instead of one per value;
-// other runs are summed and written by loops.  part: 1024 int64 of LDS.
+// other runs are summed and written by loops.  part: 32 int64 of LDS.
 constexpr int kScanRegs = 32;
 
 template <class T>
@@ -483,16 +483,29 @@ __device__ int64_t block_exclusive_scan(const T *vals, int64_t n, int64_t *offse
     } else {
         for (int64_t i = b; i < e; ++i) s += (int64_t)vals[i];
     }
-    part[threadIdx.x] = s;
-    __syncthreads();
-    // inclusive Hillis-Steele scan over the 1024 partial sums
-    for (int w = 1; w < 1024; w <<= 1) {
-        const int64_t x = threadIdx.x >= (unsigned)w ? part[threadIdx.x - w] : 0;
-        __syncthreads();
-        part[threadIdx.x] += x;
-        __syncthreads();
+    // inclusive scan of the 1024 partial sums: within each wave by shuffles,
+    // then over the 16 wave totals (part[0 .. 15]) by the first wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t x = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += x;
     }
-    int64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    if (lane == 63) part[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        int64_t t = lane < 16 ? part[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int64_t x = __shfl_up(t, o, 64);
+            if (lane >= o) t += x;
+        }
+        if (lane < 16) part[16 + lane] = t;   // inclusive prefix of the wave totals
+    }
+    __syncthreads();
+    int64_t run = (wave ? part[16 + wave - 1] : 0) + incl - s;   // exclusive prefix of this thread's run
+    const int64_t total = part[16 + 15];
     if (wide) {
         int64_t *o = offsets + b;
 #pragma unroll
@@ -512,7 +525,7 @@ __device__ int64_t block_exclusive_scan(const T *vals, int64_t n, int64_t *offse
             run += x;
         }
     }
-    return part[1023];
+    return total;
 }
 
 // Single workgroup: exclusive scan of n >= 1 values -> offsets[0 .. n)
@@ -521,7 +534,7 @@ __device__ int64_t block_exclusive_scan(const T *vals, int64_t n, int64_t *offse
 template <class T>
 __global__ void __launch_bounds__(1024) k_peak_scan(const T *vals, int64_t n, int64_t *offsets, int64_t *total,
                                                     int64_t *copy) {
-    __shared__ int64_t part[1024];
+    __shared__ int64_t part[32];
     const int64_t t = block_exclusive_scan(vals, n, offsets, copy, part);
     if (threadIdx.x == 1023) {
         offsets[n] = t;
@@ -669,7 +682,7 @@ unsigned mark_grid(int64_t total, size_t elem) {
 __global__ void __launch_bounds__(1024) k_peak_scan_batch(const int32_t *wg_totals, int64_t n_wg, int64_t *wg_offsets,
                                                           const unsigned long long *job_totals, int64_t n_lists,
                                                           int64_t *job_prefix, int64_t *n_found) {
-    __shared__ int64_t part[1024];
+    __shared__ int64_t part[32];
     const int64_t t = block_exclusive_scan(wg_totals, n_wg, wg_offsets, (int64_t *)nullptr, part);
     if (threadIdx.x == 1023) wg_offsets[n_wg] = t;
     block_exclusive_scan(job_totals, n_lists, job_prefix, n_found, part);
