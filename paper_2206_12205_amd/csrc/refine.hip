@@ -17,8 +17,14 @@
 //   M1 = int u e^{i phi} = (E1 - 1 - 2 pi i q A) / (2 pi i z)
 //   M2 = int u^2 e^{i phi} = (E1 - A - 2 pi i q M1) / (2 pi i z),  E1 = e^{i pi (2q + z)},
 //   A_q = 2 pi i M1,  A_z = i pi M2,
-// used for |z| >= 0.5; below that the three moments come from composite
-// 16-point Gauss-Legendre quadrature (panels resolving every half turn).
+// used for |z| >= kClosedFormZ; below that the three moments come from
+// composite 16-point Gauss-Legendre quadrature (panels resolving every half
+// turn).  The closed form divides by z twice: its numerators are O(z) with
+// absolute errors near eps (1 + 2 pi |q| |A|), so M2 carries about
+// eps 2 pi |q| / (2 pi z)^2, 2e-12 at z = 0.05 and |q| = 16 taps out -- far
+// inside the refinement's bars -- while the quadrature costs about
+// 32 (|q| + |z|) evaluations of exp(i phi) per tap, which made the few
+// candidates near z = 0 set the launch time.
 //
 // Ascent step (the paper prints none): a Newton step on the analytic
 // curvature of an isolated peak, r += s_r 3 / (2 pi^2 P) dP/dr and
@@ -35,10 +41,12 @@
 
 namespace fdas {
 
+constexpr double kClosedFormZ = 0.05;
+
 // A, A_q, A_z at (q, z).
 __device__ void response_d(double q, double z, cd &A, cd &Aq, cd &Az) {
     const double twopi = 2.0 * M_PI;
-    if (fabs(z) >= 0.5) {
+    if (fabs(z) >= kClosedFormZ) {
         A = response(q, z);
         const cd E1 = expipi(2.0 * q + z);
         const cd tq = {-twopi * q * A.im, twopi * q * A.re};            // 2 pi i q A

@@ -34,11 +34,13 @@ def test_refine_values_and_gradients_match_oracle(dev):
     say("[refine] oracle values")
     x = chirps_spectrum()
     g = np.random.default_rng(1)
-    r = np.concatenate([[1500.25, 3000.6, 5000.9, 10.4, 8180.5], g.uniform(20, 8000, 27)])
-    z = np.concatenate([[8.0, -24.0, 0.0, 3.0, 0.3], g.uniform(-40, 40, 27)])
+    r = np.concatenate([[1500.25, 3000.6, 5000.9, 10.4, 8180.5], g.uniform(20, 8000, 31)])
+    z = np.concatenate([[8.0, -24.0, 0.0, 3.0, 0.3], g.uniform(-40, 40, 31)])
     z[7] = 0.0
     z[8] = 1e-7
     z[9] = -0.49
+    # both sides of the switch from quadrature to the closed form (|z| = 0.05)
+    z[10], z[11], z[12], z[13] = 0.0501, -0.0499, 0.049, -0.06
     xs = torch.from_numpy(x).to(dev)
     _, _, P, gr, gz = refine(xs, torch.from_numpy(r), torch.from_numpy(z))
     P, gr, gz = (t.cpu().numpy() for t in (P, gr, gz))
