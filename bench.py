@@ -200,7 +200,8 @@ def cpu_baseline(spec, cfg, r_center, target_s=15.0):
 
 def batched_search(args, cfg, dev):
     """Many-spectra workload: 256 dedispersion trials with series lengths
-    log-uniform in [2^20, 2^23] samples (spectra of 2^19..2^22 bins), 10 % of
+    log-uniform in [2^20, 2^23] samples, even counts (spectra of 2^19..2^22
+    bins, any length in between), 10 % of
     them with an injected binary pulsar, generated on the device (seeded);
     the single-DM template grid, BF16 form, autotuned plan per length class,
     planes chunked through a 16 GB buffer and thresholded peaks of every
@@ -291,7 +292,7 @@ def batched_search(args, cfg, dev):
         if pk["n_found"] and any(np.min(np.abs(pk["r"] - r)) <= 2 for r in rb):
             found += 1
     out = {"workload": f"{len(trials)} dedispersion trials, series log-uniform in [2^20, 2^23] samples "
-                       f"snapped to 2^k / 3*2^k "
+                       f"(even counts) "
                        f"(spectra {min(lengths)}..{max(lengths)} bins, total {total}), 10 % with an injected "
                        f"binary pulsar, {c3['n_z']} templates, {c3['n_taps']} taps, BF16 form, raw BF16 "
                        f"planes chunked through a 16 GB buffer, peaks above {c3['threshold']}",

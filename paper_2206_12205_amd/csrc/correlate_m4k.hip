@@ -132,6 +132,24 @@ struct Stage<float> {
         }
     }
 };
+// Eight bf16 samples starting S (1..7) samples before the run held in c,
+// from the words of the preceding run p and of c (two samples per word,
+// lower half first).
+template <int S>
+__device__ __forceinline__ uint4 bf16_run_back(const uint4 &p, const uint4 &c) {
+    const uint32_t w[8] = {p.x, p.y, p.z, p.w, c.x, c.y, c.z, c.w};
+    constexpr int b = 4 - S / 2;
+    uint32_t o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if constexpr (S & 1)
+            o[i] = __builtin_amdgcn_alignbit(w[b + i], w[b - 1 + i], 16);   // upper half of one word, lower of the next
+        else
+            o[i] = w[b + i];
+    }
+    return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
 template <>
 struct Stage<__bf16> {
     static constexpr int kWords = kL / 2 + 4 * 16;
@@ -141,28 +159,88 @@ struct Stage<__bf16> {
         u.y = bf16_pack(c, d);
         *reinterpret_cast<uint2 *>(&st[t0 / 2 + 4 * (t0 >> 8)]) = u;
     }
-    // samples t0 .. t0 + 7 (t0 a multiple of 8): one 16-byte read, one
-    // 16-byte store; kMark: as for FP32, when the packed prefilter passes
-    template <bool kMark>
-    static __device__ __forceinline__ void flush8(const uint32_t *st, int t0, __bf16 *row, bool vec, int lo, int hi,
-                                                  const PeakMarks &m, int64_t z, int64_t seg0) {
-        const uint4 u = *reinterpret_cast<const uint4 *>(&st[t0 / 2 + 4 * (t0 >> 8)]);
-        if (vec) {
+    static __device__ __forceinline__ uint4 run(const uint32_t *st, int t0) {
+        return *reinterpret_cast<const uint4 *>(&st[t0 / 2 + 4 * (t0 >> 8)]);
+    }
+    // Eight samples per lane (t0 a multiple of 8), one 16-byte store.
+    // !kShift (launches whose rows all start on 16-byte boundaries): vec8
+    // says whether the run [t0, t0 + 8) is stored whole.  kShift: when the
+    // row starts sh samples past a 16-byte boundary (sh is the same for
+    // every lane of the workgroup), the lane stores the aligned run of
+    // samples [t0 - sh, t0 - sh + 8) instead, assembled from its own staged
+    // run and the preceding one, so rows of any length keep 16-byte stores;
+    // vmask bit k: the run [t0 - k, t0 - k + 8) lies inside the kept samples
+    // [lo, hi).  Runs not stored whole are stored element by element.
+    // kMark: as for FP32, when the packed prefilter passes.
+    template <bool kMark, bool kShift>
+    static __device__ __forceinline__ void flush8(const uint32_t *st, int t0, __bf16 *row, bool vec8, uint32_t vmask,
+                                                  int lo, int hi, const PeakMarks &m, int64_t z, int64_t seg0) {
+        if constexpr (!kShift) {
+            const uint4 u = run(st, t0);
+            if (vec8) {
+                const u32x4_t w = {u.x, u.y, u.z, u.w};
+                __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t *>(row + t0));
+            } else {
+                const uint32_t ww[4] = {u.x, u.y, u.z, u.w};
+                uint16_t *r16 = reinterpret_cast<uint16_t *>(row);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (t0 + i >= lo && t0 + i < hi) r16[t0 + i] = (uint16_t)(ww[i >> 1] >> (16 * (i & 1)));
+            }
+            if constexpr (kMark) {
+                const uint32_t w0 = u.x, w1 = u.y, w2 = u.z, w3 = u.w;
+                if (bf16x8_maybe_above(w0, w1, w2, w3, m)) {   // rare
+                    int t = t0;   // opaque copy, as for FP32
+                    asm volatile("" : "+v"(t));
+                    mark_run(m, (uint32_t)z * (uint32_t)m.n_cb, (int32_t)seg0, max(t, lo), min(t + 7, hi - 1));
+                }
+            }
+            return;
+        }
+        const int sh = (int)((reinterpret_cast<uintptr_t>(row) >> 1) & 7);
+        uint4 u = run(st, t0);
+        int t = t0;
+        if (sh != 0) {
+            // t0 = 0: the samples before it are outside every row's kept range
+            const uint4 p = run(st, max(t0 - 8, 0));
+            switch (sh) {
+                case 1: u = bf16_run_back<1>(p, u); break;
+                case 2: u = bf16_run_back<2>(p, u); break;
+                case 3: u = bf16_run_back<3>(p, u); break;
+                case 4: u = bf16_run_back<4>(p, u); break;
+                case 5: u = bf16_run_back<5>(p, u); break;
+                case 6: u = bf16_run_back<6>(p, u); break;
+                default: u = bf16_run_back<7>(p, u); break;
+            }
+            t = t0 - sh;
+        }
+        if ((vmask >> sh) & 1) {
             const u32x4_t w = {u.x, u.y, u.z, u.w};
-            __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t *>(row + t0));
+            __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t *>(row + t));
         } else {
             const uint32_t ww[4] = {u.x, u.y, u.z, u.w};
             uint16_t *r16 = reinterpret_cast<uint16_t *>(row);
 #pragma unroll
             for (int i = 0; i < 8; ++i)
-                if (t0 + i >= lo && t0 + i < hi) r16[t0 + i] = (uint16_t)(ww[i >> 1] >> (16 * (i & 1)));
+                if (t + i >= lo && t + i < hi) r16[t + i] = (uint16_t)(ww[i >> 1] >> (16 * (i & 1)));
         }
         if constexpr (kMark) {
             const uint32_t w0 = u.x, w1 = u.y, w2 = u.z, w3 = u.w;
             if (bf16x8_maybe_above(w0, w1, w2, w3, m)) {   // rare
-                int t = t0;   // opaque copy, as for FP32
-                asm volatile("" : "+v"(t));
+                asm volatile("" : "+v"(t));   // opaque copy, as for FP32
                 mark_run(m, (uint32_t)z * (uint32_t)m.n_cb, (int32_t)seg0, max(t, lo), min(t + 7, hi - 1));
+            }
+        }
+        // Shifted runs cover samples [-sh, kL - sh).  With fewer than 16 taps
+        // the kept samples reach past kL - sh: lane 0 stores that tail.
+        if (sh != 0 && t0 == 0 && hi > kL - sh) {
+            const uint4 q = run(st, kL - 8);
+            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+            uint16_t *r16 = reinterpret_cast<uint16_t *>(row);
+            for (int i = 8 - sh; i < 8 && kL - 8 + i < hi; ++i) r16[kL - 8 + i] = (uint16_t)(qq[i >> 1] >> (16 * (i & 1)));
+            if constexpr (kMark) {
+                if (bf16x8_maybe_above(q.x, q.y, q.z, q.w, m))
+                    mark_run(m, (uint32_t)z * (uint32_t)m.n_cb, (int32_t)seg0, kL - sh, hi - 1);
             }
         }
     }
@@ -174,16 +252,18 @@ struct Stage<__bf16> {
 // workgroup own 8 samples each, t0 = 8 (tid mod 512), so every store is 16
 // bytes (1 KB per wave); the halves take even and odd templates in turn.
 // vec[h] / vec8: the chunk is entirely kept, inside the plane and aligned
-// for one vector store in every template row.  Samples [lo, hi) of a row are
-// kept.
+// for one vector store in every template row; vmask8: the same for the BF16
+// run shifted back by k samples (bit k, see Stage<__bf16>::flush8).  Samples
+// [lo, hi) of a row are kept.
 constexpr int kFlushChunks = kL / (4 * kThr);
 struct FlushPlan {
     bool vec[kFlushChunks];
     bool vec8;
+    uint32_t vmask8;
     int lo, hi;
 };
 
-template <class PT>
+template <class PT, bool kShift>
 __device__ __forceinline__ FlushPlan flush_plan(const PT *plane, int64_t seg0, int64_t n, int half, int tid) {
     FlushPlan f;
     constexpr uintptr_t kChunkBytes = 4 * sizeof(PT);   // 4 elements: 8 B (bf16) or 16 B (fp32)
@@ -200,19 +280,26 @@ __device__ __forceinline__ FlushPlan flush_plan(const PT *plane, int64_t seg0, i
         const int t0 = 8 * (tid & 511);
         f.vec8 = (n % 8) == 0 && (reinterpret_cast<uintptr_t>(plane + seg0 + t0) % 16) == 0 && t0 >= f.lo &&
                  t0 + 8 <= f.hi;
+        uint32_t vm = 0;
+        if constexpr (kShift) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) vm |= (uint32_t)(t0 - k >= f.lo && t0 - k + 8 <= f.hi) << k;
+        }
+        f.vmask8 = vm;
     }
     return f;
 }
 
 // Row z of the plane (its segment starts at column seg0) from the staging
 // buffer; kMark: with its peak tiles marked.
-template <class PT, bool kMark>
+template <class PT, bool kMark, bool kShift>
 __device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const FlushPlan &f, int tid, int jpar,
                                       const PeakMarks &m, int64_t z, int64_t seg0) {
     if constexpr (sizeof(PT) == 2) {
         // lower half of the workgroup: even templates, upper half: odd ones
         if ((tid >> 9) == jpar)
-            Stage<PT>::template flush8<kMark>(stage, 8 * (tid & 511), row_seg, f.vec8, f.lo, f.hi, m, z, seg0);
+            Stage<PT>::template flush8<kMark, kShift>(stage, 8 * (tid & 511), row_seg, f.vec8, f.vmask8, f.lo, f.hi, m,
+                                                        z, seg0);
     } else {
 #pragma unroll
         for (int h = 0; h < kFlushChunks; ++h) {
@@ -224,9 +311,10 @@ __device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const 
 
 // One tile: segment s of the spectrum (n bins) against templates [j0, j1),
 // writing plane rows j0 .. j1 - 1 (row stride n); kMark: marking the peak
-// tiles (m) of the cells it stores above the threshold.  Called by the whole
+// tiles (m) of the cells it stores above the threshold; kShift: BF16 rows
+// may start anywhere (see Stage<__bf16>::flush8).  Called by the whole
 // workgroup; contains barriers.
-template <class PT, bool kOpaqueLane = false, bool kMark = false>
+template <class PT, bool kOpaqueLane = false, bool kMark = false, bool kShift = false>
 __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_t n, const uint32_t *__restrict__ bank,
                                          const uint32_t *__restrict__ tab, PT *__restrict__ plane, int32_t M,
                                          int32_t V, int64_t s, int j0, int j1, uint32_t *bufA, uint32_t *bufB,
@@ -321,7 +409,7 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
         a23im[q] = load_op(tab, OP_I23 + 2 * Q + 1, lane);
     }
 
-    const FlushPlan fp = flush_plan<PT>(plane, seg0, n, half, tid);
+    const FlushPlan fp = flush_plan<PT, kShift>(plane, seg0, n, half, tid);
     const uint4 *bank4 = reinterpret_cast<const uint4 *>(bank) + (kGpw * w) * 64 + lane;
 
     // One template: I1 (group k1 = Q) on X * H_j, I2 (group n3), I3 (group n2).
@@ -361,7 +449,7 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
             *reinterpret_cast<uint4 *>(&bufA[chunk_addr(Q, c, g)]) = o;   // (k1, n3, k2 block)
         }
         __syncthreads();
-        if (j > j0) flush<PT, kMark>(stage, plane + (int64_t)(j - 1) * n + seg0, fp, tid, (j - 1) & 1, m, j - 1, seg0);
+        if (j > j0) flush<PT, kMark, kShift>(stage, plane + (int64_t)(j - 1) * n + seg0, fp, tid, (j - 1) & 1, m, j - 1, seg0);
         // I2: DFT16 over k2 with e(16 n3 k2), transposed: lane (c, g)
         // receives n2 = c, k1 = 4 g + e -> one 16-byte chunk of buffer B
 #pragma unroll
@@ -417,14 +505,15 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
         one_template(j + 1, hB, hA, j + 2 < j1);
     }
     __syncthreads();
-    flush<PT, kMark>(stage, plane + (int64_t)(j1 - 1) * n + seg0, fp, tid, (j1 - 1) & 1, m, j1 - 1, seg0);
+    flush<PT, kMark, kShift>(stage, plane + (int64_t)(j1 - 1) * n + seg0, fp, tid, (j1 - 1) & 1, m, j1 - 1, seg0);
 }
 
 #define M4K_ATTR __attribute__((amdgpu_flat_work_group_size(kThr, kThr), amdgpu_waves_per_eu(kWavesPerEU)))
 
 // One spectrum: workgroup b takes template chunk b mod n_chunks of segment
-// b / n_chunks.  kMark: the peak tiles of the plane (m) are marked as well.
-template <class PT, bool kMark>
+// b / n_chunks.  kMark: the peak tiles of the plane (m) are marked as well;
+// kShift: some BF16 row starts are not 16-byte aligned.
+template <class PT, bool kMark, bool kShift>
 __global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int64_t n,
                                             const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
                                             PT *__restrict__ plane, int32_t M, int32_t V, int32_t n_z,
@@ -437,7 +526,7 @@ __global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int
     const int j0 = chunk * z_chunk;
     const int j1 = min(j0 + z_chunk, n_z);
     if (j0 >= j1) return;
-    m4k_tile<PT, false, kMark>(spec, n, bank, tab, plane, M, V, s, j0, j1, bufA, bufB, stage, m);
+    m4k_tile<PT, false, kMark, kShift>(spec, n, bank, tab, plane, M, V, s, j0, j1, bufA, bufB, stage, m);
 }
 
 // Many spectra in one persistent launch.  Tiles are (job, segment, template
@@ -449,10 +538,10 @@ __global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int
 // chunk's queue, so ragged lengths still balance across the CUs.  kMark:
 // the peak tiles of every job's plane are marked as well (m.flags and
 // m.cflags are the batch's arrays, each job's part at its tile_base and
-// chunk_base).
+// chunk_base).  kShift: as for one spectrum.
 constexpr int kXcds = 8;
 
-template <class PT, bool kMark>
+template <class PT, bool kMark, bool kShift>
 __global__ void M4K_ATTR correlate_mfma4096_batch(const float2 *__restrict__ spectra,
                                                   const fdas_batch_job *__restrict__ jobs, int32_t n_jobs,
                                                   int32_t n_segs, int32_t *__restrict__ counters,
@@ -504,12 +593,19 @@ __global__ void M4K_ATTR correlate_mfma4096_batch(const float2 *__restrict__ spe
             mj.cflags = m.cflags + jobs[lo].chunk_base;
             mj.n_cb = (int32_t)((nb + kPeakTileCols - 1) / kPeakTileCols);
         }
-        m4k_tile<PT, true, kMark>(spectra + spec_off + opaque, nb, bank + opaque, tab + opaque,
+        m4k_tile<PT, true, kMark, kShift>(spectra + spec_off + opaque, nb, bank + opaque, tab + opaque,
                                   planes + plane_off + opaque, M, V + opaque, s, j0, j1, bufA, bufB, stage, mj);
     }
 }
 
 namespace {
+// Do BF16 rows start on 16-byte boundaries in every segment?  Row z of the
+// segment at column s V - M / 2 starts at element plane_off + z n + s V - M / 2.
+bool rows_aligned(const fdas_plan_s &p, const void *plane, int64_t plane_off, int64_t n) {
+    return (reinterpret_cast<uintptr_t>(plane) % 16) == 0 && plane_off % 8 == 0 && n % 8 == 0 && p.V % 8 == 0 &&
+           (p.M / 2) % 8 == 0;
+}
+
 template <class PT, bool kMark>
 hipError_t launch(const fdas_plan_s &p, const void *spec, int64_t n, void *plane, const PeakMarks &m,
                   hipStream_t st) {
@@ -517,7 +613,10 @@ hipError_t launch(const fdas_plan_s &p, const void *spec, int64_t n, void *plane
     const int64_t blocks = n_seg * p.n_chunks;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const auto *ws = static_cast<const unsigned char *>(p.ws);
-    hipLaunchKernelGGL((correlate_mfma4096<PT, kMark>), dim3((unsigned)blocks), dim3(kThr), 0, st,
+    constexpr bool kBf16 = sizeof(PT) == 2;
+    auto kernel = kBf16 && !rows_aligned(p, plane, 0, n) ? correlate_mfma4096<PT, kMark, kBf16>
+                                                         : correlate_mfma4096<PT, kMark, false>;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kThr), 0, st,
                        static_cast<const float2 *>(spec), n, reinterpret_cast<const uint32_t *>(ws + p.off_bank),
                        reinterpret_cast<const uint32_t *>(ws + p.off_tab), static_cast<PT *>(plane), p.M, p.V,
                        p.cfg.n_z, p.z_chunk, p.n_chunks, m);
@@ -536,7 +635,12 @@ hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes,
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>((int64_t)cus * 2, std::max<int64_t>(p.batch_tiles, 1));
-    hipLaunchKernelGGL((correlate_mfma4096_batch<PT, kMark>), dim3((unsigned)grid), dim3(kThr), 0, st,
+    constexpr bool kBf16 = sizeof(PT) == 2;
+    bool aligned = true;
+    for (const fdas_batch_job &j : p.batch_host) aligned = aligned && rows_aligned(p, planes, j.plane_off, j.n_bins);
+    auto kernel = kBf16 && !aligned ? correlate_mfma4096_batch<PT, kMark, kBf16>
+                                    : correlate_mfma4096_batch<PT, kMark, false>;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(kThr), 0, st,
                        static_cast<const float2 *>(spectra), jobs, p.batch_jobs,
                        (int32_t)(p.batch_tiles / p.n_chunks), counters,
                        reinterpret_cast<const uint32_t *>(ws + p.off_bank),

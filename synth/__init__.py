@@ -252,10 +252,45 @@ class Trial:
         return self.n_t * self.tsamp
 
 
-def _device_spectrum(n_t: int, tsamp: float, pulsars, seed: int, device):
+def chirp_z_dft_head(x, n_out: int):
+    """Bins 0 .. n_out - 1 of the length-N DFT X[k] = sum_n x[n] exp(-2 pi i n k / N)
+    of a real or complex torch tensor x (any N, any device), complex128.
+
+    Bluestein's chirp-z form: with n k = (n^2 + k^2 - (k - n)^2) / 2 and the
+    chirp c[m] = exp(-i pi m^2 / N), X[k] = c[k] sum_n (x[n] c[n]) conj(c[k - n]),
+    a linear convolution that a cyclic one of power-of-two length M >= 2N - 1
+    computes without wrap-around, so only power-of-two FFTs run whatever N is.
+    c[m] depends on m^2 mod 2N only, which is reduced exactly in integers
+    before the angle is formed.
+    """
+    import torch
+    N = int(x.numel())
+    dev = x.device
+    M = 1 << (2 * N - 2).bit_length()
+    m = torch.arange(N, dtype=torch.int64, device=dev)
+    ang = (m * m % (2 * N)).to(torch.float64) * (-math.pi / N)
+    c = torch.polar(torch.ones_like(ang), ang)
+    del m, ang
+    a = torch.zeros(M, dtype=torch.complex128, device=dev)
+    a[:N] = x.to(torch.complex128) * c
+    b = torch.zeros(M, dtype=torch.complex128, device=dev)
+    b[:N] = c.conj()
+    if N > 1:
+        b[M - N + 1:] = c[1:].conj().flip(0)
+    fa = torch.fft.fft(a)
+    del a
+    fa *= torch.fft.fft(b)
+    del b
+    y = torch.fft.ifft(fa)[:n_out]
+    return c[:n_out] * y
+
+
+def _device_spectrum(n_t: int, tsamp: float, pulsars, seed: int, device, any_length: bool = False):
     """Gaussian series plus pulsars on the device (torch, FP64), then the
     to_spectrum recipe: real FFT, Nyquist dropped, DC zeroed, median
-    normalisation; complex64."""
+    normalisation; complex64.  any_length: the transform by chirp_z_dft_head
+    (power-of-two FFTs only), so that no FFT plan is built for the length
+    itself."""
     import torch
     gen = torch.Generator(device=device).manual_seed(int(seed))
     x = torch.randn(n_t, dtype=torch.float64, device=device, generator=gen)
@@ -270,7 +305,7 @@ def _device_spectrum(n_t: int, tsamp: float, pulsars, seed: int, device):
                 ch = ch - torch.floor(ch)
                 x += a * torch.cos(2.0 * math.pi * ch + ph)
         del t
-    X = torch.fft.rfft(x)[: n_t // 2]
+    X = chirp_z_dft_head(x, n_t // 2) if any_length else torch.fft.rfft(x)[: n_t // 2]
     del x
     X[0] = 0.0
     med = torch.median(X[1:].real ** 2 + X[1:].imag ** 2)
@@ -310,24 +345,22 @@ def config3(device, trial: int = 0, n_spec: int | None = None):
     """Batched dedispersion trials, generated on the device (torch, FP64).
 
     n_spec spectra (256 by default) with series lengths log-uniform in
-    [2^20, 2^23] samples (snapped to 2^k or 3 * 2^k), a sampling time drawn from
-    64 / 128 / 256 / 512 us, Gaussian noise, and in 10 % of them one binary
-    pulsar drawn as in the single-DM workload.  Each series goes through the
-    same recipe as to_spectrum (real FFT, Nyquist dropped, DC zeroed, median
-    normalisation), here with torch on the device so that 4.7e8 bins take
-    seconds.  Returns (packed complex64 tensor, list of Trial).
+    [2^20, 2^23] samples (rounded to an even count), a sampling time drawn
+    from 64 / 128 / 256 / 512 us, Gaussian noise, and in 10 % of them one
+    binary pulsar drawn as in the single-DM workload.  Each series goes
+    through the same recipe as to_spectrum (DFT, Nyquist dropped, DC zeroed,
+    median normalisation), here with torch on the device so that 4.7e8 bins
+    take seconds; the DFT of each length by chirp_z_dft_head, since an FFT
+    library builds (and may compile) a plan for every distinct length.
+    Returns (packed complex64 tensor, list of Trial).
     """
     import torch
     c = CONFIGS[3]
     g = rng(3, trial)
     n = c["n_spec"] if n_spec is None else int(n_spec)
-    # log-uniform lengths snapped to the nearest of 2^k and 3 * 2^k: every
-    # spectrum is the real FFT of its series, and FFT-friendly sizes keep the
-    # device FFT library from compiling a kernel for each of 256 odd lengths
-    grid = np.array(sorted(m * 2 ** k for m in (1, 3) for k in range(18, 24)
-                           if c["n_t_min"] <= m * 2 ** k <= c["n_t_max"]), dtype=np.int64)
+    # log-uniform lengths, each rounded to an even sample count (n_t / 2 bins)
     want = np.exp(g.uniform(math.log(c["n_t_min"]), math.log(c["n_t_max"]), n))
-    n_ts = grid[np.argmin(np.abs(np.log(want)[:, None] - np.log(grid)[None, :]), axis=1)]
+    n_ts = np.clip(2 * np.rint(want / 2), c["n_t_min"], c["n_t_max"]).astype(np.int64)
     tsamps = g.choice(np.array(c["tsamps"]), size=n)
     with_psr = g.permutation(n)[: int(round(c["frac_pulsar"] * n))]
     seeds = g.integers(0, 2 ** 62, size=n)
@@ -335,7 +368,7 @@ def config3(device, trial: int = 0, n_spec: int | None = None):
     for i in range(n):
         n_t, tsamp = int(n_ts[i]), float(tsamps[i])
         psr = draw_pulsar(g, n_t * tsamp, tsamp, n_t=n_t) if i in with_psr else None
-        X = _device_spectrum(n_t, tsamp, [psr] if psr else [], int(seeds[i]), device)
+        X = _device_spectrum(n_t, tsamp, [psr] if psr else [], int(seeds[i]), device, any_length=True)
         parts.append(X)
         trials.append(Trial(off, n_t // 2, n_t, tsamp, psr))
         off += n_t // 2

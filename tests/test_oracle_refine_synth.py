@@ -23,6 +23,38 @@ def test_generator_is_deterministic():
     assert abs(p.mean() - 1.0) < 0.03
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 1000, 65537, 1000003, 3 * 2 ** 19])
+def test_chirp_z_dft_matches_fft(n):
+    # the batched workload's DFT of arbitrary lengths: prime, odd, even and
+    # FFT-friendly N against the library FFT
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(n)
+    x = g.standard_normal(n)
+    k = n // 2 + 1
+    got = synth.chirp_z_dft_head(torch.from_numpy(x), k).numpy()
+    want = np.fft.fft(x)[:k]
+    assert got.shape == want.shape
+    assert np.abs(got - want).max() <= 1e-13 * max(np.abs(want).max(), 1.0)
+
+
+def test_batched_lengths_log_uniform_and_even():
+    # four spectra of the batched workload on the CPU: even lengths inside
+    # [2^20, 2^23], n_t / 2 bins each, packed back to back, normalised
+    torch = pytest.importorskip("torch")
+    x, trials = synth.config3("cpu", trial=0, n_spec=4)
+    c = synth.CONFIGS[3]
+    off = 0
+    for t in trials:
+        assert t.n_t % 2 == 0 and c["n_t_min"] <= t.n_t <= c["n_t_max"]
+        assert t.n_bins == t.n_t // 2 and t.offset == off
+        off += t.n_bins
+        p = x[t.offset + 1: t.offset + t.n_bins].abs().double() ** 2
+        assert abs(float(p.median()) - math.log(2.0)) < 1e-3
+        assert x[t.offset] == 0
+    assert x.numel() == off and x.dtype == torch.complex64
+    assert len({t.n_t for t in trials}) == len(trials)   # not snapped to a few sizes
+
+
 def test_refine_gradient_matches_finite_differences():
     x = synth.random_spectrum(512, seed=11)
     r = np.array([100.31, 200.77, 301.5, 50.2])
