@@ -122,6 +122,43 @@ def test_fused_batch_matches_oracle(dev, kw):
             assert_same_peaks(got[i], host, thr, cap, job=i, what=f"job {i} thr={thr} cap={cap}")
 
 
+@pytest.mark.parametrize("taps", [2, 130])
+def test_fused_rows_anywhere_small_and_odd_taps(dev, taps):
+    """BF16 matrix-core planes whose rows start anywhere, with 2 taps (the
+    kept samples reach the segment's last run) and 130 (an odd half-width):
+    single calls and one batch, plain and fused.  The batch's planes are
+    bitwise the single calls', the fused planes bitwise the plain ones, and
+    every list is the oracle's on its plane."""
+    import torch
+    from paper_2206_12205_amd.fdas import Plan
+    lengths = [9001, 12347, 3 * 4096 + 5, 20002, 7]
+    kw = dict(z_min=ZMIN, z_step=ZSTEP, n_z=NZ, n_taps=taps, seg_len=4096, compute="bf16",
+              plane_dtype="bf16", algo="mfma", device=dev)
+    pl = Plan(max_bins=max(lengths), max_jobs=len(lengths), **kw)
+    specs = [to_dev(spectrum(v, 700 + taps + i), dev) for i, v in enumerate(lengths)]
+    singles = []
+    for i, x in enumerate(specs):
+        say(f"[fused] rows anywhere taps={taps} single n={lengths[i]}")
+        ref = pl.correlate(x)
+        singles.append(ref)
+        for thr, cap in ((12.0, 1 << 14), (-1.0, 1 << 20)):
+            plane, got = pl.correlate_peaks(x, thr, capacity=cap, truncate=True)
+            assert torch.equal(plane.view(torch.int16), ref.view(torch.int16)), f"n={lengths[i]} fused plane"
+            assert_same_peaks(got, widen(ref), thr, cap, what=f"single n={lengths[i]} thr={thr}")
+    say(f"[fused] rows anywhere taps={taps} batch")
+    pl.set_batch(lengths)
+    spectra = torch.cat(specs)
+    planes = pl.correlate_batch(spectra)
+    for i in range(len(lengths)):
+        assert torch.equal(pl.batch_plane(planes, i).view(torch.int16), singles[i].view(torch.int16)), \
+            f"batch job {i} differs from its single call"
+    for thr, cap in ((12.0, 1 << 14), (-1.0, 1 << 20)):
+        fused, got = pl.correlate_batch_peaks(spectra, thr, capacity=cap, truncate=True)
+        assert torch.equal(fused.view(torch.int16), planes.view(torch.int16)), "fused batch planes"
+        for i in range(len(lengths)):
+            assert_same_peaks(got[i], widen(singles[i]), thr, cap, job=i, what=f"batch job {i} thr={thr}")
+
+
 def test_fused_batch_graph_replays(dev):
     """One fdas_correlate_batch_peaks recorded as a HIP graph, replayed on new
     spectra with eager work between replays; every replay equals the eager
