@@ -218,11 +218,17 @@ struct Stage<__bf16> {
             const u32x4_t w = {u.x, u.y, u.z, u.w};
             __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t *>(row + t));
         } else {
+            // the kept samples [pa, pb) of the (16-byte aligned) run: whole
+            // words as 4-byte stores, an odd sample at either end alone
             const uint32_t ww[4] = {u.x, u.y, u.z, u.w};
-            uint16_t *r16 = reinterpret_cast<uint16_t *>(row);
+            const int pa = min(max(lo - t, 0), 8), pb = min(max(hi - t, 0), 8);
+            uint16_t *r16 = reinterpret_cast<uint16_t *>(row + t);
+            uint32_t *r32 = reinterpret_cast<uint32_t *>(row + t);
+            if ((pa & 1) && pa < pb) r16[pa] = (uint16_t)(ww[pa >> 1] >> 16);
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (t + i >= lo && t + i < hi) r16[t + i] = (uint16_t)(ww[i >> 1] >> (16 * (i & 1)));
+            for (int i = 0; i < 4; ++i)
+                if (2 * i >= pa && 2 * i + 2 <= pb) r32[i] = ww[i];
+            if ((pb & 1) && pb - 1 >= pa) r16[pb - 1] = (uint16_t)ww[(pb - 1) >> 1];
         }
         if constexpr (kMark) {
             const uint32_t w0 = u.x, w1 = u.y, w2 = u.z, w3 = u.w;
@@ -260,6 +266,7 @@ struct FlushPlan {
     bool vec[kFlushChunks];
     bool vec8;
     uint32_t vmask8;
+    int t08;             // BF16 run of this thread (shifting instance)
     int lo, hi;
 };
 
@@ -277,7 +284,13 @@ __device__ __forceinline__ FlushPlan flush_plan(const PT *plane, int64_t seg0, i
                    t0 >= f.lo && t0 + 4 <= f.hi;
     }
     {
-        const int t0 = 8 * (tid & 511);
+        // The shifting instance rotates the runs over the threads of a half
+        // so that the run holding the first kept sample sits at lane 62 or 63
+        // of the first wave: with V >= 8 * 449 the run holding the last kept
+        // sample (and the tail of fewer than 16 taps) falls in that wave too,
+        // so one wave per row, not two, stores the partial runs.
+        const int t0 = kShift ? 8 * (((tid & 511) + ((f.lo >> 3) - 62)) & 511) : 8 * (tid & 511);
+        f.t08 = t0;
         f.vec8 = (n % 8) == 0 && (reinterpret_cast<uintptr_t>(plane + seg0 + t0) % 16) == 0 && t0 >= f.lo &&
                  t0 + 8 <= f.hi;
         uint32_t vm = 0;
@@ -298,7 +311,7 @@ __device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const 
     if constexpr (sizeof(PT) == 2) {
         // lower half of the workgroup: even templates, upper half: odd ones
         if ((tid >> 9) == jpar)
-            Stage<PT>::template flush8<kMark, kShift>(stage, 8 * (tid & 511), row_seg, f.vec8, f.vmask8, f.lo, f.hi, m,
+            Stage<PT>::template flush8<kMark, kShift>(stage, kShift ? f.t08 : 8 * (tid & 511), row_seg, f.vec8, f.vmask8, f.lo, f.hi, m,
                                                         z, seg0);
     } else {
 #pragma unroll
