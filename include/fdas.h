@@ -235,10 +235,11 @@ int fdas_make_templates_jerk(fdas_plan_t plan, double w, void *stream);
  *   spectrum  device, n_bins complex64 values (interleaved re, im floats)
  *   n_bins    N, 1 <= N <= max_bins
  *   plane     device, n_z x N row-major cells of the plan's plane dtype
- * Every cell of the plane is written.  Any N is served; a BF16 plane whose
- * rows all start on 16-byte boundaries (N a multiple of 8 and, with the
- * L = 4096 matrix-core kernel, M a multiple of 16) is written fastest, other
- * lengths through 16-byte stores of runs shifted to each row's alignment.
+ * Every cell of the plane is written.  Any N is served; with the L = 4096
+ * matrix-core kernel a plane whose rows all start on 16-byte boundaries (N
+ * and M / 2 multiples of 8 for BF16, of 4 for FP32) is written fastest,
+ * other lengths through 16-byte stores of runs shifted to each row's
+ * alignment.
  * FDAS_E_STATE before fdas_make_templates, FDAS_E_INVALID for bad pointers
  * or sizes. */
 int fdas_correlate(fdas_plan_t plan, const void *spectrum, int64_t n_bins,

@@ -105,29 +105,77 @@ struct Stage<float> {
     static __device__ __forceinline__ void put4(uint32_t *st, int t0, float a, float b, float c, float d) {
         *reinterpret_cast<float4 *>(&st[t0 + 4 * (t0 >> 8)]) = make_float4(a, b, c, d);
     }
+    static __device__ __forceinline__ float4 chunk(const uint32_t *st, int t0) {
+        return *reinterpret_cast<const float4 *>(&st[t0 + 4 * (t0 >> 8)]);
+    }
     // samples t0 .. t0 + 3 -> plane, vector or element-wise; kMark: the
     // peak tiles of the kept samples flagged when one of the four is above
-    // the threshold (plane row z, column seg0 + t)
-    template <bool kMark>
+    // the threshold (plane row z, column seg0 + t).  kShift: when the row
+    // starts sh floats past a 16-byte boundary (the same sh on every lane),
+    // the thread stores the aligned run [t0 - sh, t0 - sh + 4) instead, from
+    // its own staged chunk and the preceding one.
+    template <bool kMark, bool kShift>
     static __device__ __forceinline__ void flush4(const uint32_t *st, int t0, float *row, bool vec, int lo, int hi,
                                                   const PeakMarks &m, int64_t z, int64_t seg0) {
-        const float4 v = *reinterpret_cast<const float4 *>(&st[t0 + 4 * (t0 >> 8)]);
+        if constexpr (!kShift) {
+            const float4 v = chunk(st, t0);
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+            if (vec) {
+                const f32x4_t u = {v.x, v.y, v.z, v.w};
+                __builtin_nontemporal_store(u, reinterpret_cast<f32x4_t *>(row + t0));
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (t0 + i >= lo && t0 + i < hi) row[t0 + i] = vv[i];
+            }
+            if constexpr (kMark) {
+                if ((vv[0] > m.thr) | (vv[1] > m.thr) | (vv[2] > m.thr) | (vv[3] > m.thr)) {   // rare
+                    // an opaque copy keeps the run bounds (loop-invariant per
+                    // lane) from being hoisted and held across the template loop
+                    int t = t0;
+                    asm volatile("" : "+v"(t));
+                    mark_run(m, (uint32_t)z * (uint32_t)m.n_cb, (int32_t)seg0, max(t, lo), min(t + 3, hi - 1));
+                }
+            }
+            return;
+        }
+        const int sh = (int)((reinterpret_cast<uintptr_t>(row) >> 2) & 3);
+        float4 v = chunk(st, t0);
+        int t = t0;
+        if (sh != 0) {
+            // t0 = 0: the samples before it are outside every row's kept range
+            const float4 p = chunk(st, max(t0 - 4, 0));
+            v = sh == 1 ? make_float4(p.w, v.x, v.y, v.z)
+                        : (sh == 2 ? make_float4(p.z, p.w, v.x, v.y) : make_float4(p.y, p.z, p.w, v.x));
+            t = t0 - sh;
+        }
         const float vv[4] = {v.x, v.y, v.z, v.w};
-        if (vec) {
+        if (t >= lo && t + 4 <= hi) {
             const f32x4_t u = {v.x, v.y, v.z, v.w};
-            __builtin_nontemporal_store(u, reinterpret_cast<f32x4_t *>(row + t0));
+            __builtin_nontemporal_store(u, reinterpret_cast<f32x4_t *>(row + t));
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                if (t0 + i >= lo && t0 + i < hi) row[t0 + i] = vv[i];
+                if (t + i >= lo && t + i < hi) row[t + i] = vv[i];
         }
         if constexpr (kMark) {
             if ((vv[0] > m.thr) | (vv[1] > m.thr) | (vv[2] > m.thr) | (vv[3] > m.thr)) {   // rare
-                // an opaque copy keeps the run bounds (loop-invariant per
-                // lane) from being hoisted and held across the template loop
-                int t = t0;
-                asm volatile("" : "+v"(t));
+                asm volatile("" : "+v"(t));   // opaque copy, as above
                 mark_run(m, (uint32_t)z * (uint32_t)m.n_cb, (int32_t)seg0, max(t, lo), min(t + 3, hi - 1));
+            }
+        }
+        // Shifted runs cover samples [-sh, kL - sh).  With fewer than 8 taps
+        // the kept samples reach past kL - sh: thread 0 stores that tail.
+        if (sh != 0 && t0 == 0 && hi > kL - sh) {
+            const float4 q = chunk(st, kL - 4);
+            const float qq[4] = {q.x, q.y, q.z, q.w};
+            bool above = false;
+            for (int i = 4 - sh; i < 4 && kL - 4 + i < hi; ++i) {
+                row[kL - 4 + i] = qq[i];
+                above |= qq[i] > m.thr;
+            }
+            if constexpr (kMark) {
+                if (above) mark_run(m, (uint32_t)z * (uint32_t)m.n_cb, (int32_t)seg0, kL - sh, hi - 1);
             }
         }
     }
@@ -317,15 +365,15 @@ __device__ __forceinline__ void flush(const uint32_t *stage, PT *row_seg, const 
 #pragma unroll
         for (int h = 0; h < kFlushChunks; ++h) {
             const int t0 = 4 * (tid + h * kThr);
-            Stage<PT>::template flush4<kMark>(stage, t0, row_seg, f.vec[h], f.lo, f.hi, m, z, seg0);
+            Stage<PT>::template flush4<kMark, kShift>(stage, t0, row_seg, f.vec[h], f.lo, f.hi, m, z, seg0);
         }
     }
 }
 
 // One tile: segment s of the spectrum (n bins) against templates [j0, j1),
 // writing plane rows j0 .. j1 - 1 (row stride n); kMark: marking the peak
-// tiles (m) of the cells it stores above the threshold; kShift: BF16 rows
-// may start anywhere (see Stage<__bf16>::flush8).  Called by the whole
+// tiles (m) of the cells it stores above the threshold; kShift: rows may
+// start anywhere (see Stage<>::flush8 and flush4).  Called by the whole
 // workgroup; contains barriers.
 template <class PT, bool kOpaqueLane = false, bool kMark = false, bool kShift = false>
 __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_t n, const uint32_t *__restrict__ bank,
@@ -525,7 +573,7 @@ __device__ __forceinline__ void m4k_tile(const float2 *__restrict__ spec, int64_
 
 // One spectrum: workgroup b takes template chunk b mod n_chunks of segment
 // b / n_chunks.  kMark: the peak tiles of the plane (m) are marked as well;
-// kShift: some BF16 row starts are not 16-byte aligned.
+// kShift: some row starts are not 16-byte aligned.
 template <class PT, bool kMark, bool kShift>
 __global__ void M4K_ATTR correlate_mfma4096(const float2 *__restrict__ spec, int64_t n,
                                             const uint32_t *__restrict__ bank, const uint32_t *__restrict__ tab,
@@ -612,11 +660,13 @@ __global__ void M4K_ATTR correlate_mfma4096_batch(const float2 *__restrict__ spe
 }
 
 namespace {
-// Do BF16 rows start on 16-byte boundaries in every segment?  Row z of the
+// Do the rows start on 16-byte boundaries in every segment?  Row z of the
 // segment at column s V - M / 2 starts at element plane_off + z n + s V - M / 2.
+template <class PT>
 bool rows_aligned(const fdas_plan_s &p, const void *plane, int64_t plane_off, int64_t n) {
-    return (reinterpret_cast<uintptr_t>(plane) % 16) == 0 && plane_off % 8 == 0 && n % 8 == 0 && p.V % 8 == 0 &&
-           (p.M / 2) % 8 == 0;
+    constexpr int64_t e = 16 / sizeof(PT);   // elements per 16 bytes
+    return (reinterpret_cast<uintptr_t>(plane) % 16) == 0 && plane_off % e == 0 && n % e == 0 && p.V % e == 0 &&
+           (p.M / 2) % e == 0;
 }
 
 template <class PT, bool kMark>
@@ -626,9 +676,8 @@ hipError_t launch(const fdas_plan_s &p, const void *spec, int64_t n, void *plane
     const int64_t blocks = n_seg * p.n_chunks;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const auto *ws = static_cast<const unsigned char *>(p.ws);
-    constexpr bool kBf16 = sizeof(PT) == 2;
-    auto kernel = kBf16 && !rows_aligned(p, plane, 0, n) ? correlate_mfma4096<PT, kMark, kBf16>
-                                                         : correlate_mfma4096<PT, kMark, false>;
+    auto kernel = rows_aligned<PT>(p, plane, 0, n) ? correlate_mfma4096<PT, kMark, false>
+                                                   : correlate_mfma4096<PT, kMark, true>;
     hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kThr), 0, st,
                        static_cast<const float2 *>(spec), n, reinterpret_cast<const uint32_t *>(ws + p.off_bank),
                        reinterpret_cast<const uint32_t *>(ws + p.off_tab), static_cast<PT *>(plane), p.M, p.V,
@@ -648,11 +697,10 @@ hipError_t launch_batch(const fdas_plan_s &p, const void *spectra, void *planes,
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>((int64_t)cus * 2, std::max<int64_t>(p.batch_tiles, 1));
-    constexpr bool kBf16 = sizeof(PT) == 2;
     bool aligned = true;
-    for (const fdas_batch_job &j : p.batch_host) aligned = aligned && rows_aligned(p, planes, j.plane_off, j.n_bins);
-    auto kernel = kBf16 && !aligned ? correlate_mfma4096_batch<PT, kMark, kBf16>
-                                    : correlate_mfma4096_batch<PT, kMark, false>;
+    for (const fdas_batch_job &j : p.batch_host)
+        aligned = aligned && rows_aligned<PT>(p, planes, j.plane_off, j.n_bins);
+    auto kernel = aligned ? correlate_mfma4096_batch<PT, kMark, false> : correlate_mfma4096_batch<PT, kMark, true>;
     hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(kThr), 0, st,
                        static_cast<const float2 *>(spectra), jobs, p.batch_jobs,
                        (int32_t)(p.batch_tiles / p.n_chunks), counters,

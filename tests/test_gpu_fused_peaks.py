@@ -122,9 +122,10 @@ def test_fused_batch_matches_oracle(dev, kw):
             assert_same_peaks(got[i], host, thr, cap, job=i, what=f"job {i} thr={thr} cap={cap}")
 
 
+@pytest.mark.parametrize("pd", ["bf16", "fp32"])
 @pytest.mark.parametrize("taps", [2, 130])
-def test_fused_rows_anywhere_small_and_odd_taps(dev, taps):
-    """BF16 matrix-core planes whose rows start anywhere, with 2 taps (the
+def test_fused_rows_anywhere_small_and_odd_taps(dev, taps, pd):
+    """Matrix-core planes (BF16 and FP32) whose rows start anywhere, with 2 taps (the
     kept samples reach the segment's last run) and 130 (an odd half-width):
     single calls and one batch, plain and fused.  The batch's planes are
     bitwise the single calls', the fused planes bitwise the plain ones, and
@@ -133,28 +134,29 @@ def test_fused_rows_anywhere_small_and_odd_taps(dev, taps):
     from paper_2206_12205_amd.fdas import Plan
     lengths = [9001, 12347, 3 * 4096 + 5, 20002, 7]
     kw = dict(z_min=ZMIN, z_step=ZSTEP, n_z=NZ, n_taps=taps, seg_len=4096, compute="bf16",
-              plane_dtype="bf16", algo="mfma", device=dev)
+              plane_dtype=pd, algo="mfma", device=dev)
+    it = torch.int16 if pd == "bf16" else torch.int32
     pl = Plan(max_bins=max(lengths), max_jobs=len(lengths), **kw)
     specs = [to_dev(spectrum(v, 700 + taps + i), dev) for i, v in enumerate(lengths)]
     singles = []
     for i, x in enumerate(specs):
-        say(f"[fused] rows anywhere taps={taps} single n={lengths[i]}")
+        say(f"[fused] rows anywhere taps={taps} {pd} single n={lengths[i]}")
         ref = pl.correlate(x)
         singles.append(ref)
         for thr, cap in ((12.0, 1 << 14), (-1.0, 1 << 20)):
             plane, got = pl.correlate_peaks(x, thr, capacity=cap, truncate=True)
-            assert torch.equal(plane.view(torch.int16), ref.view(torch.int16)), f"n={lengths[i]} fused plane"
+            assert torch.equal(plane.view(it), ref.view(it)), f"n={lengths[i]} fused plane"
             assert_same_peaks(got, widen(ref), thr, cap, what=f"single n={lengths[i]} thr={thr}")
-    say(f"[fused] rows anywhere taps={taps} batch")
+    say(f"[fused] rows anywhere taps={taps} {pd} batch")
     pl.set_batch(lengths)
     spectra = torch.cat(specs)
     planes = pl.correlate_batch(spectra)
     for i in range(len(lengths)):
-        assert torch.equal(pl.batch_plane(planes, i).view(torch.int16), singles[i].view(torch.int16)), \
+        assert torch.equal(pl.batch_plane(planes, i).view(it), singles[i].view(it)), \
             f"batch job {i} differs from its single call"
     for thr, cap in ((12.0, 1 << 14), (-1.0, 1 << 20)):
         fused, got = pl.correlate_batch_peaks(spectra, thr, capacity=cap, truncate=True)
-        assert torch.equal(fused.view(torch.int16), planes.view(torch.int16)), "fused batch planes"
+        assert torch.equal(fused.view(it), planes.view(it)), "fused batch planes"
         for i in range(len(lengths)):
             assert_same_peaks(got[i], widen(singles[i]), thr, cap, job=i, what=f"batch job {i} thr={thr}")
 

@@ -360,12 +360,13 @@ def test_mfma_plane_vs_oracle(dev, n, M, nz, zmin, zstep, zc, pd, L):
     say(f"  max {err.max():.3e} mean {err.mean():.3e}")
 
 
+@pytest.mark.parametrize("pd", ["bf16", "fp32"])
 @pytest.mark.parametrize("M", [256, 130, 2])
-def test_mfma_bf16_rows_at_every_alignment(dev, M):
-    # The BF16 plane stores 16-byte runs aligned in memory whatever the row
-    # start: rows of n = n0 + r bins (r = 0..7) start at every offset mod 8
-    # (the persistent batch kernel, whose job planes start anywhere, is held
-    # bitwise to these single calls elsewhere).
+def test_mfma_rows_at_every_alignment(dev, M, pd):
+    # The matrix-core plane stores 16-byte runs aligned in memory whatever
+    # the row start: rows of n = n0 + r bins (r = 0..7) start at every offset
+    # mod 8 (BF16) or mod 4 (FP32) (the persistent batch kernel, whose job
+    # planes start anywhere, is held bitwise to these single calls elsewhere).
     # A cell depends on n only through its segment's window, so every
     # column whose window ends inside n0 must come out bitwise the same for
     # all n; every cell of the plane is written and nothing outside it.
@@ -374,17 +375,18 @@ def test_mfma_bf16_rows_at_every_alignment(dev, M):
     n0 = 5 * V + 1000
     x = synth.random_spectrum(n0 + 8, seed=811 + M)
     pl = plan(dev, max_bins=n0 + 8, z_min=-8.0, z_step=2.0, n_z=nz, n_taps=M, seg_len=L,
-              compute="bf16", plane_dtype="bf16", algo="mfma")
+              compute="bf16", plane_dtype=pd, algo="mfma")
+    dt, it = (torch.bfloat16, torch.int16) if pd == "bf16" else (torch.float32, torch.int32)
     n_same = max(s for s in range(1, n0 // V + 2) if (s - 1) * V - half + L <= n0) * V
     ref = None
     for r in range(8):
         n = n0 + r
-        say(f"[rows] M={M} n={n}")
-        buf = torch.full((nz * n + 16,), float("nan"), dtype=torch.bfloat16, device=dev)
+        say(f"[rows] M={M} n={n} {pd}")
+        buf = torch.full((nz * n + 16,), float("nan"), dtype=dt, device=dev)
         plane = buf[: nz * n].view(nz, n)
         pl.correlate(to_dev(x[:n], dev), plane=plane)
         torch.cuda.synchronize()
-        host = buf.view(torch.int16).cpu().numpy()
+        host = buf.view(it).cpu().numpy()
         assert np.all(host[nz * n:] == host[-1]), "a store fell outside the plane"
         cells = host[: nz * n].reshape(nz, n)
         assert np.isfinite(plane.float().cpu().numpy()).all(), "a plane cell was not written"
