@@ -167,21 +167,21 @@ int fdas_plan(const fdas_config *cfg, fdas_plan_t *out, size_t *workspace_bytes)
     p->mfma = mfma_ok && c.algo != FDAS_ALGO_VALU;
     int zc = c.z_chunk;
     if (zc == 0) {
-        // vector-ALU kernel: eight chunks, one per XCD; L = 8192 matrix-core
-        // kernel: four chunks.  L = 4096 matrix-core kernel: each chunk
+        // vector-ALU and L = 8192 matrix-core kernels: eight chunks, one per
+        // XCD (L = 8192, single-DM plane: 0.73 ms against 0.80 ms with four
+        // chunks and 0.84-1.0 ms with 7 to 15 templates per chunk, when the
+        // chunks no longer map one to an XCD).  L = 4096 matrix-core kernel: each chunk
         // repeats the segment's forward transform, so two chunks, or more
         // when the segments of max_bins give fewer than 512 workgroups (one
         // per slot of a 256-CU device at two per CU); measured on the
         // single-DM and wide planes: two chunks 1.5 % / 2 % faster than
         // three, one chunk slower.
-        if (!p->mfma) {
+        if (!p->mfma || L == fdas::m8k::kL) {
             zc = (c.n_z + 7) / 8;
         } else if (L == fdas::m4k::kL) {
             const int64_t segs = (c.max_bins + (L - c.n_taps) - 1) / (L - c.n_taps);
             const int64_t nc = std::max<int64_t>(2, (512 + segs - 1) / segs);
             zc = (int)((c.n_z + nc - 1) / nc);
-        } else {
-            zc = (c.n_z + 3) / 4;
         }
     }
     if (zc > c.n_z) zc = c.n_z;
